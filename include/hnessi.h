@@ -1,0 +1,208 @@
+/*
+ * hnessi.h - compressed history integrals of Kadanoff-Baym time stepping on one
+ * AMD Instinct MI355X (gfx950).  C ABI.
+ *
+ * What is computed (H-NESSi paper, arXiv 2604.05319):
+ *   Two-time functions are stored as lower triangles on the grid t_j = j h
+ *   (section "Green's functions and Keldysh components"):
+ *       retarded  L^R[t1][t2] = C^R(t1, t2),  t1 >= t2
+ *       lesser    L^<[t1][t2] = C^<(t2, t1),  t1 >= t2
+ *   each entry an norb x norb complex matrix, orbital indices innermost and
+ *   row-major.  Row n of a component is (n+1) x norb x norb complex128.
+ *   The finished off-diagonal parts are kept as hierarchical (HODLR) blocks,
+ *   each orbital pair of each block as a truncated SVD U S V^dagger with the
+ *   singular values below eps_SVD dropped (sections "Hierarchical
+ *   decomposition" and "Multiorbital compression"); diagonal leaves and the
+ *   rows not yet compressed are kept dense.
+ *   At step n the history integrals (right-hand sides of the retarded and
+ *   lesser Kadanoff-Baym equations, section "Kadanoff-Baym equations", with
+ *   Gregory quadrature of order k, appendix "Integral and derivative
+ *   approximations") are, for every m <= n:
+ *       I^R(n,m) = h sum_{j=m..n} w^{(n-m)}_{j-m} Sigma^R(n,j) G^R(j,m)
+ *       I^<(n,m) = h sum_{s=0..n} w^{(n)}_s Sigma^R(n,s) G^<(s,m)
+ *                + h sum_{s=0..m} w^{(m)}_s Sigma^<(n,s) G^A(s,m)
+ *   with G^<(s,m) = -[G^<(m,s)]^dagger, G^A(s,m) = [G^R(m,s)]^dagger and
+ *   Sigma^<(n,s) = -[Sigma^<(s,n)]^dagger (the paper's symmetry relations).
+ *   The interval weights w^{(L)} are unit inside and carry the Gregory end
+ *   weights omega_0..omega_k (partial sums of the (k+1)-step Adams-Moulton
+ *   coefficients) at both ends for L >= k, and are the closed Newton-Cotes
+ *   weights for 1 <= L < k; w^{(0)} = 0.
+ *
+ * Conventions for every call:
+ *   - Data pointers marked "device" are device pointers (e.g. from contiguous
+ *     complex128 torch tensors); "host" pointers are host memory.
+ *   - `stream` is a hipStream_t (NULL = default stream).  Calls enqueue work on
+ *     it and return without waiting, unless documented otherwise.
+ *   - Argument, ordering and range errors are detected on the host before any
+ *     work is enqueued; the call then returns a negative hnessi_status and
+ *     hnessi_last_error() describes it.  Device-side conditions (rank cap
+ *     reached, non-finite data in a truncation) set flags read by
+ *     hnessi_hodlr_status().
+ *   - A handle is not thread-safe; use one host thread per handle.
+ *   - The caller owns all inputs and outputs; a handle owns its own device
+ *     storage (factors, leaves, tail rows, band, scratch).
+ */
+#ifndef HNESSI_H
+#define HNESSI_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hnessi_hodlr_s* hnessi_hodlr_t;
+typedef struct hnessi_dense_s* hnessi_dense_t;
+
+typedef enum { HNESSI_RET = 0, HNESSI_LES = 1 } hnessi_comp;
+
+typedef enum {
+    HNESSI_OK = 0,
+    HNESSI_E_ARG = -1,     /* invalid argument (null pointer, size out of range)          */
+    HNESSI_E_ORDER = -2,   /* rows appended out of order, or history before the row exists */
+    HNESSI_E_RANGE = -3,   /* time index outside the grid or the stored region            */
+    HNESSI_E_NOMEM = -4,   /* device allocation failed                                    */
+    HNESSI_E_DEVICE = -5,  /* a HIP runtime call failed                                   */
+    HNESSI_E_RANK = -6,    /* a truncation needed more than max_rank singular values      */
+    HNESSI_E_VALUE = -7    /* a truncation met non-finite data (NaN or Inf in the rows)   */
+} hnessi_status;
+
+/* Flags for hnessi_hodlr_create. */
+#define HNESSI_FLAG_NONE 0
+
+/* Message for the last failing call on this host thread (never NULL). */
+const char* hnessi_last_error(void);
+
+/* Interval quadrature weights w^{(L)}_i, i = 0..L, for Gregory order k (1..5),
+ * written to w_host[0..L] (host).  Appendix "Integral and derivative
+ * approximations".  Returns HNESSI_E_ARG for k outside 1..5 or L < 0. */
+int hnessi_weights(int k, int L, double* w_host);
+
+/* ---------------------------------------------------------------------------
+ * HODLR-compressed storage of the retarded and lesser components
+ * (the paper's herm_matrix_hodlr for its R and < parts).
+ * ------------------------------------------------------------------------- */
+
+/* Create a handle for nt time steps.
+ *   nlvl     number of hierarchical levels; level l holds 2^(l-1) off-diagonal
+ *            blocks of about nt/2^l rows (section "Hierarchical decomposition");
+ *            the 2^nlvl diagonal leaves are kept dense.  The smallest leaf must
+ *            hold at least k+1 rows and the panel.
+ *   norb     orbital dimension: 1, 2, 4, 8 or 16.
+ *   k        Gregory order, 1..5.
+ *   svd_tol  absolute truncation threshold eps_SVD > 0: singular values
+ *            sigma >= svd_tol are kept.
+ *   panel    rows per compression panel P (1..16); a panel also ends at
+ *            every leaf start, so it need not divide the leaf size.
+ *   max_rank rank capacity per block and orbital pair; max_rank + panel <= 32
+ *            (the width of the small SVD solved at each merge).
+ * Every leaf must hold at most 64 rows.
+ * Allocates all device storage (synchronously).  On success *out is set. */
+int hnessi_hodlr_create(hnessi_hodlr_t* out, int nt, int nlvl, int norb, int k,
+                        double svd_tol, int panel, int max_rank, int flags, void* stream);
+
+int hnessi_hodlr_destroy(hnessi_hodlr_t H);
+
+/* Forget all rows (start a new sweep from n = 0); storage is kept. */
+int hnessi_hodlr_reset(hnessi_hodlr_t H, void* stream);
+
+/* Append row n of component c (device pointer, (n+1)*norb*norb complex128):
+ *   HNESSI_RET: G^R(t_n, t_j), j = 0..n
+ *   HNESSI_LES: G^<(t_s, t_n), s = 0..n   (the paper's stored lesser slice)
+ * n must equal the previous row of that component plus one (HNESSI_E_ORDER).
+ * When the row completes a panel, the panel is merged into the truncated SVDs
+ * of the blocks it belongs to (incremental TSVD update, section "Hierarchical
+ * decomposition").  The input may be reused once the stream reaches the call. */
+int hnessi_hodlr_append_row(hnessi_hodlr_t H, int c, int n, const void* row, void* stream);
+
+/* I^R(n, m), m = 0..n, into out (device, (n+1)*norb*norb complex128).
+ * sigR_row: Sigma^R(t_n, t_j), j = 0..n (device).  Needs retarded rows 0..n. */
+int hnessi_history_R(hnessi_hodlr_t H, int n, const void* sigR_row, double h,
+                     void* out, void* stream);
+
+/* I^<(n, m), m = 0..n, into out (device).  sigL_slice: Sigma^<(t_s, t_n),
+ * s = 0..n (device, stored orientation).  Needs both components up to row n. */
+int hnessi_history_lesser(hnessi_hodlr_t H, int n, const void* sigR_row,
+                          const void* sigL_slice, double h, void* out, void* stream);
+
+/* Both integrals of step n in one pass over the stored data (each stored
+ * factor is used for every product it enters).  outR / outL as above. */
+int hnessi_history_step(hnessi_hodlr_t H, int n, const void* sigR_row, const void* sigL_slice,
+                        double h, void* outR, void* outL, void* stream);
+
+/* A whole sweep n = n_begin..n_end-1 driven natively: for each n, append
+ * G^R row n and G^< row n, then hnessi_history_step.  All arrays are device
+ * packed lower triangles, row n at element offset n(n+1)/2 (times norb^2):
+ *   GR, GL  rows of the two components as for append_row;
+ *   SR, SL  Sigma^R rows and Sigma^< slices as for the history calls;
+ *   IR, IL  outputs I^R(n, .), I^<(n, .).
+ * n_begin must be the next row to append. */
+int hnessi_sweep(hnessi_hodlr_t H, int n_begin, int n_end, const void* GR, const void* GL,
+                 const void* SR, const void* SL, double h, void* IR, void* IL, void* stream);
+
+/* Device-side status, after synchronizing `stream`: HNESSI_OK; HNESSI_E_RANK
+ * if any truncation needed more than max_rank singular values (the excess
+ * ones were dropped and the eps_SVD guarantee does not hold); HNESSI_E_VALUE
+ * if a truncation met non-finite data (those directions were dropped).  The
+ * flags stay set until hnessi_hodlr_reset. */
+int hnessi_hodlr_status(hnessi_hodlr_t H, void* stream);
+
+/* Value of component c at (t1, t2), t1 >= t2, t1 <= last appended row,
+ * reconstructed from whichever storage holds it (dense leaf, dense row, or
+ * truncated SVD), into out_host (norb*norb complex128).  Synchronous. */
+int hnessi_hodlr_get(hnessi_hodlr_t H, int c, int t1, int t2, void* out_host);
+
+/* Ranks of component c: ranks_host[b*norb*norb + q] for block b (in the
+ * order of hnessi_hodlr_blocks) and orbital pair q.  Synchronous.  Returns the
+ * number of entries written, or a negative status. */
+int hnessi_hodlr_ranks(hnessi_hodlr_t H, int c, int* ranks_host, int capacity);
+
+/* Block table: for block b, rows [r0, r1) and columns [c0, c1), level in
+ * 1..nlvl; tab_host[5*b + {0..4}] = level, r0, r1, c0, c1.  Host only.
+ * Returns the number of blocks (or a negative status). */
+int hnessi_hodlr_blocks(hnessi_hodlr_t H, int* tab_host, int capacity);
+
+/* Leaf table: tab_host[2*i + {0,1}] = s0, s1.  Returns the number of leaves. */
+int hnessi_hodlr_leaves(hnessi_hodlr_t H, int* tab_host, int capacity);
+
+/* Device bytes held by the handle (factor capacity, leaves, tail, band, scratch). */
+size_t hnessi_hodlr_bytes(hnessi_hodlr_t H);
+
+/* ---------------------------------------------------------------------------
+ * Truncated SVD of one dense block (section "Hierarchical decomposition"):
+ * A (device, rows x cols complex128, row-major with leading dimension lda)
+ * ~ U diag(S) V^dagger keeping singular values >= tol (absolute, > 0).
+ *   U: device, column-major rows x max_rank (column r at U + r*rows)
+ *   S: device, max_rank doubles, non-increasing
+ *   V: device, column-major cols x max_rank
+ *   rank_out: device int, the kept rank (<= max_rank)
+ * Rows are merged in panels, exactly as the HODLR blocks are built.  If more
+ * than max_rank values reach tol, the largest max_rank are kept and the call
+ * still returns HNESSI_OK; compare *rank_out with max_rank to detect it.
+ * max_rank + 16 <= 64.  Synchronous with respect to the host for its own
+ * scratch allocation; the factorization itself runs on `stream`. */
+int hnessi_compress_block(const void* A, int rows, int cols, int lda, double tol, int max_rank,
+                          void* U, double* S, void* V, int* rank_out, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Dense storage (the uncompressed baseline on the same device): both
+ * components as full packed lower triangles, the same history integrals by
+ * direct summation (one read of every stored entry per step).
+ * ------------------------------------------------------------------------- */
+int hnessi_dense_create(hnessi_dense_t* out, int nt, int norb, int k, void* stream);
+int hnessi_dense_destroy(hnessi_dense_t D);
+int hnessi_dense_reset(hnessi_dense_t D, void* stream);
+int hnessi_dense_append_row(hnessi_dense_t D, int c, int n, const void* row, void* stream);
+int hnessi_dense_history_step(hnessi_dense_t D, int n, const void* sigR_row,
+                              const void* sigL_slice, double h, void* outR, void* outL,
+                              void* stream);
+int hnessi_dense_sweep(hnessi_dense_t D, int n_begin, int n_end, const void* GR, const void* GL,
+                       const void* SR, const void* SL, double h, void* IR, void* IL,
+                       void* stream);
+size_t hnessi_dense_bytes(hnessi_dense_t D);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HNESSI_H */

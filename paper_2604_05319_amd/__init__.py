@@ -1,0 +1,7 @@
+"""Compressed history integrals of Kadanoff-Baym time stepping on AMD MI355X.
+
+The compute path is the HIP library libhnessi.so (C ABI in include/hnessi.h);
+this package only marshals arguments to it.
+"""
+from ._lib import (RET, LES, Dense, Hodlr, HnessiError, compress_block,  # noqa: F401
+                   exported_names, lib, weights, LIB_PATH)

@@ -1,0 +1,241 @@
+"""ctypes binding of libhnessi.so (argument marshalling only).
+
+Every call forwards to the C ABI declared in include/hnessi.h; device arrays
+are contiguous complex128 torch tensors on the GPU and streams are torch's
+current HIP stream.  There is no fallback: if the library or the GPU is
+missing, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhnessi.so")
+
+RET, LES = 0, 1
+
+STATUS = {0: "OK", -1: "E_ARG", -2: "E_ORDER", -3: "E_RANGE", -4: "E_NOMEM", -5: "E_DEVICE",
+          -6: "E_RANK", -7: "E_VALUE"}
+
+
+class HnessiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+_SIGS = {
+    "hnessi_last_error": ([], C.c_char_p),
+    "hnessi_weights": ([C.c_int, C.c_int, C.c_void_p], C.c_int),
+    "hnessi_hodlr_create": ([C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
+                             C.c_int, C.c_int, C.c_int, C.c_void_p], C.c_int),
+    "hnessi_hodlr_destroy": ([C.c_void_p], C.c_int),
+    "hnessi_hodlr_reset": ([C.c_void_p, C.c_void_p], C.c_int),
+    "hnessi_hodlr_append_row": ([C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p], C.c_int),
+    "hnessi_history_R": ([C.c_void_p, C.c_int, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p], C.c_int),
+    "hnessi_history_lesser": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p,
+                               C.c_void_p], C.c_int),
+    "hnessi_history_step": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p,
+                             C.c_void_p, C.c_void_p], C.c_int),
+    "hnessi_sweep": ([C.c_void_p, C.c_int, C.c_int] + [C.c_void_p] * 4 + [C.c_double]
+                     + [C.c_void_p] * 3, C.c_int),
+    "hnessi_hodlr_status": ([C.c_void_p, C.c_void_p], C.c_int),
+    "hnessi_hodlr_get": ([C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p], C.c_int),
+    "hnessi_hodlr_ranks": ([C.c_void_p, C.c_int, C.c_void_p, C.c_int], C.c_int),
+    "hnessi_hodlr_blocks": ([C.c_void_p, C.c_void_p, C.c_int], C.c_int),
+    "hnessi_hodlr_leaves": ([C.c_void_p, C.c_void_p, C.c_int], C.c_int),
+    "hnessi_hodlr_bytes": ([C.c_void_p], C.c_size_t),
+    "hnessi_compress_block": ([C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, C.c_void_p,
+                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "hnessi_dense_create": ([C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_int, C.c_void_p], C.c_int),
+    "hnessi_dense_destroy": ([C.c_void_p], C.c_int),
+    "hnessi_dense_reset": ([C.c_void_p, C.c_void_p], C.c_int),
+    "hnessi_dense_append_row": ([C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p], C.c_int),
+    "hnessi_dense_history_step": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p,
+                                   C.c_void_p, C.c_void_p], C.c_int),
+    "hnessi_dense_sweep": ([C.c_void_p, C.c_int, C.c_int] + [C.c_void_p] * 4 + [C.c_double]
+                           + [C.c_void_p] * 3, C.c_int),
+    "hnessi_dense_bytes": ([C.c_void_p], C.c_size_t),
+}
+
+
+def lib():
+    """Load the library (once) and declare every exported call."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def exported_names():
+    return list(_SIGS)
+
+
+def _check(rc):
+    if rc < 0:
+        raise HnessiError(rc, lib().hnessi_last_error().decode())
+    return rc
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError("device tensor expected (the library runs on the GPU only)")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    if t.dtype not in (torch.complex128, torch.float64, torch.int32):
+        raise ValueError(f"unsupported dtype {t.dtype}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def weights(k: int, L: int) -> np.ndarray:
+    w = np.zeros(L + 1, dtype=np.float64)
+    _check(lib().hnessi_weights(k, L, w.ctypes.data_as(C.c_void_p)))
+    return w
+
+
+class Hodlr:
+    """HODLR-compressed retarded and lesser components (one handle, one stream)."""
+
+    def __init__(self, nt, nlvl, norb, k=5, tol=1e-10, panel=16, max_rank=16, flags=0):
+        h = C.c_void_p()
+        _check(lib().hnessi_hodlr_create(C.byref(h), nt, nlvl, norb, k, tol, panel, max_rank, flags,
+                                         _stream()))
+        self.h = h
+        self.nt, self.nlvl, self.norb, self.k = nt, nlvl, norb, k
+        self.tol, self.panel, self.max_rank = tol, panel, max_rank
+
+    def close(self):
+        if self.h:
+            _check(lib().hnessi_hodlr_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reset(self):
+        _check(lib().hnessi_hodlr_reset(self.h, _stream()))
+
+    def append_row(self, comp, n, row):
+        _check(lib().hnessi_hodlr_append_row(self.h, comp, n, _ptr(row), _stream()))
+
+    def history_R(self, n, sigR, h, out):
+        _check(lib().hnessi_history_R(self.h, n, _ptr(sigR), h, _ptr(out), _stream()))
+
+    def history_lesser(self, n, sigR, sigL, h, out):
+        _check(lib().hnessi_history_lesser(self.h, n, _ptr(sigR), _ptr(sigL), h, _ptr(out), _stream()))
+
+    def history_step(self, n, sigR, sigL, h, outR, outL):
+        _check(lib().hnessi_history_step(self.h, n, _ptr(sigR), _ptr(sigL), h, _ptr(outR), _ptr(outL),
+                                         _stream()))
+
+    def sweep(self, n_begin, n_end, GR, GL, SR, SL, h, IR, IL):
+        _check(lib().hnessi_sweep(self.h, n_begin, n_end, _ptr(GR), _ptr(GL), _ptr(SR), _ptr(SL), h,
+                                  _ptr(IR), _ptr(IL), _stream()))
+
+    def status(self):
+        return _check(lib().hnessi_hodlr_status(self.h, _stream()))
+
+    def get(self, comp, t1, t2):
+        out = np.zeros((self.norb, self.norb), dtype=np.complex128)
+        _check(lib().hnessi_hodlr_get(self.h, comp, t1, t2, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def blocks(self):
+        cap = 5 * (2 ** self.nlvl)
+        tab = np.zeros(cap, dtype=np.int32)
+        nb = _check(lib().hnessi_hodlr_blocks(self.h, tab.ctypes.data_as(C.c_void_p), cap))
+        return tab[:5 * nb].reshape(nb, 5)
+
+    def leaves(self):
+        cap = 2 * (2 ** self.nlvl)
+        tab = np.zeros(cap, dtype=np.int32)
+        nl = _check(lib().hnessi_hodlr_leaves(self.h, tab.ctypes.data_as(C.c_void_p), cap))
+        return tab[:2 * nl].reshape(nl, 2)
+
+    def ranks(self, comp):
+        nb = self.blocks().shape[0]
+        cap = max(nb * self.norb ** 2, 1)
+        r = np.zeros(cap, dtype=np.int32)
+        cnt = _check(lib().hnessi_hodlr_ranks(self.h, comp, r.ctypes.data_as(C.c_void_p), cap))
+        return r[:cnt].reshape(nb, self.norb ** 2)
+
+    def nbytes(self):
+        return int(lib().hnessi_hodlr_bytes(self.h))
+
+
+class Dense:
+    """Uncompressed storage of both components and direct-summation history integrals."""
+
+    def __init__(self, nt, norb, k=5):
+        h = C.c_void_p()
+        _check(lib().hnessi_dense_create(C.byref(h), nt, norb, k, _stream()))
+        self.h = h
+        self.nt, self.norb, self.k = nt, norb, k
+
+    def close(self):
+        if self.h:
+            _check(lib().hnessi_dense_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reset(self):
+        _check(lib().hnessi_dense_reset(self.h, _stream()))
+
+    def append_row(self, comp, n, row):
+        _check(lib().hnessi_dense_append_row(self.h, comp, n, _ptr(row), _stream()))
+
+    def history_step(self, n, sigR, sigL, h, outR, outL):
+        _check(lib().hnessi_dense_history_step(self.h, n, _ptr(sigR), _ptr(sigL), h, _ptr(outR),
+                                               _ptr(outL), _stream()))
+
+    def sweep(self, n_begin, n_end, GR, GL, SR, SL, h, IR, IL):
+        _check(lib().hnessi_dense_sweep(self.h, n_begin, n_end, _ptr(GR), _ptr(GL), _ptr(SR), _ptr(SL),
+                                        h, _ptr(IR), _ptr(IL), _stream()))
+
+    def nbytes(self):
+        return int(lib().hnessi_dense_bytes(self.h))
+
+
+def compress_block(A, tol, max_rank):
+    """TSVD of a dense device block A (rows x cols complex128).  Returns (U, S, V, rank)."""
+    import torch
+    rows, cols = A.shape
+    U = torch.zeros((max_rank, rows), dtype=torch.complex128, device=A.device)
+    V = torch.zeros((max_rank, cols), dtype=torch.complex128, device=A.device)
+    S = torch.zeros(max_rank, dtype=torch.float64, device=A.device)
+    rk = torch.zeros(1, dtype=torch.int32, device=A.device)
+    _check(lib().hnessi_compress_block(_ptr(A), rows, cols, cols, tol, max_rank, _ptr(U), _ptr(S),
+                                       _ptr(V), _ptr(rk), _stream()))
+    r = int(rk.item())
+    return U[:r].T.contiguous(), S[:r].clone(), V[:r].T.contiguous(), r

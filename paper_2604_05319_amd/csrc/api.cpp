@@ -1,0 +1,846 @@
+// C ABI of the compressed history-integral library (see include/hnessi.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/hnessi.h"
+#include "common.h"
+#include "dense.h"
+#include "history.h"
+#include "merge.h"
+#include "store.h"
+
+using namespace hn;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(HNESSI_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+bool g_init = false;
+int lib_init() {
+    if (g_init) return HNESSI_OK;
+    HIP_TRY(merge_init());
+    HIP_TRY(history_init());
+    HIP_TRY(dense_init());
+    g_init = true;
+    return HNESSI_OK;
+}
+
+// device allocations owned by a handle
+struct Allocs {
+    std::vector<void*> ptrs;
+    size_t bytes = 0;
+    template <class T>
+    int alloc(T*& p, size_t count, bool zero = false) {
+        p = nullptr;
+        if (count == 0) count = 1;
+        size_t nb = count * sizeof(T);
+        void* q = nullptr;
+        hipError_t e = hipMalloc(&q, nb);
+        if (e != hipSuccess) return fail(HNESSI_E_NOMEM, "hipMalloc of " + std::to_string(nb) + " bytes failed");
+        if (zero) {
+            e = hipMemset(q, 0, nb);
+            if (e != hipSuccess) {
+                hipFree(q);
+                return fail(HNESSI_E_DEVICE, "hipMemset failed");
+            }
+        }
+        ptrs.push_back(q);
+        bytes += nb;
+        p = static_cast<T*>(q);
+        return HNESSI_OK;
+    }
+    void release() {
+        for (void* q : ptrs) hipFree(q);
+        ptrs.clear();
+        bytes = 0;
+    }
+};
+
+#define ALLOC(al, p, n, z)                       \
+    do {                                         \
+        int rc_ = (al).alloc((p), (n), (z));     \
+        if (rc_ != HNESSI_OK) return rc_;        \
+    } while (0)
+
+int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+}  // namespace
+
+struct hnessi_hodlr_s {
+    int nt = 0, nlvl = 0, norb = 0, npair = 0, k = 0, P = 0, RC = 0, flags = 0;
+    double tol = 0.0;
+    Weights W{};
+    Geometry g;
+    Allocs al;
+    // geometry on the device
+    int* d_blk = nullptr;
+    int* d_leaf = nullptr;
+    int* d_cover = nullptr;
+    long long* d_Uoff = nullptr;
+    long long* d_Voff = nullptr;
+    long long* d_Loff = nullptr;
+    long long* d_partoff = nullptr;
+    std::vector<long long> Uoff, Voff, Loff;
+    // per component
+    cd* U[2] = {};
+    cd* V[2] = {};
+    double* S[2] = {};
+    int* rank[2] = {};
+    cd* leaf[2] = {};
+    cd* tail[2] = {};
+    cd* band = nullptr;
+    int last[2] = {-1, -1};
+    int n0[2] = {0, 0};
+    // projection tasks, sorted by activation row
+    FactTask* d_ft[2] = {};
+    std::vector<int> ft_act[2];
+    // history scratch
+    cd* proj = nullptr;
+    cd* part = nullptr;
+    int* cnt = nullptr;
+    cd* leafR = nullptr;
+    cd* leafLR = nullptr;
+    cd* leafLL = nullptr;
+    cd* tailcol[2] = {};
+    cd* taildot[2] = {};
+    cd* tailpart[2] = {};
+    int* tailcnt = nullptr;
+    int ntailchunk_max = 0;
+    // merge scratch
+    std::vector<long long> lvl_node_base;  // per level: first node of pair 0
+    std::vector<int> lvl_nodes;            // per level: nodes per pair
+    cd* nodeR = nullptr;
+    cd* nodeQ = nullptr;
+    int* nodecnt = nullptr;
+    cd* UK = nullptr;
+    cd* VR = nullptr;
+    double* Sold = nullptr;
+    int* rold = nullptr;
+    int* err = nullptr;
+};
+
+struct hnessi_dense_s {
+    int nt = 0, norb = 0, npair = 0, k = 0;
+    Weights W{};
+    Allocs al;
+    long long trin = 0;
+    cd* L[2] = {};
+    cd* colR = nullptr;
+    cd* colL = nullptr;
+    cd* rowL = nullptr;
+    int last[2] = {-1, -1};
+};
+
+extern "C" {
+
+const char* hnessi_last_error(void) { return g_err.c_str(); }
+
+int hnessi_weights(int k, int L, double* w_host) {
+    if (!w_host) return fail(HNESSI_E_ARG, "w_host is NULL");
+    std::vector<double> w;
+    std::string err;
+    if (!interval_weights_exact(k, L, w, err)) return fail(HNESSI_E_ARG, err);
+    std::memcpy(w_host, w.data(), w.size() * sizeof(double));
+    return HNESSI_OK;
+}
+
+int hnessi_hodlr_create(hnessi_hodlr_t* out, int nt, int nlvl, int norb, int k, double svd_tol,
+                        int panel, int max_rank, int flags, void* stream) {
+    (void)stream;
+    if (!out) return fail(HNESSI_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!(norb == 1 || norb == 2 || norb == 4 || norb == 8 || norb == 16))
+        return fail(HNESSI_E_ARG, "norb must be 1, 2, 4, 8 or 16");
+    if (!(svd_tol > 0.0)) return fail(HNESSI_E_ARG, "svd_tol must be > 0");
+    if (panel < 1 || panel > 16) return fail(HNESSI_E_ARG, "panel must be in 1..16");
+    if (max_rank < 1 || max_rank + panel > kW)
+        return fail(HNESSI_E_ARG, "need 1 <= max_rank and max_rank + panel <= " + std::to_string(kW));
+    int rc = lib_init();
+    if (rc != HNESSI_OK) return rc;
+    auto* H = new hnessi_hodlr_s();
+    std::string err;
+    if (!make_weights(k, H->W, err) || !build_geometry(nt, nlvl, H->g, err)) {
+        delete H;
+        return fail(HNESSI_E_ARG, err);
+    }
+    const Geometry& g = H->g;
+    if (g.max_leaf > 64) {
+        delete H;
+        return fail(HNESSI_E_ARG, "leaves must hold at most 64 rows (increase nlvl)");
+    }
+    if (g.min_leaf < k + 1 || g.min_leaf < panel) {
+        delete H;
+        return fail(HNESSI_E_ARG, "leaves must hold at least k+1 rows and the panel");
+    }
+    H->nt = nt;
+    H->nlvl = nlvl;
+    H->norb = norb;
+    H->npair = norb * norb;
+    H->k = k;
+    H->P = panel;
+    H->RC = max_rank;
+    H->flags = flags;
+    H->tol = svd_tol;
+    const int npair = H->npair, RC = H->RC, nb = g.nb;
+    Allocs& al = H->al;
+    auto bail = [&](int code) {
+        al.release();
+        delete H;
+        return code;
+    };
+#define HALLOC(p, n, z)                                  \
+    do {                                                 \
+        int rc_ = al.alloc((p), (n), (z));               \
+        if (rc_ != HNESSI_OK) return bail(rc_);          \
+    } while (0)
+    // geometry
+    std::vector<int> blk(5 * std::max(nb, 1)), lf(2 * g.nleaf);
+    H->Uoff.assign(nb, 0);
+    H->Voff.assign(nb, 0);
+    long long uo = 0, vo = 0;
+    for (int b = 0; b < nb; ++b) {
+        blk[5 * b] = g.level[b];
+        blk[5 * b + 1] = g.r0[b];
+        blk[5 * b + 2] = g.r1[b];
+        blk[5 * b + 3] = g.c0[b];
+        blk[5 * b + 4] = g.c1[b];
+        H->Uoff[b] = uo;
+        H->Voff[b] = vo;
+        uo += (long long)npair * RC * (g.r1[b] - g.r0[b]);
+        vo += (long long)npair * RC * (g.c1[b] - g.c0[b]);
+    }
+    H->Loff.assign(g.nleaf, 0);
+    long long lo = 0;
+    for (int i = 0; i < g.nleaf; ++i) {
+        lf[2 * i] = g.s0[i];
+        lf[2 * i + 1] = g.s1[i];
+        H->Loff[i] = lo;
+        lo += (long long)npair * tri(g.s1[i] - g.s0[i]);
+    }
+    HALLOC(H->d_blk, blk.size(), false);
+    HALLOC(H->d_leaf, lf.size(), false);
+    HALLOC(H->d_cover, g.cover.size(), false);
+    HALLOC(H->d_Uoff, std::max(nb, 1), false);
+    HALLOC(H->d_Voff, std::max(nb, 1), false);
+    HALLOC(H->d_Loff, g.nleaf, false);
+    // projection partial slots
+    std::vector<long long> partoff((size_t)2 * std::max(nb, 1) * npair * 2, 0);
+    long long ps = 0;
+    for (int c = 0; c < 2; ++c)
+        for (int b = 0; b < nb; ++b)
+            for (int q = 0; q < npair; ++q)
+                for (int w = 0; w < 2; ++w) {
+                    partoff[(((size_t)c * nb + b) * npair + q) * 2 + w] = ps;
+                    int len = w == 0 ? g.r1[b] - g.r0[b] : g.c1[b] - g.c0[b];
+                    ps += div_up(len, kCH);
+                }
+    HALLOC(H->d_partoff, partoff.size(), false);
+    // factor and dense storage
+    for (int c = 0; c < 2; ++c) {
+        HALLOC(H->U[c], uo, true);
+        HALLOC(H->V[c], vo, true);
+        HALLOC(H->S[c], (size_t)std::max(nb, 1) * npair * RC, true);
+        HALLOC(H->rank[c], (size_t)std::max(nb, 1) * npair, true);
+        HALLOC(H->leaf[c], lo, true);
+        HALLOC(H->tail[c], (size_t)panel * npair * nt, true);
+    }
+    HALLOC(H->band, (size_t)nt * (k + 1) * npair, true);
+    HALLOC(H->proj, (size_t)2 * std::max(nb, 1) * npair * 2 * norb * RC, true);
+    HALLOC(H->part, (size_t)std::max(ps, 1LL) * norb * RC, true);
+    HALLOC(H->cnt, (size_t)2 * std::max(nb, 1) * npair * 2, true);
+    HALLOC(H->leafR, (size_t)nt * npair, true);
+    HALLOC(H->leafLR, (size_t)nt * npair, true);
+    HALLOC(H->leafLL, (size_t)nt * npair, true);
+    H->ntailchunk_max = div_up(nt, kTailCH);
+    for (int c = 0; c < 2; ++c) {
+        HALLOC(H->tailcol[c], (size_t)nt * npair, true);
+        HALLOC(H->taildot[c], (size_t)panel * npair, true);
+        HALLOC(H->tailpart[c], (size_t)norb * H->ntailchunk_max * panel * norb, true);
+    }
+    HALLOC(H->tailcnt, 2 * norb, true);
+    // merge scratch: one block per level per panel
+    H->lvl_node_base.assign(nlvl + 1, 0);
+    H->lvl_nodes.assign(nlvl + 1, 0);
+    long long nodes = 0;
+    for (int l = 1; l <= nlvl; ++l) {
+        int maxc = 0;
+        for (int b = 0; b < nb; ++b)
+            if (g.level[b] == l) maxc = std::max(maxc, g.c1[b] - g.c0[b]);
+        H->lvl_nodes[l] = 2 * div_up(maxc, kMergeCH);
+        H->lvl_node_base[l] = nodes;
+        nodes += (long long)npair * H->lvl_nodes[l];
+    }
+    const long long nprob = (long long)std::max(nlvl, 1) * npair;
+    HALLOC(H->nodeR, (size_t)std::max(nodes, 1LL) * kW * kW, false);
+    HALLOC(H->nodeQ, (size_t)std::max(nodes, 1LL) * kNodeQ, false);
+    HALLOC(H->nodecnt, (size_t)std::max(nodes, 1LL), true);
+    HALLOC(H->UK, (size_t)nprob * kW * kW, false);
+    HALLOC(H->VR, (size_t)nprob * kW * kW, false);
+    HALLOC(H->Sold, (size_t)nprob * kW, false);
+    HALLOC(H->rold, (size_t)nprob, false);
+    HALLOC(H->err, 1, true);
+    // projection task lists (sorted by the row that activates them)
+    for (int c = 0; c < 2; ++c) {
+        std::vector<FactTask> ts;
+        for (int b = 0; b < nb; ++b)
+            for (int q = 0; q < npair; ++q) {
+                int nr = g.r1[b] - g.r0[b], ncol = g.c1[b] - g.c0[b];
+                for (int ch = 0; ch < div_up(nr, kCH); ++ch)
+                    ts.push_back(FactTask{c, b, q, 0, ch, g.r0[b] + ch * kCH});
+                for (int ch = 0; ch < div_up(ncol, kCH); ++ch)
+                    ts.push_back(FactTask{c, b, q, 1, ch, g.r0[b]});
+            }
+        std::stable_sort(ts.begin(), ts.end(),
+                         [](const FactTask& x, const FactTask& y) { return x.act < y.act; });
+        H->ft_act[c].resize(ts.size());
+        for (size_t i = 0; i < ts.size(); ++i) H->ft_act[c][i] = ts[i].act;
+        HALLOC(H->d_ft[c], ts.size(), false);
+        if (!ts.empty() &&
+            hipMemcpy(H->d_ft[c], ts.data(), ts.size() * sizeof(FactTask), hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(HNESSI_E_DEVICE, "copy of task table failed"));
+    }
+    if (hipMemcpy(H->d_blk, blk.data(), blk.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(H->d_leaf, lf.data(), lf.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(H->d_cover, g.cover.data(), g.cover.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        (nb > 0 && hipMemcpy(H->d_Uoff, H->Uoff.data(), nb * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess) ||
+        (nb > 0 && hipMemcpy(H->d_Voff, H->Voff.data(), nb * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess) ||
+        hipMemcpy(H->d_Loff, H->Loff.data(), g.nleaf * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(H->d_partoff, partoff.data(), partoff.size() * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(HNESSI_E_DEVICE, "copy of geometry failed"));
+#undef HALLOC
+    *out = H;
+    return HNESSI_OK;
+}
+
+int hnessi_hodlr_destroy(hnessi_hodlr_t H) {
+    if (!H) return fail(HNESSI_E_ARG, "handle is NULL");
+    hipDeviceSynchronize();
+    H->al.release();
+    delete H;
+    return HNESSI_OK;
+}
+
+int hnessi_hodlr_reset(hnessi_hodlr_t H, void* stream) {
+    if (!H) return fail(HNESSI_E_ARG, "handle is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    for (int c = 0; c < 2; ++c) {
+        HIP_TRY(hipMemsetAsync(H->rank[c], 0, sizeof(int) * std::max(H->g.nb, 1) * H->npair, st));
+        H->last[c] = -1;
+        H->n0[c] = 0;
+    }
+    HIP_TRY(hipMemsetAsync(H->err, 0, sizeof(int), st));
+    return HNESSI_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+int merge_panel(hnessi_hodlr_t H, int c, int p0, int p1, hipStream_t st) {
+    const Geometry& g = H->g;
+    MergeArgs a{};
+    a.pp = p1 - p0;
+    a.npair = H->npair;
+    a.RC = H->RC;
+    a.tol = H->tol;
+    a.U = H->U[c];
+    a.V = H->V[c];
+    a.S = H->S[c];
+    a.rank = H->rank[c];
+    a.src = H->tail[c];
+    a.src_row = (long long)H->npair * H->nt;
+    a.src_pair = H->nt;
+    a.nodeR = H->nodeR;
+    a.nodeQ = H->nodeQ;
+    a.nodecnt = H->nodecnt;
+    a.UK = H->UK;
+    a.VR = H->VR;
+    a.Sold = H->Sold;
+    a.rold = H->rold;
+    a.err = H->err;
+    int nv = 0, nu = 0, nblk = 0;
+    for (int l = 0; l < H->nlvl; ++l) {
+        int cv = g.cover[(size_t)l * H->nt + p0];
+        if (cv >= 0) continue;
+        int b = ~cv;
+        if (nblk >= kMaxMergeBlk) return fail(HNESSI_E_ARG, "too many levels for one merge");
+        MergeBlk& B = a.blk[nblk];
+        B.b = b;
+        B.c0 = g.c0[b];
+        B.ncols = g.c1[b] - g.c0[b];
+        B.ldU = g.r1[b] - g.r0[b];
+        B.kb = p0 - g.r0[b];
+        B.nchunks = div_up(B.ncols, kMergeCH);
+        B.task_off = nv;
+        B.utask_off = nu;
+        B.nutask = div_up(B.kb + a.pp, 256);
+        B.nnodes = H->lvl_nodes[g.level[b]];
+        B.node_base = H->lvl_node_base[g.level[b]];
+        B.Uoff = H->Uoff[b];
+        B.Voff = H->Voff[b];
+        nv += H->npair * B.nchunks;
+        nu += H->npair * B.nutask;
+        ++nblk;
+    }
+    if (nblk == 0) return HNESSI_OK;
+    a.nblk = nblk;
+    a.ntask_v = nv;
+    a.ntask_u = nu;
+    HIP_TRY(launch_merge(a, st));
+    return HNESSI_OK;
+}
+
+bool panel_ends(hnessi_hodlr_t H, int c, int n) {
+    if (n + 1 >= H->nt) return true;
+    if (n + 1 - H->n0[c] >= H->P) return true;
+    return H->g.row_leaf[n + 1] != H->g.row_leaf[n];
+}
+
+int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, double h, void* outR,
+               void* outL, bool wantR, bool wantL, hipStream_t st) {
+    if (n < 0 || n >= H->nt) return fail(HNESSI_E_RANGE, "n outside the grid");
+    if (!sigR) return fail(HNESSI_E_ARG, "sigR_row is NULL");
+    if (wantR && !outR) return fail(HNESSI_E_ARG, "output is NULL");
+    if (wantL && (!outL || !sigL)) return fail(HNESSI_E_ARG, "lesser input or output is NULL");
+    if (H->last[0] != n) return fail(HNESSI_E_ORDER, "retarded row n has not been appended (or later rows have)");
+    if (wantL && H->last[1] != n) return fail(HNESSI_E_ORDER, "lesser row n has not been appended (or later rows have)");
+    const Geometry& g = H->g;
+    HistArgs A{};
+    A.n = n;
+    for (int c = 0; c < 2; ++c) {
+        A.n0[c] = H->n0[c];
+        A.last[c] = H->last[c];
+        A.ls[c] = 0;
+        A.ntailchunk[c] = 0;
+        A.nf[c] = 0;
+        bool use = (c == 0) || wantL;
+        if (!use) continue;
+        A.nf[c] = (int)(std::lower_bound(H->ft_act[c].begin(), H->ft_act[c].end(), H->n0[c]) -
+                        H->ft_act[c].begin());
+        if (H->last[c] >= H->n0[c]) {
+            A.ls[c] = g.s0[g.row_leaf[H->n0[c]]];
+            A.ntailchunk[c] = div_up(A.ls[c], kTailCH);
+        }
+    }
+    A.nt = H->nt;
+    A.norb = H->norb;
+    A.npair = H->npair;
+    A.RC = H->RC;
+    A.nlvl = H->nlvl;
+    A.nb = g.nb;
+    A.P = H->P;
+    A.wantR = wantR;
+    A.wantL = wantL;
+    A.h = h;
+    A.W = H->W;
+    A.sigR = static_cast<const cd*>(sigR);
+    A.sigL = static_cast<const cd*>(sigL);
+    for (int c = 0; c < 2; ++c) {
+        A.U[c] = H->U[c];
+        A.V[c] = H->V[c];
+        A.S[c] = H->S[c];
+        A.rank[c] = H->rank[c];
+        A.leaf[c] = H->leaf[c];
+        A.tail[c] = H->tail[c];
+        A.ft[c] = H->d_ft[c];
+        A.tailcol[c] = H->tailcol[c];
+        A.taildot[c] = H->taildot[c];
+        A.tailpart[c] = H->tailpart[c];
+    }
+    A.band = H->band;
+    A.blk = H->d_blk;
+    A.leafs = H->d_leaf;
+    A.cover = H->d_cover;
+    A.Uoff = H->d_Uoff;
+    A.Voff = H->d_Voff;
+    A.Loff = H->d_Loff;
+    A.partoff = H->d_partoff;
+    A.nleaf = g.row_leaf[n] + 1;
+    A.nleaftask = div_up(2 * A.nleaf, 8) * 8 * H->norb;
+    A.ntailtask = div_up(A.ntailchunk[0] + A.ntailchunk[1], 8) * 8 * H->norb;
+    A.proj = H->proj;
+    A.part = H->part;
+    A.cnt = H->cnt;
+    A.leafR = H->leafR;
+    A.leafLR = H->leafLR;
+    A.leafLL = H->leafLL;
+    A.tailcnt = H->tailcnt;
+    A.outR = static_cast<cd*>(outR);
+    A.outL = static_cast<cd*>(outL);
+    HIP_TRY(launch_history(A, st));
+    return HNESSI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hnessi_hodlr_append_row(hnessi_hodlr_t H, int c, int n, const void* row, void* stream) {
+    if (!H) return fail(HNESSI_E_ARG, "handle is NULL");
+    if (c != HNESSI_RET && c != HNESSI_LES) return fail(HNESSI_E_ARG, "component must be RET or LES");
+    if (!row) return fail(HNESSI_E_ARG, "row is NULL");
+    if (n < 0 || n >= H->nt) return fail(HNESSI_E_RANGE, "n outside the grid");
+    if (n != H->last[c] + 1) return fail(HNESSI_E_ORDER, "rows must be appended in order");
+    hipStream_t st = (hipStream_t)stream;
+    const Geometry& g = H->g;
+    const int leaf = g.row_leaf[n];
+    AppendArgs a{};
+    a.row = static_cast<const cd*>(row);
+    a.n = n;
+    a.npair = H->npair;
+    a.nt = H->nt;
+    a.k = H->k;
+    a.ls = g.s0[leaf];
+    a.lw = g.s1[leaf] - g.s0[leaf];
+    a.slot = n - H->n0[c];
+    a.leaf = H->leaf[c] + H->Loff[leaf];
+    a.tail = H->tail[c];
+    a.band = c == HNESSI_RET ? H->band : nullptr;
+    HIP_TRY(launch_append_hodlr(a, st));
+    H->last[c] = n;
+    if (panel_ends(H, c, n)) {
+        int rc = merge_panel(H, c, H->n0[c], n + 1, st);
+        if (rc != HNESSI_OK) return rc;
+        H->n0[c] = n + 1;
+    }
+    return HNESSI_OK;
+}
+
+int hnessi_history_R(hnessi_hodlr_t H, int n, const void* sigR_row, double h, void* out, void* stream) {
+    if (!H) return fail(HNESSI_E_ARG, "handle is NULL");
+    return do_history(H, n, sigR_row, nullptr, h, out, nullptr, true, false, (hipStream_t)stream);
+}
+
+int hnessi_history_lesser(hnessi_hodlr_t H, int n, const void* sigR_row, const void* sigL_slice,
+                          double h, void* out, void* stream) {
+    if (!H) return fail(HNESSI_E_ARG, "handle is NULL");
+    return do_history(H, n, sigR_row, sigL_slice, h, nullptr, out, false, true, (hipStream_t)stream);
+}
+
+int hnessi_history_step(hnessi_hodlr_t H, int n, const void* sigR_row, const void* sigL_slice,
+                        double h, void* outR, void* outL, void* stream) {
+    if (!H) return fail(HNESSI_E_ARG, "handle is NULL");
+    return do_history(H, n, sigR_row, sigL_slice, h, outR, outL, true, true, (hipStream_t)stream);
+}
+
+int hnessi_sweep(hnessi_hodlr_t H, int n_begin, int n_end, const void* GR, const void* GL,
+                 const void* SR, const void* SL, double h, void* IR, void* IL, void* stream) {
+    if (!H) return fail(HNESSI_E_ARG, "handle is NULL");
+    if (!GR || !GL || !SR || !SL || !IR || !IL) return fail(HNESSI_E_ARG, "NULL array");
+    if (n_begin < 0 || n_end > H->nt || n_begin > n_end) return fail(HNESSI_E_RANGE, "bad sweep range");
+    const size_t np = H->npair;
+    for (int n = n_begin; n < n_end; ++n) {
+        const size_t off = (size_t)tri(n) * np;
+        int rc = hnessi_hodlr_append_row(H, HNESSI_RET, n, static_cast<const cd*>(GR) + off, stream);
+        if (rc != HNESSI_OK) return rc;
+        rc = hnessi_hodlr_append_row(H, HNESSI_LES, n, static_cast<const cd*>(GL) + off, stream);
+        if (rc != HNESSI_OK) return rc;
+        rc = hnessi_history_step(H, n, static_cast<const cd*>(SR) + off, static_cast<const cd*>(SL) + off,
+                                 h, static_cast<cd*>(IR) + off, static_cast<cd*>(IL) + off, stream);
+        if (rc != HNESSI_OK) return rc;
+    }
+    return HNESSI_OK;
+}
+
+int hnessi_hodlr_status(hnessi_hodlr_t H, void* stream) {
+    if (!H) return fail(HNESSI_E_ARG, "handle is NULL");
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    int e = 0;
+    HIP_TRY(hipMemcpy(&e, H->err, sizeof(int), hipMemcpyDeviceToHost));
+    if (e & 2) return fail(HNESSI_E_VALUE, "a truncation met non-finite data (NaN or Inf in the rows)");
+    if (e & 1) return fail(HNESSI_E_RANK, "a truncation needed more than max_rank singular values");
+    return HNESSI_OK;
+}
+
+int hnessi_hodlr_get(hnessi_hodlr_t H, int c, int t1, int t2, void* out_host) {
+    if (!H || !out_host) return fail(HNESSI_E_ARG, "NULL argument");
+    if (c != HNESSI_RET && c != HNESSI_LES) return fail(HNESSI_E_ARG, "component must be RET or LES");
+    if (t2 < 0 || t2 > t1 || t1 > H->last[c]) return fail(HNESSI_E_RANGE, "(t1, t2) outside the stored region");
+    HIP_TRY(hipDeviceSynchronize());
+    const Geometry& g = H->g;
+    const int npair = H->npair;
+    std::vector<cd> out(npair);
+    const int leaf = g.row_leaf[t1];
+    const int ls = g.s0[leaf];
+    if (t2 >= ls) {
+        const int lw = g.s1[leaf] - ls;
+        for (int q = 0; q < npair; ++q)
+            HIP_TRY(hipMemcpy(&out[q], H->leaf[c] + H->Loff[leaf] + (size_t)q * tri(lw) + tri(t1 - ls) + (t2 - ls),
+                              sizeof(cd), hipMemcpyDeviceToHost));
+    } else if (t1 >= H->n0[c]) {
+        const int slot = t1 - H->n0[c];
+        for (int q = 0; q < npair; ++q)
+            HIP_TRY(hipMemcpy(&out[q], H->tail[c] + ((size_t)slot * npair + q) * H->nt + t2, sizeof(cd),
+                              hipMemcpyDeviceToHost));
+    } else {
+        int b = -1;
+        for (int l = 0; l < H->nlvl; ++l) {
+            int c1 = g.cover[(size_t)l * H->nt + t1], c2 = g.cover[(size_t)l * H->nt + t2];
+            if (c1 < 0 && c2 == ~c1) { b = c2; break; }
+        }
+        if (b < 0) return fail(HNESSI_E_RANGE, "no block holds (t1, t2)");
+        const int RC = H->RC;
+        const int ldU = g.r1[b] - g.r0[b], ldV = g.c1[b] - g.c0[b];
+        std::vector<int> rk(npair);
+        HIP_TRY(hipMemcpy(rk.data(), H->rank[c] + (size_t)b * npair, npair * sizeof(int), hipMemcpyDeviceToHost));
+        std::vector<double> S(RC);
+        for (int q = 0; q < npair; ++q) {
+            cd acc = mk(0.0, 0.0);
+            HIP_TRY(hipMemcpy(S.data(), H->S[c] + ((size_t)b * npair + q) * RC, RC * sizeof(double),
+                              hipMemcpyDeviceToHost));
+            for (int r = 0; r < rk[q]; ++r) {
+                cd u, v;
+                HIP_TRY(hipMemcpy(&u, H->U[c] + H->Uoff[b] + ((size_t)q * RC + r) * ldU + (t1 - g.r0[b]),
+                                  sizeof(cd), hipMemcpyDeviceToHost));
+                HIP_TRY(hipMemcpy(&v, H->V[c] + H->Voff[b] + ((size_t)q * RC + r) * ldV + (t2 - g.c0[b]),
+                                  sizeof(cd), hipMemcpyDeviceToHost));
+                acc = acc + S[r] * (u * conj(v));
+            }
+            out[q] = acc;
+        }
+    }
+    std::memcpy(out_host, out.data(), npair * sizeof(cd));
+    return HNESSI_OK;
+}
+
+int hnessi_hodlr_ranks(hnessi_hodlr_t H, int c, int* ranks_host, int capacity) {
+    if (!H || !ranks_host) return fail(HNESSI_E_ARG, "NULL argument");
+    if (c != HNESSI_RET && c != HNESSI_LES) return fail(HNESSI_E_ARG, "component must be RET or LES");
+    int total = H->g.nb * H->npair;
+    if (capacity < total) return fail(HNESSI_E_ARG, "capacity too small");
+    HIP_TRY(hipDeviceSynchronize());
+    if (total > 0) HIP_TRY(hipMemcpy(ranks_host, H->rank[c], total * sizeof(int), hipMemcpyDeviceToHost));
+    return total;
+}
+
+int hnessi_hodlr_blocks(hnessi_hodlr_t H, int* tab_host, int capacity) {
+    if (!H || !tab_host) return fail(HNESSI_E_ARG, "NULL argument");
+    const Geometry& g = H->g;
+    if (capacity < 5 * g.nb) return fail(HNESSI_E_ARG, "capacity too small");
+    for (int b = 0; b < g.nb; ++b) {
+        tab_host[5 * b] = g.level[b];
+        tab_host[5 * b + 1] = g.r0[b];
+        tab_host[5 * b + 2] = g.r1[b];
+        tab_host[5 * b + 3] = g.c0[b];
+        tab_host[5 * b + 4] = g.c1[b];
+    }
+    return g.nb;
+}
+
+int hnessi_hodlr_leaves(hnessi_hodlr_t H, int* tab_host, int capacity) {
+    if (!H || !tab_host) return fail(HNESSI_E_ARG, "NULL argument");
+    const Geometry& g = H->g;
+    if (capacity < 2 * g.nleaf) return fail(HNESSI_E_ARG, "capacity too small");
+    for (int i = 0; i < g.nleaf; ++i) {
+        tab_host[2 * i] = g.s0[i];
+        tab_host[2 * i + 1] = g.s1[i];
+    }
+    return g.nleaf;
+}
+
+size_t hnessi_hodlr_bytes(hnessi_hodlr_t H) { return H ? H->al.bytes : 0; }
+
+int hnessi_compress_block(const void* A, int rows, int cols, int lda, double tol, int max_rank, void* U,
+                          double* S, void* V, int* rank_out, void* stream) {
+    if (!A || !U || !S || !V || !rank_out) return fail(HNESSI_E_ARG, "NULL argument");
+    if (rows < 1 || cols < 1 || lda < cols) return fail(HNESSI_E_ARG, "bad matrix shape");
+    if (!(tol > 0.0)) return fail(HNESSI_E_ARG, "tol must be > 0");
+    if (max_rank < 1 || max_rank > kW - 1) return fail(HNESSI_E_ARG, "max_rank must be in 1..31");
+    int rc = lib_init();
+    if (rc != HNESSI_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int P = std::max(1, std::min(16, kW - max_rank));
+    const int nch = div_up(cols, kMergeCH);
+    Allocs al;
+    cd *nodeR, *nodeQ, *UK, *VR;
+    int *nodecnt, *rold, *err;
+    double* Sold;
+    ALLOC(al, nodeR, (size_t)2 * nch * kW * kW, false);
+    ALLOC(al, nodeQ, (size_t)2 * nch * kNodeQ, false);
+    ALLOC(al, nodecnt, (size_t)2 * nch, true);
+    ALLOC(al, UK, (size_t)kW * kW, false);
+    ALLOC(al, VR, (size_t)kW * kW, false);
+    ALLOC(al, Sold, kW, false);
+    ALLOC(al, rold, 1, false);
+    ALLOC(al, err, 1, true);
+    HIP_TRY(hipMemsetAsync(rank_out, 0, sizeof(int), st));
+    for (int p0 = 0; p0 < rows; p0 += P) {
+        MergeArgs a{};
+        a.pp = std::min(P, rows - p0);
+        a.npair = 1;
+        a.RC = max_rank;
+        a.tol = tol;
+        a.U = static_cast<cd*>(U);
+        a.V = static_cast<cd*>(V);
+        a.S = S;
+        a.rank = rank_out;
+        a.src = static_cast<const cd*>(A) + (size_t)p0 * lda;
+        a.src_row = lda;
+        a.src_pair = 0;
+        a.nodeR = nodeR;
+        a.nodeQ = nodeQ;
+        a.nodecnt = nodecnt;
+        a.UK = UK;
+        a.VR = VR;
+        a.Sold = Sold;
+        a.rold = rold;
+        a.err = err;
+        MergeBlk& B = a.blk[0];
+        B.b = 0;
+        B.c0 = 0;
+        B.ncols = cols;
+        B.ldU = rows;
+        B.kb = p0;
+        B.nchunks = nch;
+        B.task_off = 0;
+        B.utask_off = 0;
+        B.nutask = div_up(p0 + a.pp, 256);
+        B.nnodes = 2 * nch;
+        B.node_base = 0;
+        B.Uoff = 0;
+        B.Voff = 0;
+        a.nblk = 1;
+        a.ntask_v = nch;
+        a.ntask_u = B.nutask;
+        hipError_t e = launch_merge(a, st);
+        if (e != hipSuccess) {
+            hipStreamSynchronize(st);
+            al.release();
+            return fail(HNESSI_E_DEVICE, std::string("merge launch: ") + hipGetErrorString(e));
+        }
+    }
+    hipError_t e = hipStreamSynchronize(st);
+    al.release();
+    if (e != hipSuccess) return fail(HNESSI_E_DEVICE, std::string("compress_block: ") + hipGetErrorString(e));
+    return HNESSI_OK;
+}
+
+// ---------------------------------------------------------------------------
+int hnessi_dense_create(hnessi_dense_t* out, int nt, int norb, int k, void* stream) {
+    (void)stream;
+    if (!out) return fail(HNESSI_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!(norb == 1 || norb == 2 || norb == 4)) return fail(HNESSI_E_ARG, "dense storage supports norb 1, 2, 4");
+    if (nt < 2) return fail(HNESSI_E_ARG, "nt must be >= 2");
+    int rc = lib_init();
+    if (rc != HNESSI_OK) return rc;
+    auto* D = new hnessi_dense_s();
+    std::string err;
+    if (!make_weights(k, D->W, err)) {
+        delete D;
+        return fail(HNESSI_E_ARG, err);
+    }
+    D->nt = nt;
+    D->norb = norb;
+    D->npair = norb * norb;
+    D->k = k;
+    D->trin = tri(nt);
+    const int nbands = dense_band_count(nt);
+    auto bail = [&](int code) {
+        D->al.release();
+        delete D;
+        return code;
+    };
+    for (int c = 0; c < 2; ++c) {
+        int r = D->al.alloc(D->L[c], (size_t)D->npair * D->trin, false);
+        if (r != HNESSI_OK) return bail(r);
+    }
+    int r1 = D->al.alloc(D->colR, (size_t)nbands * nt * D->npair, false);
+    if (r1 != HNESSI_OK) return bail(r1);
+    r1 = D->al.alloc(D->colL, (size_t)nbands * nt * D->npair, false);
+    if (r1 != HNESSI_OK) return bail(r1);
+    r1 = D->al.alloc(D->rowL, (size_t)nbands * nt * D->npair, false);
+    if (r1 != HNESSI_OK) return bail(r1);
+    *out = D;
+    return HNESSI_OK;
+}
+
+int hnessi_dense_destroy(hnessi_dense_t D) {
+    if (!D) return fail(HNESSI_E_ARG, "handle is NULL");
+    hipDeviceSynchronize();
+    D->al.release();
+    delete D;
+    return HNESSI_OK;
+}
+
+int hnessi_dense_reset(hnessi_dense_t D, void* stream) {
+    (void)stream;
+    if (!D) return fail(HNESSI_E_ARG, "handle is NULL");
+    D->last[0] = D->last[1] = -1;
+    return HNESSI_OK;
+}
+
+int hnessi_dense_append_row(hnessi_dense_t D, int c, int n, const void* row, void* stream) {
+    if (!D || !row) return fail(HNESSI_E_ARG, "NULL argument");
+    if (c != HNESSI_RET && c != HNESSI_LES) return fail(HNESSI_E_ARG, "component must be RET or LES");
+    if (n < 0 || n >= D->nt) return fail(HNESSI_E_RANGE, "n outside the grid");
+    if (n != D->last[c] + 1) return fail(HNESSI_E_ORDER, "rows must be appended in order");
+    HIP_TRY(launch_append_dense(D->L[c], static_cast<const cd*>(row), n, D->npair, D->trin, (hipStream_t)stream));
+    D->last[c] = n;
+    return HNESSI_OK;
+}
+
+int hnessi_dense_history_step(hnessi_dense_t D, int n, const void* sigR_row, const void* sigL_slice,
+                              double h, void* outR, void* outL, void* stream) {
+    if (!D || !sigR_row || !sigL_slice || !outR || !outL) return fail(HNESSI_E_ARG, "NULL argument");
+    if (n < 0 || n >= D->nt) return fail(HNESSI_E_RANGE, "n outside the grid");
+    if (D->last[0] != n || D->last[1] != n) return fail(HNESSI_E_ORDER, "rows 0..n of both components are needed");
+    DenseArgs a{};
+    a.n = n;
+    a.nt = D->nt;
+    a.norb = D->norb;
+    a.h = h;
+    a.W = D->W;
+    a.sigR = static_cast<const cd*>(sigR_row);
+    a.sigL = static_cast<const cd*>(sigL_slice);
+    a.L[0] = D->L[0];
+    a.L[1] = D->L[1];
+    a.trin = D->trin;
+    a.colR = D->colR;
+    a.colL = D->colL;
+    a.rowL = D->rowL;
+    a.outR = static_cast<cd*>(outR);
+    a.outL = static_cast<cd*>(outL);
+    HIP_TRY(launch_dense_history(a, (hipStream_t)stream));
+    return HNESSI_OK;
+}
+
+int hnessi_dense_sweep(hnessi_dense_t D, int n_begin, int n_end, const void* GR, const void* GL,
+                       const void* SR, const void* SL, double h, void* IR, void* IL, void* stream) {
+    if (!D) return fail(HNESSI_E_ARG, "handle is NULL");
+    if (!GR || !GL || !SR || !SL || !IR || !IL) return fail(HNESSI_E_ARG, "NULL array");
+    if (n_begin < 0 || n_end > D->nt || n_begin > n_end) return fail(HNESSI_E_RANGE, "bad sweep range");
+    const size_t np = D->npair;
+    for (int n = n_begin; n < n_end; ++n) {
+        const size_t off = (size_t)tri(n) * np;
+        int rc = hnessi_dense_append_row(D, HNESSI_RET, n, static_cast<const cd*>(GR) + off, stream);
+        if (rc != HNESSI_OK) return rc;
+        rc = hnessi_dense_append_row(D, HNESSI_LES, n, static_cast<const cd*>(GL) + off, stream);
+        if (rc != HNESSI_OK) return rc;
+        rc = hnessi_dense_history_step(D, n, static_cast<const cd*>(SR) + off, static_cast<const cd*>(SL) + off, h,
+                                       static_cast<cd*>(IR) + off, static_cast<cd*>(IL) + off, stream);
+        if (rc != HNESSI_OK) return rc;
+    }
+    return HNESSI_OK;
+}
+
+size_t hnessi_dense_bytes(hnessi_dense_t D) { return D ? D->al.bytes : 0; }
+
+}  // extern "C"

@@ -1,0 +1,90 @@
+// Internal declarations shared by the host code and the HIP kernels of the
+// compressed history-integral library.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace hn {
+
+// ---------------------------------------------------------------------------
+// complex double
+struct cd {
+    double x, y;
+};
+
+__host__ __device__ inline cd mk(double a, double b) { return cd{a, b}; }
+__host__ __device__ inline cd operator+(cd a, cd b) { return cd{a.x + b.x, a.y + b.y}; }
+__host__ __device__ inline cd operator-(cd a, cd b) { return cd{a.x - b.x, a.y - b.y}; }
+__host__ __device__ inline cd operator-(cd a) { return cd{-a.x, -a.y}; }
+__host__ __device__ inline cd operator*(cd a, cd b) {
+    return cd{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__host__ __device__ inline cd operator*(double s, cd a) { return cd{s * a.x, s * a.y}; }
+__host__ __device__ inline cd conj(cd a) { return cd{a.x, -a.y}; }
+__host__ __device__ inline double norm2(cd a) { return a.x * a.x + a.y * a.y; }
+// acc += a * b
+__host__ __device__ inline void fma_(cd& acc, cd a, cd b) {
+    acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
+    acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
+}
+// acc += conj(a) * b
+__host__ __device__ inline void fmac_(cd& acc, cd a, cd b) {
+    acc.x = fma(a.x, b.x, fma(a.y, b.y, acc.x));
+    acc.y = fma(a.x, b.y, fma(-a.y, b.x, acc.y));
+}
+
+__host__ __device__ inline long long tri(long long n) { return n * (n + 1) / 2; }
+
+// ---------------------------------------------------------------------------
+// quadrature weights passed by value to kernels
+struct Weights {
+    int k;
+    double om[6];      // Gregory end weights omega_0..omega_k
+    double nc[6][7];   // nc[L][i]: interval weights for 0 <= L < k (L = 0: empty)
+};
+
+// interval weight w^{(L)}_i, any L >= 0 (device and host)
+__host__ __device__ inline double interval_w(const Weights& W, int L, int i) {
+    if (L < W.k) return W.nc[L][i];
+    double w = 1.0;
+    if (i <= W.k) w += W.om[i] - 1.0;
+    if (L - i <= W.k) w += W.om[L - i] - 1.0;
+    return w;
+}
+// end-weight fold of the retarded row: 1 + (omega_{n-j} - 1)[n-j <= k]
+__host__ __device__ inline double w_end(const Weights& W, int n, int j) {
+    int d = n - j;
+    return d <= W.k ? W.om[d] : 1.0;
+}
+// start-weight fold: 1 + (omega_s - 1)[s <= k]
+__host__ __device__ inline double w_start(const Weights& W, int s) {
+    return s <= W.k ? W.om[s] : 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// host plan: HODLR geometry
+struct Geometry {
+    int nt = 0, nlvl = 0, nb = 0, nleaf = 0;
+    std::vector<int> level, r0, r1, c0, c1;   // per block
+    std::vector<int> s0, s1;                  // per leaf
+    std::vector<int> row_leaf;                // leaf index of each row
+    std::vector<int> cover;                   // [l][m], l = 0..nlvl-1: b (column role) or ~b (row role)
+    int max_leaf = 0, min_leaf = 0;
+};
+
+bool build_geometry(int nt, int nlvl, Geometry& g, std::string& err);
+bool make_weights(int k, Weights& W, std::string& err);
+// exact-rational interval weights, for the public hnessi_weights
+bool interval_weights_exact(int k, int L, std::vector<double>& w, std::string& err);
+
+// ---------------------------------------------------------------------------
+// constants of the device kernels
+constexpr int kCH = 128;      // factor/chunk rows per task (projections, merges)
+constexpr int kTailCH = 256;  // columns per tail task
+
+}  // namespace hn

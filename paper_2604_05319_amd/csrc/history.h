@@ -1,0 +1,62 @@
+// History-integral kernels over HODLR storage: argument structs and launchers.
+#pragma once
+
+#include "common.h"
+
+namespace hn {
+
+// A projection task: one chunk of kCH rows of U (which = 0) or V (which = 1)
+// of block b, orbital pair q, component comp.  Active once row `act` is merged.
+struct FactTask {
+    int comp, b, q, which, chunk, act;
+};
+
+struct HistArgs {
+    int n;          // current step
+    int n0[2];      // first row not yet merged, per component
+    int last[2];    // last appended row, per component
+    int ls[2];      // columns [0, ls) of the rows still held dense (tail), per component
+    int nt, norb, npair, RC, nlvl, nb, P;
+    int wantR, wantL;
+    double h;
+    Weights W;
+    const cd* sigR;   // Sigma^R(n, j), j = 0..n
+    const cd* sigL;   // Sigma^<(s, n), s = 0..n
+    const cd* U[2];
+    const cd* V[2];
+    const double* S[2];
+    const int* rank[2];
+    const cd* leaf[2];
+    const cd* tail[2];
+    const cd* band;   // retarded band: band[(m*(k+1) + i)*npair + q] = G^R(m+i, m)
+    const int* blk;   // 5 per block: level, r0, r1, c0, c1
+    const int* leafs; // 2 per leaf: s0, s1
+    const int* cover; // [l*nt + m]
+    const long long* Uoff;
+    const long long* Voff;
+    const long long* Loff;
+    const long long* partoff;  // per (comp, b, q, which): first partial slot
+    const FactTask* ft[2];
+    int nf[2];       // active projection tasks per component
+    int nleaf;       // active leaves
+    int nleaftask;   // leaf tasks in the grid (after the XCD-grouping remap)
+    int ntailchunk[2];
+    int ntailtask;
+    cd* proj;        // [comp][b][q][which][a][RC]  (S_r * projection)
+    cd* part;        // partial projections
+    int* cnt;        // [comp][b][q][which]
+    cd* leafR;       // [m][a][c]
+    cd* leafLR;
+    cd* leafLL;
+    cd* tailcol[2];  // [m][a][c]
+    cd* taildot[2];  // [slot][a][c]
+    cd* tailpart[2]; // [a][chunk][slot][c]
+    int* tailcnt;    // [comp][a]
+    cd* outR;
+    cd* outL;
+};
+
+hipError_t launch_history(const HistArgs& a, hipStream_t st);
+hipError_t history_init();
+
+}  // namespace hn

@@ -1,0 +1,533 @@
+// Incremental truncated-SVD update of HODLR blocks (section "Hierarchical
+// decomposition": finished rows are folded into the block's TSVD as they
+// arrive; singular values below eps_SVD are dropped).
+//
+// A block B (rows so far) ~ U S V^dagger receives a panel A_p of Pp new rows.
+// With Z = [V S, A_p^dagger] (cols x w, w = r + Pp) and Z = Q R (QR),
+//     [B; A_p] = blkdiag(U, I) Z^dagger = blkdiag(U, I) R^dagger Q^dagger,
+// so an SVD R^dagger = U_K Sigma V_R^dagger gives the updated factors
+//     U' = blkdiag(U, I) U_K,   S' = Sigma,   V' = Q V_R,
+// truncated to the singular values >= eps.  The paper updates one row at a
+// time; here a panel of rows is merged at once.
+//
+// Device design (one problem = one block x one orbital pair):
+//   merge_up:   the columns of the block are cut into chunks of kCH rows of Z;
+//               each workgroup builds its chunk of Z in LDS and factors it with
+//               Householder reflections.  The R factors are combined pairwise
+//               up a binary tree; the last workgroup to arrive at a node does
+//               the combine (no waiting), and the one arriving at the root
+//               runs a one-sided Jacobi SVD of R^dagger and truncates.
+//   merge_down: each chunk workgroup recomputes its chunk QR, pulls V_R down
+//               the tree to its chunk, applies its reflectors and writes its
+//               rows of V'; further workgroups rewrite the rows of U'.
+#include "merge.h"
+
+namespace hn {
+
+namespace {
+
+constexpr int NT = 256;
+
+__device__ inline double warp_sum(double v, int width) {
+    for (int o = width / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, width);
+    return v;
+}
+
+// block-wide sum of one double (all threads get the result)
+__device__ double block_sum(double v, double* red) {
+    v = warp_sum(v, 64);
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < NT / 64; ++i) s += red[i];
+    return s;
+}
+
+// Householder QR of an nrows x ncols column-major LDS matrix A (lda = nrows),
+// nrows >= ncols.  On exit R is in the upper triangle, the reflector vectors
+// (v_j = 1 implicit) below it, and tau[j] holds the scalars: A = H_0..H_{n-1} R
+// with H_j = I - tau_j v_j v_j^dagger.
+template <int W>
+__device__ __attribute__((noinline)) void hh_qr(cd* A, int nrows, int ncols, cd* tau,
+                                                double* red) {
+    constexpr int TPC = NT / W;  // threads per trailing column
+    const int tid = threadIdx.x;
+    for (int j = 0; j < ncols; ++j) {
+        cd* aj = A + (size_t)j * nrows;
+        double part = 0.0;
+        for (int i = j + 1 + tid; i < nrows; i += NT) part += norm2(aj[i]);
+        double sig2 = block_sum(part, red);
+        cd alpha = aj[j];
+        cd t = mk(0.0, 0.0), scale = mk(0.0, 0.0);
+        double beta = alpha.x;
+        const double nrm0 = sqrt(norm2(alpha) + sig2);
+        // no reflection for an exactly zero column, or one so small (or not
+        // finite) that 1/(alpha - beta) would overflow: tau = 0, H_j = I
+        if (!(sig2 == 0.0 && alpha.y == 0.0) && nrm0 > 1e-150 && nrm0 < 1e150) {
+            double nrm = nrm0;
+            beta = alpha.x >= 0.0 ? -nrm : nrm;
+            t = mk((beta - alpha.x) / beta, -alpha.y / beta);
+            cd d = alpha - mk(beta, 0.0);  // 1/(alpha - beta)
+            double dn = norm2(d);
+            scale = mk(d.x / dn, -d.y / dn);
+        }
+        __syncthreads();
+        for (int i = j + 1 + tid; i < nrows; i += NT) aj[i] = aj[i] * scale;
+        if (tid == 0) {
+            aj[j] = mk(beta, 0.0);
+            tau[j] = t;
+        }
+        __syncthreads();
+        // apply H_j^dagger to the trailing columns: a_c -= conj(tau) v (v^dagger a_c)
+        const int g = tid / TPC, l = tid % TPC;
+        const int c = j + 1 + g;
+        cd dot = mk(0.0, 0.0);
+        if (c < ncols) {
+            cd* ac = A + (size_t)c * nrows;
+            for (int i = j + l; i < nrows; i += TPC) {
+                cd v = (i == j) ? mk(1.0, 0.0) : aj[i];
+                fmac_(dot, v, ac[i]);
+            }
+        }
+        dot.x = warp_sum(dot.x, TPC);
+        dot.y = warp_sum(dot.y, TPC);
+        if (c < ncols) {
+            cd* ac = A + (size_t)c * nrows;
+            cd f = conj(t) * dot;
+            for (int i = j + l; i < nrows; i += TPC) {
+                cd v = (i == j) ? mk(1.0, 0.0) : aj[i];
+                ac[i] = ac[i] - v * f;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// X (nrows x nx, column-major, ldx = nrows) <- H_0 H_1 .. H_{nref-1} X
+template <int W>
+__device__ __attribute__((noinline)) void hh_apply_q(const cd* A, int nrows, int nref,
+                                                     const cd* tau, cd* X, int nx) {
+    constexpr int TPC = NT / W;
+    const int tid = threadIdx.x;
+    const int g = tid / TPC, l = tid % TPC;
+    for (int j = nref - 1; j >= 0; --j) {
+        const cd* aj = A + (size_t)j * nrows;
+        cd t = tau[j];
+        cd dot = mk(0.0, 0.0);
+        if (g < nx) {
+            cd* xc = X + (size_t)g * nrows;
+            for (int i = j + l; i < nrows; i += TPC) {
+                cd v = (i == j) ? mk(1.0, 0.0) : aj[i];
+                fmac_(dot, v, xc[i]);
+            }
+        }
+        dot.x = warp_sum(dot.x, TPC);
+        dot.y = warp_sum(dot.y, TPC);
+        if (g < nx) {
+            cd* xc = X + (size_t)g * nrows;
+            cd f = t * dot;
+            for (int i = j + l; i < nrows; i += TPC) {
+                cd v = (i == j) ? mk(1.0, 0.0) : aj[i];
+                xc[i] = xc[i] - v * f;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// one-sided (Hestenes) Jacobi on the columns of M (n x n, column-major, n even,
+// ld = n), accumulating the rotations in J (starts as identity).
+__device__ __attribute__((noinline)) void jacobi_svd(cd* M, cd* J, int n, int* flag) {
+    const int tid = threadIdx.x;
+    const int npairs = n / 2;
+    int tpp = NT / npairs;
+    if (tpp > 64) tpp = 64;
+    // round down to a power of two
+    int p2 = 1;
+    while (p2 * 2 <= tpp) p2 *= 2;
+    tpp = p2;
+    for (int i = tid; i < n * n; i += NT) J[i] = mk((i % (n + 1)) == 0 ? 1.0 : 0.0, 0.0);
+    __syncthreads();
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        if (tid == 0) *flag = 0;
+        __syncthreads();
+        for (int round = 0; round < n - 1; ++round) {
+            const int pi = tid / tpp, l = tid % tpp;
+            int p = -1, q = -1;
+            if (pi < npairs) {
+                // circle method: position 0 fixed, positions 1..n-1 rotate
+                auto player = [&](int pos) { return pos == 0 ? 0 : ((pos - 1 + round) % (n - 1)) + 1; };
+                p = player(pi);
+                q = player(n - 1 - pi);
+            }
+            double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
+            if (pi < npairs) {
+                const cd* mp = M + (size_t)p * n;
+                const cd* mq = M + (size_t)q * n;
+                for (int i = l; i < n; i += tpp) {
+                    cd x = mp[i], y = mq[i];
+                    al += norm2(x);
+                    be += norm2(y);
+                    gr += x.x * y.x + x.y * y.y;  // conj(x) y
+                    gi += x.x * y.y - x.y * y.x;
+                }
+            }
+            al = warp_sum(al, tpp);
+            be = warp_sum(be, tpp);
+            gr = warp_sum(gr, tpp);
+            gi = warp_sum(gi, tpp);
+            if (pi < npairs) {
+                double ag = sqrt(gr * gr + gi * gi);
+                if (ag > 1e-15 * sqrt(al * be) && ag > 1e-300) {
+                    double zeta = (be - al) / (2.0 * ag);
+                    double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                    double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
+                    cd e = mk(gr / ag, gi / ag);  // e^{i theta}
+                    cd se = s * e, sec = s * conj(e);
+                    cd* mp = M + (size_t)p * n;
+                    cd* mq = M + (size_t)q * n;
+                    cd* jp = J + (size_t)p * n;
+                    cd* jq = J + (size_t)q * n;
+                    for (int i = l; i < n; i += tpp) {
+                        cd x = mp[i], y = mq[i];
+                        mp[i] = c * x - sec * y;
+                        mq[i] = se * x + c * y;
+                        cd u = jp[i], v = jq[i];
+                        jp[i] = c * u - sec * v;
+                        jq[i] = se * u + c * v;
+                    }
+                    if (l == 0) *flag = 1;
+                }
+            }
+            __syncthreads();
+        }
+        if (*flag == 0) break;
+        __syncthreads();
+    }
+    __syncthreads();
+}
+
+// ranks come from device memory; every index derived from them is kept
+// inside the capacity the host allocated, whatever the memory holds
+__device__ inline int clamp_rank(int r, int cap) { return r < 0 ? 0 : (r > cap ? cap : r); }
+
+struct Ctx {
+    int slot, q, chunk;
+    const MergeBlk* B;
+};
+
+__device__ inline Ctx decode_task(const MergeArgs& a, int task) {
+    Ctx c{};
+    int s = 0;
+    while (s + 1 < a.nblk && task >= a.blk[s + 1].task_off) ++s;
+    c.slot = s;
+    c.B = &a.blk[s];
+    int local = task - a.blk[s].task_off;
+    c.q = local / c.B->nchunks;
+    c.chunk = local % c.B->nchunks;
+    return c;
+}
+
+__device__ inline size_t prob_index(const MergeArgs& a, const Ctx& c) {
+    return (size_t)c.slot * a.npair + c.q;
+}
+
+// tree levels: cnt[0] = nchunks, cnt[L+1] = ceil(cnt[L]/2); node (L, i) at levoff[L] + i
+__device__ inline int tree_levoff(int nc, int L) {
+    int off = 0, cnt = nc;
+    for (int i = 0; i < L; ++i) {
+        off += cnt;
+        cnt = (cnt + 1) / 2;
+    }
+    return off;
+}
+
+// Build the chunk of Z = [V S, A_p^dagger] into LDS (column-major, kCH rows,
+// zero padded) and factor it.
+template <int W>
+__device__ void chunk_qr(const MergeArgs& a, const Ctx& c, int r_old, const double* s_old,
+                         cd* A, cd* tau, double* red) {
+    constexpr int kCH = kMergeCH;
+    const MergeBlk& B = *c.B;
+    const int w = r_old + a.pp;
+    const int row0 = c.chunk * kCH;
+    const int nr = min(kCH, B.ncols - row0);
+    const cd* V = a.V + B.Voff + (size_t)c.q * a.RC * B.ncols;
+    for (int idx = threadIdx.x; idx < kCH * w; idx += NT) {
+        int col = idx / kCH, i = idx % kCH;
+        cd z = mk(0.0, 0.0);
+        if (i < nr) {
+            int s = row0 + i;  // column of the block (relative)
+            if (col < r_old) {
+                z = s_old[col] * V[(size_t)col * B.ncols + s];
+            } else {
+                int pr = col - r_old;
+                z = conj(a.src[(size_t)pr * a.src_row + (size_t)c.q * a.src_pair + B.c0 + s]);
+            }
+        }
+        A[idx] = z;
+    }
+    __syncthreads();
+    hh_qr<W>(A, kCH, w, tau, red);
+}
+
+}  // namespace
+
+
+__global__ void __launch_bounds__(NT) merge_up_kernel(MergeArgs a) {
+    constexpr int W = kW, CH = kMergeCH;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cd* A = reinterpret_cast<cd*>(smem_raw);               // CH x W (also 2W x W, and M, J)
+    cd* tau = A + (size_t)CH * W;                          // W
+    double* red = reinterpret_cast<double*>(tau + W);      // 8
+    __shared__ int sflag;
+    __shared__ double s_old[W];
+    __shared__ double ssig[W];
+    __shared__ int sperm[W];
+
+    Ctx c = decode_task(a, blockIdx.x);
+    const MergeBlk& B = *c.B;
+    const size_t pidx = prob_index(a, c);
+    const size_t fq = (size_t)B.b * a.npair + c.q;
+    const int r_old = clamp_rank(a.rank[fq], a.RC);
+    const int w = r_old + a.pp;
+    for (int i = threadIdx.x; i < W; i += NT) s_old[i] = i < r_old ? a.S[fq * a.RC + i] : 0.0;
+    __syncthreads();
+
+    chunk_qr<W>(a, c, r_old, s_old, A, tau, red);
+
+    const long long nbase = B.node_base + (long long)c.q * B.nnodes;
+    cd* nodeR = a.nodeR + (size_t)nbase * W * W;
+    cd* nodeQ = a.nodeQ + (size_t)nbase * kNodeQ;
+    int* nodecnt = a.nodecnt + nbase;
+    {
+        cd* dst = nodeR + (size_t)c.chunk * W * W;
+        for (int e = threadIdx.x; e < W * W; e += NT) {
+            int col = e / W, i = e % W;
+            dst[e] = (col < w && i <= col) ? A[(size_t)col * CH + i] : mk(0.0, 0.0);
+        }
+    }
+    __threadfence();
+    __syncthreads();
+
+    int idx = c.chunk, L = 0, cnt = B.nchunks;
+    while (cnt > 1) {
+        const int parent = idx >> 1;
+        const int offL = tree_levoff(B.nchunks, L), offP = tree_levoff(B.nchunks, L + 1);
+        if ((idx ^ 1) < cnt) {
+            if (threadIdx.x == 0) sflag = atomicAdd(&nodecnt[offP + parent], 1);
+            __syncthreads();
+            if (sflag == 0) return;  // first to arrive: the sibling finishes this node
+            __threadfence();
+            if (threadIdx.x == 0) nodecnt[offP + parent] = 0;
+            const cd* rl = nodeR + (size_t)(offL + 2 * parent) * W * W;
+            const cd* rr = nodeR + (size_t)(offL + 2 * parent + 1) * W * W;
+            const int nr2 = 2 * w;
+            for (int e = threadIdx.x; e < nr2 * w; e += NT) {
+                int col = e / nr2, i = e % nr2;
+                A[e] = (i < w) ? rl[(size_t)col * W + i] : rr[(size_t)col * W + (i - w)];
+            }
+            __syncthreads();
+            hh_qr<W>(A, nr2, w, tau, red);
+            cd* dst = nodeR + (size_t)(offP + parent) * W * W;
+            for (int e = threadIdx.x; e < W * W; e += NT) {
+                int col = e / W, i = e % W;
+                dst[e] = (col < w && i <= col) ? A[(size_t)col * nr2 + i] : mk(0.0, 0.0);
+            }
+            cd* qd = nodeQ + (size_t)(offP + parent) * kNodeQ;
+            for (int e = threadIdx.x; e < nr2 * w; e += NT) qd[e] = A[e];
+            for (int e = threadIdx.x; e < w; e += NT) qd[2 * W * W + e] = tau[e];
+            __threadfence();
+            __syncthreads();
+        } else {
+            const cd* src = nodeR + (size_t)(offL + idx) * W * W;
+            cd* dst = nodeR + (size_t)(offP + parent) * W * W;
+            for (int e = threadIdx.x; e < W * W; e += NT) dst[e] = src[e];
+            __threadfence();
+            __syncthreads();
+        }
+        idx = parent;
+        cnt = (cnt + 1) / 2;
+        ++L;
+    }
+
+    // root: one-sided Jacobi SVD of R^dagger, truncation, commit rank and S
+    const cd* R = nodeR + (size_t)tree_levoff(B.nchunks, L) * W * W;
+    const int ne = (w + 1) & ~1;
+    cd* M = A;
+    cd* J = A + (size_t)ne * ne;
+    for (int e = threadIdx.x; e < ne * ne; e += NT) {
+        int col = e / ne, i = e % ne;  // M[i][col] = conj(R[col][i])
+        M[e] = (i < w && col < w) ? conj(R[(size_t)i * W + col]) : mk(0.0, 0.0);
+    }
+    __syncthreads();
+    jacobi_svd(M, J, ne, &sflag);
+    for (int i = threadIdx.x; i < ne; i += NT) {
+        double s = 0.0;
+        for (int r = 0; r < ne; ++r) s += norm2(M[(size_t)i * ne + r]);
+        s = sqrt(s);
+        // a non-finite norm (non-finite input data) sorts last and is never kept
+        if (!(s <= 1e300)) {
+            if (s != s || s > 1e300) atomicOr(a.err, 2);
+            s = -1.0;
+        }
+        ssig[i] = s;
+    }
+    __syncthreads();
+    // descending order; all keys are finite, so this is a permutation of 0..ne-1
+    for (int i = threadIdx.x; i < ne; i += NT) {
+        int pos = 0;
+        for (int j = 0; j < ne; ++j) pos += (ssig[j] > ssig[i]) || (ssig[j] == ssig[i] && j < i);
+        sperm[pos] = i;
+    }
+    __syncthreads();
+    int rnew = 0;
+    for (int i = 0; i < ne; ++i) rnew += (ssig[sperm[i]] >= a.tol) ? 1 : 0;
+    if (rnew > a.RC) {
+        if (threadIdx.x == 0) atomicOr(a.err, 1);
+        rnew = a.RC;
+    }
+    if (threadIdx.x == 0) {
+        a.rold[pidx] = r_old;
+        a.rank[fq] = rnew;
+    }
+    for (int i = threadIdx.x; i < W; i += NT) a.Sold[pidx * W + i] = s_old[i];
+    for (int i = threadIdx.x; i < a.RC; i += NT) a.S[fq * a.RC + i] = i < rnew ? ssig[sperm[i]] : 0.0;
+    cd* UK = a.UK + pidx * W * W;
+    cd* VR = a.VR + pidx * W * W;
+    for (int e = threadIdx.x; e < w * rnew; e += NT) {
+        int col = e / w, i = e % w;
+        int src = min(max(sperm[col], 0), ne - 1);
+        double inv = 1.0 / ssig[src];
+        UK[(size_t)col * W + i] = inv * M[(size_t)src * ne + i];
+        VR[(size_t)col * W + i] = J[(size_t)src * ne + i];
+    }
+}
+
+__global__ void __launch_bounds__(NT) merge_down_kernel(MergeArgs a) {
+    constexpr int W = kW, CH = kMergeCH;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cd* A = reinterpret_cast<cd*>(smem_raw);       // CH x W
+    cd* X = A + (size_t)CH * W;                     // CH x W
+    cd* T = X + (size_t)CH * W;                     // W x W
+    cd* tau = T + (size_t)W * W;                    // W
+    double* red = reinterpret_cast<double*>(tau + W);
+    __shared__ double s_old[W];
+
+    if ((int)blockIdx.x < a.ntask_v) {
+        Ctx c = decode_task(a, blockIdx.x);
+        const MergeBlk& B = *c.B;
+        const size_t pidx = prob_index(a, c);
+        const size_t fq = (size_t)B.b * a.npair + c.q;
+        const int r_old = clamp_rank(a.rold[pidx], a.RC);
+        const int rnew = clamp_rank(a.rank[fq], a.RC);
+        const int w = r_old + a.pp;
+        for (int i = threadIdx.x; i < W; i += NT) s_old[i] = a.Sold[pidx * W + i];
+        __syncthreads();
+        chunk_qr<W>(a, c, r_old, s_old, A, tau, red);
+        const cd* VR = a.VR + pidx * W * W;
+        for (int e = threadIdx.x; e < W * W; e += NT) {
+            int col = e / W, i = e % W;
+            T[e] = (col < rnew && i < w) ? VR[(size_t)col * W + i] : mk(0.0, 0.0);
+        }
+        __syncthreads();
+        const long long nbase = B.node_base + (long long)c.q * B.nnodes;
+        const cd* nodeQ = a.nodeQ + (size_t)nbase * kNodeQ;
+        int depth = 0;
+        for (int cnt = B.nchunks; cnt > 1; cnt = (cnt + 1) / 2) ++depth;
+        for (int L = depth; L >= 1; --L) {
+            int cntBelow = B.nchunks;
+            for (int i = 0; i < L - 1; ++i) cntBelow = (cntBelow + 1) / 2;
+            const int node = c.chunk >> L;
+            const int child = c.chunk >> (L - 1);
+            if (2 * node + 1 >= cntBelow) continue;  // single child: Q = identity
+            const int slot = child & 1;
+            const int nr2 = 2 * w;
+            const cd* Qn = nodeQ + (size_t)(tree_levoff(B.nchunks, L) + node) * kNodeQ;
+            for (int e = threadIdx.x; e < nr2 * rnew; e += NT) {
+                int col = e / nr2, i = e % nr2;
+                X[e] = (i < w) ? T[(size_t)col * W + i] : mk(0.0, 0.0);
+            }
+            __syncthreads();
+            hh_apply_q<W>(Qn, nr2, w, Qn + 2 * W * W, X, rnew);
+            for (int e = threadIdx.x; e < w * rnew; e += NT) {
+                int col = e / w, i = e % w;
+                T[(size_t)col * W + i] = X[(size_t)col * nr2 + slot * w + i];
+            }
+            __syncthreads();
+        }
+        for (int e = threadIdx.x; e < CH * rnew; e += NT) {
+            int col = e / CH, i = e % CH;
+            X[e] = (i < w) ? T[(size_t)col * W + i] : mk(0.0, 0.0);
+        }
+        __syncthreads();
+        hh_apply_q<W>(A, CH, w, tau, X, rnew);
+        const int row0 = c.chunk * CH;
+        const int nr = min(CH, B.ncols - row0);
+        cd* V = a.V + B.Voff + (size_t)c.q * a.RC * B.ncols;
+        for (int e = threadIdx.x; e < nr * rnew; e += NT) {
+            int col = e / nr, i = e % nr;
+            V[(size_t)col * B.ncols + row0 + i] = X[(size_t)col * CH + i];
+        }
+        return;
+    }
+    // U rows: old rows U' = U U_K[0:r_old, :], new rows U' = U_K[r_old + i, :]
+    const int t = blockIdx.x - a.ntask_v;
+    int s = 0;
+    while (s + 1 < a.nblk && t >= a.blk[s + 1].utask_off) ++s;
+    const MergeBlk& B = a.blk[s];
+    const int local = t - B.utask_off;
+    const int q = local / B.nutask, ut = local % B.nutask;
+    const size_t pidx = (size_t)s * a.npair + q;
+    const size_t fq = (size_t)B.b * a.npair + q;
+    const int r_old = clamp_rank(a.rold[pidx], a.RC);
+    const int rnew = clamp_rank(a.rank[fq], a.RC);
+    const cd* UK = a.UK + pidx * W * W;
+    cd* U = a.U + B.Uoff + (size_t)q * a.RC * B.ldU;
+    const int row = ut * NT + threadIdx.x;
+    const int nrows = B.kb + a.pp;
+    if (row >= nrows) return;
+    if (row < B.kb) {
+        cd u[W];
+#pragma unroll
+        for (int r = 0; r < W; ++r) u[r] = (r < r_old) ? U[(size_t)r * B.ldU + row] : mk(0.0, 0.0);
+        for (int col = 0; col < rnew; ++col) {
+            cd acc = mk(0.0, 0.0);
+#pragma unroll
+            for (int r = 0; r < W; ++r)
+                if (r < r_old) fma_(acc, u[r], UK[(size_t)col * W + r]);
+            U[(size_t)col * B.ldU + row] = acc;
+        }
+    } else {
+        const int pr = r_old + (row - B.kb);
+        for (int col = 0; col < rnew; ++col) U[(size_t)col * B.ldU + row] = UK[(size_t)col * W + pr];
+    }
+}
+
+static size_t merge_up_smem() {
+    return (size_t)kMergeCH * kW * sizeof(cd) + (size_t)kW * sizeof(cd) + 8 * sizeof(double);
+}
+static size_t merge_down_smem() {
+    return (size_t)2 * kMergeCH * kW * sizeof(cd) + (size_t)kW * kW * sizeof(cd) +
+           (size_t)kW * sizeof(cd) + 8 * sizeof(double);
+}
+
+hipError_t launch_merge(const MergeArgs& a, hipStream_t st) {
+    if (a.ntask_v == 0) return hipSuccess;
+    merge_up_kernel<<<a.ntask_v, NT, merge_up_smem(), st>>>(a);
+    merge_down_kernel<<<a.ntask_v + a.ntask_u, NT, merge_down_smem(), st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t merge_init() {
+    hipError_t e = hipFuncSetAttribute((const void*)merge_up_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)merge_up_smem());
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)merge_down_kernel,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)merge_down_smem());
+}
+
+}  // namespace hn

@@ -1,0 +1,22 @@
+// Row append kernels: argument struct and launchers.
+#pragma once
+
+#include "common.h"
+
+namespace hn {
+
+struct AppendArgs {
+    const cd* row;  // (n+1) x npair
+    int n, npair, nt, k;
+    int ls, lw;     // leaf of row n: first row/column and width
+    int slot;       // tail slot of row n (n - first unmerged row)
+    cd* leaf;       // leaf triangle base (pair 0)
+    cd* tail;       // tail base
+    cd* band;       // retarded band or nullptr
+};
+
+hipError_t launch_append_hodlr(const AppendArgs& a, hipStream_t st);
+hipError_t launch_append_dense(cd* dst, const cd* row, int n, int npair, long long trin,
+                               hipStream_t st);
+
+}  // namespace hn
