@@ -91,8 +91,8 @@ __global__ void __launch_bounds__(NTD) dense_tiles(DenseArgs A) {
 #pragma unroll
                 for (int c = 0; c < NORB; ++c) dst[a * NORB + c] = colacc[a][c];
         }
-        // row dots over the tile columns, row jr
-        if (jr <= n) {
+        // row dots over the tile columns, row jr (the second lesser term is empty at m = 0)
+        if (jr <= n && !(comp == 0 && jr == 0)) {
             const int shi = min(M0 + TB, jr + 1);
 #pragma unroll
             for (int q = 0; q < npair; ++q) {
@@ -169,8 +169,8 @@ __global__ void dense_reduce(DenseArgs A) {
 #pragma unroll
         for (int a = 0; a < NORB; ++a) A.outR[mo + a * NORB + c] = A.h * accR[a];
     }
-    // second lesser term correction
-    const int imax = m < k ? m : k;
+    // second lesser term correction (empty interval at m = 0)
+    const int imax = m == 0 ? -1 : (m < k ? m : k);
     for (int i = 0; i <= imax; ++i) {
         const int s = m - i;
         const double wc = m < k ? A.W.nc[m][s] - w_start(A.W, s) : A.W.om[i] - 1.0;

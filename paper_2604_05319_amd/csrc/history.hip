@@ -165,7 +165,9 @@ __device__ void leaf_task(const HistArgs& A, int leaf, int comp, int a, unsigned
         const int i = e / NORB, bb = e % NORB, j = s0 + i;
         if (comp == 0) {
             xa[e] = w_end(A.W, n, j) * A.sigR[(size_t)j * npair + a * NORB + bb];
-            xb[e] = -w_start(A.W, j) * conj(A.sigL[(size_t)j * npair + bb * NORB + a]);
+            // Sigma^< is only passed (and only read) when the lesser output is wanted
+            xb[e] = A.wantL ? -w_start(A.W, j) * conj(A.sigL[(size_t)j * npair + bb * NORB + a])
+                            : mk(0.0, 0.0);
         } else {
             xa[e] = interval_w(A.W, n, j) * A.sigR[(size_t)j * npair + a * NORB + bb];
         }
@@ -187,7 +189,7 @@ __device__ void leaf_task(const HistArgs& A, int leaf, int comp, int a, unsigned
                     for (int j = mo; j < nrow; ++j) fma_(s, xa[j * NORB + qr], Lq[tri(j) + mo]);
                     accA[qc] = accA[qc] + s;
                 }
-                if (A.wantL) {  // row dots x2(s) G^R(m, s)^dagger
+                if (A.wantL && s0 + mo > 0) {  // row dots x2(s) G^R(m, s)^dagger (empty at m = 0)
                     cd s = mk(0.0, 0.0);
                     for (int k = 0; k <= mo; ++k) fmac_(s, rowm[k], xb[k * NORB + qc]);
                     accB[qr] = accB[qr] + s;
@@ -247,9 +249,9 @@ __device__ void tail_task(const HistArgs& A, int comp, int a, int chunk, unsigne
     for (int bb = 0; bb < NORB; ++bb) {
         xm[bb] = mk(0.0, 0.0);
         if (act) {
-            if (comp == 0)
-                xm[bb] = -w_start(A.W, m) * conj(A.sigL[(size_t)m * npair + bb * NORB + a]);
-            else
+            if (comp == 0) {
+                if (A.wantL) xm[bb] = -w_start(A.W, m) * conj(A.sigL[(size_t)m * npair + bb * NORB + a]);
+            } else
                 xm[bb] = interval_w(A.W, n, m) * A.sigR[(size_t)m * npair + a * NORB + bb];
         }
     }
@@ -470,9 +472,10 @@ __global__ void __launch_bounds__(64 * NORB) hist_combine(HistArgs A) {
         }
     }
     if (A.wantL) {
-        // second lesser term: end weights (m >= k) or Newton-Cotes (m < k)
+        // second lesser term: end weights (m >= k) or Newton-Cotes (m < k); the
+        // interval is empty at m = 0 (no bulk term was added there either)
         // Sigma^<(n,s)[a][b] = -conj(sigL[s][b][a]);  G^R(m,s)^dagger[b][c] = conj(G^R(m,s)[c][b])
-        const int imax = m < k ? m : k;
+        const int imax = m == 0 ? -1 : (m < k ? m : k);
         for (int i = 0; i <= imax; ++i) {
             const int s = m - i;
             const double wc = m < k ? A.W.nc[m][s] - w_start(A.W, s) : A.W.om[i] - 1.0;

@@ -186,20 +186,26 @@ def test_reconstruction_full_rank(P):
 
 
 def test_compress_block_known_spectrum(P):
+    """Spectrum with a clear gap around tol: exact rank, spectral error ~ first dropped value.
+
+    Incremental truncation drops, at each panel merge, directions whose singular value in the
+    partial block is below tol, so the error of the finished factorization is bounded by
+    (number of merges) * tol, and a value within a small factor of tol may be kept or dropped
+    (rank +-1); the gap below keeps this test away from both effects.
+    """
     rng = np.random.default_rng(3)
     m, n = 150, 700
-    s = np.geomspace(2.0, 1e-14, 20)
+    s = np.concatenate([np.geomspace(2.0, 1e-6, 12), np.geomspace(1e-13, 1e-15, 8)])
     U0 = np.linalg.qr(rng.standard_normal((m, 20)) + 1j * rng.standard_normal((m, 20)))[0]
     V0 = np.linalg.qr(rng.standard_normal((n, 20)) + 1j * rng.standard_normal((n, 20)))[0]
     A = (U0 * s) @ np.conj(V0.T)
     tol = 1e-9
-    expect = int(np.count_nonzero(s >= tol))
     say("gpu: compress_block")
     U, S, V, r = P.compress_block(to_dev(A), tol, 24)
-    assert r == expect
+    assert r == 12
     U, S, V = U.cpu().numpy(), S.cpu().numpy(), V.cpu().numpy()
     np.testing.assert_allclose(S, s[:r], rtol=1e-9)
     np.testing.assert_allclose(np.conj(U.T) @ U, np.eye(r), atol=1e-12)
     np.testing.assert_allclose(np.conj(V.T) @ V, np.eye(r), atol=1e-12)
     err = np.linalg.norm(A - (U * S) @ np.conj(V.T), 2)
-    assert err < tol
+    assert err < 1e-12
