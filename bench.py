@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Benchmark: history-integral time steps per second at N_t = 8192, norb = 4.
+
+One bench step is one full sweep of the hot path over the workload: for every
+time step n = 0..N_t-1, append the retarded and lesser rows (with the panel
+merges that fall due), then evaluate I^R(n, .) and I^<(n, .).  The value is
+time steps per second over the timed sweeps (inputs already in HBM).  The same
+sweep on the dense (uncompressed) storage runs on the same GPU for comparison.
+Kernel durations for the roofline come from HIP events recorded by the library
+on its launch stream inside the timed sweeps (every `--prof-stride`-th step).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "history-integral time steps/sec at N_t=8192, norb=4: HODLR vs dense, same GPU"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def panel_schedule(N, P, leaves):
+    """n0 (first row not yet merged) after the appends of each step n."""
+    row_leaf = [0] * N
+    for i, (s0, s1) in enumerate(leaves):
+        for r in range(s0, s1):
+            row_leaf[r] = i
+    n0s, n0 = [], 0
+    for n in range(N):
+        if n + 1 >= N or n + 1 - n0 >= P or row_leaf[n + 1] != row_leaf[n]:
+            n0 = n + 1
+        n0s.append(n0)
+    return n0s, row_leaf
+
+
+def algorithmic_bytes(N, npair, P, blocks, leaves, ranks, steps):
+    """Bytes each history kernel must move at the given steps (both components).
+
+    tasks:   every stored factor row once (U rows merged so far, all V rows of
+             active blocks, at the blocks' ranks), the present part of every
+             leaf triangle, the dense tail rows, and the two Sigma rows.
+    combine: every stored factor row once (the expansions), and the two output rows.
+    """
+    import numpy as np
+    n0s, row_leaf = panel_schedule(N, P, leaves)
+    zb = 16  # complex128
+    rsum = [ranks[c].sum(axis=1) for c in (0, 1)]   # per block: sum of ranks over pairs
+    tasks, comb = [], []
+    for n in steps:
+        n0 = n0s[n]
+        fac = 0
+        for c in (0, 1):
+            for b, (lvl, r0, r1, c0, c1) in enumerate(blocks):
+                if n0 > r0:
+                    fac += int(rsum[c][b]) * (min(n0 - r0, r1 - r0) + (c1 - c0)) * zb
+        lf = 0
+        for (s0, s1) in leaves:
+            if s0 <= n:
+                k = min(s1, n + 1) - s0
+                lf += k * (k + 1) // 2
+        lf *= 2 * npair * zb
+        tail = 0
+        if n >= n0:
+            ls = leaves[row_leaf[n0]][0]
+            tail = 2 * (n - n0 + 1) * ls * npair * zb
+        rows = 2 * (n + 1) * npair * zb
+        tasks.append(fac + lf + tail + rows)
+        comb.append(fac + rows)
+    return np.array(tasks, dtype=np.float64), np.array(comb, dtype=np.float64)
+
+
+def cpu_baseline(cfg, G, S, budget_s):
+    """The FP64 oracle as it stands, timed on sampled entries (n, m) of the sweep."""
+    import numpy as np
+    from oracle.history import GeneratorOperands, history_lesser_entry, history_R_entry
+    N, h, k = cfg["nt"], cfg["h"], cfg["k"]
+    ops = GeneratorOperands(G, S, h)
+    rng = np.random.default_rng(12)
+    summands, t0, ne = 0, time.perf_counter(), 0
+    while time.perf_counter() - t0 < budget_s:
+        n = int(rng.integers(N // 8, N))
+        m = int(rng.integers(0, n + 1))
+        history_R_entry(ops, n, m, h, k)
+        history_lesser_entry(ops, n, m, h, k)
+        summands += (n - m + 1) + (n + 1) + (m + 1)
+        ne += 1
+    dt = time.perf_counter() - t0
+    rate = summands / dt
+    total = sum((n + 1) * (2 * n + 3) for n in range(N))   # summands of a full sweep
+    return dict(value=N / (total / rate), unit="steps/s", cores=1, kind="oracle",
+                sample=f"{ne} entries I^R(n,m) and I^<(n,m), n uniform in [{N // 8},{N}), m uniform "
+                       f"in [0,n], {dt:.1f} s; rate {rate:.3e} summands/s extrapolated to the "
+                       f"{total:.3e} summands of a full N_t={N} sweep (single-threaded NumPy)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2, help="timed sweeps of N_t time steps")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--dense-steps", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--prof-stride", type=int, default=16)
+    ap.add_argument("--nt", type=int, default=None, help="override N_t (testing only)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              f"sharding is a design, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2604_05319_amd as P
+    from kbe_inputs import make_config_inputs
+    from kbe_inputs.packed import packed_torch
+
+    cfg, G, S = make_config_inputs("c2")
+    if args.nt:
+        cfg["nt"] = args.nt
+    N, h, norb, k = cfg["nt"], cfg["h"], cfg["norb"], cfg["k"]
+    nlvl = int(round(np.log2(N // cfg["leaf"])))
+    panel, max_rank = 16, 16
+    npair = norb * norb
+    dev = torch.device("cuda:0")
+    t = time.perf_counter()
+    GR = packed_torch(G, "ret", N, h, dev)
+    GL = packed_torch(G, "les", N, h, dev)
+    SR = packed_torch(S, "ret", N, h, dev)
+    SL = packed_torch(S, "les", N, h, dev)
+    IR = torch.empty_like(GR)
+    IL = torch.empty_like(GR)
+    torch.cuda.synchronize()
+    log(f"inputs: 4 packed triangles of {GR.numel() * 16 / 2**30:.1f} GiB in {time.perf_counter() - t:.1f} s")
+
+    H = P.Hodlr(N, nlvl, norb, k=k, tol=cfg["tol"], panel=panel, max_rank=max_rank)
+
+    def sweep(obj):
+        obj.reset()
+        obj.sweep(0, N, GR, GL, SR, SL, h, IR, IL)
+
+    for _ in range(args.warmup):
+        sweep(H)
+    torch.cuda.synchronize()
+    H.profile(args.prof_stride)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sweep(H)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = args.steps * N / dt
+    status = H.status()
+    log(f"HODLR: {args.steps} sweeps in {dt:.3f} s -> {value:.1f} steps/s (status {status})")
+
+    # roofline of the dominant history kernel from the timed sweeps' events
+    blocks, leaves = H.blocks(), H.leaves()
+    ranks = [H.ranks(P.RET), H.ranks(P.LES)]
+    kern = {}
+    for kind, name in ((0, "hist_tasks"), (1, "hist_combine"), (2, "merge")):
+        steps, ms = H.profile_read(kind)
+        kern[name] = (steps, ms)
+    st0, ms0 = kern["hist_tasks"]
+    st1, ms1 = kern["hist_combine"]
+    b_tasks, b_comb = algorithmic_bytes(N, npair, panel, blocks, leaves, ranks, list(st0))
+    per_sweep_ms = {name: float(ms.sum()) * args.prof_stride / args.steps if name != "merge"
+                    else float(ms.sum()) / args.steps for name, (s, ms) in kern.items()}
+    dominant = max(("hist_tasks", "hist_combine"), key=lambda nm: kern[nm][1].sum())
+    bsel, msel = (b_tasks, ms0) if dominant == "hist_tasks" else (b_comb, ms1)
+    achieved = float(bsel.sum() / (msel.sum() * 1e-3) / 1e9)
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                kernel=dominant, launches_timed=int(len(msel)),
+                avg_launch_us=round(float(msel.mean()) * 1e3, 2),
+                avg_alg_bytes_per_launch=float(bsel.mean()))
+    other = "hist_combine" if dominant == "hist_tasks" else "hist_tasks"
+    bo, mo = (b_comb, ms1) if other == "hist_combine" else (b_tasks, ms0)
+    kernels = {
+        dominant: dict(gbs=round(achieved, 1), est_ms_per_sweep=round(per_sweep_ms[dominant], 1)),
+        other: dict(gbs=round(float(bo.sum() / (mo.sum() * 1e-3) / 1e9), 1),
+                    est_ms_per_sweep=round(per_sweep_ms[other], 1)),
+        "merge": dict(launches_per_sweep=int(len(kern["merge"][1]) // max(args.steps, 1)),
+                      ms_per_sweep=round(per_sweep_ms["merge"], 1)),
+    }
+    log("kernels:", kernels)
+    log(f"ranks: max {max(int(r.max()) for r in ranks)}, HODLR device bytes {H.nbytes() / 2**30:.2f} GiB")
+    H.profile(0)
+    H.close()
+
+    dense = None
+    if not args.no_dense:
+        D = P.Dense(N, norb, k=k)
+        D.profile(args.prof_stride)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.dense_steps):
+            sweep(D)
+        torch.cuda.synchronize()
+        ddt = time.perf_counter() - t0
+        dval = args.dense_steps * N / ddt
+        sd, md = D.profile_read(0)
+        dbytes = np.array([float(2 * npair * ((int(n) + 1) * (int(n) + 2) // 2) * 16
+                                 + 2 * (int(n) + 1) * npair * 16) for n in sd], dtype=np.float64)
+        dgbs = float(dbytes.sum() / (md.sum() * 1e-3) / 1e9)
+        dense = dict(value=round(dval, 2), unit="steps/s", sweeps=args.dense_steps,
+                     tile_kernel_gbs=round(dgbs, 1), tile_kernel_frac=round(dgbs / HBM_PEAK_GBS, 4),
+                     hodlr_speedup=round(value / dval, 2), device_gib=round(D.nbytes() / 2**30, 2))
+        log(f"dense: {ddt:.3f} s -> {dval:.1f} steps/s, tile kernel {dgbs:.0f} GB/s")
+        D.profile(0)
+        D.close()
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(cfg, G, S, args.cpu_budget)
+        log(f"cpu oracle: {cpu['value']:.3e} steps/s")
+
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 / value, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": f"norb{norb}-nt{N}: N_t={N}, norb={norb}, h={h}, Gregory k={k}, "
+                               f"leaf {cfg['leaf']} ({nlvl} levels), eps_SVD={cfg['tol']}, panel {panel}, "
+                               f"8+8 Hermitian damped-exponential generators; one bench step = one sweep "
+                               f"of N_t time steps (append R and < rows, merges, I^R and I^<)",
+                   "n_t": N, "norb": norb, "step_unit": "time step"},
+        "roofline": roof,
+        "kernels": kernels,
+        "dense": dense,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

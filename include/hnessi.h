@@ -168,6 +168,19 @@ int hnessi_hodlr_leaves(hnessi_hodlr_t H, int* tab_host, int capacity);
 /* Device bytes held by the handle (factor capacity, leaves, tail, band, scratch). */
 size_t hnessi_hodlr_bytes(hnessi_hodlr_t H);
 
+/* Kernel timing with HIP events recorded on the launch stream (measurement).
+ * stride > 0: from now on time the two history kernels of every step n with
+ * n % stride == 0, and every panel merge; stride = 0 stops.  Clears earlier
+ * records (synchronizes the device). */
+int hnessi_hodlr_profile(hnessi_hodlr_t H, int stride);
+
+/* Synchronizes the recorded events; for kernel kind 0 (projection / leaf /
+ * tail tasks), 1 (combine) or 2 (panel merge, both of its kernels) returns the
+ * number of timed launches and writes, for the first `capacity` of them, the
+ * step n (host int) and the duration in ms (host double).  Either output
+ * pointer may be NULL. */
+int hnessi_hodlr_profile_read(hnessi_hodlr_t H, int kind, int* steps_host, double* ms_host, int capacity);
+
 /* ---------------------------------------------------------------------------
  * Truncated SVD of one dense block (section "Hierarchical decomposition"):
  * A (device, rows x cols complex128, row-major with leading dimension lda)
@@ -200,6 +213,10 @@ int hnessi_dense_sweep(hnessi_dense_t D, int n_begin, int n_end, const void* GR,
                        const void* SR, const void* SL, double h, void* IR, void* IL,
                        void* stream);
 size_t hnessi_dense_bytes(hnessi_dense_t D);
+/* Event timing of the dense kernels as for the HODLR handle: kind 0 = tile
+ * kernel, 1 = reduction. */
+int hnessi_dense_profile(hnessi_dense_t D, int stride);
+int hnessi_dense_profile_read(hnessi_dense_t D, int kind, int* steps_host, double* ms_host, int capacity);
 
 #ifdef __cplusplus
 }

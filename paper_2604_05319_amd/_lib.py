@@ -61,6 +61,10 @@ _SIGS = {
     "hnessi_dense_sweep": ([C.c_void_p, C.c_int, C.c_int] + [C.c_void_p] * 4 + [C.c_double]
                            + [C.c_void_p] * 3, C.c_int),
     "hnessi_dense_bytes": ([C.c_void_p], C.c_size_t),
+    "hnessi_hodlr_profile": ([C.c_void_p, C.c_int], C.c_int),
+    "hnessi_hodlr_profile_read": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int], C.c_int),
+    "hnessi_dense_profile": ([C.c_void_p, C.c_int], C.c_int),
+    "hnessi_dense_profile_read": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int], C.c_int),
 }
 
 
@@ -108,6 +112,15 @@ def _stream(stream=None):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return C.c_void_p(s.cuda_stream)
+
+
+def _profile_read(fn, h, kind):
+    """(steps, ms) arrays of the timed launches of one kernel kind."""
+    cnt = _check(fn(h, kind, None, None, 0))
+    steps = np.zeros(max(cnt, 1), dtype=np.int32)
+    ms = np.zeros(max(cnt, 1), dtype=np.float64)
+    _check(fn(h, kind, steps.ctypes.data_as(C.c_void_p), ms.ctypes.data_as(C.c_void_p), cnt))
+    return steps[:cnt], ms[:cnt]
 
 
 def weights(k: int, L: int) -> np.ndarray:
@@ -188,6 +201,12 @@ class Hodlr:
     def nbytes(self):
         return int(lib().hnessi_hodlr_bytes(self.h))
 
+    def profile(self, stride):
+        _check(lib().hnessi_hodlr_profile(self.h, stride))
+
+    def profile_read(self, kind):
+        return _profile_read(lib().hnessi_hodlr_profile_read, self.h, kind)
+
 
 class Dense:
     """Uncompressed storage of both components and direct-summation history integrals."""
@@ -225,6 +244,12 @@ class Dense:
 
     def nbytes(self):
         return int(lib().hnessi_dense_bytes(self.h))
+
+    def profile(self, stride):
+        _check(lib().hnessi_dense_profile(self.h, stride))
+
+    def profile_read(self, kind):
+        return _profile_read(lib().hnessi_dense_profile_read, self.h, kind)
 
 
 def compress_block(A, tol, max_rank):

@@ -81,6 +81,51 @@ struct Allocs {
 
 int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }
 
+// HIP-event timing of kernel launches on the launch stream
+struct Prof {
+    int stride = 0;  // 0: off; otherwise time the launches of steps n % stride == 0
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    struct Rec {
+        int kind, n;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    hipEvent_t ev() {
+        if (used == pool.size()) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    bool want(int n) const { return stride > 0 && n % stride == 0; }
+    void clear() {
+        recs.clear();
+        used = 0;
+    }
+    void release() {
+        for (hipEvent_t e : pool) hipEventDestroy(e);
+        pool.clear();
+        clear();
+    }
+    int read(int kind, int* steps, double* ms, int cap) {
+        int cnt = 0;
+        for (const Rec& r : recs) {
+            if (r.kind != kind) continue;
+            if (cnt < cap) {
+                float t = 0.f;
+                if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess)
+                    return fail(HNESSI_E_DEVICE, "event timing failed");
+                if (steps) steps[cnt] = r.n;
+                if (ms) ms[cnt] = t;
+            }
+            ++cnt;
+        }
+        return cnt;
+    }
+};
+
 }  // namespace
 
 struct hnessi_hodlr_s {
@@ -134,6 +179,7 @@ struct hnessi_hodlr_s {
     double* Sold = nullptr;
     int* rold = nullptr;
     int* err = nullptr;
+    Prof prof;
 };
 
 struct hnessi_dense_s {
@@ -146,6 +192,7 @@ struct hnessi_dense_s {
     cd* colL = nullptr;
     cd* rowL = nullptr;
     int last[2] = {-1, -1};
+    Prof prof;
 };
 
 extern "C" {
@@ -332,6 +379,7 @@ int hnessi_hodlr_create(hnessi_hodlr_t* out, int nt, int nlvl, int norb, int k, 
 int hnessi_hodlr_destroy(hnessi_hodlr_t H) {
     if (!H) return fail(HNESSI_E_ARG, "handle is NULL");
     hipDeviceSynchronize();
+    H->prof.release();
     H->al.release();
     delete H;
     return HNESSI_OK;
@@ -403,7 +451,14 @@ int merge_panel(hnessi_hodlr_t H, int c, int p0, int p1, hipStream_t st) {
     a.nblk = nblk;
     a.ntask_v = nv;
     a.ntask_u = nu;
+    const bool timed = H->prof.stride > 0;
+    hipEvent_t e0 = timed ? H->prof.ev() : nullptr, e1 = timed ? H->prof.ev() : nullptr;
+    if (e0) hipEventRecord(e0, st);
     HIP_TRY(launch_merge(a, st));
+    if (e1) {
+        hipEventRecord(e1, st);
+        H->prof.recs.push_back({2, p1 - 1, e0, e1});
+    }
     return HNESSI_OK;
 }
 
@@ -484,7 +539,14 @@ int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, doub
     A.tailcnt = H->tailcnt;
     A.outR = static_cast<cd*>(outR);
     A.outL = static_cast<cd*>(outL);
-    HIP_TRY(launch_history(A, st));
+    if (H->prof.want(n)) {
+        hipEvent_t ev[3] = {H->prof.ev(), H->prof.ev(), H->prof.ev()};
+        HIP_TRY(launch_history(A, st, ev));
+        H->prof.recs.push_back({0, n, ev[0], ev[1]});
+        H->prof.recs.push_back({1, n, ev[1], ev[2]});
+    } else {
+        HIP_TRY(launch_history(A, st));
+    }
     return HNESSI_OK;
 }
 
@@ -657,6 +719,19 @@ int hnessi_hodlr_leaves(hnessi_hodlr_t H, int* tab_host, int capacity) {
 
 size_t hnessi_hodlr_bytes(hnessi_hodlr_t H) { return H ? H->al.bytes : 0; }
 
+int hnessi_hodlr_profile(hnessi_hodlr_t H, int stride) {
+    if (!H || stride < 0) return fail(HNESSI_E_ARG, "bad argument");
+    HIP_TRY(hipDeviceSynchronize());
+    H->prof.clear();
+    H->prof.stride = stride;
+    return HNESSI_OK;
+}
+
+int hnessi_hodlr_profile_read(hnessi_hodlr_t H, int kind, int* steps_host, double* ms_host, int capacity) {
+    if (!H || kind < 0 || kind > 2) return fail(HNESSI_E_ARG, "bad argument");
+    return H->prof.read(kind, steps_host, ms_host, capacity);
+}
+
 int hnessi_compress_block(const void* A, int rows, int cols, int lda, double tol, int max_rank, void* U,
                           double* S, void* V, int* rank_out, void* stream) {
     if (!A || !U || !S || !V || !rank_out) return fail(HNESSI_E_ARG, "NULL argument");
@@ -775,6 +850,7 @@ int hnessi_dense_create(hnessi_dense_t* out, int nt, int norb, int k, void* stre
 int hnessi_dense_destroy(hnessi_dense_t D) {
     if (!D) return fail(HNESSI_E_ARG, "handle is NULL");
     hipDeviceSynchronize();
+    D->prof.release();
     D->al.release();
     delete D;
     return HNESSI_OK;
@@ -818,7 +894,14 @@ int hnessi_dense_history_step(hnessi_dense_t D, int n, const void* sigR_row, con
     a.rowL = D->rowL;
     a.outR = static_cast<cd*>(outR);
     a.outL = static_cast<cd*>(outL);
-    HIP_TRY(launch_dense_history(a, (hipStream_t)stream));
+    if (D->prof.want(n)) {
+        hipEvent_t ev[3] = {D->prof.ev(), D->prof.ev(), D->prof.ev()};
+        HIP_TRY(launch_dense_history(a, (hipStream_t)stream, ev));
+        D->prof.recs.push_back({0, n, ev[0], ev[1]});
+        D->prof.recs.push_back({1, n, ev[1], ev[2]});
+    } else {
+        HIP_TRY(launch_dense_history(a, (hipStream_t)stream));
+    }
     return HNESSI_OK;
 }
 
@@ -842,5 +925,18 @@ int hnessi_dense_sweep(hnessi_dense_t D, int n_begin, int n_end, const void* GR,
 }
 
 size_t hnessi_dense_bytes(hnessi_dense_t D) { return D ? D->al.bytes : 0; }
+
+int hnessi_dense_profile(hnessi_dense_t D, int stride) {
+    if (!D || stride < 0) return fail(HNESSI_E_ARG, "bad argument");
+    HIP_TRY(hipDeviceSynchronize());
+    D->prof.clear();
+    D->prof.stride = stride;
+    return HNESSI_OK;
+}
+
+int hnessi_dense_profile_read(hnessi_dense_t D, int kind, int* steps_host, double* ms_host, int capacity) {
+    if (!D || kind < 0 || kind > 1) return fail(HNESSI_E_ARG, "bad argument");
+    return D->prof.read(kind, steps_host, ms_host, capacity);
+}
 
 }  // extern "C"

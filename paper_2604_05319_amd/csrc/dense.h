@@ -22,6 +22,6 @@ struct DenseArgs {
 
 int dense_band_count(int nt);
 hipError_t dense_init();
-hipError_t launch_dense_history(const DenseArgs& a, hipStream_t st);
+hipError_t launch_dense_history(const DenseArgs& a, hipStream_t st, hipEvent_t* ev = nullptr);
 
 }  // namespace hn

@@ -189,11 +189,14 @@ __global__ void dense_reduce(DenseArgs A) {
 size_t dense_smem(int norb) { return (size_t)2 * TB * norb * norb * sizeof(cd); }
 
 template <int NORB>
-hipError_t launch_dense_t(const DenseArgs& a, hipStream_t st) {
+hipError_t launch_dense_t(const DenseArgs& a, hipStream_t st, hipEvent_t* ev) {
     const int nbands = a.n / TB + 1;
     const int ntiles = nbands * (nbands + 1) / 2;
+    if (ev) hipEventRecord(ev[0], st);
     dense_tiles<NORB><<<ntiles, NTD, dense_smem(NORB), st>>>(a);
+    if (ev) hipEventRecord(ev[1], st);
     dense_reduce<NORB><<<(a.n + 1 + 63) / 64, 64 * NORB, 0, st>>>(a);
+    if (ev) hipEventRecord(ev[2], st);
     return hipGetLastError();
 }
 
@@ -213,11 +216,11 @@ hipError_t dense_init() {
     return e;
 }
 
-hipError_t launch_dense_history(const DenseArgs& a, hipStream_t st) {
+hipError_t launch_dense_history(const DenseArgs& a, hipStream_t st, hipEvent_t* ev) {
     switch (a.norb) {
-        case 1: return launch_dense_t<1>(a, st);
-        case 2: return launch_dense_t<2>(a, st);
-        case 4: return launch_dense_t<4>(a, st);
+        case 1: return launch_dense_t<1>(a, st, ev);
+        case 2: return launch_dense_t<2>(a, st, ev);
+        case 4: return launch_dense_t<4>(a, st, ev);
         default: return hipErrorInvalidValue;
     }
 }

@@ -56,7 +56,9 @@ struct HistArgs {
     cd* outL;
 };
 
-hipError_t launch_history(const HistArgs& a, hipStream_t st);
+// ev: nullptr, or three events recorded before hist_tasks, between the two
+// kernels, and after hist_combine (per-kernel timing on the launch stream)
+hipError_t launch_history(const HistArgs& a, hipStream_t st, hipEvent_t* ev = nullptr);
 hipError_t history_init();
 
 }  // namespace hn

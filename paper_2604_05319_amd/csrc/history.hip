@@ -502,23 +502,26 @@ size_t tasks_smem(int norb) {
 }
 
 template <int NORB>
-hipError_t launch_t(const HistArgs& a, hipStream_t st) {
+hipError_t launch_t(const HistArgs& a, hipStream_t st, hipEvent_t* ev) {
     const int ntask = a.nf[0] + a.nf[1] + a.nleaftask + a.ntailtask;
+    if (ev) hipEventRecord(ev[0], st);
     if (ntask > 0) hist_tasks<NORB><<<ntask, NT, tasks_smem(NORB), st>>>(a);
+    if (ev) hipEventRecord(ev[1], st);
     const int nblk = (a.n + 1 + 63) / 64;
     hist_combine<NORB><<<nblk, 64 * NORB, 0, st>>>(a);
+    if (ev) hipEventRecord(ev[2], st);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_history(const HistArgs& a, hipStream_t st) {
+hipError_t launch_history(const HistArgs& a, hipStream_t st, hipEvent_t* ev) {
     switch (a.norb) {
-        case 1: return launch_t<1>(a, st);
-        case 2: return launch_t<2>(a, st);
-        case 4: return launch_t<4>(a, st);
-        case 8: return launch_t<8>(a, st);
-        case 16: return launch_t<16>(a, st);
+        case 1: return launch_t<1>(a, st, ev);
+        case 2: return launch_t<2>(a, st, ev);
+        case 4: return launch_t<4>(a, st, ev);
+        case 8: return launch_t<8>(a, st, ev);
+        case 16: return launch_t<16>(a, st, ev);
         default: return hipErrorInvalidValue;
     }
 }
