@@ -164,9 +164,7 @@ struct hnessi_hodlr_s {
     cd* leafLR = nullptr;
     cd* leafLL = nullptr;
     cd* tailcol[2] = {};
-    cd* taildot[2] = {};
     cd* tailpart[2] = {};
-    int* tailcnt = nullptr;
     int ntailchunk_max = 0;
     // merge scratch
     std::vector<long long> lvl_node_base;  // per level: first node of pair 0
@@ -318,10 +316,8 @@ int hnessi_hodlr_create(hnessi_hodlr_t* out, int nt, int nlvl, int norb, int k, 
     H->ntailchunk_max = div_up(nt, kTailCH);
     for (int c = 0; c < 2; ++c) {
         HALLOC(H->tailcol[c], (size_t)nt * npair, true);
-        HALLOC(H->taildot[c], (size_t)panel * npair, true);
-        HALLOC(H->tailpart[c], (size_t)norb * H->ntailchunk_max * panel * norb, true);
+        HALLOC(H->tailpart[c], (size_t)H->ntailchunk_max * panel * npair, true);
     }
-    HALLOC(H->tailcnt, 2 * norb, true);
     // merge scratch: one block per level per panel
     H->lvl_node_base.assign(nlvl + 1, 0);
     H->lvl_nodes.assign(nlvl + 1, 0);
@@ -516,7 +512,6 @@ int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, doub
         A.tail[c] = H->tail[c];
         A.ft[c] = H->d_ft[c];
         A.tailcol[c] = H->tailcol[c];
-        A.taildot[c] = H->taildot[c];
         A.tailpart[c] = H->tailpart[c];
     }
     A.band = H->band;
@@ -528,15 +523,15 @@ int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, doub
     A.Loff = H->d_Loff;
     A.partoff = H->d_partoff;
     A.nleaf = g.row_leaf[n] + 1;
-    A.nleaftask = div_up(2 * A.nleaf, 8) * 8 * H->norb;
-    A.ntailtask = div_up(A.ntailchunk[0] + A.ntailchunk[1], 8) * 8 * H->norb;
+    const int ngroups = H->norb <= 4 ? 1 : H->norb / 4;   // left-orbital groups of 4 waves
+    A.nleaftask = div_up(2 * A.nleaf, 8) * 8 * ngroups;
+    A.ntailtask = div_up(A.ntailchunk[0] + A.ntailchunk[1], 8) * 8 * ngroups;
     A.proj = H->proj;
     A.part = H->part;
     A.cnt = H->cnt;
     A.leafR = H->leafR;
     A.leafLR = H->leafLR;
     A.leafLL = H->leafLL;
-    A.tailcnt = H->tailcnt;
     A.outR = static_cast<cd*>(outR);
     A.outL = static_cast<cd*>(outL);
     if (H->prof.want(n)) {

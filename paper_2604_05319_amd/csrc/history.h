@@ -48,10 +48,8 @@ struct HistArgs {
     cd* leafR;       // [m][a][c]
     cd* leafLR;
     cd* leafLL;
-    cd* tailcol[2];  // [m][a][c]
-    cd* taildot[2];  // [slot][a][c]
-    cd* tailpart[2]; // [a][chunk][slot][c]
-    int* tailcnt;    // [comp][a]
+    cd* tailcol[2];  // [m][a][c]       column sums over the tail rows
+    cd* tailpart[2]; // [chunk][slot][a][c]  row dots of the tail rows, per column chunk
     cd* outR;
     cd* outL;
 };

@@ -54,13 +54,27 @@ __device__ inline size_t proj_slot(const HistArgs& A, int comp, int b, int q, in
     return (((size_t)comp * A.nb + b) * A.npair + q) * 2 + which;
 }
 
+// left orbital indices handled by one workgroup (one wave each) and the
+// number of such groups
+template <int NORB>
+struct AGroups {
+    static constexpr int AG = NORB < 4 ? NORB : 4;
+    static constexpr int NG = NORB / AG;
+};
+
 // ---------------------------------------------------------------------------
+// Projection of one chunk of kCH rows of U (which = 0) or V (which = 1) of one
+// block and orbital pair.  Wave w takes the ranks r = w, w+4, ...; its lanes
+// run over the chunk's rows (kCH/64 rows each) before one wave reduction.
 template <int NORB>
 __device__ void fact_task(const HistArgs& A, const FactTask& t, unsigned char* smem) {
     const int comp = t.comp, b = t.b, q = t.q, which = t.which, chunk = t.chunk;
     if (comp == 0 && which == 0 && !A.wantR) return;
     if ((comp == 1 || which == 1) && !A.wantL) return;
-    const int npair = NORB * NORB, RC = A.RC;
+    constexpr int npair = NORB * NORB;
+    constexpr bool kStage = NORB <= 4;             // Sigma rows staged in LDS
+    constexpr int RW = 4;                          // ranks per wave (rank capacity <= 16)
+    const int RC = A.RC;
     const int qr = q / NORB, qc = q % NORB;
     const int rk = rank_of(A, comp, b, q);
     if (rk == 0) return;
@@ -82,48 +96,50 @@ __device__ void fact_task(const HistArgs& A, const FactTask& t, unsigned char* s
     const int nchunks = (len + CH - 1) / CH;
     const int i0 = chunk * CH, i1 = min(len, i0 + CH);
     const int n = A.n;
+    // folded Sigma entry multiplying row i of the factor, left orbital a
+    auto xval = [&](int i, int a) -> cd {
+        const int j = base + i;
+        if (comp == 0 && which == 0) return w_end(A.W, n, j) * A.sigR[(size_t)j * npair + a * NORB + qr];
+        if (comp == 0) return -w_start(A.W, j) * conj(A.sigL[(size_t)j * npair + qc * NORB + a]);
+        return interval_w(A.W, n, j) * A.sigR[(size_t)j * npair + a * NORB + (which == 0 ? qc : qr)];
+    };
     cd* xs = reinterpret_cast<cd*>(smem);  // CH x NORB
-    for (int e = threadIdx.x; e < (i1 - i0) * NORB; e += NT) {
-        const int i = e / NORB, a = e % NORB;
-        const int j = base + i0 + i;
-        cd v;
-        if (comp == 0 && which == 0) {
-            v = w_end(A.W, n, j) * A.sigR[(size_t)j * npair + a * NORB + qr];
-        } else if (comp == 0) {
-            v = -w_start(A.W, j) * conj(A.sigL[(size_t)j * npair + qc * NORB + a]);
-        } else {
-            v = interval_w(A.W, n, j) * A.sigR[(size_t)j * npair + a * NORB + (which == 0 ? qc : qr)];
-        }
-        xs[e] = v;
+    if (kStage) {
+        for (int e = threadIdx.x; e < (i1 - i0) * NORB; e += NT) xs[e] = xval(i0 + e / NORB, e % NORB);
+        __syncthreads();
     }
-    __syncthreads();
     const bool cj = (comp == 1);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const size_t slot = proj_slot(A, comp, b, q, which);
     cd* part = A.part + (A.partoff[slot] + chunk) * (size_t)NORB * RC;
-    for (int rb = 0; rb < rk; rb += NT / 64) {
-        const int r = rb + wave;
-        cd acc[NORB];
+    cd acc[RW][NORB];
 #pragma unroll
-        for (int a = 0; a < NORB; ++a) acc[a] = mk(0.0, 0.0);
-        if (r < rk) {
-            const cd* Fr = F + (size_t)r * ld;
-            for (int i = i0 + lane; i < i1; i += 64) {
-                cd f = Fr[i];
+    for (int k = 0; k < RW; ++k)
+#pragma unroll
+        for (int a = 0; a < NORB; ++a) acc[k][a] = mk(0.0, 0.0);
+    for (int i = i0 + lane; i < i1; i += 64) {
+        cd xv[NORB];
+#pragma unroll
+        for (int a = 0; a < NORB; ++a) xv[a] = kStage ? xs[(size_t)(i - i0) * NORB + a] : xval(i, a);
+#pragma unroll
+        for (int k = 0; k < RW; ++k) {
+            const int r = wave + 4 * k;
+            if (r < rk) {
+                cd f = F[(size_t)r * ld + i];
                 if (cj) f = conj(f);
-                const cd* xi = xs + (size_t)(i - i0) * NORB;
 #pragma unroll
-                for (int a = 0; a < NORB; ++a) fma_(acc[a], xi[a], f);
+                for (int a = 0; a < NORB; ++a) fma_(acc[k][a], xv[a], f);
             }
         }
+    }
+#pragma unroll
+    for (int k = 0; k < RW; ++k) {
+        const int r = wave + 4 * k;
+        if (r >= rk) continue;   // wave-uniform
 #pragma unroll
         for (int a = 0; a < NORB; ++a) {
-            acc[a].x = wsum64(acc[a].x);
-            acc[a].y = wsum64(acc[a].y);
-        }
-        if (lane == 0 && r < rk) {
-#pragma unroll
-            for (int a = 0; a < NORB; ++a) part[(size_t)a * RC + r] = acc[a];
+            const double re = wsum64(acc[k][a].x), im = wsum64(acc[k][a].y);
+            if (lane == 0) part[(size_t)a * RC + r] = mk(re, im);
         }
     }
     __threadfence();
@@ -138,191 +154,195 @@ __device__ void fact_task(const HistArgs& A, const FactTask& t, unsigned char* s
     cd* out = A.proj + slot * (size_t)NORB * RC;
     for (int e = threadIdx.x; e < NORB * rk; e += NT) {
         const int a = e / rk, r = e % rk;
-        cd s = mk(0.0, 0.0);
-        for (int c = 0; c < nchunks; ++c) s = s + p0[((size_t)c * NORB + a) * RC + r];
-        out[(size_t)a * RC + r] = S[r] * s;
+        cd sum = mk(0.0, 0.0);
+        for (int c = 0; c < nchunks; ++c) sum = sum + p0[((size_t)c * NORB + a) * RC + r];
+        out[(size_t)a * RC + r] = S[r] * sum;
     }
     if (threadIdx.x == 0) A.cnt[slot] = 0;
 }
 
 // ---------------------------------------------------------------------------
-// One leaf triangle, one component, one left orbital index a; the four waves
-// split the orbital pairs, lanes run over the leaf's columns m.
+// One leaf triangle and component; wave w handles the left orbital index
+// a = 4*ag + w, lanes the leaf's columns m.  Each orbital pair's triangle is
+// staged in LDS with coalesced loads; the column sum (rows j >= m) and the row
+// dot (columns s <= m) of lane m run in one loop over LDS.
 template <int NORB>
-__device__ void leaf_task(const HistArgs& A, int leaf, int comp, int a, unsigned char* smem) {
+__device__ void leaf_task(const HistArgs& A, int leaf, int comp, int ag, unsigned char* smem) {
     if (comp == 1 && !A.wantL) return;
-    constexpr int npair = NORB * NORB;
+    constexpr int npair = NORB * NORB, AG = AGroups<NORB>::AG;
     const int n = A.n;
     const int s0 = A.leafs[2 * leaf], s1 = A.leafs[2 * leaf + 1];
     const int lw = s1 - s0;
     const int nrow = min(s1, n + 1) - s0;
     const cd* L = A.leaf[comp] + A.Loff[leaf];
-    const long long tsz = tri(lw);
-    cd* xa = reinterpret_cast<cd*>(smem);  // 64 x NORB
-    cd* xb = xa + 64 * NORB;               // 64 x NORB
-    cd* red = xb + 64 * NORB;              // 3 x 64 x NORB
-    for (int e = threadIdx.x; e < nrow * NORB; e += NT) {
-        const int i = e / NORB, bb = e % NORB, j = s0 + i;
-        if (comp == 0) {
-            xa[e] = w_end(A.W, n, j) * A.sigR[(size_t)j * npair + a * NORB + bb];
-            // Sigma^< is only passed (and only read) when the lesser output is wanted
-            xb[e] = A.wantL ? -w_start(A.W, j) * conj(A.sigL[(size_t)j * npair + bb * NORB + a])
-                            : mk(0.0, 0.0);
-        } else {
-            xa[e] = interval_w(A.W, n, j) * A.sigR[(size_t)j * npair + a * NORB + bb];
-        }
-    }
-    __syncthreads();
+    const long long tsz = tri(lw), tnow = tri(nrow);
+    cd* T = reinterpret_cast<cd*>(smem);   // tri(64)
+    cd* xa = T + tri(64);                  // 64 x AG
+    cd* xb = xa + 64 * AG;                 // 64 x AG
     const int wave = threadIdx.x >> 6, mo = threadIdx.x & 63;
-    const bool act = mo < nrow;
+    const int a = ag * AG + wave;
+    const bool act = wave < AG && mo < nrow;
+    const bool doR = A.wantR, doL = A.wantL;
     cd accA[NORB], accB[NORB];
 #pragma unroll
     for (int c = 0; c < NORB; ++c) accA[c] = accB[c] = mk(0.0, 0.0);
-    if (act) {
-        for (int q = wave; q < npair; q += NT / 64) {
-            const int qr = q / NORB, qc = q % NORB;
-            const cd* Lq = L + (size_t)q * tsz;
-            const cd* rowm = Lq + tri(mo);
+    for (int q = 0; q < npair; ++q) {
+        const int qr = q / NORB, qc = q % NORB;
+        const cd* Lq = L + (size_t)q * tsz;
+        __syncthreads();
+        for (long long e = threadIdx.x; e < tnow; e += NT) T[e] = Lq[e];
+        for (int e = threadIdx.x; e < nrow * AG; e += NT) {
+            const int i = e / AG, aa = ag * AG + e % AG, j = s0 + i;
             if (comp == 0) {
-                if (A.wantR) {  // P1: column sums x(j) G^R(j, m)
-                    cd s = mk(0.0, 0.0);
-                    for (int j = mo; j < nrow; ++j) fma_(s, xa[j * NORB + qr], Lq[tri(j) + mo]);
-                    accA[qc] = accA[qc] + s;
-                }
-                if (A.wantL && s0 + mo > 0) {  // row dots x2(s) G^R(m, s)^dagger (empty at m = 0)
-                    cd s = mk(0.0, 0.0);
-                    for (int k = 0; k <= mo; ++k) fmac_(s, rowm[k], xb[k * NORB + qc]);
-                    accB[qr] = accB[qr] + s;
-                }
+                xa[e] = w_end(A.W, n, j) * A.sigR[(size_t)j * npair + aa * NORB + qr];
+                xb[e] = doL ? -w_start(A.W, j) * conj(A.sigL[(size_t)j * npair + qc * NORB + aa]) : mk(0.0, 0.0);
             } else {
-                cd s = mk(0.0, 0.0);  // row dots x1(s) G^<(s, m), s <= m
-                for (int k = 0; k <= mo; ++k) fma_(s, xa[k * NORB + qr], rowm[k]);
-                accA[qc] = accA[qc] + s;
-                cd u = mk(0.0, 0.0);  // column sums x1(s) G^<(s, m), s > m
-                for (int j = mo + 1; j < nrow; ++j) fmac_(u, Lq[tri(j) + mo], xa[j * NORB + qc]);
-                accA[qr] = accA[qr] - u;
+                xa[e] = interval_w(A.W, n, j) * A.sigR[(size_t)j * npair + aa * NORB + qr];
+                xb[e] = interval_w(A.W, n, j) * A.sigR[(size_t)j * npair + aa * NORB + qc];
+            }
+        }
+        __syncthreads();
+        if (act) {
+            cd colsum = mk(0.0, 0.0), rowdot = mk(0.0, 0.0);
+            const cd* rowm = T + tri(mo);
+            const int w = wave;
+            if (comp == 0) {
+                // column sum x(j) G^R(j, m), j = m..; row dot x2(s) G^R(m, s)^dagger, s <= m
+                const bool rowok = doL && (s0 + mo > 0);   // second lesser term is empty at m = 0
+                for (int t = 0; t < nrow; ++t) {
+                    const int j = mo + t;
+                    if (doR && j < nrow) fma_(colsum, xa[j * AG + w], T[tri(j) + mo]);
+                    if (rowok && t <= mo) fmac_(rowdot, rowm[t], xb[t * AG + w]);
+                }
+                accA[qc] = accA[qc] + colsum;   // -> I^R column m
+                accB[qr] = accB[qr] + rowdot;   // -> I^< (second term) row m
+            } else {
+                // row dot x1(s) G^<(s, m) for s <= m; column sum -x1(s) G^<(m, s)^dagger for s > m
+                for (int t = 0; t < nrow; ++t) {
+                    const int j = mo + 1 + t;
+                    if (t <= mo) fma_(rowdot, xa[t * AG + w], rowm[t]);
+                    if (j < nrow) fmac_(colsum, T[tri(j) + mo], xb[j * AG + w]);
+                }
+                accA[qc] = accA[qc] + rowdot;
+                accA[qr] = accA[qr] - colsum;
             }
         }
     }
-    // reduce the four waves
-    for (int pass = 0; pass < (comp == 0 ? 2 : 1); ++pass) {
-        cd* acc = pass == 0 ? accA : accB;
-        if (wave > 0) {
+    if (act) {
+        const int m = s0 + mo;
 #pragma unroll
-            for (int c = 0; c < NORB; ++c) red[((wave - 1) * 64 + mo) * NORB + c] = acc[c];
-        }
-        __syncthreads();
-        if (wave == 0 && act) {
-            const int m = s0 + mo;
-            cd* dst = comp == 1 ? A.leafLL : (pass == 0 ? A.leafR : A.leafLR);
-#pragma unroll
-            for (int c = 0; c < NORB; ++c) {
-                cd v = acc[c];
-                for (int w = 0; w < NT / 64 - 1; ++w) v = v + red[(w * 64 + mo) * NORB + c];
-                dst[(size_t)m * npair + a * NORB + c] = v;
+        for (int c = 0; c < NORB; ++c) {
+            const size_t o = (size_t)m * npair + a * NORB + c;
+            if (comp == 0) {
+                A.leafR[o] = accA[c];
+                A.leafLR[o] = accB[c];
+            } else {
+                A.leafLL[o] = accA[c];
             }
         }
-        __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
-// Rows appended since the last panel merge (dense), columns [0, ls):
-// column sums into tailcol, row dots (partial per column chunk) into taildot.
+// Rows appended since the last panel merge (dense), columns [chunk*64, +64) of
+// [0, ls): the column sums over those rows are complete here; the row dots are
+// written per column chunk and summed by the combine.
 template <int NORB>
-__device__ void tail_task(const HistArgs& A, int comp, int a, int chunk, unsigned char* smem) {
+__device__ void tail_task(const HistArgs& A, int comp, int ag, int chunk, unsigned char* smem) {
     if (comp == 1 && !A.wantL) return;
-    constexpr int npair = NORB * NORB;
+    constexpr int npair = NORB * NORB, AG = AGroups<NORB>::AG;
     const int n = A.n;
     const int n0 = A.n0[comp], nrows = A.last[comp] - n0 + 1, ls = A.ls[comp];
-    const int m = chunk * kTailCH + threadIdx.x;
-    const bool act = m < ls;
-    cd* xr = reinterpret_cast<cd*>(smem);  // P x NORB
-    cd* red = xr + (size_t)A.P * NORB;     // 4 x NORB
-    for (int e = threadIdx.x; e < nrows * NORB; e += NT) {
-        const int i = e / NORB, bb = e % NORB, j = n0 + i;
-        const double w = comp == 0 ? w_end(A.W, n, j) : interval_w(A.W, n, j);
-        xr[e] = w * A.sigR[(size_t)j * npair + a * NORB + bb];
-    }
-    cd xm[NORB];
-#pragma unroll
-    for (int bb = 0; bb < NORB; ++bb) {
-        xm[bb] = mk(0.0, 0.0);
-        if (act) {
-            if (comp == 0) {
-                if (A.wantL) xm[bb] = -w_start(A.W, m) * conj(A.sigL[(size_t)m * npair + bb * NORB + a]);
-            } else
-                xm[bb] = interval_w(A.W, n, m) * A.sigR[(size_t)m * npair + a * NORB + bb];
-        }
-    }
-    __syncthreads();
-    const cd* T = A.tail[comp];
+    const int cbeg = chunk * kTailCH, ncol = min(kTailCH, ls - cbeg);
+    cd* T = reinterpret_cast<cd*>(smem);       // P x 64
+    cd* xr = T + (size_t)A.P * kTailCH;        // P x AG   (row-side Sigma)
+    cd* xm = xr + (size_t)A.P * AG;            // 64 x AG  (column-side Sigma)
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    cd col[NORB];
+    const int a = ag * AG + wave;
+    const bool wok = wave < AG;
+    const bool doR = A.wantR, doL = A.wantL;
+    const cd* Tg = A.tail[comp];
+    cd col[NORB], row[NORB];
 #pragma unroll
-    for (int c = 0; c < NORB; ++c) col[c] = mk(0.0, 0.0);
-    cd* tp = A.tailpart[comp] + ((size_t)a * A.ntailchunk[comp] + chunk) * A.P * NORB;
-    for (int i = 0; i < nrows; ++i) {
-        cd row[NORB];
-#pragma unroll
-        for (int c = 0; c < NORB; ++c) row[c] = mk(0.0, 0.0);
-        if (act) {
-#pragma unroll
-            for (int q = 0; q < npair; ++q) {
-                const int qr = q / NORB, qc = q % NORB;
-                const cd t = T[((size_t)i * npair + q) * A.nt + m];
+    for (int c = 0; c < NORB; ++c) col[c] = row[c] = mk(0.0, 0.0);
+    const int ri = lane & 15, part = lane >> 4;   // row-dot mapping: row ri, 16 columns per part
+    for (int q = 0; q < npair; ++q) {
+        const int qr = q / NORB, qc = q % NORB;
+        __syncthreads();
+        for (int e = threadIdx.x; e < nrows * kTailCH; e += NT) {
+            const int i = e / kTailCH, mm = e % kTailCH;
+            T[e] = mm < ncol ? Tg[((size_t)i * npair + q) * A.nt + cbeg + mm] : mk(0.0, 0.0);
+        }
+        for (int e = threadIdx.x; e < nrows * AG; e += NT) {
+            const int i = e / AG, aa = ag * AG + e % AG, j = n0 + i;
+            xr[e] = comp == 0 ? w_end(A.W, n, j) * A.sigR[(size_t)j * npair + aa * NORB + qr]
+                              : interval_w(A.W, n, j) * A.sigR[(size_t)j * npair + aa * NORB + qc];
+        }
+        for (int e = threadIdx.x; e < kTailCH * AG; e += NT) {
+            const int mm = e / AG, aa = ag * AG + e % AG, m = cbeg + mm;
+            cd v = mk(0.0, 0.0);
+            if (mm < ncol) {
                 if (comp == 0) {
-                    if (A.wantR) fma_(col[qc], xr[i * NORB + qr], t);   // x(j) G^R(j, m)
-                    if (A.wantL) fmac_(row[qr], t, xm[qc]);              // x2(m) G^R(j, m)^dagger
+                    if (doL) v = -w_start(A.W, m) * conj(A.sigL[(size_t)m * npair + qc * NORB + aa]);
                 } else {
-                    fmac_(col[qr], t, -xr[i * NORB + qc]);               // -x1(j) G^<(m, j)^dagger
-                    fma_(row[qc], xm[qr], t);                            // x1(m) G^<(m, j)
+                    v = interval_w(A.W, n, m) * A.sigR[(size_t)m * npair + aa * NORB + qr];
                 }
             }
-        }
-#pragma unroll
-        for (int c = 0; c < NORB; ++c) {
-            row[c].x = wsum64(row[c].x);
-            row[c].y = wsum64(row[c].y);
-        }
-        if (lane == 0) {
-#pragma unroll
-            for (int c = 0; c < NORB; ++c) red[wave * NORB + c] = row[c];
+            xm[e] = v;
         }
         __syncthreads();
-        if (threadIdx.x < NORB) {
-            cd v = mk(0.0, 0.0);
-            for (int w = 0; w < NT / 64; ++w) v = v + red[w * NORB + threadIdx.x];
-            tp[(size_t)i * NORB + threadIdx.x] = v;
+        if (wok) {
+            // column sums (lane = column)
+            cd cs = mk(0.0, 0.0);
+            for (int i = 0; i < nrows; ++i) {
+                if (comp == 0) fma_(cs, xr[i * AG + wave], T[i * kTailCH + lane]);
+                else fmac_(cs, T[i * kTailCH + lane], xr[i * AG + wave]);
+            }
+            if (comp == 0) {
+                if (doR) col[qc] = col[qc] + cs;     // x(j) G^R(j, m)
+            } else {
+                col[qr] = col[qr] - cs;              // -x1(j) G^<(m, j)^dagger
+            }
+            // row dots (lane = row ri, columns 16*part .. +16)
+            cd rd = mk(0.0, 0.0);
+            if (ri < nrows) {
+                for (int mm = part * 16; mm < part * 16 + 16; ++mm) {
+                    if (comp == 0) fmac_(rd, T[ri * kTailCH + mm], xm[mm * AG + wave]);
+                    else fma_(rd, xm[mm * AG + wave], T[ri * kTailCH + mm]);
+                }
+            }
+            if (comp == 0) row[qr] = row[qr] + rd;   // x2(m) G^R(j, m)^dagger
+            else row[qc] = row[qc] + rd;             // x1(m) G^<(m, j)
         }
-        __syncthreads();
     }
-    if (act) {
+    // reduce the four column parts of each row dot (lanes ri, ri+16, ri+32, ri+48)
 #pragma unroll
-        for (int c = 0; c < NORB; ++c) A.tailcol[comp][(size_t)m * npair + a * NORB + c] = col[c];
+    for (int c = 0; c < NORB; ++c) {
+        double re = row[c].x, im = row[c].y;
+        re += __shfl_xor(re, 16, 64);
+        im += __shfl_xor(im, 16, 64);
+        re += __shfl_xor(re, 32, 64);
+        im += __shfl_xor(im, 32, 64);
+        row[c] = mk(re, im);
     }
-    __threadfence();
-    __syncthreads();
-    __shared__ int s_last;
-    const int nch = A.ntailchunk[comp];
-    int* cnt = A.tailcnt + comp * NORB + a;
-    if (threadIdx.x == 0) s_last = (atomicAdd(cnt, 1) == nch - 1);
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    const cd* tp0 = A.tailpart[comp] + (size_t)a * nch * A.P * NORB;
-    for (int e = threadIdx.x; e < nrows * NORB; e += NT) {
-        const int i = e / NORB, c = e % NORB;
-        cd v = mk(0.0, 0.0);
-        for (int ch = 0; ch < nch; ++ch) v = v + tp0[((size_t)ch * A.P + i) * NORB + c];
-        A.taildot[comp][((size_t)i * NORB + a) * NORB + c] = v;
+    if (wok) {
+        if (lane < ncol) {
+#pragma unroll
+            for (int c = 0; c < NORB; ++c)
+                A.tailcol[comp][(size_t)(cbeg + lane) * npair + a * NORB + c] = col[c];
+        }
+        if (part == 0 && ri < nrows) {
+            cd* tp = A.tailpart[comp] + ((size_t)chunk * A.P + ri) * npair + a * NORB;
+#pragma unroll
+            for (int c = 0; c < NORB; ++c) tp[c] = row[c];
+        }
     }
-    if (threadIdx.x == 0) *cnt = 0;
 }
 
 template <int NORB>
 __global__ void __launch_bounds__(NT) hist_tasks(HistArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int NG = AGroups<NORB>::NG;
     int id = blockIdx.x;
     if (id < A.nf[0]) {
         fact_task<NORB>(A, A.ft[0][id], smem);
@@ -335,19 +355,19 @@ __global__ void __launch_bounds__(NT) hist_tasks(HistArgs A) {
     }
     id -= A.nf[1];
     if (id < A.nleaftask) {
-        int g, a;
-        if (!xcd_group(id, 2 * A.nleaf, NORB, g, a)) return;
-        leaf_task<NORB>(A, g >> 1, g & 1, a, smem);
+        int g, ag;
+        if (!xcd_group(id, 2 * A.nleaf, NG, g, ag)) return;
+        leaf_task<NORB>(A, g >> 1, g & 1, ag, smem);
         return;
     }
     id -= A.nleaftask;
-    int g, a;
+    int g, ag;
     const int ng = A.ntailchunk[0] + A.ntailchunk[1];
-    if (!xcd_group(id, ng, NORB, g, a)) return;
+    if (!xcd_group(id, ng, NG, g, ag)) return;
     if (g < A.ntailchunk[0])
-        tail_task<NORB>(A, 0, a, g, smem);
+        tail_task<NORB>(A, 0, ag, g, smem);
     else
-        tail_task<NORB>(A, 1, a, g - A.ntailchunk[0], smem);
+        tail_task<NORB>(A, 1, ag, g - A.ntailchunk[0], smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -437,12 +457,14 @@ __global__ void __launch_bounds__(64 * NORB) hist_combine(HistArgs A) {
         }
         if (A.wantL) {
             accL[a] = accL[a] + A.leafLR[o] + A.leafLL[o];
-            if (A.last[0] >= A.n0[0] && m >= A.n0[0] && m <= A.last[0])
-                accL[a] = accL[a] + A.taildot[0][(size_t)(m - A.n0[0]) * npair + a * NORB + c];
-            if (A.last[1] >= A.n0[1]) {
-                if (m < A.ls[1]) accL[a] = accL[a] + A.tailcol[1][o];
-                if (m >= A.n0[1] && m <= A.last[1])
-                    accL[a] = accL[a] + A.taildot[1][(size_t)(m - A.n0[1]) * npair + a * NORB + c];
+            for (int comp = 0; comp < 2; ++comp) {
+                if (A.last[comp] < A.n0[comp]) continue;   // no tail rows
+                if (comp == 1 && m < A.ls[1]) accL[a] = accL[a] + A.tailcol[1][o];
+                if (m >= A.n0[comp] && m <= A.last[comp]) {
+                    const cd* tp = A.tailpart[comp] + (size_t)(m - A.n0[comp]) * npair + a * NORB + c;
+                    for (int ch = 0; ch < A.ntailchunk[comp]; ++ch)
+                        accL[a] = accL[a] + tp[(size_t)ch * A.P * npair];
+                }
             }
         }
     }
@@ -494,9 +516,10 @@ __global__ void __launch_bounds__(64 * NORB) hist_combine(HistArgs A) {
 }
 
 size_t tasks_smem(int norb) {
-    size_t fact = (size_t)CH * norb * sizeof(cd);
-    size_t leaf = (size_t)(2 * 64 + 3 * 64) * norb * sizeof(cd);
-    size_t tail = (size_t)(32 + 4) * norb * sizeof(cd);
+    const int ag = norb < 4 ? norb : 4;
+    size_t fact = norb <= 4 ? (size_t)CH * norb * sizeof(cd) : 0;
+    size_t leaf = (size_t)(tri(64) + 2 * 64 * ag) * sizeof(cd);
+    size_t tail = (size_t)(16 * kTailCH + (16 + kTailCH) * ag) * sizeof(cd);
     size_t s = fact > leaf ? fact : leaf;
     return s > tail ? s : tail;
 }

@@ -209,3 +209,57 @@ def test_compress_block_known_spectrum(P):
     np.testing.assert_allclose(np.conj(V.T) @ V, np.eye(r), atol=1e-12)
     err = np.linalg.norm(A - (U * S) @ np.conj(V.T), 2)
     assert err < 1e-12
+
+
+def _full_size_sweep(P, cls):
+    """C2 (N_t=8192, norb=4) in the bench's configuration; returns (cfg, ops, IR, IL)."""
+    from kbe_inputs.packed import packed_torch
+    from oracle.history import GeneratorOperands
+    cfg, G, S = make_config_inputs("c2")
+    N, h, norb, k = cfg["nt"], cfg["h"], cfg["norb"], cfg["k"]
+    dev = torch.device("cuda:0")
+    GR, GL = packed_torch(G, "ret", N, h, dev), packed_torch(G, "les", N, h, dev)
+    SR, SL = packed_torch(S, "ret", N, h, dev), packed_torch(S, "les", N, h, dev)
+    IR, IL = torch.empty_like(GR), torch.empty_like(GR)
+    obj = cls(N)
+    say("gpu: full-size sweep", cls.__name__ if hasattr(cls, "__name__") else cls)
+    obj.sweep(0, N, GR, GL, SR, SL, h, IR, IL)
+    torch.cuda.synchronize()
+    del GR, GL, SR, SL
+    return cfg, GeneratorOperands(G, S, h), IR, IL, obj
+
+
+def _check_sampled(cfg, ops, IR, IL, label):
+    from oracle.history import history_lesser_entry, history_R_entry
+    N, h, k = cfg["nt"], cfg["h"], cfg["k"]
+    rng = np.random.default_rng(2024)
+    rows = sorted(set([0, 1, 4, 5, 6, 10, 11, 63, 64, 65, 127, 128, 511, 4095, 4096, N - 1]
+                      + list(rng.integers(0, N, 8))))
+    worst = 0.0
+    for n in rows:
+        a = n * (n + 1) // 2
+        gR = IR[a:a + n + 1].cpu().numpy()
+        gL = IL[a:a + n + 1].cpu().numpy()
+        ms = sorted(set([0, 1, max(n - 6, 0), max(n - 5, 0), max(n - 1, 0), n]
+                        + list(rng.integers(0, n + 1, 6))))
+        scaleR, scaleL = np.abs(gR).max(), np.abs(gL).max()
+        for m in ms:
+            eR = np.abs(gR[m] - history_R_entry(ops, n, m, h, k)).max() / max(scaleR, 1e-300)
+            eL = np.abs(gL[m] - history_lesser_entry(ops, n, m, h, k)).max() / max(scaleL, 1e-300)
+            worst = max(worst, eR, eL)
+            assert eR <= TOL, (label, "R", n, m, eR)
+            assert eL <= TOL, (label, "L", n, m, eL)
+    say(label, "worst sampled relative error", worst)
+
+
+def test_c2_full_size_hodlr_sampled(P):
+    cfg, ops, IR, IL, H = _full_size_sweep(
+        P, lambda N: P.Hodlr(N, 7, 4, k=5, tol=1e-10, panel=16, max_rank=16))
+    assert H.status() == 0
+    assert H.ranks(P.RET).max() <= 8 and H.ranks(P.LES).max() <= 8   # 8 exponentials per pair
+    _check_sampled(cfg, ops, IR, IL, "hodlr c2")
+
+
+def test_c2_full_size_dense_sampled(P):
+    cfg, ops, IR, IL, D = _full_size_sweep(P, lambda N: P.Dense(N, 4, k=5))
+    _check_sampled(cfg, ops, IR, IL, "dense c2")
