@@ -141,7 +141,6 @@ struct hnessi_hodlr_s {
     long long* d_Uoff = nullptr;
     long long* d_Voff = nullptr;
     long long* d_Loff = nullptr;
-    long long* d_partoff = nullptr;
     std::vector<long long> Uoff, Voff, Loff;
     // per component
     cd* U[2] = {};
@@ -158,8 +157,6 @@ struct hnessi_hodlr_s {
     std::vector<int> ft_act[2];
     // history scratch
     cd* proj = nullptr;
-    cd* part = nullptr;
-    int* cnt = nullptr;
     cd* leafR = nullptr;
     cd* leafLR = nullptr;
     cd* leafLL = nullptr;
@@ -285,18 +282,6 @@ int hnessi_hodlr_create(hnessi_hodlr_t* out, int nt, int nlvl, int norb, int k, 
     HALLOC(H->d_Uoff, std::max(nb, 1), false);
     HALLOC(H->d_Voff, std::max(nb, 1), false);
     HALLOC(H->d_Loff, g.nleaf, false);
-    // projection partial slots
-    std::vector<long long> partoff((size_t)2 * std::max(nb, 1) * npair * 2, 0);
-    long long ps = 0;
-    for (int c = 0; c < 2; ++c)
-        for (int b = 0; b < nb; ++b)
-            for (int q = 0; q < npair; ++q)
-                for (int w = 0; w < 2; ++w) {
-                    partoff[(((size_t)c * nb + b) * npair + q) * 2 + w] = ps;
-                    int len = w == 0 ? g.r1[b] - g.r0[b] : g.c1[b] - g.c0[b];
-                    ps += div_up(len, kCH);
-                }
-    HALLOC(H->d_partoff, partoff.size(), false);
     // factor and dense storage
     for (int c = 0; c < 2; ++c) {
         HALLOC(H->U[c], uo, true);
@@ -308,11 +293,10 @@ int hnessi_hodlr_create(hnessi_hodlr_t* out, int nt, int nlvl, int norb, int k, 
     }
     HALLOC(H->band, (size_t)nt * (k + 1) * npair, true);
     HALLOC(H->proj, (size_t)2 * std::max(nb, 1) * npair * 2 * norb * RC, true);
-    HALLOC(H->part, (size_t)std::max(ps, 1LL) * norb * RC, true);
-    HALLOC(H->cnt, (size_t)2 * std::max(nb, 1) * npair * 2, true);
-    HALLOC(H->leafR, (size_t)nt * npair, true);
-    HALLOC(H->leafLR, (size_t)nt * npair, true);
-    HALLOC(H->leafLL, (size_t)nt * npair, true);
+    const int leaf_slots = norb == 1 ? 1 : 4;   // orbital-pair groups of the leaf tasks
+    HALLOC(H->leafR, (size_t)leaf_slots * nt * npair, true);
+    HALLOC(H->leafLR, (size_t)leaf_slots * nt * npair, true);
+    HALLOC(H->leafLL, (size_t)leaf_slots * nt * npair, true);
     H->ntailchunk_max = div_up(nt, kTailCH);
     for (int c = 0; c < 2; ++c) {
         HALLOC(H->tailcol[c], (size_t)nt * npair, true);
@@ -344,11 +328,8 @@ int hnessi_hodlr_create(hnessi_hodlr_t* out, int nt, int nlvl, int norb, int k, 
         std::vector<FactTask> ts;
         for (int b = 0; b < nb; ++b)
             for (int q = 0; q < npair; ++q) {
-                int nr = g.r1[b] - g.r0[b], ncol = g.c1[b] - g.c0[b];
-                for (int ch = 0; ch < div_up(nr, kCH); ++ch)
-                    ts.push_back(FactTask{c, b, q, 0, ch, g.r0[b] + ch * kCH});
-                for (int ch = 0; ch < div_up(ncol, kCH); ++ch)
-                    ts.push_back(FactTask{c, b, q, 1, ch, g.r0[b]});
+                ts.push_back(FactTask{c, b, q, 0, g.r0[b]});
+                ts.push_back(FactTask{c, b, q, 1, g.r0[b]});
             }
         std::stable_sort(ts.begin(), ts.end(),
                          [](const FactTask& x, const FactTask& y) { return x.act < y.act; });
@@ -364,8 +345,7 @@ int hnessi_hodlr_create(hnessi_hodlr_t* out, int nt, int nlvl, int norb, int k, 
         hipMemcpy(H->d_cover, g.cover.data(), g.cover.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
         (nb > 0 && hipMemcpy(H->d_Uoff, H->Uoff.data(), nb * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess) ||
         (nb > 0 && hipMemcpy(H->d_Voff, H->Voff.data(), nb * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess) ||
-        hipMemcpy(H->d_Loff, H->Loff.data(), g.nleaf * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(H->d_partoff, partoff.data(), partoff.size() * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess)
+        hipMemcpy(H->d_Loff, H->Loff.data(), g.nleaf * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess)
         return bail(fail(HNESSI_E_DEVICE, "copy of geometry failed"));
 #undef HALLOC
     *out = H;
@@ -521,14 +501,12 @@ int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, doub
     A.Uoff = H->d_Uoff;
     A.Voff = H->d_Voff;
     A.Loff = H->d_Loff;
-    A.partoff = H->d_partoff;
     A.nleaf = g.row_leaf[n] + 1;
     const int ngroups = H->norb <= 4 ? 1 : H->norb / 4;   // left-orbital groups of 4 waves
-    A.nleaftask = div_up(2 * A.nleaf, 8) * 8 * ngroups;
+    const int leafgroups = H->norb == 1 ? 1 : 4;                   // orbital-pair groups per leaf
+    A.nleaftask = div_up(2 * A.nleaf, 8) * 8 * ngroups * leafgroups;
     A.ntailtask = div_up(A.ntailchunk[0] + A.ntailchunk[1], 8) * 8 * ngroups;
     A.proj = H->proj;
-    A.part = H->part;
-    A.cnt = H->cnt;
     A.leafR = H->leafR;
     A.leafLR = H->leafLR;
     A.leafLL = H->leafLL;

@@ -5,10 +5,10 @@
 
 namespace hn {
 
-// A projection task: one chunk of kCH rows of U (which = 0) or V (which = 1)
-// of block b, orbital pair q, component comp.  Active once row `act` is merged.
+// A projection task: U (which = 0) or V (which = 1) of block b, orbital pair
+// q, component comp.  Active once row `act` (the block's first row) is merged.
 struct FactTask {
-    int comp, b, q, which, chunk, act;
+    int comp, b, q, which, act;
 };
 
 struct HistArgs {
@@ -35,7 +35,6 @@ struct HistArgs {
     const long long* Uoff;
     const long long* Voff;
     const long long* Loff;
-    const long long* partoff;  // per (comp, b, q, which): first partial slot
     const FactTask* ft[2];
     int nf[2];       // active projection tasks per component
     int nleaf;       // active leaves
@@ -43,9 +42,7 @@ struct HistArgs {
     int ntailchunk[2];
     int ntailtask;
     cd* proj;        // [comp][b][q][which][a][RC]  (S_r * projection)
-    cd* part;        // partial projections
-    int* cnt;        // [comp][b][q][which]
-    cd* leafR;       // [m][a][c]
+    cd* leafR;       // [pair group][m][a][c]   leaf pieces, one slot per pair group
     cd* leafLR;
     cd* leafLL;
     cd* tailcol[2];  // [m][a][c]       column sums over the tail rows

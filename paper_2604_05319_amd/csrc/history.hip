@@ -61,14 +61,21 @@ struct AGroups {
     static constexpr int AG = NORB < 4 ? NORB : 4;
     static constexpr int NG = NORB / AG;
 };
+// orbital-pair groups of a leaf, each a workgroup with its own output slot
+template <int NORB>
+struct LeafGroups {
+    static constexpr int LG = NORB == 1 ? 1 : 4;
+};
 
 // ---------------------------------------------------------------------------
-// Projection of one chunk of kCH rows of U (which = 0) or V (which = 1) of one
-// block and orbital pair.  Wave w takes the ranks r = w, w+4, ...; its lanes
-// run over the chunk's rows (kCH/64 rows each) before one wave reduction.
+// Projection of the whole U (which = 0, rows merged so far) or V (which = 1)
+// of one block and orbital pair, by one workgroup (no cross-workgroup
+// reduction, hence no device-scope fences).  Wave w takes the ranks
+// r = w, w+4, ...; its lanes run over the rows; the Sigma rows are staged in
+// LDS per kCH rows and shared by the four waves.
 template <int NORB>
 __device__ void fact_task(const HistArgs& A, const FactTask& t, unsigned char* smem) {
-    const int comp = t.comp, b = t.b, q = t.q, which = t.which, chunk = t.chunk;
+    const int comp = t.comp, b = t.b, q = t.q, which = t.which;
     if (comp == 0 && which == 0 && !A.wantR) return;
     if ((comp == 1 || which == 1) && !A.wantL) return;
     constexpr int npair = NORB * NORB;
@@ -93,8 +100,6 @@ __device__ void fact_task(const HistArgs& A, const FactTask& t, unsigned char* s
         ld = c1 - c0;
         F = A.V[comp] + A.Voff[b] + (size_t)q * RC * ld;
     }
-    const int nchunks = (len + CH - 1) / CH;
-    const int i0 = chunk * CH, i1 = min(len, i0 + CH);
     const int n = A.n;
     // folded Sigma entry multiplying row i of the factor, left orbital a
     auto xval = [&](int i, int a) -> cd {
@@ -104,61 +109,49 @@ __device__ void fact_task(const HistArgs& A, const FactTask& t, unsigned char* s
         return interval_w(A.W, n, j) * A.sigR[(size_t)j * npair + a * NORB + (which == 0 ? qc : qr)];
     };
     cd* xs = reinterpret_cast<cd*>(smem);  // CH x NORB
-    if (kStage) {
-        for (int e = threadIdx.x; e < (i1 - i0) * NORB; e += NT) xs[e] = xval(i0 + e / NORB, e % NORB);
-        __syncthreads();
-    }
     const bool cj = (comp == 1);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const size_t slot = proj_slot(A, comp, b, q, which);
-    cd* part = A.part + (A.partoff[slot] + chunk) * (size_t)NORB * RC;
     cd acc[RW][NORB];
 #pragma unroll
     for (int k = 0; k < RW; ++k)
 #pragma unroll
         for (int a = 0; a < NORB; ++a) acc[k][a] = mk(0.0, 0.0);
-    for (int i = i0 + lane; i < i1; i += 64) {
-        cd xv[NORB];
+    for (int i0 = 0; i0 < len; i0 += CH) {
+        const int i1 = min(len, i0 + CH);
+        if (kStage) {
+            __syncthreads();
+            for (int e = threadIdx.x; e < (i1 - i0) * NORB; e += NT) xs[e] = xval(i0 + e / NORB, e % NORB);
+            __syncthreads();
+        }
+        for (int i = i0 + lane; i < i1; i += 64) {
+            cd xv[NORB];
 #pragma unroll
-        for (int a = 0; a < NORB; ++a) xv[a] = kStage ? xs[(size_t)(i - i0) * NORB + a] : xval(i, a);
+            for (int a = 0; a < NORB; ++a) xv[a] = kStage ? xs[(size_t)(i - i0) * NORB + a] : xval(i, a);
 #pragma unroll
-        for (int k = 0; k < RW; ++k) {
-            const int r = wave + 4 * k;
-            if (r < rk) {
-                cd f = F[(size_t)r * ld + i];
-                if (cj) f = conj(f);
+            for (int k = 0; k < RW; ++k) {
+                const int r = wave + 4 * k;
+                if (r < rk) {
+                    cd f = F[(size_t)r * ld + i];
+                    if (cj) f = conj(f);
 #pragma unroll
-                for (int a = 0; a < NORB; ++a) fma_(acc[k][a], xv[a], f);
+                    for (int a = 0; a < NORB; ++a) fma_(acc[k][a], xv[a], f);
+                }
             }
         }
     }
+    const double* S = A.S[comp] + ((size_t)b * npair + q) * RC;
+    cd* out = A.proj + proj_slot(A, comp, b, q, which) * (size_t)NORB * RC;
 #pragma unroll
     for (int k = 0; k < RW; ++k) {
         const int r = wave + 4 * k;
         if (r >= rk) continue;   // wave-uniform
+        const double sr = S[r];
 #pragma unroll
         for (int a = 0; a < NORB; ++a) {
             const double re = wsum64(acc[k][a].x), im = wsum64(acc[k][a].y);
-            if (lane == 0) part[(size_t)a * RC + r] = mk(re, im);
+            if (lane == 0) out[(size_t)a * RC + r] = mk(sr * re, sr * im);
         }
     }
-    __threadfence();
-    __syncthreads();
-    __shared__ int s_last;
-    if (threadIdx.x == 0) s_last = (atomicAdd(&A.cnt[slot], 1) == nchunks - 1);
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    const double* S = A.S[comp] + ((size_t)b * npair + q) * RC;
-    const cd* p0 = A.part + A.partoff[slot] * (size_t)NORB * RC;
-    cd* out = A.proj + slot * (size_t)NORB * RC;
-    for (int e = threadIdx.x; e < NORB * rk; e += NT) {
-        const int a = e / rk, r = e % rk;
-        cd sum = mk(0.0, 0.0);
-        for (int c = 0; c < nchunks; ++c) sum = sum + p0[((size_t)c * NORB + a) * RC + r];
-        out[(size_t)a * RC + r] = S[r] * sum;
-    }
-    if (threadIdx.x == 0) A.cnt[slot] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -167,9 +160,10 @@ __device__ void fact_task(const HistArgs& A, const FactTask& t, unsigned char* s
 // staged in LDS with coalesced loads; the column sum (rows j >= m) and the row
 // dot (columns s <= m) of lane m run in one loop over LDS.
 template <int NORB>
-__device__ void leaf_task(const HistArgs& A, int leaf, int comp, int ag, unsigned char* smem) {
+__device__ void leaf_task(const HistArgs& A, int leaf, int comp, int ag, int pg, unsigned char* smem) {
     if (comp == 1 && !A.wantL) return;
     constexpr int npair = NORB * NORB, AG = AGroups<NORB>::AG;
+    constexpr int PPG = npair / LeafGroups<NORB>::LG;   // orbital pairs per group
     const int n = A.n;
     const int s0 = A.leafs[2 * leaf], s1 = A.leafs[2 * leaf + 1];
     const int lw = s1 - s0;
@@ -186,7 +180,7 @@ __device__ void leaf_task(const HistArgs& A, int leaf, int comp, int ag, unsigne
     cd accA[NORB], accB[NORB];
 #pragma unroll
     for (int c = 0; c < NORB; ++c) accA[c] = accB[c] = mk(0.0, 0.0);
-    for (int q = 0; q < npair; ++q) {
+    for (int q = pg * PPG; q < (pg + 1) * PPG; ++q) {
         const int qr = q / NORB, qc = q % NORB;
         const cd* Lq = L + (size_t)q * tsz;
         __syncthreads();
@@ -232,7 +226,7 @@ __device__ void leaf_task(const HistArgs& A, int leaf, int comp, int ag, unsigne
         const int m = s0 + mo;
 #pragma unroll
         for (int c = 0; c < NORB; ++c) {
-            const size_t o = (size_t)m * npair + a * NORB + c;
+            const size_t o = ((size_t)pg * A.nt + m) * npair + a * NORB + c;
             if (comp == 0) {
                 A.leafR[o] = accA[c];
                 A.leafLR[o] = accB[c];
@@ -355,9 +349,10 @@ __global__ void __launch_bounds__(NT) hist_tasks(HistArgs A) {
     }
     id -= A.nf[1];
     if (id < A.nleaftask) {
-        int g, ag;
-        if (!xcd_group(id, 2 * A.nleaf, NG, g, ag)) return;
-        leaf_task<NORB>(A, g >> 1, g & 1, ag, smem);
+        constexpr int LG = LeafGroups<NORB>::LG;
+        int g, mem;
+        if (!xcd_group(id, 2 * A.nleaf, NG * LG, g, mem)) return;
+        leaf_task<NORB>(A, g >> 1, g & 1, mem % NG, mem / NG, smem);
         return;
     }
     id -= A.nleaftask;
@@ -448,15 +443,19 @@ __global__ void __launch_bounds__(64 * NORB) hist_combine(HistArgs A) {
         }
     }
     const size_t mo = (size_t)m * npair;
+    constexpr int LG = LeafGroups<NORB>::LG;
 #pragma unroll
     for (int a = 0; a < NORB; ++a) {
         const size_t o = mo + a * NORB + c;
+        for (int pg = 0; pg < LG; ++pg) {
+            const size_t op = (size_t)pg * A.nt * npair + o;
+            if (A.wantR) accR[a] = accR[a] + A.leafR[op];
+            if (A.wantL) accL[a] = accL[a] + A.leafLR[op] + A.leafLL[op];
+        }
         if (A.wantR) {
-            accR[a] = accR[a] + A.leafR[o];
             if (A.last[0] >= A.n0[0] && m < A.ls[0]) accR[a] = accR[a] + A.tailcol[0][o];
         }
         if (A.wantL) {
-            accL[a] = accL[a] + A.leafLR[o] + A.leafLL[o];
             for (int comp = 0; comp < 2; ++comp) {
                 if (A.last[comp] < A.n0[comp]) continue;   // no tail rows
                 if (comp == 1 && m < A.ls[1]) accL[a] = accL[a] + A.tailcol[1][o];

@@ -240,8 +240,8 @@ def _check_sampled(cfg, ops, IR, IL, label):
         a = n * (n + 1) // 2
         gR = IR[a:a + n + 1].cpu().numpy()
         gL = IL[a:a + n + 1].cpu().numpy()
-        ms = sorted(set([0, 1, max(n - 6, 0), max(n - 5, 0), max(n - 1, 0), n]
-                        + list(rng.integers(0, n + 1, 6))))
+        ms = sorted(set(m for m in [0, 1, n - 6, n - 5, n - 1, n] + list(rng.integers(0, n + 1, 6))
+                        if 0 <= m <= n))
         scaleR, scaleL = np.abs(gR).max(), np.abs(gL).max()
         for m in ms:
             eR = np.abs(gR[m] - history_R_entry(ops, n, m, h, k)).max() / max(scaleR, 1e-300)
