@@ -167,7 +167,7 @@ def main():
     blocks, leaves = H.blocks(), H.leaves()
     ranks = [H.ranks(P.RET), H.ranks(P.LES)]
     kern = {}
-    for kind, name in ((0, "hist_tasks"), (1, "hist_combine"), (2, "merge")):
+    for kind, name in ((0, "hist_tasks"), (1, "hist_combine"), (2, "merge"), (3, "proj_reduce")):
         steps, ms = H.profile_read(kind)
         kern[name] = (steps, ms)
     st0, ms0 = kern["hist_tasks"]
@@ -191,6 +191,7 @@ def main():
                     est_ms_per_sweep=round(per_sweep_ms[other], 1)),
         "merge": dict(launches_per_sweep=int(len(kern["merge"][1]) // max(args.steps, 1)),
                       ms_per_sweep=round(per_sweep_ms["merge"], 1)),
+        "proj_reduce": dict(est_ms_per_sweep=round(per_sweep_ms["proj_reduce"], 1)),
     }
     log("kernels:", kernels)
     log(f"ranks: max {max(int(r.max()) for r in ranks)}, HODLR device bytes {H.nbytes() / 2**30:.2f} GiB")

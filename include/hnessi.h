@@ -169,13 +169,14 @@ int hnessi_hodlr_leaves(hnessi_hodlr_t H, int* tab_host, int capacity);
 size_t hnessi_hodlr_bytes(hnessi_hodlr_t H);
 
 /* Kernel timing with HIP events recorded on the launch stream (measurement).
- * stride > 0: from now on time the two history kernels of every step n with
+ * stride > 0: from now on time the three history kernels of every step n with
  * n % stride == 0, and every panel merge; stride = 0 stops.  Clears earlier
  * records (synchronizes the device). */
 int hnessi_hodlr_profile(hnessi_hodlr_t H, int stride);
 
 /* Synchronizes the recorded events; for kernel kind 0 (projection / leaf /
- * tail tasks), 1 (combine) or 2 (panel merge, both of its kernels) returns the
+ * tail tasks), 1 (combine), 2 (panel merge, both of its kernels) or 3 (sum of
+ * the projection chunk partials) returns the
  * number of timed launches and writes, for the first `capacity` of them, the
  * step n (host int) and the duration in ms (host double).  Either output
  * pointer may be NULL. */

@@ -155,7 +155,9 @@ struct hnessi_hodlr_s {
     // projection tasks, sorted by activation row
     FactTask* d_ft[2] = {};
     std::vector<int> ft_act[2];
+    long long* d_partoff = nullptr;
     // history scratch
+    cd* part = nullptr;
     cd* proj = nullptr;
     cd* leafR = nullptr;
     cd* leafLR = nullptr;
@@ -293,6 +295,18 @@ int hnessi_hodlr_create(hnessi_hodlr_t* out, int nt, int nlvl, int norb, int k, 
     }
     HALLOC(H->band, (size_t)nt * (k + 1) * npair, true);
     HALLOC(H->proj, (size_t)2 * std::max(nb, 1) * npair * 2 * norb * RC, true);
+    // chunk partials of the projections: one slot per kCH factor rows
+    std::vector<long long> partoff((size_t)2 * std::max(nb, 1) * npair * 2, 0);
+    long long ps = 0;
+    for (int c = 0; c < 2; ++c)
+        for (int b = 0; b < nb; ++b)
+            for (int q = 0; q < npair; ++q)
+                for (int w = 0; w < 2; ++w) {
+                    partoff[(((size_t)c * nb + b) * npair + q) * 2 + w] = ps;
+                    ps += div_up(w == 0 ? g.r1[b] - g.r0[b] : g.c1[b] - g.c0[b], kCH);
+                }
+    HALLOC(H->d_partoff, partoff.size(), false);
+    HALLOC(H->part, (size_t)std::max(ps, 1LL) * norb * RC, true);
     const int leaf_slots = norb == 1 ? 1 : 4;   // orbital-pair groups of the leaf tasks
     HALLOC(H->leafR, (size_t)leaf_slots * nt * npair, true);
     HALLOC(H->leafLR, (size_t)leaf_slots * nt * npair, true);
@@ -328,8 +342,10 @@ int hnessi_hodlr_create(hnessi_hodlr_t* out, int nt, int nlvl, int norb, int k, 
         std::vector<FactTask> ts;
         for (int b = 0; b < nb; ++b)
             for (int q = 0; q < npair; ++q) {
-                ts.push_back(FactTask{c, b, q, 0, g.r0[b]});
-                ts.push_back(FactTask{c, b, q, 1, g.r0[b]});
+                for (int ch = 0; ch < div_up(g.r1[b] - g.r0[b], kCH); ++ch)
+                    ts.push_back(FactTask{c, b, q, 0, ch, g.r0[b] + ch * kCH});
+                for (int ch = 0; ch < div_up(g.c1[b] - g.c0[b], kCH); ++ch)
+                    ts.push_back(FactTask{c, b, q, 1, ch, g.r0[b]});
             }
         std::stable_sort(ts.begin(), ts.end(),
                          [](const FactTask& x, const FactTask& y) { return x.act < y.act; });
@@ -345,7 +361,8 @@ int hnessi_hodlr_create(hnessi_hodlr_t* out, int nt, int nlvl, int norb, int k, 
         hipMemcpy(H->d_cover, g.cover.data(), g.cover.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
         (nb > 0 && hipMemcpy(H->d_Uoff, H->Uoff.data(), nb * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess) ||
         (nb > 0 && hipMemcpy(H->d_Voff, H->Voff.data(), nb * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess) ||
-        hipMemcpy(H->d_Loff, H->Loff.data(), g.nleaf * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess)
+        hipMemcpy(H->d_Loff, H->Loff.data(), g.nleaf * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(H->d_partoff, partoff.data(), partoff.size() * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess)
         return bail(fail(HNESSI_E_DEVICE, "copy of geometry failed"));
 #undef HALLOC
     *out = H;
@@ -501,11 +518,14 @@ int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, doub
     A.Uoff = H->d_Uoff;
     A.Voff = H->d_Voff;
     A.Loff = H->d_Loff;
+    A.partoff = H->d_partoff;
+    A.nfpad = div_up(A.nf[0] + A.nf[1], 8) * 8;
     A.nleaf = g.row_leaf[n] + 1;
     const int ngroups = H->norb <= 4 ? 1 : H->norb / 4;   // left-orbital groups of 4 waves
     const int leafgroups = H->norb == 1 ? 1 : 4;                   // orbital-pair groups per leaf
     A.nleaftask = div_up(2 * A.nleaf, 8) * 8 * ngroups * leafgroups;
     A.ntailtask = div_up(A.ntailchunk[0] + A.ntailchunk[1], 8) * 8 * ngroups;
+    A.part = H->part;
     A.proj = H->proj;
     A.leafR = H->leafR;
     A.leafLR = H->leafLR;
@@ -513,10 +533,11 @@ int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, doub
     A.outR = static_cast<cd*>(outR);
     A.outL = static_cast<cd*>(outL);
     if (H->prof.want(n)) {
-        hipEvent_t ev[3] = {H->prof.ev(), H->prof.ev(), H->prof.ev()};
+        hipEvent_t ev[4] = {H->prof.ev(), H->prof.ev(), H->prof.ev(), H->prof.ev()};
         HIP_TRY(launch_history(A, st, ev));
         H->prof.recs.push_back({0, n, ev[0], ev[1]});
-        H->prof.recs.push_back({1, n, ev[1], ev[2]});
+        H->prof.recs.push_back({3, n, ev[1], ev[2]});
+        H->prof.recs.push_back({1, n, ev[2], ev[3]});
     } else {
         HIP_TRY(launch_history(A, st));
     }
@@ -701,7 +722,7 @@ int hnessi_hodlr_profile(hnessi_hodlr_t H, int stride) {
 }
 
 int hnessi_hodlr_profile_read(hnessi_hodlr_t H, int kind, int* steps_host, double* ms_host, int capacity) {
-    if (!H || kind < 0 || kind > 2) return fail(HNESSI_E_ARG, "bad argument");
+    if (!H || kind < 0 || kind > 3) return fail(HNESSI_E_ARG, "bad argument");
     return H->prof.read(kind, steps_host, ms_host, capacity);
 }
 

@@ -84,7 +84,7 @@ bool interval_weights_exact(int k, int L, std::vector<double>& w, std::string& e
 
 // ---------------------------------------------------------------------------
 // constants of the device kernels
-constexpr int kCH = 512;      // factor rows per projection task
+constexpr int kCH = 256;      // factor rows per projection task
 constexpr int kTailCH = 64;   // columns per tail task
 
 }  // namespace hn

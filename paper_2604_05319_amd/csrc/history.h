@@ -5,10 +5,11 @@
 
 namespace hn {
 
-// A projection task: U (which = 0) or V (which = 1) of block b, orbital pair
-// q, component comp.  Active once row `act` (the block's first row) is merged.
+// A projection task: rows [chunk*kCH, +kCH) of U (which = 0) or V (which = 1)
+// of block b, orbital pair q, component comp.  Active once row `act` is merged
+// (U: the chunk's first row; V: the block's first row).
 struct FactTask {
-    int comp, b, q, which, act;
+    int comp, b, q, which, chunk, act;
 };
 
 struct HistArgs {
@@ -36,12 +37,15 @@ struct HistArgs {
     const long long* Voff;
     const long long* Loff;
     const FactTask* ft[2];
+    const long long* partoff;  // per (comp, b, q, which): first chunk-partial slot
     int nf[2];       // active projection tasks per component
+    int nfpad;       // nf[0] + nf[1] rounded up to a multiple of 8
     int nleaf;       // active leaves
     int nleaftask;   // leaf tasks in the grid (after the XCD-grouping remap)
     int ntailchunk[2];
     int ntailtask;
-    cd* proj;        // [comp][b][q][which][a][RC]  (S_r * projection)
+    cd* part;        // [partial slot][a][RC]  S_r * projection of one chunk
+    cd* proj;        // [comp][b][q][which][a][RC]  S_r * projection (sum of the chunks)
     cd* leafR;       // [pair group][m][a][c]   leaf pieces, one slot per pair group
     cd* leafLR;
     cd* leafLL;
@@ -51,8 +55,8 @@ struct HistArgs {
     cd* outL;
 };
 
-// ev: nullptr, or three events recorded before hist_tasks, between the two
-// kernels, and after hist_combine (per-kernel timing on the launch stream)
+// ev: nullptr, or four events recorded before hist_tasks, after it, after
+// proj_reduce and after hist_combine (per-kernel timing on the launch stream)
 hipError_t launch_history(const HistArgs& a, hipStream_t st, hipEvent_t* ev = nullptr);
 hipError_t history_init();
 

@@ -28,7 +28,6 @@ namespace hn {
 namespace {
 
 constexpr int NT = 256;
-constexpr int CH = kCH;
 
 __device__ inline double wsum64(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -42,6 +41,14 @@ __device__ inline bool xcd_group(int id, int ngroups, int nmem, int& g, int& mem
     mem = rem / 8;
     g = blk * 8 + rem % 8;
     return g < ngroups;
+}
+
+// acc[idx] += v with a run-time idx, without dynamic register indexing
+template <int N>
+__device__ inline void add_at(cd (&acc)[N], int idx, cd v) {
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        if (i == idx) acc[i] = acc[i] + v;
 }
 
 // ranks come from device memory: clamp them to the allocated capacity
@@ -68,19 +75,27 @@ struct LeafGroups {
 };
 
 // ---------------------------------------------------------------------------
-// Projection of the whole U (which = 0, rows merged so far) or V (which = 1)
-// of one block and orbital pair, by one workgroup (no cross-workgroup
-// reduction, hence no device-scope fences).  Wave w takes the ranks
-// r = w, w+4, ...; its lanes run over the rows; the Sigma rows are staged in
-// LDS per kCH rows and shared by the four waves.
+// Ranks per wave in one pass of a projection task (register budget of the
+// NORB accumulators per rank); a pass covers 4 * RW ranks.
+template <int NORB>
+struct ProjRanks {
+    static constexpr int RW = NORB <= 4 ? 4 : (NORB == 8 ? 2 : 1);
+};
+
+// Projection of rows [chunk*kCH, +kCH) of U (which = 0, rows merged so far) or
+// V (which = 1) of one block and orbital pair onto the folded Sigma row,
+// scaled by S; the chunk partials are summed by proj_reduce.  Wave w takes the
+// ranks w, w+4, ... of a pass; its lanes run over the rows, kCH/64 rows each,
+// with every load of a pass independent of the others.
 template <int NORB>
 __device__ void fact_task(const HistArgs& A, const FactTask& t, unsigned char* smem) {
     const int comp = t.comp, b = t.b, q = t.q, which = t.which;
     if (comp == 0 && which == 0 && !A.wantR) return;
     if ((comp == 1 || which == 1) && !A.wantL) return;
     constexpr int npair = NORB * NORB;
-    constexpr bool kStage = NORB <= 4;             // Sigma rows staged in LDS
-    constexpr int RW = 4;                          // ranks per wave (rank capacity <= 16)
+    constexpr bool kStage = NORB <= 8;             // Sigma rows staged in LDS
+    constexpr int RW = ProjRanks<NORB>::RW;
+    constexpr int RPL = kCH / 64;                  // rows per lane
     const int RC = A.RC;
     const int qr = q / NORB, qc = q % NORB;
     const int rk = rank_of(A, comp, b, q);
@@ -100,6 +115,8 @@ __device__ void fact_task(const HistArgs& A, const FactTask& t, unsigned char* s
         ld = c1 - c0;
         F = A.V[comp] + A.Voff[b] + (size_t)q * RC * ld;
     }
+    const int i0 = t.chunk * kCH, i1 = min(len, i0 + kCH);
+    if (i0 >= i1) return;
     const int n = A.n;
     // folded Sigma entry multiplying row i of the factor, left orbital a
     auto xval = [&](int i, int a) -> cd {
@@ -108,48 +125,51 @@ __device__ void fact_task(const HistArgs& A, const FactTask& t, unsigned char* s
         if (comp == 0) return -w_start(A.W, j) * conj(A.sigL[(size_t)j * npair + qc * NORB + a]);
         return interval_w(A.W, n, j) * A.sigR[(size_t)j * npair + a * NORB + (which == 0 ? qc : qr)];
     };
-    cd* xs = reinterpret_cast<cd*>(smem);  // CH x NORB
+    cd* xs = reinterpret_cast<cd*>(smem);  // kCH x NORB
+    if (kStage) {
+        for (int e = threadIdx.x; e < (i1 - i0) * NORB; e += NT) xs[e] = xval(i0 + e / NORB, e % NORB);
+        __syncthreads();
+    }
     const bool cj = (comp == 1);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    cd acc[RW][NORB];
+    const double* S = A.S[comp] + ((size_t)b * npair + q) * RC;
+    const size_t slot = proj_slot(A, comp, b, q, which);
+    cd* out = A.part + (size_t)(A.partoff[slot] + t.chunk) * NORB * RC;
+    for (int rp = 0; rp < rk; rp += 4 * RW) {
+        cd acc[RW][NORB];
 #pragma unroll
-    for (int k = 0; k < RW; ++k)
+        for (int k = 0; k < RW; ++k)
 #pragma unroll
-        for (int a = 0; a < NORB; ++a) acc[k][a] = mk(0.0, 0.0);
-    for (int i0 = 0; i0 < len; i0 += CH) {
-        const int i1 = min(len, i0 + CH);
-        if (kStage) {
-            __syncthreads();
-            for (int e = threadIdx.x; e < (i1 - i0) * NORB; e += NT) xs[e] = xval(i0 + e / NORB, e % NORB);
-            __syncthreads();
-        }
-        for (int i = i0 + lane; i < i1; i += 64) {
-            cd xv[NORB];
+            for (int a = 0; a < NORB; ++a) acc[k][a] = mk(0.0, 0.0);
 #pragma unroll
-            for (int a = 0; a < NORB; ++a) xv[a] = kStage ? xs[(size_t)(i - i0) * NORB + a] : xval(i, a);
+        for (int u = 0; u < RPL; ++u) {
+            const int i = i0 + u * 64 + lane;
+            if (i < i1) {
+                cd xv[NORB];
 #pragma unroll
-            for (int k = 0; k < RW; ++k) {
-                const int r = wave + 4 * k;
-                if (r < rk) {
-                    cd f = F[(size_t)r * ld + i];
-                    if (cj) f = conj(f);
+                for (int a = 0; a < NORB; ++a) xv[a] = kStage ? xs[(size_t)(i - i0) * NORB + a] : xval(i, a);
 #pragma unroll
-                    for (int a = 0; a < NORB; ++a) fma_(acc[k][a], xv[a], f);
+                for (int k = 0; k < RW; ++k) {
+                    const int r = rp + wave + 4 * k;
+                    if (r < rk) {
+                        cd f = F[(size_t)r * ld + i];
+                        if (cj) f = conj(f);
+#pragma unroll
+                        for (int a = 0; a < NORB; ++a) fma_(acc[k][a], xv[a], f);
+                    }
                 }
             }
         }
-    }
-    const double* S = A.S[comp] + ((size_t)b * npair + q) * RC;
-    cd* out = A.proj + proj_slot(A, comp, b, q, which) * (size_t)NORB * RC;
 #pragma unroll
-    for (int k = 0; k < RW; ++k) {
-        const int r = wave + 4 * k;
-        if (r >= rk) continue;   // wave-uniform
-        const double sr = S[r];
+        for (int k = 0; k < RW; ++k) {
+            const int r = rp + wave + 4 * k;
+            if (r >= rk) continue;   // wave-uniform
+            const double sr = S[r];
 #pragma unroll
-        for (int a = 0; a < NORB; ++a) {
-            const double re = wsum64(acc[k][a].x), im = wsum64(acc[k][a].y);
-            if (lane == 0) out[(size_t)a * RC + r] = mk(sr * re, sr * im);
+            for (int a = 0; a < NORB; ++a) {
+                const double re = wsum64(acc[k][a].x), im = wsum64(acc[k][a].y);
+                if (lane == 0) out[(size_t)a * RC + r] = mk(sr * re, sr * im);
+            }
         }
     }
 }
@@ -208,8 +228,8 @@ __device__ void leaf_task(const HistArgs& A, int leaf, int comp, int ag, int pg,
                     if (doR && j < nrow) fma_(colsum, xa[j * AG + w], T[tri(j) + mo]);
                     if (rowok && t <= mo) fmac_(rowdot, rowm[t], xb[t * AG + w]);
                 }
-                accA[qc] = accA[qc] + colsum;   // -> I^R column m
-                accB[qr] = accB[qr] + rowdot;   // -> I^< (second term) row m
+                add_at(accA, qc, colsum);   // -> I^R column m
+                add_at(accB, qr, rowdot);   // -> I^< (second term) row m
             } else {
                 // row dot x1(s) G^<(s, m) for s <= m; column sum -x1(s) G^<(m, s)^dagger for s > m
                 for (int t = 0; t < nrow; ++t) {
@@ -217,8 +237,8 @@ __device__ void leaf_task(const HistArgs& A, int leaf, int comp, int ag, int pg,
                     if (t <= mo) fma_(rowdot, xa[t * AG + w], rowm[t]);
                     if (j < nrow) fmac_(colsum, T[tri(j) + mo], xb[j * AG + w]);
                 }
-                accA[qc] = accA[qc] + rowdot;
-                accA[qr] = accA[qr] - colsum;
+                add_at(accA, qc, rowdot);
+                add_at(accA, qr, -colsum);
             }
         }
     }
@@ -293,9 +313,9 @@ __device__ void tail_task(const HistArgs& A, int comp, int ag, int chunk, unsign
                 else fmac_(cs, T[i * kTailCH + lane], xr[i * AG + wave]);
             }
             if (comp == 0) {
-                if (doR) col[qc] = col[qc] + cs;     // x(j) G^R(j, m)
+                if (doR) add_at(col, qc, cs);       // x(j) G^R(j, m)
             } else {
-                col[qr] = col[qr] - cs;              // -x1(j) G^<(m, j)^dagger
+                add_at(col, qr, -cs);               // -x1(j) G^<(m, j)^dagger
             }
             // row dots (lane = row ri, columns 16*part .. +16)
             cd rd = mk(0.0, 0.0);
@@ -305,8 +325,8 @@ __device__ void tail_task(const HistArgs& A, int comp, int ag, int chunk, unsign
                     else fma_(rd, xm[mm * AG + wave], T[ri * kTailCH + mm]);
                 }
             }
-            if (comp == 0) row[qr] = row[qr] + rd;   // x2(m) G^R(j, m)^dagger
-            else row[qc] = row[qc] + rd;             // x1(m) G^<(m, j)
+            if (comp == 0) add_at(row, qr, rd);     // x2(m) G^R(j, m)^dagger
+            else add_at(row, qc, rd);               // x1(m) G^<(m, j)
         }
     }
     // reduce the four column parts of each row dot (lanes ri, ri+16, ri+32, ri+48)
@@ -337,28 +357,26 @@ template <int NORB>
 __global__ void __launch_bounds__(NT) hist_tasks(HistArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NG = AGroups<NORB>::NG;
-    int id = blockIdx.x;
-    if (id < A.nf[0]) {
-        fact_task<NORB>(A, A.ft[0][id], smem);
+    const int id = blockIdx.x;
+    if (id < A.nfpad) {
+        if (id < A.nf[0]) fact_task<NORB>(A, A.ft[0][id], smem);
+        else if (id - A.nf[0] < A.nf[1]) fact_task<NORB>(A, A.ft[1][id - A.nf[0]], smem);
         return;
     }
-    id -= A.nf[0];
-    if (id < A.nf[1]) {
-        fact_task<NORB>(A, A.ft[1][id], smem);
-        return;
-    }
-    id -= A.nf[1];
-    if (id < A.nleaftask) {
+    // leaf and tail sections start at multiples of 8, so workgroup id % 8 is
+    // the XCD that xcd_group assumes
+    int rel = id - A.nfpad;
+    if (rel < A.nleaftask) {
         constexpr int LG = LeafGroups<NORB>::LG;
         int g, mem;
-        if (!xcd_group(id, 2 * A.nleaf, NG * LG, g, mem)) return;
+        if (!xcd_group(rel, 2 * A.nleaf, NG * LG, g, mem)) return;
         leaf_task<NORB>(A, g >> 1, g & 1, mem % NG, mem / NG, smem);
         return;
     }
-    id -= A.nleaftask;
+    rel -= A.nleaftask;
     int g, ag;
     const int ng = A.ntailchunk[0] + A.ntailchunk[1];
-    if (!xcd_group(id, ng, NG, g, ag)) return;
+    if (!xcd_group(rel, ng, NG, g, ag)) return;
     if (g < A.ntailchunk[0])
         tail_task<NORB>(A, 0, ag, g, smem);
     else
@@ -366,157 +384,207 @@ __global__ void __launch_bounds__(NT) hist_tasks(HistArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-// One thread per output (m, c); all left orbital indices a in registers.
+// Sum of the chunk partials of every active projection, one thread per
+// (slot, a, r); slots of inactive blocks, ranks beyond the block's rank and
+// components not asked for are neither written nor read by the combine.
 template <int NORB>
-__global__ void __launch_bounds__(64 * NORB) hist_combine(HistArgs A) {
-    constexpr int npair = NORB * NORB;
-    const int m = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int c = threadIdx.x >> 6;
-    const int n = A.n;
-    if (m > n) return;
+__global__ void __launch_bounds__(256) proj_reduce(HistArgs A) {
     const int RC = A.RC;
-    cd accR[NORB], accL[NORB];
-#pragma unroll
-    for (int a = 0; a < NORB; ++a) accR[a] = accL[a] = mk(0.0, 0.0);
-    for (int l = 0; l < A.nlvl; ++l) {
-        const int cv = A.cover[(size_t)l * A.nt + m];
-        if (cv >= 0) {  // m is a column of block b: expand through V
-            const int b = cv;
-            const int r0 = A.blk[5 * b + 1], c0 = A.blk[5 * b + 3], c1 = A.blk[5 * b + 4];
-            const int ldV = c1 - c0;
-            if (A.wantR && A.n0[0] > r0) {
-                for (int qr = 0; qr < NORB; ++qr) {
-                    const int q = qr * NORB + c;
-                    const int rk = rank_of(A, 0, b, q);
-                    const cd* Vq = A.V[0] + A.Voff[b] + (size_t)q * RC * ldV + (m - c0);
-                    const cd* z = A.proj + proj_slot(A, 0, b, q, 0) * NORB * RC;
-                    for (int r = 0; r < rk; ++r) {
-                        const cd v = Vq[(size_t)r * ldV];
-#pragma unroll
-                        for (int a = 0; a < NORB; ++a) fmac_(accR[a], v, z[a * RC + r]);
-                    }
-                }
-            }
-            if (A.wantL && A.n0[1] > r0) {
-                for (int qc = 0; qc < NORB; ++qc) {
-                    const int q = c * NORB + qc;
-                    const int rk = rank_of(A, 1, b, q);
-                    const cd* Vq = A.V[1] + A.Voff[b] + (size_t)q * RC * ldV + (m - c0);
-                    const cd* z = A.proj + proj_slot(A, 1, b, q, 0) * NORB * RC;
-                    for (int r = 0; r < rk; ++r) {
-                        const cd v = -Vq[(size_t)r * ldV];
-#pragma unroll
-                        for (int a = 0; a < NORB; ++a) fma_(accL[a], v, z[a * RC + r]);
-                    }
-                }
-            }
-        } else if (A.wantL) {  // m is a row of block b: expand through U
-            const int b = ~cv;
-            const int r0 = A.blk[5 * b + 1], r1 = A.blk[5 * b + 2];
-            const int ldU = r1 - r0;
-            if (m < A.n0[0]) {
-                for (int qc = 0; qc < NORB; ++qc) {
-                    const int q = c * NORB + qc;
-                    const int rk = rank_of(A, 0, b, q);
-                    const cd* Uq = A.U[0] + A.Uoff[b] + (size_t)q * RC * ldU + (m - r0);
-                    const cd* z = A.proj + proj_slot(A, 0, b, q, 1) * NORB * RC;
-                    for (int r = 0; r < rk; ++r) {
-                        const cd u = Uq[(size_t)r * ldU];
-#pragma unroll
-                        for (int a = 0; a < NORB; ++a) fmac_(accL[a], u, z[a * RC + r]);
-                    }
-                }
-            }
-            if (m < A.n0[1]) {
-                for (int qr = 0; qr < NORB; ++qr) {
-                    const int q = qr * NORB + c;
-                    const int rk = rank_of(A, 1, b, q);
-                    const cd* Uq = A.U[1] + A.Uoff[b] + (size_t)q * RC * ldU + (m - r0);
-                    const cd* z = A.proj + proj_slot(A, 1, b, q, 1) * NORB * RC;
-                    for (int r = 0; r < rk; ++r) {
-                        const cd u = Uq[(size_t)r * ldU];
-#pragma unroll
-                        for (int a = 0; a < NORB; ++a) fma_(accL[a], u, z[a * RC + r]);
-                    }
-                }
-            }
-        }
-    }
-    const size_t mo = (size_t)m * npair;
-    constexpr int LG = LeafGroups<NORB>::LG;
-#pragma unroll
-    for (int a = 0; a < NORB; ++a) {
-        const size_t o = mo + a * NORB + c;
-        for (int pg = 0; pg < LG; ++pg) {
-            const size_t op = (size_t)pg * A.nt * npair + o;
-            if (A.wantR) accR[a] = accR[a] + A.leafR[op];
-            if (A.wantL) accL[a] = accL[a] + A.leafLR[op] + A.leafLL[op];
-        }
-        if (A.wantR) {
-            if (A.last[0] >= A.n0[0] && m < A.ls[0]) accR[a] = accR[a] + A.tailcol[0][o];
-        }
-        if (A.wantL) {
-            for (int comp = 0; comp < 2; ++comp) {
-                if (A.last[comp] < A.n0[comp]) continue;   // no tail rows
-                if (comp == 1 && m < A.ls[1]) accL[a] = accL[a] + A.tailcol[1][o];
-                if (m >= A.n0[comp] && m <= A.last[comp]) {
-                    const cd* tp = A.tailpart[comp] + (size_t)(m - A.n0[comp]) * npair + a * NORB + c;
-                    for (int ch = 0; ch < A.ntailchunk[comp]; ++ch)
-                        accL[a] = accL[a] + tp[(size_t)ch * A.P * npair];
-                }
-            }
-        }
-    }
+    const long long per = (long long)NORB * RC;
+    const long long tid = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long slot = tid / per;
+    if (slot >= 4LL * A.nb * A.npair) return;
+    const int e = (int)(tid - slot * per);   // a * RC + r
+    const int r = e % RC;
+    const int which = (int)(slot & 1);
+    const long long bq = slot >> 1;
+    const int q = (int)(bq % A.npair);
+    const int b = (int)((bq / A.npair) % A.nb);
+    const int comp = (int)(bq / ((long long)A.npair * A.nb));
+    if (comp == 0 && which == 0 && !A.wantR) return;
+    if ((comp == 1 || which == 1) && !A.wantL) return;
+    if (r >= rank_of(A, comp, b, q)) return;
+    const int* bk = A.blk + 5 * b;
+    const int r0 = bk[1];
+    if (A.n0[comp] <= r0) return;
+    const int len = which == 0 ? min(A.n0[comp] - r0, bk[2] - r0) : bk[4] - bk[3];
+    const int nch = (len + kCH - 1) / kCH;
+    const cd* p = A.part + (size_t)A.partoff[slot] * per + e;
+    cd s = mk(0.0, 0.0);
+    for (int ch = 0; ch < nch; ++ch) s = s + p[(size_t)ch * per];
+    A.proj[(size_t)slot * per + e] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Combine.  A wave handles MW consecutive columns m and one output orbital c
+// (c = wave, wave + 4, ...); its G = min(NORB, 4) lane groups split the summed
+// orbital index of the expansions (lane group g takes the orbitals g, g+G, ...)
+// and are summed by shuffles; lane group g then adds the leaf, tail and band
+// pieces of the outputs a = g, g+G, ... and writes them.
+template <int NORB>
+struct CombMap {
+    static constexpr int G = NORB < 4 ? NORB : 4;
+    static constexpr int MW = 64 / G;
+    static constexpr int WAVES = NORB < 4 ? NORB : 4;
+    static constexpr int NCI = NORB / WAVES;
+};
+
+template <int NORB>
+__global__ void __launch_bounds__(64 * CombMap<NORB>::WAVES) hist_combine(HistArgs A) {
+    using M = CombMap<NORB>;
+    constexpr int npair = NORB * NORB, G = M::G, MW = M::MW;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane / MW;
+    const int m = blockIdx.x * MW + lane % MW;
+    const int n = A.n;
+    const bool live = m <= n;
+    const int RC = A.RC;
     const int k = A.W.k;
     const int kb = k + 1;
-    if (A.wantR) {
-        // band correction: start weights (n-m >= k) or Newton-Cotes (n-m < k)
-        const int L = n - m;
-        if (L == 0) {
+    constexpr int LG = LeafGroups<NORB>::LG;
+    for (int ci = 0; ci < M::NCI; ++ci) {
+        const int c = wave + M::WAVES * ci;
+        cd accR[NORB], accL[NORB];
 #pragma unroll
-            for (int a = 0; a < NORB; ++a) A.outR[mo + a * NORB + c] = mk(0.0, 0.0);
-        } else {
-            const int imax = L < k ? L : k;
-            for (int i = 0; i <= imax; ++i) {
-                const double wc = L < k ? A.W.nc[L][i] - w_end(A.W, n, m + i) : A.W.om[i] - 1.0;
-                const cd* sg = A.sigR + (size_t)(m + i) * npair;
-                const cd* bd = A.band + ((size_t)m * kb + i) * npair;
+        for (int a = 0; a < NORB; ++a) accR[a] = accL[a] = mk(0.0, 0.0);
+        if (live) {
+            for (int l = 0; l < A.nlvl; ++l) {
+                const int cv = A.cover[(size_t)l * A.nt + m];
+                if (cv >= 0) {  // m is a column of block b: expand through V
+                    const int b = cv;
+                    const int r0 = A.blk[5 * b + 1], c0 = A.blk[5 * b + 3], c1 = A.blk[5 * b + 4];
+                    const int ldV = c1 - c0;
+                    if (A.wantR && A.n0[0] > r0) {
+                        for (int o = g; o < NORB; o += G) {
+                            const int q = o * NORB + c;
+                            const int rk = rank_of(A, 0, b, q);
+                            const cd* Vq = A.V[0] + A.Voff[b] + (size_t)q * RC * ldV + (m - c0);
+                            const cd* z = A.proj + proj_slot(A, 0, b, q, 0) * NORB * RC;
+                            for (int r = 0; r < rk; ++r) {
+                                const cd v = Vq[(size_t)r * ldV];
 #pragma unroll
-                for (int bb = 0; bb < NORB; ++bb) {
-                    const cd g = wc * bd[bb * NORB + c];
+                                for (int a = 0; a < NORB; ++a) fmac_(accR[a], v, z[a * RC + r]);
+                            }
+                        }
+                    }
+                    if (A.wantL && A.n0[1] > r0) {
+                        for (int o = g; o < NORB; o += G) {
+                            const int q = c * NORB + o;
+                            const int rk = rank_of(A, 1, b, q);
+                            const cd* Vq = A.V[1] + A.Voff[b] + (size_t)q * RC * ldV + (m - c0);
+                            const cd* z = A.proj + proj_slot(A, 1, b, q, 0) * NORB * RC;
+                            for (int r = 0; r < rk; ++r) {
+                                const cd v = -Vq[(size_t)r * ldV];
 #pragma unroll
-                    for (int a = 0; a < NORB; ++a) fma_(accR[a], sg[a * NORB + bb], g);
+                                for (int a = 0; a < NORB; ++a) fma_(accL[a], v, z[a * RC + r]);
+                            }
+                        }
+                    }
+                } else if (A.wantL) {  // m is a row of block b: expand through U
+                    const int b = ~cv;
+                    const int r0 = A.blk[5 * b + 1], r1 = A.blk[5 * b + 2];
+                    const int ldU = r1 - r0;
+                    if (m < A.n0[0]) {
+                        for (int o = g; o < NORB; o += G) {
+                            const int q = c * NORB + o;
+                            const int rk = rank_of(A, 0, b, q);
+                            const cd* Uq = A.U[0] + A.Uoff[b] + (size_t)q * RC * ldU + (m - r0);
+                            const cd* z = A.proj + proj_slot(A, 0, b, q, 1) * NORB * RC;
+                            for (int r = 0; r < rk; ++r) {
+                                const cd u = Uq[(size_t)r * ldU];
+#pragma unroll
+                                for (int a = 0; a < NORB; ++a) fmac_(accL[a], u, z[a * RC + r]);
+                            }
+                        }
+                    }
+                    if (m < A.n0[1]) {
+                        for (int o = g; o < NORB; o += G) {
+                            const int q = o * NORB + c;
+                            const int rk = rank_of(A, 1, b, q);
+                            const cd* Uq = A.U[1] + A.Uoff[b] + (size_t)q * RC * ldU + (m - r0);
+                            const cd* z = A.proj + proj_slot(A, 1, b, q, 1) * NORB * RC;
+                            for (int r = 0; r < rk; ++r) {
+                                const cd u = Uq[(size_t)r * ldU];
+#pragma unroll
+                                for (int a = 0; a < NORB; ++a) fma_(accL[a], u, z[a * RC + r]);
+                            }
+                        }
+                    }
                 }
             }
-#pragma unroll
-            for (int a = 0; a < NORB; ++a) A.outR[mo + a * NORB + c] = A.h * accR[a];
         }
-    }
-    if (A.wantL) {
-        // second lesser term: end weights (m >= k) or Newton-Cotes (m < k); the
-        // interval is empty at m = 0 (no bulk term was added there either)
-        // Sigma^<(n,s)[a][b] = -conj(sigL[s][b][a]);  G^R(m,s)^dagger[b][c] = conj(G^R(m,s)[c][b])
-        const int imax = m == 0 ? -1 : (m < k ? m : k);
-        for (int i = 0; i <= imax; ++i) {
-            const int s = m - i;
-            const double wc = m < k ? A.W.nc[m][s] - w_start(A.W, s) : A.W.om[i] - 1.0;
-            const cd* sl = A.sigL + (size_t)s * npair;
-            const cd* bd = A.band + ((size_t)s * kb + i) * npair;
+        // sum over the lane groups (every lane of the wave takes part)
 #pragma unroll
-            for (int bb = 0; bb < NORB; ++bb) {
-                const cd g = mk(-wc, 0.0) * conj(bd[c * NORB + bb]);
+        for (int a = 0; a < NORB; ++a) {
 #pragma unroll
-                for (int a = 0; a < NORB; ++a) fmac_(accL[a], sl[bb * NORB + a], g);
+            for (int sh = MW; sh < 64; sh <<= 1) {
+                accR[a].x += __shfl_xor(accR[a].x, sh, 64);
+                accR[a].y += __shfl_xor(accR[a].y, sh, 64);
+                accL[a].x += __shfl_xor(accL[a].x, sh, 64);
+                accL[a].y += __shfl_xor(accL[a].y, sh, 64);
             }
         }
+        if (!live) continue;
+        const size_t mo = (size_t)m * npair;
 #pragma unroll
-        for (int a = 0; a < NORB; ++a) A.outL[mo + a * NORB + c] = A.h * accL[a];
+        for (int a = 0; a < NORB; ++a) {
+            if (a % G != g) continue;
+            const size_t o = mo + a * NORB + c;
+            cd sR = accR[a], sL = accL[a];
+            for (int pg = 0; pg < LG; ++pg) {
+                const size_t op = (size_t)pg * A.nt * npair + o;
+                if (A.wantR) sR = sR + A.leafR[op];
+                if (A.wantL) sL = sL + A.leafLR[op] + A.leafLL[op];
+            }
+            if (A.wantR) {
+                if (A.last[0] >= A.n0[0] && m < A.ls[0]) sR = sR + A.tailcol[0][o];
+                // band correction: start weights (n-m >= k) or Newton-Cotes (n-m < k)
+                const int L = n - m;
+                if (L == 0) {
+                    A.outR[o] = mk(0.0, 0.0);
+                } else {
+                    const int imax = L < k ? L : k;
+                    for (int i = 0; i <= imax; ++i) {
+                        const double wc = L < k ? A.W.nc[L][i] - w_end(A.W, n, m + i) : A.W.om[i] - 1.0;
+                        const cd* sg = A.sigR + (size_t)(m + i) * npair + a * NORB;
+                        const cd* bd = A.band + ((size_t)m * kb + i) * npair + c;
+#pragma unroll
+                        for (int bb = 0; bb < NORB; ++bb) fma_(sR, sg[bb], wc * bd[bb * NORB]);
+                    }
+                    A.outR[o] = A.h * sR;
+                }
+            }
+            if (A.wantL) {
+                for (int comp = 0; comp < 2; ++comp) {
+                    if (A.last[comp] < A.n0[comp]) continue;   // no tail rows
+                    if (comp == 1 && m < A.ls[1]) sL = sL + A.tailcol[1][o];
+                    if (m >= A.n0[comp] && m <= A.last[comp]) {
+                        const cd* tp = A.tailpart[comp] + (size_t)(m - A.n0[comp]) * npair + a * NORB + c;
+                        for (int ch = 0; ch < A.ntailchunk[comp]; ++ch) sL = sL + tp[(size_t)ch * A.P * npair];
+                    }
+                }
+                // second lesser term: end weights (m >= k) or Newton-Cotes (m < k); the
+                // interval is empty at m = 0 (no bulk term was added there either)
+                // Sigma^<(n,s)[a][b] = -conj(sigL[s][b][a]);  G^R(m,s)^dagger[b][c] = conj(G^R(m,s)[c][b])
+                const int imax = m == 0 ? -1 : (m < k ? m : k);
+                for (int i = 0; i <= imax; ++i) {
+                    const int s = m - i;
+                    const double wc = m < k ? A.W.nc[m][s] - w_start(A.W, s) : A.W.om[i] - 1.0;
+                    const cd* sl = A.sigL + (size_t)s * npair + a;
+                    const cd* bd = A.band + ((size_t)s * kb + i) * npair + c * NORB;
+#pragma unroll
+                    for (int bb = 0; bb < NORB; ++bb)
+                        fmac_(sL, sl[bb * NORB], mk(-wc, 0.0) * conj(bd[bb]));
+                }
+                A.outL[o] = A.h * sL;
+            }
+        }
     }
 }
 
 size_t tasks_smem(int norb) {
     const int ag = norb < 4 ? norb : 4;
-    size_t fact = norb <= 4 ? (size_t)CH * norb * sizeof(cd) : 0;
+    size_t fact = norb <= 8 ? (size_t)kCH * norb * sizeof(cd) : 0;
     size_t leaf = (size_t)(tri(64) + 2 * 64 * ag) * sizeof(cd);
     size_t tail = (size_t)(16 * kTailCH + (16 + kTailCH) * ag) * sizeof(cd);
     size_t s = fact > leaf ? fact : leaf;
@@ -525,13 +593,19 @@ size_t tasks_smem(int norb) {
 
 template <int NORB>
 hipError_t launch_t(const HistArgs& a, hipStream_t st, hipEvent_t* ev) {
-    const int ntask = a.nf[0] + a.nf[1] + a.nleaftask + a.ntailtask;
+    const int ntask = a.nfpad + a.nleaftask + a.ntailtask;
     if (ev) hipEventRecord(ev[0], st);
     if (ntask > 0) hist_tasks<NORB><<<ntask, NT, tasks_smem(NORB), st>>>(a);
     if (ev) hipEventRecord(ev[1], st);
-    const int nblk = (a.n + 1 + 63) / 64;
-    hist_combine<NORB><<<nblk, 64 * NORB, 0, st>>>(a);
+    if (a.nf[0] + a.nf[1] > 0) {
+        const long long nthr = 4LL * a.nb * a.npair * NORB * a.RC;
+        proj_reduce<NORB><<<(unsigned)((nthr + 255) / 256), 256, 0, st>>>(a);
+    }
     if (ev) hipEventRecord(ev[2], st);
+    using M = CombMap<NORB>;
+    const int nblk = (a.n + 1 + M::MW - 1) / M::MW;
+    hist_combine<NORB><<<nblk, 64 * M::WAVES, 0, st>>>(a);
+    if (ev) hipEventRecord(ev[3], st);
     return hipGetLastError();
 }
 

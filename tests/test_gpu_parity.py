@@ -77,7 +77,7 @@ def test_c1_full_sweep_dense(P):
     _check_rows(IRg, ILg, d["IR"], d["IL"], "dense c1")
 
 
-@pytest.mark.parametrize("norb,k,panel", [(2, 5, 8), (4, 3, 16), (4, 1, 4)])
+@pytest.mark.parametrize("norb,k,panel", [(2, 5, 8), (4, 3, 16), (4, 1, 4), (8, 5, 8)])
 def test_multiorbital_sweep(P, norb, k, panel):
     N, h, nlvl = 160, 0.03, 3   # leaves of 20 rows: ragged panels, several blocks per level
     G = hermitian_terms(11 + norb, 6, norb)
@@ -96,6 +96,25 @@ def test_multiorbital_sweep(P, norb, k, panel):
         D = P.Dense(N, norb, k=k)
         IRg, ILg = _sweep(D, inp, N, h, norb)
         _check_rows(IRg, ILg, IR, IL, f"dense norb={norb} k={k}")
+
+
+def test_ranks_above_sixteen(P):
+    """Blocks whose rank exceeds 16 (a projection pass covers 16 ranks)."""
+    from kbe_inputs import scalar_terms
+    N, h, nlvl, k = 256, 0.15, 2, 5
+    G, S = scalar_terms(31, 22), scalar_terms(32, 22)
+    inp = host_inputs(G, S, N, h)
+    rows = [0, 1, 5, 63, 64, 65, 127, 128, 129, 191, 192, 200, 255]
+    say("oracle: ranks above 16")
+    IR, IL = oracle_rows(*inp, N, h, k, rows=rows)
+    say("gpu: hodlr ranks above 16")
+    H = P.Hodlr(N, nlvl, 1, k=k, tol=1e-12, panel=8, max_rank=24)
+    IRg, ILg = _sweep(H, inp, N, h, 1)
+    assert H.status() == 0
+    rmax = max(int(H.ranks(c).max()) for c in (0, 1))
+    say("max rank", rmax)
+    assert 16 < rmax <= 24
+    _check_rows(IRg, ILg, IR, IL, "hodlr ranks above 16")
 
 
 def test_separate_calls_match_fused(P):
