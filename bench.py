@@ -42,8 +42,8 @@ def panel_schedule(N, P, leaves):
     return n0s, row_leaf
 
 
-def algorithmic_bytes(N, npair, P, blocks, leaves, ranks, steps):
-    """Bytes each history kernel must move at the given steps (both components).
+def algorithmic_bytes(N, npair, P, blocks, leaves, ranks, steps, nk=1):
+    """Bytes each history kernel must move at the given steps (both components, all nk objects).
 
     tasks:   every stored factor row once (U rows merged so far, all V rows of
              active blocks, at the blocks' ranks), the present part of every
@@ -53,7 +53,8 @@ def algorithmic_bytes(N, npair, P, blocks, leaves, ranks, steps):
     import numpy as np
     n0s, row_leaf = panel_schedule(N, P, leaves)
     zb = 16  # complex128
-    rsum = [ranks[c].sum(axis=1) for c in (0, 1)]   # per block: sum of ranks over pairs
+    # per block: sum of ranks over pairs (and objects)
+    rsum = [ranks[c].reshape(-1, ranks[c].shape[-2], ranks[c].shape[-1]).sum(axis=(0, 2)) for c in (0, 1)]
     tasks, comb = [], []
     for n in steps:
         n0 = n0s[n]
@@ -67,12 +68,12 @@ def algorithmic_bytes(N, npair, P, blocks, leaves, ranks, steps):
             if s0 <= n:
                 k = min(s1, n + 1) - s0
                 lf += k * (k + 1) // 2
-        lf *= 2 * npair * zb
+        lf *= 2 * npair * zb * nk
         tail = 0
         if n >= n0:
             ls = leaves[row_leaf[n0]][0]
-            tail = 2 * (n - n0 + 1) * ls * npair * zb
-        rows = 2 * (n + 1) * npair * zb
+            tail = 2 * (n - n0 + 1) * ls * npair * zb * nk
+        rows = 2 * (n + 1) * npair * zb * nk
         tasks.append(fac + lf + tail + rows)
         comb.append(fac + rows)
     return np.array(tasks, dtype=np.float64), np.array(comb, dtype=np.float64)
@@ -102,6 +103,70 @@ def cpu_baseline(cfg, G, S, budget_s):
                        f"{total:.3e} summands of a full N_t={N} sweep (single-threaded NumPy)")
 
 
+def lattice_bench(P, prof_stride):
+    """Batched form at the lattice workload: 32x32 momenta (nk = 1024), N_t = 2048, norb = 1,
+    one handle for all momenta; one timed sweep (append both rows, merges, history step)."""
+    import ctypes as C
+    import numpy as np
+    import torch
+    from kbe_inputs import make_config_inputs
+    from kbe_inputs.packed import packed_torch
+    cfg, G, S = make_config_inputs("c3")
+    N, h, k = cfg["nt"], cfg["h"], cfg["k"]
+    nk = len(G)
+    nlvl = int(round(np.log2(N // cfg["leaf"])))
+    tot = N * (N + 1) // 2
+    dev = torch.device("cuda:0")
+    t = time.perf_counter()
+    arrs = []
+    for src, kind in ((G, "ret"), (G, "les"), (S, "ret"), (S, "les")):
+        a = torch.empty((nk * tot,), dtype=torch.complex128, device=dev)
+        for o in range(nk):
+            a[o * tot:(o + 1) * tot] = packed_torch(src[o], kind, N, h, dev).reshape(-1)
+        arrs.append(a)
+    torch.cuda.synchronize()
+    log(f"lattice inputs: 4 x {nk} packed triangles ({4 * nk * tot * 16 / 2**30:.1f} GiB) in "
+        f"{time.perf_counter() - t:.1f} s")
+    outR = torch.empty((nk, N), dtype=torch.complex128, device=dev)
+    outL = torch.empty_like(outR)
+    B = P.HodlrBatch(nk, N, nlvl, 1, k=k, tol=cfg["tol"], panel=16, max_rank=16)
+    L, chk, st = P.lib(), P._lib._check, P._lib._stream()
+    ptr = [a.data_ptr() for a in arrs]
+    oR, oL = C.c_void_p(outR.data_ptr()), C.c_void_p(outL.data_ptr())
+
+    def run(n_end):
+        B.reset()
+        for n in range(n_end):
+            off = n * (n + 1) // 2 * 16
+            chk(L.hnessi_hodlr_append_row_batched(B.h, 0, n, C.c_void_p(ptr[0] + off), tot, st))
+            chk(L.hnessi_hodlr_append_row_batched(B.h, 1, n, C.c_void_p(ptr[1] + off), tot, st))
+            chk(L.hnessi_history_step_batched(B.h, n, C.c_void_p(ptr[2] + off), C.c_void_p(ptr[3] + off), tot,
+                                              h, oR, oL, N, st))
+
+    run(256)
+    torch.cuda.synchronize()
+    B.profile(prof_stride)
+    t0 = time.perf_counter()
+    run(N)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    status = B.status()
+    ranks = [B.ranks(P.RET), B.ranks(P.LES)]
+    st0, ms0 = B.profile_read(0)
+    _, ms1 = B.profile_read(1)
+    b_tasks, b_comb = algorithmic_bytes(N, 1, 16, B.blocks(), B.leaves(), ranks, list(st0), nk=nk)
+    out = dict(value=round(N / dt, 2), unit="time steps/s (all momenta)", nk=nk, n_t=N, norb=1,
+               sweep_s=round(dt, 3), status=status,
+               hist_tasks_gbs=round(float(b_tasks.sum() / (ms0.sum() * 1e-3) / 1e9), 1),
+               hist_combine_gbs=round(float(b_comb.sum() / (ms1.sum() * 1e-3) / 1e9), 1),
+               max_rank=int(max(r.max() for r in ranks)), device_gib=round(B.nbytes() / 2**30, 2))
+    B.profile(0)
+    B.close()
+    del arrs
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +178,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--prof-stride", type=int, default=16)
     ap.add_argument("--nt", type=int, default=None, help="override N_t (testing only)")
+    ap.add_argument("--no-lattice", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -194,6 +260,7 @@ def main():
         "proj_reduce": dict(est_ms_per_sweep=round(per_sweep_ms["proj_reduce"], 1)),
     }
     log("kernels:", kernels)
+    hodlr_step_ms = dict(zip(st0.tolist(), (ms0 + kern["proj_reduce"][1] + ms1).tolist()))
     log(f"ranks: max {max(int(r.max()) for r in ranks)}, HODLR device bytes {H.nbytes() / 2**30:.2f} GiB")
     H.profile(0)
     H.close()
@@ -210,15 +277,31 @@ def main():
         ddt = time.perf_counter() - t0
         dval = args.dense_steps * N / ddt
         sd, md = D.profile_read(0)
+        _, md1 = D.profile_read(1)
+        dense_step_ms = dict(zip(sd.tolist(), (md + md1).tolist()))
+        common = sorted(set(hodlr_step_ms) & set(dense_step_ms))
+        cross = next((n for n in common if hodlr_step_ms[n] < dense_step_ms[n]), None)
+        end = [n for n in common if n >= N - 256]
         dbytes = np.array([float(2 * npair * ((int(n) + 1) * (int(n) + 2) // 2) * 16
                                  + 2 * (int(n) + 1) * npair * 16) for n in sd], dtype=np.float64)
         dgbs = float(dbytes.sum() / (md.sum() * 1e-3) / 1e9)
         dense = dict(value=round(dval, 2), unit="steps/s", sweeps=args.dense_steps,
                      tile_kernel_gbs=round(dgbs, 1), tile_kernel_frac=round(dgbs / HBM_PEAK_GBS, 4),
-                     hodlr_speedup=round(value / dval, 2), device_gib=round(D.nbytes() / 2**30, 2))
+                     hodlr_speedup=round(value / dval, 2), device_gib=round(D.nbytes() / 2**30, 2),
+                     history_kernels_us_last_256_steps=dict(
+                         hodlr=round(1e3 * float(np.mean([hodlr_step_ms[n] for n in end])), 1),
+                         dense=round(1e3 * float(np.mean([dense_step_ms[n] for n in end])), 1)),
+                     crossover_n=cross)
         log(f"dense: {ddt:.3f} s -> {dval:.1f} steps/s, tile kernel {dgbs:.0f} GB/s")
         D.profile(0)
         D.close()
+
+    del GR, GL, SR, SL, IR, IL
+    torch.cuda.empty_cache()
+    lattice = None
+    if not args.no_lattice:
+        lattice = lattice_bench(P, args.prof_stride)
+        log("lattice:", lattice)
 
     cpu = None
     if not args.no_cpu:
@@ -238,6 +321,7 @@ def main():
         "roofline": roof,
         "kernels": kernels,
         "dense": dense,
+        "lattice": lattice,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

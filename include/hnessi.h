@@ -147,6 +147,46 @@ int hnessi_sweep(hnessi_hodlr_t H, int n_begin, int n_end, const void* GR, const
  * flags stay set until hnessi_hodlr_reset. */
 int hnessi_hodlr_status(hnessi_hodlr_t H, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Batched objects: the k-point lattice form (section on the 2D Hubbard model,
+ * where every momentum k carries its own Green's function and self-energy and
+ * the history integrals of different k are independent).
+ *
+ * One handle holds nk objects of one geometry (nt, nlvl, norb, k, svd_tol,
+ * panel, max_rank), advanced together: every call acts on all nk objects in
+ * the same kernel launches (grid dimension y = object).  Ranks, factors and
+ * truncations are per object.  Device arrays are object-major: object o's
+ * data starts o * stride complex128 elements after object 0's; a stride must
+ * be at least one object's data (HNESSI_E_ARG otherwise).  The single-object
+ * calls (append_row, history_*, sweep, get) return HNESSI_E_ARG on a batched
+ * handle; status, reset, ranks (nk * nb * norb^2 entries, object-major),
+ * blocks, leaves, bytes and profiling work on both.
+ * ------------------------------------------------------------------------- */
+
+/* nk in 1..65535; other arguments as for hnessi_hodlr_create. */
+int hnessi_hodlr_create_batched(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k,
+                                double svd_tol, int panel, int max_rank, int flags, void* stream);
+
+/* Number of objects of the handle (1 for hnessi_hodlr_create). */
+int hnessi_hodlr_nk(hnessi_hodlr_t H);
+
+/* Row n of component c of every object: object o's row at rows + o*k_stride. */
+int hnessi_hodlr_append_row_batched(hnessi_hodlr_t H, int c, int n, const void* rows, long long k_stride,
+                                    void* stream);
+
+/* hnessi_history_step for every object: inputs of object o at sigR_rows +
+ * o*in_stride and sigL_slices + o*in_stride, outputs at outR + o*out_stride
+ * and outL + o*out_stride. */
+int hnessi_history_step_batched(hnessi_hodlr_t H, int n, const void* sigR_rows, const void* sigL_slices,
+                                long long in_stride, double h, void* outR, void* outL, long long out_stride,
+                                void* stream);
+
+/* hnessi_sweep for every object: the six packed triangles of object o start
+ * at o*k_stride elements (k_stride >= nt(nt+1)/2 * norb^2). */
+int hnessi_sweep_batched(hnessi_hodlr_t H, int n_begin, int n_end, const void* GR, const void* GL,
+                         const void* SR, const void* SL, long long k_stride, double h, void* IR, void* IL,
+                         void* stream);
+
 /* Value of component c at (t1, t2), t1 >= t2, t1 <= last appended row,
  * reconstructed from whichever storage holds it (dense leaf, dense row, or
  * truncated SVD), into out_host (norb*norb complex128).  Synchronous. */

@@ -34,6 +34,15 @@ _SIGS = {
     "hnessi_weights": ([C.c_int, C.c_int, C.c_void_p], C.c_int),
     "hnessi_hodlr_create": ([C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
                              C.c_int, C.c_int, C.c_int, C.c_void_p], C.c_int),
+    "hnessi_hodlr_create_batched": ([C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                     C.c_double, C.c_int, C.c_int, C.c_int, C.c_void_p], C.c_int),
+    "hnessi_hodlr_nk": ([C.c_void_p], C.c_int),
+    "hnessi_hodlr_append_row_batched": ([C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_longlong, C.c_void_p],
+                                        C.c_int),
+    "hnessi_history_step_batched": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_longlong, C.c_double,
+                                     C.c_void_p, C.c_void_p, C.c_longlong, C.c_void_p], C.c_int),
+    "hnessi_sweep_batched": ([C.c_void_p, C.c_int, C.c_int] + [C.c_void_p] * 4 + [C.c_longlong, C.c_double]
+                             + [C.c_void_p] * 3, C.c_int),
     "hnessi_hodlr_destroy": ([C.c_void_p], C.c_int),
     "hnessi_hodlr_reset": ([C.c_void_p, C.c_void_p], C.c_int),
     "hnessi_hodlr_append_row": ([C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p], C.c_int),
@@ -192,11 +201,14 @@ class Hodlr:
         return tab[:2 * nl].reshape(nl, 2)
 
     def ranks(self, comp):
+        """(nb, norb^2) ranks; (nk, nb, norb^2) for a batch."""
         nb = self.blocks().shape[0]
-        cap = max(nb * self.norb ** 2, 1)
+        nk = getattr(self, "nk", 1)
+        cap = max(nk * nb * self.norb ** 2, 1)
         r = np.zeros(cap, dtype=np.int32)
         cnt = _check(lib().hnessi_hodlr_ranks(self.h, comp, r.ctypes.data_as(C.c_void_p), cap))
-        return r[:cnt].reshape(nb, self.norb ** 2)
+        r = r[:cnt].reshape(nk, nb, self.norb ** 2)
+        return r if nk > 1 else r[0]
 
     def nbytes(self):
         return int(lib().hnessi_hodlr_bytes(self.h))
@@ -206,6 +218,39 @@ class Hodlr:
 
     def profile_read(self, kind):
         return _profile_read(lib().hnessi_hodlr_profile_read, self.h, kind)
+
+
+class HodlrBatch(Hodlr):
+    """nk independent objects of one geometry (a k-point lattice), advanced in lockstep.
+
+    Device arrays are object-major: object o's data starts o * stride elements
+    (complex128) after the first object's."""
+
+    def __init__(self, nk, nt, nlvl, norb, k=5, tol=1e-10, panel=16, max_rank=16, flags=0):
+        h = C.c_void_p()
+        _check(lib().hnessi_hodlr_create_batched(C.byref(h), nk, nt, nlvl, norb, k, tol, panel, max_rank,
+                                                 flags, _stream()))
+        self.h = h
+        self.nk = nk
+        self.nt, self.nlvl, self.norb, self.k = nt, nlvl, norb, k
+        self.tol, self.panel, self.max_rank = tol, panel, max_rank
+
+    def append_row(self, comp, n, rows, k_stride):
+        _check(lib().hnessi_hodlr_append_row_batched(self.h, comp, n, _ptr(rows), k_stride, _stream()))
+
+    def history_step(self, n, sigR, sigL, in_stride, h, outR, outL, out_stride):
+        _check(lib().hnessi_history_step_batched(self.h, n, _ptr(sigR), _ptr(sigL), in_stride, h, _ptr(outR),
+                                                 _ptr(outL), out_stride, _stream()))
+
+    def sweep(self, n_begin, n_end, GR, GL, SR, SL, h, IR, IL, k_stride=None):
+        """Packed triangles of every object, object-major (k_stride defaults to one triangle)."""
+        if k_stride is None:
+            k_stride = self.nt * (self.nt + 1) // 2 * self.norb ** 2
+        for t in (GR, GL, SR, SL, IR, IL):
+            if t.numel() < self.nk * k_stride:
+                raise ValueError("array smaller than nk objects")
+        _check(lib().hnessi_sweep_batched(self.h, n_begin, n_end, _ptr(GR), _ptr(GL), _ptr(SR), _ptr(SL),
+                                          k_stride, h, _ptr(IR), _ptr(IL), _stream()))
 
 
 class Dense:

@@ -130,6 +130,11 @@ struct Prof {
 
 struct hnessi_hodlr_s {
     int nt = 0, nlvl = 0, norb = 0, npair = 0, k = 0, P = 0, RC = 0, flags = 0;
+    int nk = 1;  // objects of a batch (same geometry, independent data)
+    // per-object element counts of the batched arrays (the stride between objects)
+    long long oU = 0, oV = 0, oS = 0, oRank = 0, oLeaf = 0, oTail = 0, oBand = 0, oProj = 0, oPart = 0,
+              oLeafOut = 0, oTailcol = 0, oTailpart = 0, oTailrow = 0, oNodeR = 0, oNodeQ = 0, oNodeCnt = 0, oProbW2 = 0,
+              oProbW = 0, oProb = 0;
     double tol = 0.0;
     Weights W{};
     Geometry g;
@@ -164,6 +169,7 @@ struct hnessi_hodlr_s {
     cd* leafLL = nullptr;
     cd* tailcol[2] = {};
     cd* tailpart[2] = {};
+    cd* tailrow[2] = {};
     int ntailchunk_max = 0;
     // merge scratch
     std::vector<long long> lvl_node_base;  // per level: first node of pair 0
@@ -205,11 +211,15 @@ int hnessi_weights(int k, int L, double* w_host) {
     return HNESSI_OK;
 }
 
-int hnessi_hodlr_create(hnessi_hodlr_t* out, int nt, int nlvl, int norb, int k, double svd_tol,
-                        int panel, int max_rank, int flags, void* stream) {
-    (void)stream;
+}  // extern "C"
+
+namespace {
+
+int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, double svd_tol, int panel,
+                int max_rank, int flags) {
     if (!out) return fail(HNESSI_E_ARG, "out is NULL");
     *out = nullptr;
+    if (nk < 1 || nk > 65535) return fail(HNESSI_E_ARG, "nk must be in 1..65535");
     if (!(norb == 1 || norb == 2 || norb == 4 || norb == 8 || norb == 16))
         return fail(HNESSI_E_ARG, "norb must be 1, 2, 4, 8 or 16");
     if (!(svd_tol > 0.0)) return fail(HNESSI_E_ARG, "svd_tol must be > 0");
@@ -233,6 +243,7 @@ int hnessi_hodlr_create(hnessi_hodlr_t* out, int nt, int nlvl, int norb, int k, 
         delete H;
         return fail(HNESSI_E_ARG, "leaves must hold at least k+1 rows and the panel");
     }
+    H->nk = nk;
     H->nt = nt;
     H->nlvl = nlvl;
     H->norb = norb;
@@ -253,6 +264,12 @@ int hnessi_hodlr_create(hnessi_hodlr_t* out, int nt, int nlvl, int norb, int k, 
     do {                                                 \
         int rc_ = al.alloc((p), (n), (z));               \
         if (rc_ != HNESSI_OK) return bail(rc_);          \
+    } while (0)
+    // one allocation holding nk objects; o receives the per-object count
+#define HALLOC_K(p, n, z, o)                             \
+    do {                                                 \
+        (o) = (long long)(n);                            \
+        HALLOC(p, (size_t)(o) * nk, z);                  \
     } while (0)
     // geometry
     std::vector<int> blk(5 * std::max(nb, 1)), lf(2 * g.nleaf);
@@ -286,15 +303,15 @@ int hnessi_hodlr_create(hnessi_hodlr_t* out, int nt, int nlvl, int norb, int k, 
     HALLOC(H->d_Loff, g.nleaf, false);
     // factor and dense storage
     for (int c = 0; c < 2; ++c) {
-        HALLOC(H->U[c], uo, true);
-        HALLOC(H->V[c], vo, true);
-        HALLOC(H->S[c], (size_t)std::max(nb, 1) * npair * RC, true);
-        HALLOC(H->rank[c], (size_t)std::max(nb, 1) * npair, true);
-        HALLOC(H->leaf[c], lo, true);
-        HALLOC(H->tail[c], (size_t)panel * npair * nt, true);
+        HALLOC_K(H->U[c], uo, true, H->oU);
+        HALLOC_K(H->V[c], vo, true, H->oV);
+        HALLOC_K(H->S[c], (size_t)std::max(nb, 1) * npair * RC, true, H->oS);
+        HALLOC_K(H->rank[c], (size_t)std::max(nb, 1) * npair, true, H->oRank);
+        HALLOC_K(H->leaf[c], lo, true, H->oLeaf);
+        HALLOC_K(H->tail[c], (size_t)panel * npair * nt, true, H->oTail);
     }
-    HALLOC(H->band, (size_t)nt * (k + 1) * npair, true);
-    HALLOC(H->proj, (size_t)2 * std::max(nb, 1) * npair * 2 * norb * RC, true);
+    HALLOC_K(H->band, (size_t)nt * (k + 1) * npair, true, H->oBand);
+    HALLOC_K(H->proj, (size_t)2 * std::max(nb, 1) * npair * 2 * norb * RC, true, H->oProj);
     // chunk partials of the projections: one slot per kCH factor rows
     std::vector<long long> partoff((size_t)2 * std::max(nb, 1) * npair * 2, 0);
     long long ps = 0;
@@ -306,15 +323,16 @@ int hnessi_hodlr_create(hnessi_hodlr_t* out, int nt, int nlvl, int norb, int k, 
                     ps += div_up(w == 0 ? g.r1[b] - g.r0[b] : g.c1[b] - g.c0[b], kCH);
                 }
     HALLOC(H->d_partoff, partoff.size(), false);
-    HALLOC(H->part, (size_t)std::max(ps, 1LL) * norb * RC, true);
+    HALLOC_K(H->part, (size_t)std::max(ps, 1LL) * norb * RC, true, H->oPart);
     const int leaf_slots = norb == 1 ? 1 : 4;   // orbital-pair groups of the leaf tasks
-    HALLOC(H->leafR, (size_t)leaf_slots * nt * npair, true);
-    HALLOC(H->leafLR, (size_t)leaf_slots * nt * npair, true);
-    HALLOC(H->leafLL, (size_t)leaf_slots * nt * npair, true);
+    HALLOC_K(H->leafR, (size_t)leaf_slots * nt * npair, true, H->oLeafOut);
+    HALLOC_K(H->leafLR, (size_t)leaf_slots * nt * npair, true, H->oLeafOut);
+    HALLOC_K(H->leafLL, (size_t)leaf_slots * nt * npair, true, H->oLeafOut);
     H->ntailchunk_max = div_up(nt, kTailCH);
     for (int c = 0; c < 2; ++c) {
-        HALLOC(H->tailcol[c], (size_t)nt * npair, true);
-        HALLOC(H->tailpart[c], (size_t)H->ntailchunk_max * panel * npair, true);
+        HALLOC_K(H->tailcol[c], (size_t)nt * npair, true, H->oTailcol);
+        HALLOC_K(H->tailpart[c], (size_t)H->ntailchunk_max * panel * npair, true, H->oTailpart);
+        HALLOC_K(H->tailrow[c], (size_t)panel * npair, true, H->oTailrow);
     }
     // merge scratch: one block per level per panel
     H->lvl_node_base.assign(nlvl + 1, 0);
@@ -329,13 +347,13 @@ int hnessi_hodlr_create(hnessi_hodlr_t* out, int nt, int nlvl, int norb, int k, 
         nodes += (long long)npair * H->lvl_nodes[l];
     }
     const long long nprob = (long long)std::max(nlvl, 1) * npair;
-    HALLOC(H->nodeR, (size_t)std::max(nodes, 1LL) * kW * kW, false);
-    HALLOC(H->nodeQ, (size_t)std::max(nodes, 1LL) * kNodeQ, false);
-    HALLOC(H->nodecnt, (size_t)std::max(nodes, 1LL), true);
-    HALLOC(H->UK, (size_t)nprob * kW * kW, false);
-    HALLOC(H->VR, (size_t)nprob * kW * kW, false);
-    HALLOC(H->Sold, (size_t)nprob * kW, false);
-    HALLOC(H->rold, (size_t)nprob, false);
+    HALLOC_K(H->nodeR, (size_t)std::max(nodes, 1LL) * kW * kW, false, H->oNodeR);
+    HALLOC_K(H->nodeQ, (size_t)std::max(nodes, 1LL) * kNodeQ, false, H->oNodeQ);
+    HALLOC_K(H->nodecnt, (size_t)std::max(nodes, 1LL), true, H->oNodeCnt);
+    HALLOC_K(H->UK, (size_t)nprob * kW * kW, false, H->oProbW2);
+    HALLOC_K(H->VR, (size_t)nprob * kW * kW, false, H->oProbW2);
+    HALLOC_K(H->Sold, (size_t)nprob * kW, false, H->oProbW);
+    HALLOC_K(H->rold, (size_t)nprob, false, H->oProb);
     HALLOC(H->err, 1, true);
     // projection task lists (sorted by the row that activates them)
     for (int c = 0; c < 2; ++c) {
@@ -364,10 +382,29 @@ int hnessi_hodlr_create(hnessi_hodlr_t* out, int nt, int nlvl, int norb, int k, 
         hipMemcpy(H->d_Loff, H->Loff.data(), g.nleaf * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(H->d_partoff, partoff.data(), partoff.size() * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess)
         return bail(fail(HNESSI_E_DEVICE, "copy of geometry failed"));
+#undef HALLOC_K
 #undef HALLOC
     *out = H;
     return HNESSI_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+int hnessi_hodlr_create(hnessi_hodlr_t* out, int nt, int nlvl, int norb, int k, double svd_tol,
+                        int panel, int max_rank, int flags, void* stream) {
+    (void)stream;
+    return create_impl(out, 1, nt, nlvl, norb, k, svd_tol, panel, max_rank, flags);
+}
+
+int hnessi_hodlr_create_batched(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k,
+                                double svd_tol, int panel, int max_rank, int flags, void* stream) {
+    (void)stream;
+    return create_impl(out, nk, nt, nlvl, norb, k, svd_tol, panel, max_rank, flags);
+}
+
+int hnessi_hodlr_nk(hnessi_hodlr_t H) { return H ? H->nk : fail(HNESSI_E_ARG, "handle is NULL"); }
 
 int hnessi_hodlr_destroy(hnessi_hodlr_t H) {
     if (!H) return fail(HNESSI_E_ARG, "handle is NULL");
@@ -382,7 +419,7 @@ int hnessi_hodlr_reset(hnessi_hodlr_t H, void* stream) {
     if (!H) return fail(HNESSI_E_ARG, "handle is NULL");
     hipStream_t st = (hipStream_t)stream;
     for (int c = 0; c < 2; ++c) {
-        HIP_TRY(hipMemsetAsync(H->rank[c], 0, sizeof(int) * std::max(H->g.nb, 1) * H->npair, st));
+        HIP_TRY(hipMemsetAsync(H->rank[c], 0, sizeof(int) * H->oRank * H->nk, st));
         H->last[c] = -1;
         H->n0[c] = 0;
     }
@@ -416,6 +453,17 @@ int merge_panel(hnessi_hodlr_t H, int c, int p0, int p1, hipStream_t st) {
     a.Sold = H->Sold;
     a.rold = H->rold;
     a.err = H->err;
+    a.kU = H->oU;
+    a.kV = H->oV;
+    a.kS = H->oS;
+    a.kRank = H->oRank;
+    a.kSrc = H->oTail;
+    a.kNodeR = H->oNodeR;
+    a.kNodeQ = H->oNodeQ;
+    a.kNodeCnt = H->oNodeCnt;
+    a.kProbW2 = H->oProbW2;
+    a.kProbW = H->oProbW;
+    a.kProb = H->oProb;
     int nv = 0, nu = 0, nblk = 0;
     for (int l = 0; l < H->nlvl; ++l) {
         int cv = g.cover[(size_t)l * H->nt + p0];
@@ -447,7 +495,7 @@ int merge_panel(hnessi_hodlr_t H, int c, int p0, int p1, hipStream_t st) {
     const bool timed = H->prof.stride > 0;
     hipEvent_t e0 = timed ? H->prof.ev() : nullptr, e1 = timed ? H->prof.ev() : nullptr;
     if (e0) hipEventRecord(e0, st);
-    HIP_TRY(launch_merge(a, st));
+    HIP_TRY(launch_merge(a, H->nk, st));
     if (e1) {
         hipEventRecord(e1, st);
         H->prof.recs.push_back({2, p1 - 1, e0, e1});
@@ -462,7 +510,8 @@ bool panel_ends(hnessi_hodlr_t H, int c, int n) {
 }
 
 int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, double h, void* outR,
-               void* outL, bool wantR, bool wantL, hipStream_t st) {
+               void* outL, bool wantR, bool wantL, hipStream_t st, long long in_stride = 0,
+               long long out_stride = 0) {
     if (n < 0 || n >= H->nt) return fail(HNESSI_E_RANGE, "n outside the grid");
     if (!sigR) return fail(HNESSI_E_ARG, "sigR_row is NULL");
     if (wantR && !outR) return fail(HNESSI_E_ARG, "output is NULL");
@@ -510,6 +559,7 @@ int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, doub
         A.ft[c] = H->d_ft[c];
         A.tailcol[c] = H->tailcol[c];
         A.tailpart[c] = H->tailpart[c];
+        A.tailrow[c] = H->tailrow[c];
     }
     A.band = H->band;
     A.blk = H->d_blk;
@@ -532,6 +582,22 @@ int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, doub
     A.leafLL = H->leafLL;
     A.outR = static_cast<cd*>(outR);
     A.outL = static_cast<cd*>(outL);
+    A.nk = H->nk;
+    A.kIn = in_stride;
+    A.kOut = out_stride;
+    A.kU = H->oU;
+    A.kV = H->oV;
+    A.kS = H->oS;
+    A.kRank = H->oRank;
+    A.kLeaf = H->oLeaf;
+    A.kTail = H->oTail;
+    A.kBand = H->oBand;
+    A.kProj = H->oProj;
+    A.kPart = H->oPart;
+    A.kLeafOut = H->oLeafOut;
+    A.kTailcol = H->oTailcol;
+    A.kTailpart = H->oTailpart;
+    A.kTailrow = H->oTailrow;
     if (H->prof.want(n)) {
         hipEvent_t ev[4] = {H->prof.ev(), H->prof.ev(), H->prof.ev(), H->prof.ev()};
         HIP_TRY(launch_history(A, st, ev));
@@ -548,13 +614,15 @@ int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, doub
 
 extern "C" {
 
-int hnessi_hodlr_append_row(hnessi_hodlr_t H, int c, int n, const void* row, void* stream) {
-    if (!H) return fail(HNESSI_E_ARG, "handle is NULL");
+}  // extern "C"
+
+namespace {
+
+int append_impl(hnessi_hodlr_t H, int c, int n, const void* row, long long k_stride, hipStream_t st) {
     if (c != HNESSI_RET && c != HNESSI_LES) return fail(HNESSI_E_ARG, "component must be RET or LES");
     if (!row) return fail(HNESSI_E_ARG, "row is NULL");
     if (n < 0 || n >= H->nt) return fail(HNESSI_E_RANGE, "n outside the grid");
     if (n != H->last[c] + 1) return fail(HNESSI_E_ORDER, "rows must be appended in order");
-    hipStream_t st = (hipStream_t)stream;
     const Geometry& g = H->g;
     const int leaf = g.row_leaf[n];
     AppendArgs a{};
@@ -569,7 +637,11 @@ int hnessi_hodlr_append_row(hnessi_hodlr_t H, int c, int n, const void* row, voi
     a.leaf = H->leaf[c] + H->Loff[leaf];
     a.tail = H->tail[c];
     a.band = c == HNESSI_RET ? H->band : nullptr;
-    HIP_TRY(launch_append_hodlr(a, st));
+    a.kRow = k_stride;
+    a.kLeaf = H->oLeaf;
+    a.kTail = H->oTail;
+    a.kBand = H->oBand;
+    HIP_TRY(launch_append_hodlr(a, H->nk, st));
     H->last[c] = n;
     if (panel_ends(H, c, n)) {
         int rc = merge_panel(H, c, H->n0[c], n + 1, st);
@@ -579,40 +651,105 @@ int hnessi_hodlr_append_row(hnessi_hodlr_t H, int c, int n, const void* row, voi
     return HNESSI_OK;
 }
 
-int hnessi_history_R(hnessi_hodlr_t H, int n, const void* sigR_row, double h, void* out, void* stream) {
+int single_only(hnessi_hodlr_t H) {
     if (!H) return fail(HNESSI_E_ARG, "handle is NULL");
+    if (H->nk != 1) return fail(HNESSI_E_ARG, "batched handle: use the _batched calls");
+    return HNESSI_OK;
+}
+
+int batched_stride(hnessi_hodlr_t H, long long stride, long long need) {
+    if (!H) return fail(HNESSI_E_ARG, "handle is NULL");
+    if (H->nk > 1 && stride < need) return fail(HNESSI_E_ARG, "object stride smaller than one object's data");
+    return HNESSI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hnessi_hodlr_append_row(hnessi_hodlr_t H, int c, int n, const void* row, void* stream) {
+    int rc = single_only(H);
+    if (rc != HNESSI_OK) return rc;
+    return append_impl(H, c, n, row, 0, (hipStream_t)stream);
+}
+
+int hnessi_hodlr_append_row_batched(hnessi_hodlr_t H, int c, int n, const void* rows, long long k_stride,
+                                    void* stream) {
+    int rc = batched_stride(H, k_stride, (long long)(n + 1) * (H ? H->npair : 0));
+    if (rc != HNESSI_OK) return rc;
+    return append_impl(H, c, n, rows, k_stride, (hipStream_t)stream);
+}
+
+int hnessi_history_R(hnessi_hodlr_t H, int n, const void* sigR_row, double h, void* out, void* stream) {
+    int rc = single_only(H);
+    if (rc != HNESSI_OK) return rc;
     return do_history(H, n, sigR_row, nullptr, h, out, nullptr, true, false, (hipStream_t)stream);
 }
 
 int hnessi_history_lesser(hnessi_hodlr_t H, int n, const void* sigR_row, const void* sigL_slice,
                           double h, void* out, void* stream) {
-    if (!H) return fail(HNESSI_E_ARG, "handle is NULL");
+    int rc = single_only(H);
+    if (rc != HNESSI_OK) return rc;
     return do_history(H, n, sigR_row, sigL_slice, h, nullptr, out, false, true, (hipStream_t)stream);
 }
 
 int hnessi_history_step(hnessi_hodlr_t H, int n, const void* sigR_row, const void* sigL_slice,
                         double h, void* outR, void* outL, void* stream) {
-    if (!H) return fail(HNESSI_E_ARG, "handle is NULL");
+    int rc = single_only(H);
+    if (rc != HNESSI_OK) return rc;
     return do_history(H, n, sigR_row, sigL_slice, h, outR, outL, true, true, (hipStream_t)stream);
 }
 
-int hnessi_sweep(hnessi_hodlr_t H, int n_begin, int n_end, const void* GR, const void* GL,
-                 const void* SR, const void* SL, double h, void* IR, void* IL, void* stream) {
-    if (!H) return fail(HNESSI_E_ARG, "handle is NULL");
+int hnessi_history_step_batched(hnessi_hodlr_t H, int n, const void* sigR_rows, const void* sigL_slices,
+                                long long in_stride, double h, void* outR, void* outL, long long out_stride,
+                                void* stream) {
+    const long long need = (long long)(n + 1) * (H ? H->npair : 0);
+    int rc = batched_stride(H, in_stride, need);
+    if (rc == HNESSI_OK) rc = batched_stride(H, out_stride, need);
+    if (rc != HNESSI_OK) return rc;
+    return do_history(H, n, sigR_rows, sigL_slices, h, outR, outL, true, true, (hipStream_t)stream, in_stride,
+                      out_stride);
+}
+
+}  // extern "C"
+
+namespace {
+
+int sweep_impl(hnessi_hodlr_t H, int n_begin, int n_end, const void* GR, const void* GL, const void* SR,
+               const void* SL, long long k_stride, double h, void* IR, void* IL, hipStream_t st) {
     if (!GR || !GL || !SR || !SL || !IR || !IL) return fail(HNESSI_E_ARG, "NULL array");
     if (n_begin < 0 || n_end > H->nt || n_begin > n_end) return fail(HNESSI_E_RANGE, "bad sweep range");
     const size_t np = H->npair;
     for (int n = n_begin; n < n_end; ++n) {
         const size_t off = (size_t)tri(n) * np;
-        int rc = hnessi_hodlr_append_row(H, HNESSI_RET, n, static_cast<const cd*>(GR) + off, stream);
+        int rc = append_impl(H, HNESSI_RET, n, static_cast<const cd*>(GR) + off, k_stride, st);
         if (rc != HNESSI_OK) return rc;
-        rc = hnessi_hodlr_append_row(H, HNESSI_LES, n, static_cast<const cd*>(GL) + off, stream);
+        rc = append_impl(H, HNESSI_LES, n, static_cast<const cd*>(GL) + off, k_stride, st);
         if (rc != HNESSI_OK) return rc;
-        rc = hnessi_history_step(H, n, static_cast<const cd*>(SR) + off, static_cast<const cd*>(SL) + off,
-                                 h, static_cast<cd*>(IR) + off, static_cast<cd*>(IL) + off, stream);
+        rc = do_history(H, n, static_cast<const cd*>(SR) + off, static_cast<const cd*>(SL) + off, h,
+                        static_cast<cd*>(IR) + off, static_cast<cd*>(IL) + off, true, true, st, k_stride, k_stride);
         if (rc != HNESSI_OK) return rc;
     }
     return HNESSI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hnessi_sweep(hnessi_hodlr_t H, int n_begin, int n_end, const void* GR, const void* GL,
+                 const void* SR, const void* SL, double h, void* IR, void* IL, void* stream) {
+    int rc = single_only(H);
+    if (rc != HNESSI_OK) return rc;
+    return sweep_impl(H, n_begin, n_end, GR, GL, SR, SL, 0, h, IR, IL, (hipStream_t)stream);
+}
+
+int hnessi_sweep_batched(hnessi_hodlr_t H, int n_begin, int n_end, const void* GR, const void* GL,
+                         const void* SR, const void* SL, long long k_stride, double h, void* IR, void* IL,
+                         void* stream) {
+    int rc = batched_stride(H, k_stride, tri(H ? H->nt : 0) * (H ? H->npair : 0));
+    if (rc != HNESSI_OK) return rc;
+    return sweep_impl(H, n_begin, n_end, GR, GL, SR, SL, k_stride, h, IR, IL, (hipStream_t)stream);
 }
 
 int hnessi_hodlr_status(hnessi_hodlr_t H, void* stream) {
@@ -627,6 +764,7 @@ int hnessi_hodlr_status(hnessi_hodlr_t H, void* stream) {
 
 int hnessi_hodlr_get(hnessi_hodlr_t H, int c, int t1, int t2, void* out_host) {
     if (!H || !out_host) return fail(HNESSI_E_ARG, "NULL argument");
+    if (H->nk != 1) return fail(HNESSI_E_ARG, "batched handle: reconstruction is for single objects");
     if (c != HNESSI_RET && c != HNESSI_LES) return fail(HNESSI_E_ARG, "component must be RET or LES");
     if (t2 < 0 || t2 > t1 || t1 > H->last[c]) return fail(HNESSI_E_RANGE, "(t1, t2) outside the stored region");
     HIP_TRY(hipDeviceSynchronize());
@@ -679,11 +817,14 @@ int hnessi_hodlr_get(hnessi_hodlr_t H, int c, int t1, int t2, void* out_host) {
 int hnessi_hodlr_ranks(hnessi_hodlr_t H, int c, int* ranks_host, int capacity) {
     if (!H || !ranks_host) return fail(HNESSI_E_ARG, "NULL argument");
     if (c != HNESSI_RET && c != HNESSI_LES) return fail(HNESSI_E_ARG, "component must be RET or LES");
-    int total = H->g.nb * H->npair;
+    const int per = H->g.nb * H->npair;
+    const long long total = (long long)per * H->nk;
     if (capacity < total) return fail(HNESSI_E_ARG, "capacity too small");
     HIP_TRY(hipDeviceSynchronize());
-    if (total > 0) HIP_TRY(hipMemcpy(ranks_host, H->rank[c], total * sizeof(int), hipMemcpyDeviceToHost));
-    return total;
+    for (int o = 0; o < H->nk && per > 0; ++o)
+        HIP_TRY(hipMemcpy(ranks_host + (size_t)o * per, H->rank[c] + (size_t)o * H->oRank, per * sizeof(int),
+                          hipMemcpyDeviceToHost));
+    return (int)total;
 }
 
 int hnessi_hodlr_blocks(hnessi_hodlr_t H, int* tab_host, int capacity) {
@@ -788,7 +929,7 @@ int hnessi_compress_block(const void* A, int rows, int cols, int lda, double tol
         a.nblk = 1;
         a.ntask_v = nch;
         a.ntask_u = B.nutask;
-        hipError_t e = launch_merge(a, st);
+        hipError_t e = launch_merge(a, 1, st);
         if (e != hipSuccess) {
             hipStreamSynchronize(st);
             al.release();

@@ -18,6 +18,7 @@ struct HistArgs {
     int last[2];    // last appended row, per component
     int ls[2];      // columns [0, ls) of the rows still held dense (tail), per component
     int nt, norb, npair, RC, nlvl, nb, P;
+    int nk;         // objects in the batch (grid dimension y)
     int wantR, wantL;
     double h;
     Weights W;
@@ -51,8 +52,14 @@ struct HistArgs {
     cd* leafLL;
     cd* tailcol[2];  // [m][a][c]       column sums over the tail rows
     cd* tailpart[2]; // [chunk][slot][a][c]  row dots of the tail rows, per column chunk
+    cd* tailrow[2];  // [slot][a][c]         row dots of the tail rows (sum over the chunks)
     cd* outR;
     cd* outL;
+    // batched objects (grid dimension y): element strides from one object's
+    // data to the next; the geometry and the task lists are shared
+    long long kIn, kOut;   // Sigma rows, output rows
+    long long kU, kV, kS, kRank, kLeaf, kTail, kBand;
+    long long kProj, kPart, kLeafOut, kTailcol, kTailpart, kTailrow;
 };
 
 // ev: nullptr, or four events recorded before hist_tasks, after it, after

@@ -51,9 +51,32 @@ __device__ inline void add_at(cd (&acc)[N], int idx, cd v) {
         if (i == idx) acc[i] = acc[i] + v;
 }
 
+// per-object data of object blockIdx.y of a batch (the kernel arguments
+// hold object 0 and the strides)
+#define OBJ ((long long)blockIdx.y)
+__device__ inline const cd* p_sigR(const HistArgs& A) { return A.sigR + OBJ * A.kIn; }
+__device__ inline const cd* p_sigL(const HistArgs& A) { return A.sigL ? A.sigL + OBJ * A.kIn : nullptr; }
+__device__ inline cd* p_outR(const HistArgs& A) { return A.outR ? A.outR + OBJ * A.kOut : nullptr; }
+__device__ inline cd* p_outL(const HistArgs& A) { return A.outL ? A.outL + OBJ * A.kOut : nullptr; }
+__device__ inline const cd* p_U(const HistArgs& A, int c) { return A.U[c] + OBJ * A.kU; }
+__device__ inline const cd* p_V(const HistArgs& A, int c) { return A.V[c] + OBJ * A.kV; }
+__device__ inline const double* p_S(const HistArgs& A, int c) { return A.S[c] + OBJ * A.kS; }
+__device__ inline const int* p_rank(const HistArgs& A, int c) { return A.rank[c] + OBJ * A.kRank; }
+__device__ inline const cd* p_leaf(const HistArgs& A, int c) { return A.leaf[c] + OBJ * A.kLeaf; }
+__device__ inline const cd* p_tail(const HistArgs& A, int c) { return A.tail[c] + OBJ * A.kTail; }
+__device__ inline cd* p_tailcol(const HistArgs& A, int c) { return A.tailcol[c] + OBJ * A.kTailcol; }
+__device__ inline cd* p_tailpart(const HistArgs& A, int c) { return A.tailpart[c] + OBJ * A.kTailpart; }
+__device__ inline cd* p_tailrow(const HistArgs& A, int c) { return A.tailrow[c] + OBJ * A.kTailrow; }
+__device__ inline const cd* p_band(const HistArgs& A) { return A.band + OBJ * A.kBand; }
+__device__ inline cd* p_proj(const HistArgs& A) { return A.proj + OBJ * A.kProj; }
+__device__ inline cd* p_part(const HistArgs& A) { return A.part + OBJ * A.kPart; }
+__device__ inline cd* p_leafR(const HistArgs& A) { return A.leafR + OBJ * A.kLeafOut; }
+__device__ inline cd* p_leafLR(const HistArgs& A) { return A.leafLR + OBJ * A.kLeafOut; }
+__device__ inline cd* p_leafLL(const HistArgs& A) { return A.leafLL + OBJ * A.kLeafOut; }
+
 // ranks come from device memory: clamp them to the allocated capacity
 __device__ inline int rank_of(const HistArgs& A, int comp, int b, int q) {
-    const int r = A.rank[comp][(size_t)b * A.npair + q];
+    const int r = p_rank(A, comp)[(size_t)b * A.npair + q];
     return r < 0 ? 0 : (r > A.RC ? A.RC : r);
 }
 
@@ -108,12 +131,12 @@ __device__ void fact_task(const HistArgs& A, const FactTask& t, unsigned char* s
         len = min(A.n0[comp] - r0, r1 - r0);
         base = r0;
         ld = r1 - r0;
-        F = A.U[comp] + A.Uoff[b] + (size_t)q * RC * ld;
+        F = p_U(A, comp) + A.Uoff[b] + (size_t)q * RC * ld;
     } else {
         len = c1 - c0;
         base = c0;
         ld = c1 - c0;
-        F = A.V[comp] + A.Voff[b] + (size_t)q * RC * ld;
+        F = p_V(A, comp) + A.Voff[b] + (size_t)q * RC * ld;
     }
     const int i0 = t.chunk * kCH, i1 = min(len, i0 + kCH);
     if (i0 >= i1) return;
@@ -121,21 +144,37 @@ __device__ void fact_task(const HistArgs& A, const FactTask& t, unsigned char* s
     // folded Sigma entry multiplying row i of the factor, left orbital a
     auto xval = [&](int i, int a) -> cd {
         const int j = base + i;
-        if (comp == 0 && which == 0) return w_end(A.W, n, j) * A.sigR[(size_t)j * npair + a * NORB + qr];
-        if (comp == 0) return -w_start(A.W, j) * conj(A.sigL[(size_t)j * npair + qc * NORB + a]);
-        return interval_w(A.W, n, j) * A.sigR[(size_t)j * npair + a * NORB + (which == 0 ? qc : qr)];
+        if (comp == 0 && which == 0) return w_end(A.W, n, j) * p_sigR(A)[(size_t)j * npair + a * NORB + qr];
+        if (comp == 0) return -w_start(A.W, j) * conj(p_sigL(A)[(size_t)j * npair + qc * NORB + a]);
+        return interval_w(A.W, n, j) * p_sigR(A)[(size_t)j * npair + a * NORB + (which == 0 ? qc : qr)];
     };
+    const bool cj = (comp == 1);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // factor entries of one pass; indices clamped into range so that every
+    // load is issued unconditionally (out-of-range terms are zeroed)
+    cd fr[RPL][RW];
+    auto load_pass = [&](int rp) {
+#pragma unroll
+        for (int u = 0; u < RPL; ++u)
+#pragma unroll
+            for (int k = 0; k < RW; ++k) {
+                const int i = i0 + u * 64 + lane, r = rp + wave + 4 * k;
+                cd f = F[(size_t)min(r, rk - 1) * ld + min(i, i1 - 1)];
+                if (cj) f = conj(f);
+                fr[u][k] = (i < i1 && r < rk) ? f : mk(0.0, 0.0);
+            }
+    };
+    load_pass(0);   // in flight while the Sigma rows are staged
     cd* xs = reinterpret_cast<cd*>(smem);  // kCH x NORB
     if (kStage) {
         for (int e = threadIdx.x; e < (i1 - i0) * NORB; e += NT) xs[e] = xval(i0 + e / NORB, e % NORB);
         __syncthreads();
     }
-    const bool cj = (comp == 1);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const double* S = A.S[comp] + ((size_t)b * npair + q) * RC;
+    const double* S = p_S(A, comp) + ((size_t)b * npair + q) * RC;
     const size_t slot = proj_slot(A, comp, b, q, which);
-    cd* out = A.part + (size_t)(A.partoff[slot] + t.chunk) * NORB * RC;
+    cd* out = p_part(A) + (size_t)(A.partoff[slot] + t.chunk) * NORB * RC;
     for (int rp = 0; rp < rk; rp += 4 * RW) {
+        if (rp > 0) load_pass(rp);
         cd acc[RW][NORB];
 #pragma unroll
         for (int k = 0; k < RW; ++k)
@@ -149,15 +188,9 @@ __device__ void fact_task(const HistArgs& A, const FactTask& t, unsigned char* s
 #pragma unroll
                 for (int a = 0; a < NORB; ++a) xv[a] = kStage ? xs[(size_t)(i - i0) * NORB + a] : xval(i, a);
 #pragma unroll
-                for (int k = 0; k < RW; ++k) {
-                    const int r = rp + wave + 4 * k;
-                    if (r < rk) {
-                        cd f = F[(size_t)r * ld + i];
-                        if (cj) f = conj(f);
+                for (int k = 0; k < RW; ++k)
 #pragma unroll
-                        for (int a = 0; a < NORB; ++a) fma_(acc[k][a], xv[a], f);
-                    }
-                }
+                    for (int a = 0; a < NORB; ++a) fma_(acc[k][a], xv[a], fr[u][k]);
             }
         }
 #pragma unroll
@@ -188,7 +221,7 @@ __device__ void leaf_task(const HistArgs& A, int leaf, int comp, int ag, int pg,
     const int s0 = A.leafs[2 * leaf], s1 = A.leafs[2 * leaf + 1];
     const int lw = s1 - s0;
     const int nrow = min(s1, n + 1) - s0;
-    const cd* L = A.leaf[comp] + A.Loff[leaf];
+    const cd* L = p_leaf(A, comp) + A.Loff[leaf];
     const long long tsz = tri(lw), tnow = tri(nrow);
     cd* T = reinterpret_cast<cd*>(smem);   // tri(64)
     cd* xa = T + tri(64);                  // 64 x AG
@@ -208,11 +241,11 @@ __device__ void leaf_task(const HistArgs& A, int leaf, int comp, int ag, int pg,
         for (int e = threadIdx.x; e < nrow * AG; e += NT) {
             const int i = e / AG, aa = ag * AG + e % AG, j = s0 + i;
             if (comp == 0) {
-                xa[e] = w_end(A.W, n, j) * A.sigR[(size_t)j * npair + aa * NORB + qr];
-                xb[e] = doL ? -w_start(A.W, j) * conj(A.sigL[(size_t)j * npair + qc * NORB + aa]) : mk(0.0, 0.0);
+                xa[e] = w_end(A.W, n, j) * p_sigR(A)[(size_t)j * npair + aa * NORB + qr];
+                xb[e] = doL ? -w_start(A.W, j) * conj(p_sigL(A)[(size_t)j * npair + qc * NORB + aa]) : mk(0.0, 0.0);
             } else {
-                xa[e] = interval_w(A.W, n, j) * A.sigR[(size_t)j * npair + aa * NORB + qr];
-                xb[e] = interval_w(A.W, n, j) * A.sigR[(size_t)j * npair + aa * NORB + qc];
+                xa[e] = interval_w(A.W, n, j) * p_sigR(A)[(size_t)j * npair + aa * NORB + qr];
+                xb[e] = interval_w(A.W, n, j) * p_sigR(A)[(size_t)j * npair + aa * NORB + qc];
             }
         }
         __syncthreads();
@@ -248,10 +281,10 @@ __device__ void leaf_task(const HistArgs& A, int leaf, int comp, int ag, int pg,
         for (int c = 0; c < NORB; ++c) {
             const size_t o = ((size_t)pg * A.nt + m) * npair + a * NORB + c;
             if (comp == 0) {
-                A.leafR[o] = accA[c];
-                A.leafLR[o] = accB[c];
+                p_leafR(A)[o] = accA[c];
+                p_leafLR(A)[o] = accB[c];
             } else {
-                A.leafLL[o] = accA[c];
+                p_leafLL(A)[o] = accA[c];
             }
         }
     }
@@ -275,7 +308,7 @@ __device__ void tail_task(const HistArgs& A, int comp, int ag, int chunk, unsign
     const int a = ag * AG + wave;
     const bool wok = wave < AG;
     const bool doR = A.wantR, doL = A.wantL;
-    const cd* Tg = A.tail[comp];
+    const cd* Tg = p_tail(A, comp);
     cd col[NORB], row[NORB];
 #pragma unroll
     for (int c = 0; c < NORB; ++c) col[c] = row[c] = mk(0.0, 0.0);
@@ -289,17 +322,17 @@ __device__ void tail_task(const HistArgs& A, int comp, int ag, int chunk, unsign
         }
         for (int e = threadIdx.x; e < nrows * AG; e += NT) {
             const int i = e / AG, aa = ag * AG + e % AG, j = n0 + i;
-            xr[e] = comp == 0 ? w_end(A.W, n, j) * A.sigR[(size_t)j * npair + aa * NORB + qr]
-                              : interval_w(A.W, n, j) * A.sigR[(size_t)j * npair + aa * NORB + qc];
+            xr[e] = comp == 0 ? w_end(A.W, n, j) * p_sigR(A)[(size_t)j * npair + aa * NORB + qr]
+                              : interval_w(A.W, n, j) * p_sigR(A)[(size_t)j * npair + aa * NORB + qc];
         }
         for (int e = threadIdx.x; e < kTailCH * AG; e += NT) {
             const int mm = e / AG, aa = ag * AG + e % AG, m = cbeg + mm;
             cd v = mk(0.0, 0.0);
             if (mm < ncol) {
                 if (comp == 0) {
-                    if (doL) v = -w_start(A.W, m) * conj(A.sigL[(size_t)m * npair + qc * NORB + aa]);
+                    if (doL) v = -w_start(A.W, m) * conj(p_sigL(A)[(size_t)m * npair + qc * NORB + aa]);
                 } else {
-                    v = interval_w(A.W, n, m) * A.sigR[(size_t)m * npair + aa * NORB + qr];
+                    v = interval_w(A.W, n, m) * p_sigR(A)[(size_t)m * npair + aa * NORB + qr];
                 }
             }
             xm[e] = v;
@@ -343,10 +376,10 @@ __device__ void tail_task(const HistArgs& A, int comp, int ag, int chunk, unsign
         if (lane < ncol) {
 #pragma unroll
             for (int c = 0; c < NORB; ++c)
-                A.tailcol[comp][(size_t)(cbeg + lane) * npair + a * NORB + c] = col[c];
+                p_tailcol(A, comp)[(size_t)(cbeg + lane) * npair + a * NORB + c] = col[c];
         }
         if (part == 0 && ri < nrows) {
-            cd* tp = A.tailpart[comp] + ((size_t)chunk * A.P + ri) * npair + a * NORB;
+            cd* tp = p_tailpart(A, comp) + ((size_t)chunk * A.P + ri) * npair + a * NORB;
 #pragma unroll
             for (int c = 0; c < NORB; ++c) tp[c] = row[c];
         }
@@ -384,13 +417,42 @@ __global__ void __launch_bounds__(NT) hist_tasks(HistArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-// Sum of the chunk partials of every active projection, one thread per
-// (slot, a, r); slots of inactive blocks, ranks beyond the block's rank and
-// components not asked for are neither written nor read by the combine.
+// Second phase of the tasks: (i) the sum of the chunk partials of every active
+// projection, one thread per (slot, a, r) (slots of inactive blocks, ranks
+// beyond the block's rank and components not asked for are neither written
+// nor read by the combine); (ii) the sum over the column chunks of the row
+// dots of every tail row, one wave per (component, row, orbital pair), lanes
+// over the chunks and a fixed-order wave reduction.
+inline long long proj_reduce_blocks(const HistArgs& A) {
+    return (4LL * A.nb * A.npair * A.norb * A.RC + 255) / 256;
+}
+
 template <int NORB>
 __global__ void __launch_bounds__(256) proj_reduce(HistArgs A) {
     const int RC = A.RC;
     const long long per = (long long)NORB * RC;
+    const long long nblk = (4LL * A.nb * A.npair * per + 255) / 256;
+    if ((long long)blockIdx.x >= nblk) {
+        constexpr int npair = NORB * NORB;
+        const long long w = ((long long)blockIdx.x - nblk) * 4 + (threadIdx.x >> 6);
+        const int lane = threadIdx.x & 63;
+        const int q = (int)(w % npair);
+        const int slot = (int)((w / npair) % A.P);
+        const int comp = (int)(w / ((long long)npair * A.P));
+        if (comp > 1 || !A.wantL) return;
+        if (slot > A.last[comp] - A.n0[comp]) return;   // also: no tail rows at all
+        const cd* tp = p_tailpart(A, comp) + (size_t)slot * npair + q;
+        double re = 0.0, im = 0.0;
+        for (int ch = lane; ch < A.ntailchunk[comp]; ch += 64) {
+            const cd v = tp[(size_t)ch * A.P * npair];
+            re += v.x;
+            im += v.y;
+        }
+        re = wsum64(re);
+        im = wsum64(im);
+        if (lane == 0) p_tailrow(A, comp)[(size_t)slot * npair + q] = mk(re, im);
+        return;
+    }
     const long long tid = (long long)blockIdx.x * 256 + threadIdx.x;
     const long long slot = tid / per;
     if (slot >= 4LL * A.nb * A.npair) return;
@@ -409,10 +471,34 @@ __global__ void __launch_bounds__(256) proj_reduce(HistArgs A) {
     if (A.n0[comp] <= r0) return;
     const int len = which == 0 ? min(A.n0[comp] - r0, bk[2] - r0) : bk[4] - bk[3];
     const int nch = (len + kCH - 1) / kCH;
-    const cd* p = A.part + (size_t)A.partoff[slot] * per + e;
+    const cd* p = p_part(A) + (size_t)A.partoff[slot] * per + e;
     cd s = mk(0.0, 0.0);
     for (int ch = 0; ch < nch; ++ch) s = s + p[(size_t)ch * per];
-    A.proj[(size_t)slot * per + e] = s;
+    p_proj(A)[(size_t)slot * per + e] = s;
+}
+
+// ---------------------------------------------------------------------------
+// acc[a] (+|-)= op(F[r*ld]) z[a*RC + r] over r < rk, op = conj or identity.
+// The factor loads of a batch of eight ranks are issued together (indices
+// clamped to rk - 1, surplus terms skipped) so that they overlap in flight.
+template <int NORB, bool CONJ, bool NEG>
+__device__ inline void expand_ranks(cd (&acc)[NORB], const cd* F, int ld, const cd* z, int RC, int rk) {
+    constexpr int B = 8;
+    for (int r0 = 0; r0 < rk; r0 += B) {
+        cd f[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) f[u] = F[(size_t)min(r0 + u, rk - 1) * ld];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            if (r0 + u >= rk) break;
+            const cd fv = NEG ? -f[u] : f[u];
+#pragma unroll
+            for (int a = 0; a < NORB; ++a) {
+                if (CONJ) fmac_(acc[a], fv, z[a * RC + r0 + u]);
+                else fma_(acc[a], fv, z[a * RC + r0 + u]);
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -458,26 +544,18 @@ __global__ void __launch_bounds__(64 * CombMap<NORB>::WAVES) hist_combine(HistAr
                         for (int o = g; o < NORB; o += G) {
                             const int q = o * NORB + c;
                             const int rk = rank_of(A, 0, b, q);
-                            const cd* Vq = A.V[0] + A.Voff[b] + (size_t)q * RC * ldV + (m - c0);
-                            const cd* z = A.proj + proj_slot(A, 0, b, q, 0) * NORB * RC;
-                            for (int r = 0; r < rk; ++r) {
-                                const cd v = Vq[(size_t)r * ldV];
-#pragma unroll
-                                for (int a = 0; a < NORB; ++a) fmac_(accR[a], v, z[a * RC + r]);
-                            }
+                            const cd* Vq = p_V(A, 0) + A.Voff[b] + (size_t)q * RC * ldV + (m - c0);
+                            const cd* z = p_proj(A) + proj_slot(A, 0, b, q, 0) * NORB * RC;
+                            if (rk > 0) expand_ranks<NORB, true, false>(accR, Vq, ldV, z, RC, rk);
                         }
                     }
                     if (A.wantL && A.n0[1] > r0) {
                         for (int o = g; o < NORB; o += G) {
                             const int q = c * NORB + o;
                             const int rk = rank_of(A, 1, b, q);
-                            const cd* Vq = A.V[1] + A.Voff[b] + (size_t)q * RC * ldV + (m - c0);
-                            const cd* z = A.proj + proj_slot(A, 1, b, q, 0) * NORB * RC;
-                            for (int r = 0; r < rk; ++r) {
-                                const cd v = -Vq[(size_t)r * ldV];
-#pragma unroll
-                                for (int a = 0; a < NORB; ++a) fma_(accL[a], v, z[a * RC + r]);
-                            }
+                            const cd* Vq = p_V(A, 1) + A.Voff[b] + (size_t)q * RC * ldV + (m - c0);
+                            const cd* z = p_proj(A) + proj_slot(A, 1, b, q, 0) * NORB * RC;
+                            if (rk > 0) expand_ranks<NORB, false, true>(accL, Vq, ldV, z, RC, rk);
                         }
                     }
                 } else if (A.wantL) {  // m is a row of block b: expand through U
@@ -488,26 +566,18 @@ __global__ void __launch_bounds__(64 * CombMap<NORB>::WAVES) hist_combine(HistAr
                         for (int o = g; o < NORB; o += G) {
                             const int q = c * NORB + o;
                             const int rk = rank_of(A, 0, b, q);
-                            const cd* Uq = A.U[0] + A.Uoff[b] + (size_t)q * RC * ldU + (m - r0);
-                            const cd* z = A.proj + proj_slot(A, 0, b, q, 1) * NORB * RC;
-                            for (int r = 0; r < rk; ++r) {
-                                const cd u = Uq[(size_t)r * ldU];
-#pragma unroll
-                                for (int a = 0; a < NORB; ++a) fmac_(accL[a], u, z[a * RC + r]);
-                            }
+                            const cd* Uq = p_U(A, 0) + A.Uoff[b] + (size_t)q * RC * ldU + (m - r0);
+                            const cd* z = p_proj(A) + proj_slot(A, 0, b, q, 1) * NORB * RC;
+                            if (rk > 0) expand_ranks<NORB, true, false>(accL, Uq, ldU, z, RC, rk);
                         }
                     }
                     if (m < A.n0[1]) {
                         for (int o = g; o < NORB; o += G) {
                             const int q = o * NORB + c;
                             const int rk = rank_of(A, 1, b, q);
-                            const cd* Uq = A.U[1] + A.Uoff[b] + (size_t)q * RC * ldU + (m - r0);
-                            const cd* z = A.proj + proj_slot(A, 1, b, q, 1) * NORB * RC;
-                            for (int r = 0; r < rk; ++r) {
-                                const cd u = Uq[(size_t)r * ldU];
-#pragma unroll
-                                for (int a = 0; a < NORB; ++a) fma_(accL[a], u, z[a * RC + r]);
-                            }
+                            const cd* Uq = p_U(A, 1) + A.Uoff[b] + (size_t)q * RC * ldU + (m - r0);
+                            const cd* z = p_proj(A) + proj_slot(A, 1, b, q, 1) * NORB * RC;
+                            if (rk > 0) expand_ranks<NORB, false, false>(accL, Uq, ldU, z, RC, rk);
                         }
                     }
                 }
@@ -533,35 +603,33 @@ __global__ void __launch_bounds__(64 * CombMap<NORB>::WAVES) hist_combine(HistAr
             cd sR = accR[a], sL = accL[a];
             for (int pg = 0; pg < LG; ++pg) {
                 const size_t op = (size_t)pg * A.nt * npair + o;
-                if (A.wantR) sR = sR + A.leafR[op];
-                if (A.wantL) sL = sL + A.leafLR[op] + A.leafLL[op];
+                if (A.wantR) sR = sR + p_leafR(A)[op];
+                if (A.wantL) sL = sL + p_leafLR(A)[op] + p_leafLL(A)[op];
             }
             if (A.wantR) {
-                if (A.last[0] >= A.n0[0] && m < A.ls[0]) sR = sR + A.tailcol[0][o];
+                if (A.last[0] >= A.n0[0] && m < A.ls[0]) sR = sR + p_tailcol(A, 0)[o];
                 // band correction: start weights (n-m >= k) or Newton-Cotes (n-m < k)
                 const int L = n - m;
                 if (L == 0) {
-                    A.outR[o] = mk(0.0, 0.0);
+                    p_outR(A)[o] = mk(0.0, 0.0);
                 } else {
                     const int imax = L < k ? L : k;
                     for (int i = 0; i <= imax; ++i) {
                         const double wc = L < k ? A.W.nc[L][i] - w_end(A.W, n, m + i) : A.W.om[i] - 1.0;
-                        const cd* sg = A.sigR + (size_t)(m + i) * npair + a * NORB;
-                        const cd* bd = A.band + ((size_t)m * kb + i) * npair + c;
+                        const cd* sg = p_sigR(A) + (size_t)(m + i) * npair + a * NORB;
+                        const cd* bd = p_band(A) + ((size_t)m * kb + i) * npair + c;
 #pragma unroll
                         for (int bb = 0; bb < NORB; ++bb) fma_(sR, sg[bb], wc * bd[bb * NORB]);
                     }
-                    A.outR[o] = A.h * sR;
+                    p_outR(A)[o] = A.h * sR;
                 }
             }
             if (A.wantL) {
                 for (int comp = 0; comp < 2; ++comp) {
                     if (A.last[comp] < A.n0[comp]) continue;   // no tail rows
-                    if (comp == 1 && m < A.ls[1]) sL = sL + A.tailcol[1][o];
-                    if (m >= A.n0[comp] && m <= A.last[comp]) {
-                        const cd* tp = A.tailpart[comp] + (size_t)(m - A.n0[comp]) * npair + a * NORB + c;
-                        for (int ch = 0; ch < A.ntailchunk[comp]; ++ch) sL = sL + tp[(size_t)ch * A.P * npair];
-                    }
+                    if (comp == 1 && m < A.ls[1]) sL = sL + p_tailcol(A, 1)[o];
+                    if (m >= A.n0[comp] && m <= A.last[comp])
+                        sL = sL + p_tailrow(A, comp)[(size_t)(m - A.n0[comp]) * npair + a * NORB + c];
                 }
                 // second lesser term: end weights (m >= k) or Newton-Cotes (m < k); the
                 // interval is empty at m = 0 (no bulk term was added there either)
@@ -570,13 +638,13 @@ __global__ void __launch_bounds__(64 * CombMap<NORB>::WAVES) hist_combine(HistAr
                 for (int i = 0; i <= imax; ++i) {
                     const int s = m - i;
                     const double wc = m < k ? A.W.nc[m][s] - w_start(A.W, s) : A.W.om[i] - 1.0;
-                    const cd* sl = A.sigL + (size_t)s * npair + a;
-                    const cd* bd = A.band + ((size_t)s * kb + i) * npair + c * NORB;
+                    const cd* sl = p_sigL(A) + (size_t)s * npair + a;
+                    const cd* bd = p_band(A) + ((size_t)s * kb + i) * npair + c * NORB;
 #pragma unroll
                     for (int bb = 0; bb < NORB; ++bb)
                         fmac_(sL, sl[bb * NORB], mk(-wc, 0.0) * conj(bd[bb]));
                 }
-                A.outL[o] = A.h * sL;
+                p_outL(A)[o] = A.h * sL;
             }
         }
     }
@@ -595,16 +663,16 @@ template <int NORB>
 hipError_t launch_t(const HistArgs& a, hipStream_t st, hipEvent_t* ev) {
     const int ntask = a.nfpad + a.nleaftask + a.ntailtask;
     if (ev) hipEventRecord(ev[0], st);
-    if (ntask > 0) hist_tasks<NORB><<<ntask, NT, tasks_smem(NORB), st>>>(a);
+    if (ntask > 0) hist_tasks<NORB><<<dim3(ntask, a.nk), NT, tasks_smem(NORB), st>>>(a);
     if (ev) hipEventRecord(ev[1], st);
-    if (a.nf[0] + a.nf[1] > 0) {
-        const long long nthr = 4LL * a.nb * a.npair * NORB * a.RC;
-        proj_reduce<NORB><<<(unsigned)((nthr + 255) / 256), 256, 0, st>>>(a);
+    {
+        const long long nb1 = proj_reduce_blocks(a), nb2 = (2LL * a.P * NORB * NORB + 3) / 4;
+        proj_reduce<NORB><<<dim3((unsigned)(nb1 + nb2), a.nk), 256, 0, st>>>(a);
     }
     if (ev) hipEventRecord(ev[2], st);
     using M = CombMap<NORB>;
     const int nblk = (a.n + 1 + M::MW - 1) / M::MW;
-    hist_combine<NORB><<<nblk, 64 * M::WAVES, 0, st>>>(a);
+    hist_combine<NORB><<<dim3(nblk, a.nk), 64 * M::WAVES, 0, st>>>(a);
     if (ev) hipEventRecord(ev[3], st);
     return hipGetLastError();
 }

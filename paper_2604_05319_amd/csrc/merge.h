@@ -50,9 +50,11 @@ struct MergeArgs {
     double* Sold;  // [problem][W]
     int* rold;     // [problem]
     int* err;      // device error flags (bit 0: rank cap reached)
+    // batched objects (grid dimension y): element strides from one object to the next
+    long long kU, kV, kS, kRank, kSrc, kNodeR, kNodeQ, kNodeCnt, kProbW2, kProbW, kProb;
 };
 
-hipError_t launch_merge(const MergeArgs& a, hipStream_t st);
+hipError_t launch_merge(const MergeArgs& a, int nk, hipStream_t st);
 hipError_t merge_init();
 
 }  // namespace hn

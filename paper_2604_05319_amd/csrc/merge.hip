@@ -209,6 +209,22 @@ __device__ __attribute__((noinline)) void jacobi_svd(cd* M, cd* J, int n, int* f
     __syncthreads();
 }
 
+// per-object data of object blockIdx.y of a batch (the kernel arguments
+// hold object 0 and the strides)
+#define OBJ ((long long)blockIdx.y)
+__device__ inline cd* m_U(const MergeArgs& a) { return a.U + OBJ * a.kU; }
+__device__ inline cd* m_V(const MergeArgs& a) { return a.V + OBJ * a.kV; }
+__device__ inline double* m_S(const MergeArgs& a) { return a.S + OBJ * a.kS; }
+__device__ inline int* m_rank(const MergeArgs& a) { return a.rank + OBJ * a.kRank; }
+__device__ inline const cd* m_src(const MergeArgs& a) { return a.src + OBJ * a.kSrc; }
+__device__ inline cd* m_nodeR(const MergeArgs& a) { return a.nodeR + OBJ * a.kNodeR; }
+__device__ inline cd* m_nodeQ(const MergeArgs& a) { return a.nodeQ + OBJ * a.kNodeQ; }
+__device__ inline int* m_nodecnt(const MergeArgs& a) { return a.nodecnt + OBJ * a.kNodeCnt; }
+__device__ inline cd* m_UK(const MergeArgs& a) { return a.UK + OBJ * a.kProbW2; }
+__device__ inline cd* m_VR(const MergeArgs& a) { return a.VR + OBJ * a.kProbW2; }
+__device__ inline double* m_Sold(const MergeArgs& a) { return a.Sold + OBJ * a.kProbW; }
+__device__ inline int* m_rold(const MergeArgs& a) { return a.rold + OBJ * a.kProb; }
+
 // ranks come from device memory; every index derived from them is kept
 // inside the capacity the host allocated, whatever the memory holds
 __device__ inline int clamp_rank(int r, int cap) { return r < 0 ? 0 : (r > cap ? cap : r); }
@@ -254,7 +270,7 @@ __device__ void chunk_qr(const MergeArgs& a, const Ctx& c, int r_old, const doub
     const int w = r_old + a.pp;
     const int row0 = c.chunk * kCH;
     const int nr = min(kCH, B.ncols - row0);
-    const cd* V = a.V + B.Voff + (size_t)c.q * a.RC * B.ncols;
+    const cd* V = m_V(a) + B.Voff + (size_t)c.q * a.RC * B.ncols;
     for (int idx = threadIdx.x; idx < kCH * w; idx += NT) {
         int col = idx / kCH, i = idx % kCH;
         cd z = mk(0.0, 0.0);
@@ -264,7 +280,7 @@ __device__ void chunk_qr(const MergeArgs& a, const Ctx& c, int r_old, const doub
                 z = s_old[col] * V[(size_t)col * B.ncols + s];
             } else {
                 int pr = col - r_old;
-                z = conj(a.src[(size_t)pr * a.src_row + (size_t)c.q * a.src_pair + B.c0 + s]);
+                z = conj(m_src(a)[(size_t)pr * a.src_row + (size_t)c.q * a.src_pair + B.c0 + s]);
             }
         }
         A[idx] = z;
@@ -291,17 +307,17 @@ __global__ void __launch_bounds__(NT) merge_up_kernel(MergeArgs a) {
     const MergeBlk& B = *c.B;
     const size_t pidx = prob_index(a, c);
     const size_t fq = (size_t)B.b * a.npair + c.q;
-    const int r_old = clamp_rank(a.rank[fq], a.RC);
+    const int r_old = clamp_rank(m_rank(a)[fq], a.RC);
     const int w = r_old + a.pp;
-    for (int i = threadIdx.x; i < W; i += NT) s_old[i] = i < r_old ? a.S[fq * a.RC + i] : 0.0;
+    for (int i = threadIdx.x; i < W; i += NT) s_old[i] = i < r_old ? m_S(a)[fq * a.RC + i] : 0.0;
     __syncthreads();
 
     chunk_qr<W>(a, c, r_old, s_old, A, tau, red);
 
     const long long nbase = B.node_base + (long long)c.q * B.nnodes;
-    cd* nodeR = a.nodeR + (size_t)nbase * W * W;
-    cd* nodeQ = a.nodeQ + (size_t)nbase * kNodeQ;
-    int* nodecnt = a.nodecnt + nbase;
+    cd* nodeR = m_nodeR(a) + (size_t)nbase * W * W;
+    cd* nodeQ = m_nodeQ(a) + (size_t)nbase * kNodeQ;
+    int* nodecnt = m_nodecnt(a) + nbase;
     {
         cd* dst = nodeR + (size_t)c.chunk * W * W;
         for (int e = threadIdx.x; e < W * W; e += NT) {
@@ -390,13 +406,13 @@ __global__ void __launch_bounds__(NT) merge_up_kernel(MergeArgs a) {
         rnew = a.RC;
     }
     if (threadIdx.x == 0) {
-        a.rold[pidx] = r_old;
-        a.rank[fq] = rnew;
+        m_rold(a)[pidx] = r_old;
+        m_rank(a)[fq] = rnew;
     }
-    for (int i = threadIdx.x; i < W; i += NT) a.Sold[pidx * W + i] = s_old[i];
-    for (int i = threadIdx.x; i < a.RC; i += NT) a.S[fq * a.RC + i] = i < rnew ? ssig[sperm[i]] : 0.0;
-    cd* UK = a.UK + pidx * W * W;
-    cd* VR = a.VR + pidx * W * W;
+    for (int i = threadIdx.x; i < W; i += NT) m_Sold(a)[pidx * W + i] = s_old[i];
+    for (int i = threadIdx.x; i < a.RC; i += NT) m_S(a)[fq * a.RC + i] = i < rnew ? ssig[sperm[i]] : 0.0;
+    cd* UK = m_UK(a) + pidx * W * W;
+    cd* VR = m_VR(a) + pidx * W * W;
     for (int e = threadIdx.x; e < w * rnew; e += NT) {
         int col = e / w, i = e % w;
         int src = min(max(sperm[col], 0), ne - 1);
@@ -421,20 +437,20 @@ __global__ void __launch_bounds__(NT) merge_down_kernel(MergeArgs a) {
         const MergeBlk& B = *c.B;
         const size_t pidx = prob_index(a, c);
         const size_t fq = (size_t)B.b * a.npair + c.q;
-        const int r_old = clamp_rank(a.rold[pidx], a.RC);
-        const int rnew = clamp_rank(a.rank[fq], a.RC);
+        const int r_old = clamp_rank(m_rold(a)[pidx], a.RC);
+        const int rnew = clamp_rank(m_rank(a)[fq], a.RC);
         const int w = r_old + a.pp;
-        for (int i = threadIdx.x; i < W; i += NT) s_old[i] = a.Sold[pidx * W + i];
+        for (int i = threadIdx.x; i < W; i += NT) s_old[i] = m_Sold(a)[pidx * W + i];
         __syncthreads();
         chunk_qr<W>(a, c, r_old, s_old, A, tau, red);
-        const cd* VR = a.VR + pidx * W * W;
+        const cd* VR = m_VR(a) + pidx * W * W;
         for (int e = threadIdx.x; e < W * W; e += NT) {
             int col = e / W, i = e % W;
             T[e] = (col < rnew && i < w) ? VR[(size_t)col * W + i] : mk(0.0, 0.0);
         }
         __syncthreads();
         const long long nbase = B.node_base + (long long)c.q * B.nnodes;
-        const cd* nodeQ = a.nodeQ + (size_t)nbase * kNodeQ;
+        const cd* nodeQ = m_nodeQ(a) + (size_t)nbase * kNodeQ;
         int depth = 0;
         for (int cnt = B.nchunks; cnt > 1; cnt = (cnt + 1) / 2) ++depth;
         for (int L = depth; L >= 1; --L) {
@@ -466,7 +482,7 @@ __global__ void __launch_bounds__(NT) merge_down_kernel(MergeArgs a) {
         hh_apply_q<W>(A, CH, w, tau, X, rnew);
         const int row0 = c.chunk * CH;
         const int nr = min(CH, B.ncols - row0);
-        cd* V = a.V + B.Voff + (size_t)c.q * a.RC * B.ncols;
+        cd* V = m_V(a) + B.Voff + (size_t)c.q * a.RC * B.ncols;
         for (int e = threadIdx.x; e < nr * rnew; e += NT) {
             int col = e / nr, i = e % nr;
             V[(size_t)col * B.ncols + row0 + i] = X[(size_t)col * CH + i];
@@ -482,10 +498,10 @@ __global__ void __launch_bounds__(NT) merge_down_kernel(MergeArgs a) {
     const int q = local / B.nutask, ut = local % B.nutask;
     const size_t pidx = (size_t)s * a.npair + q;
     const size_t fq = (size_t)B.b * a.npair + q;
-    const int r_old = clamp_rank(a.rold[pidx], a.RC);
-    const int rnew = clamp_rank(a.rank[fq], a.RC);
-    const cd* UK = a.UK + pidx * W * W;
-    cd* U = a.U + B.Uoff + (size_t)q * a.RC * B.ldU;
+    const int r_old = clamp_rank(m_rold(a)[pidx], a.RC);
+    const int rnew = clamp_rank(m_rank(a)[fq], a.RC);
+    const cd* UK = m_UK(a) + pidx * W * W;
+    cd* U = m_U(a) + B.Uoff + (size_t)q * a.RC * B.ldU;
     const int row = ut * NT + threadIdx.x;
     const int nrows = B.kb + a.pp;
     if (row >= nrows) return;
@@ -514,10 +530,10 @@ static size_t merge_down_smem() {
            (size_t)kW * sizeof(cd) + 8 * sizeof(double);
 }
 
-hipError_t launch_merge(const MergeArgs& a, hipStream_t st) {
+hipError_t launch_merge(const MergeArgs& a, int nk, hipStream_t st) {
     if (a.ntask_v == 0) return hipSuccess;
-    merge_up_kernel<<<a.ntask_v, NT, merge_up_smem(), st>>>(a);
-    merge_down_kernel<<<a.ntask_v + a.ntask_u, NT, merge_down_smem(), st>>>(a);
+    merge_up_kernel<<<dim3(a.ntask_v, nk), NT, merge_up_smem(), st>>>(a);
+    merge_down_kernel<<<dim3(a.ntask_v + a.ntask_u, nk), NT, merge_down_smem(), st>>>(a);
     return hipGetLastError();
 }
 

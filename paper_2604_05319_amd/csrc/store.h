@@ -13,9 +13,11 @@ struct AppendArgs {
     cd* leaf;       // leaf triangle base (pair 0)
     cd* tail;       // tail base
     cd* band;       // retarded band or nullptr
+    // batched objects (grid dimension y): element strides from one object to the next
+    long long kRow, kLeaf, kTail, kBand;
 };
 
-hipError_t launch_append_hodlr(const AppendArgs& a, hipStream_t st);
+hipError_t launch_append_hodlr(const AppendArgs& a, int nk, hipStream_t st);
 hipError_t launch_append_dense(cd* dst, const cd* row, int n, int npair, long long trin,
                                hipStream_t st);
 

@@ -18,14 +18,15 @@ __global__ void append_hodlr_kernel(AppendArgs a) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long total = (long long)(a.n + 1) * a.npair;
     if (e >= total) return;
+    const long long o = blockIdx.y;   // object of the batch
     const int j = (int)(e / a.npair), q = (int)(e % a.npair);
-    const cd v = a.row[e];
+    const cd v = a.row[o * a.kRow + e];
     if (j >= a.ls) {
-        a.leaf[(size_t)q * tri(a.lw) + tri(a.n - a.ls) + (j - a.ls)] = v;
+        a.leaf[o * a.kLeaf + (size_t)q * tri(a.lw) + tri(a.n - a.ls) + (j - a.ls)] = v;
     } else {
-        a.tail[((size_t)a.slot * a.npair + q) * a.nt + j] = v;
+        a.tail[o * a.kTail + ((size_t)a.slot * a.npair + q) * a.nt + j] = v;
     }
-    if (a.band && a.n - j <= a.k) a.band[((size_t)j * (a.k + 1) + (a.n - j)) * a.npair + q] = v;
+    if (a.band && a.n - j <= a.k) a.band[o * a.kBand + ((size_t)j * (a.k + 1) + (a.n - j)) * a.npair + q] = v;
 }
 
 __global__ void append_dense_kernel(cd* dst, const cd* row, int n, int npair, long long trin) {
@@ -36,10 +37,10 @@ __global__ void append_dense_kernel(cd* dst, const cd* row, int n, int npair, lo
     dst[(size_t)q * trin + tri(n) + j] = row[e];
 }
 
-hipError_t launch_append_hodlr(const AppendArgs& a, hipStream_t st) {
+hipError_t launch_append_hodlr(const AppendArgs& a, int nk, hipStream_t st) {
     const long long total = (long long)(a.n + 1) * a.npair;
     const int nb = (int)((total + 255) / 256);
-    append_hodlr_kernel<<<nb, 256, 0, st>>>(a);
+    append_hodlr_kernel<<<dim3(nb, nk), 256, 0, st>>>(a);
     return hipGetLastError();
 }
 
