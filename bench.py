@@ -51,18 +51,22 @@ def algorithmic_bytes(N, npair, P, blocks, leaves, ranks, steps, nk=1):
     combine: every stored factor row once (the expansions), and the two output rows.
     """
     import numpy as np
+    leaves = [(int(a), int(b)) for a, b in leaves]
+    blocks = [tuple(int(x) for x in blk) for blk in blocks]
     n0s, row_leaf = panel_schedule(N, P, leaves)
     zb = 16  # complex128
     # per block: sum of ranks over pairs (and objects)
-    rsum = [ranks[c].reshape(-1, ranks[c].shape[-2], ranks[c].shape[-1]).sum(axis=(0, 2)) for c in (0, 1)]
+    rsum = [[int(x) for x in ranks[c].reshape(-1, ranks[c].shape[-2], ranks[c].shape[-1]).sum(axis=(0, 2))]
+            for c in (0, 1)]
     tasks, comb = [], []
     for n in steps:
+        n = int(n)
         n0 = n0s[n]
         fac = 0
         for c in (0, 1):
             for b, (lvl, r0, r1, c0, c1) in enumerate(blocks):
                 if n0 > r0:
-                    fac += int(rsum[c][b]) * (min(n0 - r0, r1 - r0) + (c1 - c0)) * zb
+                    fac += rsum[c][b] * (min(n0 - r0, r1 - r0) + (c1 - c0)) * zb
         lf = 0
         for (s0, s1) in leaves:
             if s0 <= n:
@@ -74,8 +78,8 @@ def algorithmic_bytes(N, npair, P, blocks, leaves, ranks, steps, nk=1):
             ls = leaves[row_leaf[n0]][0]
             tail = 2 * (n - n0 + 1) * ls * npair * zb * nk
         rows = 2 * (n + 1) * npair * zb * nk
-        tasks.append(fac + lf + tail + rows)
-        comb.append(fac + rows)
+        tasks.append(float(fac + lf + tail + rows))
+        comb.append(float(fac + rows))
     return np.array(tasks, dtype=np.float64), np.array(comb, dtype=np.float64)
 
 
