@@ -69,6 +69,15 @@ typedef enum {
 
 /* Flags for hnessi_hodlr_create. */
 #define HNESSI_FLAG_NONE 0
+/* The history kernels read complex-float mirrors of the low-rank factors U
+ * and V (half the factor bytes of every step), the precision split whose
+ * error amplification the paper discusses next to the choice of eps_SVD.  The
+ * merges keep working on the FP64 factors and refresh both copies, so FP32
+ * rounding never enters a truncation (it would otherwise show up as singular
+ * values near 6e-8 * sigma_max, above an absolute eps_SVD); leaves, dense
+ * rows, band, singular values and all arithmetic stay FP64.  The added
+ * relative error of I is about 1e-7, below 1e-5. */
+#define HNESSI_FLAG_FP32_FACTORS 1
 
 /* Message for the last failing call on this host thread (never NULL). */
 const char* hnessi_last_error(void);
@@ -96,6 +105,7 @@ int hnessi_weights(int k, int L, double* w_host);
  *            every leaf start, so it need not divide the leaf size.
  *   max_rank rank capacity per block and orbital pair; max_rank + panel <= 32
  *            (the width of the small SVD solved at each merge).
+ *   flags    HNESSI_FLAG_NONE or HNESSI_FLAG_FP32_FACTORS.
  * Every leaf must hold at most 64 rows.
  * Allocates all device storage (synchronously).  On success *out is set. */
 int hnessi_hodlr_create(hnessi_hodlr_t* out, int nt, int nlvl, int norb, int k,

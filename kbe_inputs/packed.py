@@ -72,3 +72,46 @@ def row_of(packed, n: int):
     """View of row n of a packed triangle."""
     a = n * (n + 1) // 2
     return packed[a:a + n + 1]
+
+
+class RowSource:
+    """Rows of C^R and C^< generated on a device one step at a time, for grids whose
+    packed triangles do not fit in memory (norb = 16, N = 8192: 137 GB per triangle).
+
+    The retarded part depends on t_n - t_j only, so row n is the contiguous slice
+    [N-1-n, N) of one reversed table of C^R(d h, 0), d = 0..N-1.  The lesser part
+    factorizes per term into a function of t_s times a function of t_n; row n is
+    (E[:n+1] * c(n)) @ H with E[s, p] = exp(-(i w_p + g_p / 2) t_s) tabulated once.
+    Input construction only.
+    """
+
+    def __init__(self, p: DampedExpSum, N: int, h: float, device):
+        import torch
+        self.N, self.h, self.norb = N, h, p.norb
+        P, npair = p.nterms, p.norb * p.norb
+        dev = torch.device(device)
+        omega = torch.as_tensor(p.omega, dtype=torch.float64, device=dev)
+        gamma = torch.as_tensor(p.gamma, dtype=torch.float64, device=dev)
+        self.fermi = torch.as_tensor(p.fermi, dtype=torch.float64, device=dev)
+        amp = torch.as_tensor(p.amp.reshape(P, npair), dtype=torch.complex128, device=dev)
+        self.hamp = torch.as_tensor(p.herm_amp.reshape(P, npair), dtype=torch.complex128, device=dev)
+        self.omega, self.gamma = omega, gamma
+        t = torch.arange(N, dtype=torch.float64, device=dev) * h
+        tau = t.flip(0)[:, None]                                   # (N-1-i) h at index i
+        ph = torch.exp(torch.complex(-gamma[None, :] * tau, -omega[None, :] * tau))
+        self.ret_rev = ((-1j) * (ph @ amp)).reshape(N, p.norb, p.norb).contiguous()
+        self.E = torch.exp(torch.complex(-0.5 * gamma[None, :] * t[:, None], -omega[None, :] * t[:, None]))
+        self.buf = torch.empty((N, p.norb, p.norb), dtype=torch.complex128, device=dev)
+
+    def ret(self, n: int):
+        """C^R(t_n, t_j), j = 0..n (a view)."""
+        return self.ret_rev[self.N - 1 - n:]
+
+    def les(self, n: int, out=None):
+        """C^<(t_s, t_n), s = 0..n, written into out (default: an internal buffer)."""
+        import torch
+        tn = n * self.h
+        coef = 1j * self.fermi * torch.exp(torch.complex(-0.5 * self.gamma * tn, self.omega * tn))
+        dst = self.buf if out is None else out
+        torch.matmul(self.E[:n + 1] * coef[None, :], self.hamp, out=dst[:n + 1].view(n + 1, -1))
+        return dst[:n + 1]

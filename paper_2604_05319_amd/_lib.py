@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhnessi.so")
 
 RET, LES = 0, 1
+FLAG_FP32_FACTORS = 1   # U, V stored as complex float
 
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_ORDER", -3: "E_RANGE", -4: "E_NOMEM", -5: "E_DEVICE",
           -6: "E_RANK", -7: "E_VALUE"}

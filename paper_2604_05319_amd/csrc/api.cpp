@@ -148,8 +148,11 @@ struct hnessi_hodlr_s {
     long long* d_Loff = nullptr;
     std::vector<long long> Uoff, Voff, Loff;
     // per component
-    cd* U[2] = {};
+    bool f32 = false;    // complex-float mirrors of the factors feed the history kernels
+    cd* U[2] = {};       // FP64 factors (merges, reconstruction)
     cd* V[2] = {};
+    cf* U32[2] = {};     // mirrors, or nullptr
+    cf* V32[2] = {};
     double* S[2] = {};
     int* rank[2] = {};
     cd* leaf[2] = {};
@@ -220,6 +223,7 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
     if (!out) return fail(HNESSI_E_ARG, "out is NULL");
     *out = nullptr;
     if (nk < 1 || nk > 65535) return fail(HNESSI_E_ARG, "nk must be in 1..65535");
+    if (flags & ~HNESSI_FLAG_FP32_FACTORS) return fail(HNESSI_E_ARG, "unknown flags");
     if (!(norb == 1 || norb == 2 || norb == 4 || norb == 8 || norb == 16))
         return fail(HNESSI_E_ARG, "norb must be 1, 2, 4, 8 or 16");
     if (!(svd_tol > 0.0)) return fail(HNESSI_E_ARG, "svd_tol must be > 0");
@@ -252,6 +256,7 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
     H->P = panel;
     H->RC = max_rank;
     H->flags = flags;
+    H->f32 = (flags & HNESSI_FLAG_FP32_FACTORS) != 0;
     H->tol = svd_tol;
     const int npair = H->npair, RC = H->RC, nb = g.nb;
     Allocs& al = H->al;
@@ -305,6 +310,10 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
     for (int c = 0; c < 2; ++c) {
         HALLOC_K(H->U[c], uo, true, H->oU);
         HALLOC_K(H->V[c], vo, true, H->oV);
+        if (H->f32) {
+            HALLOC(H->U32[c], (size_t)uo * nk, true);
+            HALLOC(H->V32[c], (size_t)vo * nk, true);
+        }
         HALLOC_K(H->S[c], (size_t)std::max(nb, 1) * npair * RC, true, H->oS);
         HALLOC_K(H->rank[c], (size_t)std::max(nb, 1) * npair, true, H->oRank);
         HALLOC_K(H->leaf[c], lo, true, H->oLeaf);
@@ -440,6 +449,8 @@ int merge_panel(hnessi_hodlr_t H, int c, int p0, int p1, hipStream_t st) {
     a.tol = H->tol;
     a.U = H->U[c];
     a.V = H->V[c];
+    a.U32 = H->U32[c];
+    a.V32 = H->V32[c];
     a.S = H->S[c];
     a.rank = H->rank[c];
     a.src = H->tail[c];
@@ -550,8 +561,8 @@ int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, doub
     A.sigR = static_cast<const cd*>(sigR);
     A.sigL = static_cast<const cd*>(sigL);
     for (int c = 0; c < 2; ++c) {
-        A.U[c] = H->U[c];
-        A.V[c] = H->V[c];
+        A.U[c] = H->f32 ? (const void*)H->U32[c] : (const void*)H->U[c];
+        A.V[c] = H->f32 ? (const void*)H->V32[c] : (const void*)H->V[c];
         A.S[c] = H->S[c];
         A.rank[c] = H->rank[c];
         A.leaf[c] = H->leaf[c];
@@ -583,6 +594,7 @@ int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, doub
     A.outR = static_cast<cd*>(outR);
     A.outL = static_cast<cd*>(outL);
     A.nk = H->nk;
+    A.f32 = H->f32;
     A.kIn = in_stride;
     A.kOut = out_stride;
     A.kU = H->oU;

@@ -40,6 +40,20 @@ __host__ __device__ inline void fmac_(cd& acc, cd a, cd b) {
 
 __host__ __device__ inline long long tri(long long n) { return n * (n + 1) / 2; }
 
+// complex float: the storage type of the low-rank factors in the FP32-factor form
+struct cf {
+    float x, y;
+};
+// factor element <-> complex double (the arithmetic type of every kernel)
+__host__ __device__ inline cd to_cd(cd v) { return v; }
+__host__ __device__ inline cd to_cd(cf v) { return cd{(double)v.x, (double)v.y}; }
+template <class FT>
+__host__ __device__ inline FT from_cd(cd v);
+template <>
+__host__ __device__ inline cd from_cd<cd>(cd v) { return v; }
+template <>
+__host__ __device__ inline cf from_cd<cf>(cd v) { return cf{(float)v.x, (float)v.y}; }
+
 // ---------------------------------------------------------------------------
 // quadrature weights passed by value to kernels
 struct Weights {

@@ -24,8 +24,9 @@ struct HistArgs {
     Weights W;
     const cd* sigR;   // Sigma^R(n, j), j = 0..n
     const cd* sigL;   // Sigma^<(s, n), s = 0..n
-    const cd* U[2];
-    const cd* V[2];
+    int f32;          // factors stored as complex float (cf) instead of complex double
+    const void* U[2]; // factor storage, element type cd or cf
+    const void* V[2];
     const double* S[2];
     const int* rank[2];
     const cd* leaf[2];

@@ -58,8 +58,10 @@ __device__ inline const cd* p_sigR(const HistArgs& A) { return A.sigR + OBJ * A.
 __device__ inline const cd* p_sigL(const HistArgs& A) { return A.sigL ? A.sigL + OBJ * A.kIn : nullptr; }
 __device__ inline cd* p_outR(const HistArgs& A) { return A.outR ? A.outR + OBJ * A.kOut : nullptr; }
 __device__ inline cd* p_outL(const HistArgs& A) { return A.outL ? A.outL + OBJ * A.kOut : nullptr; }
-__device__ inline const cd* p_U(const HistArgs& A, int c) { return A.U[c] + OBJ * A.kU; }
-__device__ inline const cd* p_V(const HistArgs& A, int c) { return A.V[c] + OBJ * A.kV; }
+template <class FT>
+__device__ inline const FT* p_U(const HistArgs& A, int c) { return static_cast<const FT*>(A.U[c]) + OBJ * A.kU; }
+template <class FT>
+__device__ inline const FT* p_V(const HistArgs& A, int c) { return static_cast<const FT*>(A.V[c]) + OBJ * A.kV; }
 __device__ inline const double* p_S(const HistArgs& A, int c) { return A.S[c] + OBJ * A.kS; }
 __device__ inline const int* p_rank(const HistArgs& A, int c) { return A.rank[c] + OBJ * A.kRank; }
 __device__ inline const cd* p_leaf(const HistArgs& A, int c) { return A.leaf[c] + OBJ * A.kLeaf; }
@@ -110,7 +112,7 @@ struct ProjRanks {
 // scaled by S; the chunk partials are summed by proj_reduce.  Wave w takes the
 // ranks w, w+4, ... of a pass; its lanes run over the rows, kCH/64 rows each,
 // with every load of a pass independent of the others.
-template <int NORB>
+template <int NORB, class FT>
 __device__ void fact_task(const HistArgs& A, const FactTask& t, unsigned char* smem) {
     const int comp = t.comp, b = t.b, q = t.q, which = t.which;
     if (comp == 0 && which == 0 && !A.wantR) return;
@@ -126,17 +128,17 @@ __device__ void fact_task(const HistArgs& A, const FactTask& t, unsigned char* s
     const int* bk = A.blk + 5 * b;
     const int r0 = bk[1], r1 = bk[2], c0 = bk[3], c1 = bk[4];
     int len, base, ld;
-    const cd* F;
+    const FT* F;
     if (which == 0) {
         len = min(A.n0[comp] - r0, r1 - r0);
         base = r0;
         ld = r1 - r0;
-        F = p_U(A, comp) + A.Uoff[b] + (size_t)q * RC * ld;
+        F = p_U<FT>(A, comp) + A.Uoff[b] + (size_t)q * RC * ld;
     } else {
         len = c1 - c0;
         base = c0;
         ld = c1 - c0;
-        F = p_V(A, comp) + A.Voff[b] + (size_t)q * RC * ld;
+        F = p_V<FT>(A, comp) + A.Voff[b] + (size_t)q * RC * ld;
     }
     const int i0 = t.chunk * kCH, i1 = min(len, i0 + kCH);
     if (i0 >= i1) return;
@@ -159,7 +161,7 @@ __device__ void fact_task(const HistArgs& A, const FactTask& t, unsigned char* s
 #pragma unroll
             for (int k = 0; k < RW; ++k) {
                 const int i = i0 + u * 64 + lane, r = rp + wave + 4 * k;
-                cd f = F[(size_t)min(r, rk - 1) * ld + min(i, i1 - 1)];
+                cd f = to_cd(F[(size_t)min(r, rk - 1) * ld + min(i, i1 - 1)]);
                 if (cj) f = conj(f);
                 fr[u][k] = (i < i1 && r < rk) ? f : mk(0.0, 0.0);
             }
@@ -386,14 +388,14 @@ __device__ void tail_task(const HistArgs& A, int comp, int ag, int chunk, unsign
     }
 }
 
-template <int NORB>
+template <int NORB, class FT>
 __global__ void __launch_bounds__(NT) hist_tasks(HistArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NG = AGroups<NORB>::NG;
     const int id = blockIdx.x;
     if (id < A.nfpad) {
-        if (id < A.nf[0]) fact_task<NORB>(A, A.ft[0][id], smem);
-        else if (id - A.nf[0] < A.nf[1]) fact_task<NORB>(A, A.ft[1][id - A.nf[0]], smem);
+        if (id < A.nf[0]) fact_task<NORB, FT>(A, A.ft[0][id], smem);
+        else if (id - A.nf[0] < A.nf[1]) fact_task<NORB, FT>(A, A.ft[1][id - A.nf[0]], smem);
         return;
     }
     // leaf and tail sections start at multiples of 8, so workgroup id % 8 is
@@ -481,13 +483,13 @@ __global__ void __launch_bounds__(256) proj_reduce(HistArgs A) {
 // acc[a] (+|-)= op(F[r*ld]) z[a*RC + r] over r < rk, op = conj or identity.
 // The factor loads of a batch of eight ranks are issued together (indices
 // clamped to rk - 1, surplus terms skipped) so that they overlap in flight.
-template <int NORB, bool CONJ, bool NEG>
-__device__ inline void expand_ranks(cd (&acc)[NORB], const cd* F, int ld, const cd* z, int RC, int rk) {
+template <int NORB, bool CONJ, bool NEG, class FT>
+__device__ inline void expand_ranks(cd (&acc)[NORB], const FT* F, int ld, const cd* z, int RC, int rk) {
     constexpr int B = 8;
     for (int r0 = 0; r0 < rk; r0 += B) {
         cd f[B];
 #pragma unroll
-        for (int u = 0; u < B; ++u) f[u] = F[(size_t)min(r0 + u, rk - 1) * ld];
+        for (int u = 0; u < B; ++u) f[u] = to_cd(F[(size_t)min(r0 + u, rk - 1) * ld]);
 #pragma unroll
         for (int u = 0; u < B; ++u) {
             if (r0 + u >= rk) break;
@@ -515,7 +517,7 @@ struct CombMap {
     static constexpr int NCI = NORB / WAVES;
 };
 
-template <int NORB>
+template <int NORB, class FT>
 __global__ void __launch_bounds__(64 * CombMap<NORB>::WAVES) hist_combine(HistArgs A) {
     using M = CombMap<NORB>;
     constexpr int npair = NORB * NORB, G = M::G, MW = M::MW;
@@ -544,7 +546,7 @@ __global__ void __launch_bounds__(64 * CombMap<NORB>::WAVES) hist_combine(HistAr
                         for (int o = g; o < NORB; o += G) {
                             const int q = o * NORB + c;
                             const int rk = rank_of(A, 0, b, q);
-                            const cd* Vq = p_V(A, 0) + A.Voff[b] + (size_t)q * RC * ldV + (m - c0);
+                            const FT* Vq = p_V<FT>(A, 0) + A.Voff[b] + (size_t)q * RC * ldV + (m - c0);
                             const cd* z = p_proj(A) + proj_slot(A, 0, b, q, 0) * NORB * RC;
                             if (rk > 0) expand_ranks<NORB, true, false>(accR, Vq, ldV, z, RC, rk);
                         }
@@ -553,7 +555,7 @@ __global__ void __launch_bounds__(64 * CombMap<NORB>::WAVES) hist_combine(HistAr
                         for (int o = g; o < NORB; o += G) {
                             const int q = c * NORB + o;
                             const int rk = rank_of(A, 1, b, q);
-                            const cd* Vq = p_V(A, 1) + A.Voff[b] + (size_t)q * RC * ldV + (m - c0);
+                            const FT* Vq = p_V<FT>(A, 1) + A.Voff[b] + (size_t)q * RC * ldV + (m - c0);
                             const cd* z = p_proj(A) + proj_slot(A, 1, b, q, 0) * NORB * RC;
                             if (rk > 0) expand_ranks<NORB, false, true>(accL, Vq, ldV, z, RC, rk);
                         }
@@ -566,7 +568,7 @@ __global__ void __launch_bounds__(64 * CombMap<NORB>::WAVES) hist_combine(HistAr
                         for (int o = g; o < NORB; o += G) {
                             const int q = c * NORB + o;
                             const int rk = rank_of(A, 0, b, q);
-                            const cd* Uq = p_U(A, 0) + A.Uoff[b] + (size_t)q * RC * ldU + (m - r0);
+                            const FT* Uq = p_U<FT>(A, 0) + A.Uoff[b] + (size_t)q * RC * ldU + (m - r0);
                             const cd* z = p_proj(A) + proj_slot(A, 0, b, q, 1) * NORB * RC;
                             if (rk > 0) expand_ranks<NORB, true, false>(accL, Uq, ldU, z, RC, rk);
                         }
@@ -575,7 +577,7 @@ __global__ void __launch_bounds__(64 * CombMap<NORB>::WAVES) hist_combine(HistAr
                         for (int o = g; o < NORB; o += G) {
                             const int q = o * NORB + c;
                             const int rk = rank_of(A, 1, b, q);
-                            const cd* Uq = p_U(A, 1) + A.Uoff[b] + (size_t)q * RC * ldU + (m - r0);
+                            const FT* Uq = p_U<FT>(A, 1) + A.Uoff[b] + (size_t)q * RC * ldU + (m - r0);
                             const cd* z = p_proj(A) + proj_slot(A, 1, b, q, 1) * NORB * RC;
                             if (rk > 0) expand_ranks<NORB, false, false>(accL, Uq, ldU, z, RC, rk);
                         }
@@ -659,11 +661,11 @@ size_t tasks_smem(int norb) {
     return s > tail ? s : tail;
 }
 
-template <int NORB>
+template <int NORB, class FT>
 hipError_t launch_t(const HistArgs& a, hipStream_t st, hipEvent_t* ev) {
     const int ntask = a.nfpad + a.nleaftask + a.ntailtask;
     if (ev) hipEventRecord(ev[0], st);
-    if (ntask > 0) hist_tasks<NORB><<<dim3(ntask, a.nk), NT, tasks_smem(NORB), st>>>(a);
+    if (ntask > 0) hist_tasks<NORB, FT><<<dim3(ntask, a.nk), NT, tasks_smem(NORB), st>>>(a);
     if (ev) hipEventRecord(ev[1], st);
     {
         const long long nb1 = proj_reduce_blocks(a), nb2 = (2LL * a.P * NORB * NORB + 3) / 4;
@@ -672,20 +674,25 @@ hipError_t launch_t(const HistArgs& a, hipStream_t st, hipEvent_t* ev) {
     if (ev) hipEventRecord(ev[2], st);
     using M = CombMap<NORB>;
     const int nblk = (a.n + 1 + M::MW - 1) / M::MW;
-    hist_combine<NORB><<<dim3(nblk, a.nk), 64 * M::WAVES, 0, st>>>(a);
+    hist_combine<NORB, FT><<<dim3(nblk, a.nk), 64 * M::WAVES, 0, st>>>(a);
     if (ev) hipEventRecord(ev[3], st);
     return hipGetLastError();
+}
+
+template <int NORB>
+hipError_t launch_n(const HistArgs& a, hipStream_t st, hipEvent_t* ev) {
+    return a.f32 ? launch_t<NORB, cf>(a, st, ev) : launch_t<NORB, cd>(a, st, ev);
 }
 
 }  // namespace
 
 hipError_t launch_history(const HistArgs& a, hipStream_t st, hipEvent_t* ev) {
     switch (a.norb) {
-        case 1: return launch_t<1>(a, st, ev);
-        case 2: return launch_t<2>(a, st, ev);
-        case 4: return launch_t<4>(a, st, ev);
-        case 8: return launch_t<8>(a, st, ev);
-        case 16: return launch_t<16>(a, st, ev);
+        case 1: return launch_n<1>(a, st, ev);
+        case 2: return launch_n<2>(a, st, ev);
+        case 4: return launch_n<4>(a, st, ev);
+        case 8: return launch_n<8>(a, st, ev);
+        case 16: return launch_n<16>(a, st, ev);
         default: return hipErrorInvalidValue;
     }
 }
@@ -696,11 +703,16 @@ hipError_t history_init() {
         if (e == hipSuccess)
             e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tasks_smem(norb));
     };
-    set((const void*)hist_tasks<1>, 1);
-    set((const void*)hist_tasks<2>, 2);
-    set((const void*)hist_tasks<4>, 4);
-    set((const void*)hist_tasks<8>, 8);
-    set((const void*)hist_tasks<16>, 16);
+    set((const void*)hist_tasks<1, cd>, 1);
+    set((const void*)hist_tasks<1, cf>, 1);
+    set((const void*)hist_tasks<2, cd>, 2);
+    set((const void*)hist_tasks<2, cf>, 2);
+    set((const void*)hist_tasks<4, cd>, 4);
+    set((const void*)hist_tasks<4, cf>, 4);
+    set((const void*)hist_tasks<8, cd>, 8);
+    set((const void*)hist_tasks<8, cf>, 8);
+    set((const void*)hist_tasks<16, cd>, 16);
+    set((const void*)hist_tasks<16, cf>, 16);
     return e;
 }
 

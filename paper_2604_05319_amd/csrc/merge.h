@@ -34,8 +34,10 @@ struct MergeArgs {
     MergeBlk blk[kMaxMergeBlk];
     int ntask_v;   // chunk tasks (merge_up grid; first part of merge_down grid)
     int ntask_u;   // U-row tasks (second part of merge_down grid)
-    cd* U;
+    cd* U;         // FP64 factors (the merge works on these)
     cd* V;
+    cf* U32;       // complex-float mirrors of U and V read by the history kernels, or nullptr
+    cf* V32;
     double* S;
     int* rank;
     // panel row i, pair q, absolute column s at src[i*src_row + q*src_pair + s]

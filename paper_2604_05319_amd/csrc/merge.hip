@@ -214,6 +214,8 @@ __device__ __attribute__((noinline)) void jacobi_svd(cd* M, cd* J, int n, int* f
 #define OBJ ((long long)blockIdx.y)
 __device__ inline cd* m_U(const MergeArgs& a) { return a.U + OBJ * a.kU; }
 __device__ inline cd* m_V(const MergeArgs& a) { return a.V + OBJ * a.kV; }
+__device__ inline cf* m_U32(const MergeArgs& a) { return a.U32 ? a.U32 + OBJ * a.kU : nullptr; }
+__device__ inline cf* m_V32(const MergeArgs& a) { return a.V32 ? a.V32 + OBJ * a.kV : nullptr; }
 __device__ inline double* m_S(const MergeArgs& a) { return a.S + OBJ * a.kS; }
 __device__ inline int* m_rank(const MergeArgs& a) { return a.rank + OBJ * a.kRank; }
 __device__ inline const cd* m_src(const MergeArgs& a) { return a.src + OBJ * a.kSrc; }
@@ -482,10 +484,14 @@ __global__ void __launch_bounds__(NT) merge_down_kernel(MergeArgs a) {
         hh_apply_q<W>(A, CH, w, tau, X, rnew);
         const int row0 = c.chunk * CH;
         const int nr = min(CH, B.ncols - row0);
-        cd* V = m_V(a) + B.Voff + (size_t)c.q * a.RC * B.ncols;
+        const size_t vo = B.Voff + (size_t)c.q * a.RC * B.ncols;
+        cd* V = m_V(a) + vo;
+        cf* V32 = a.V32 ? m_V32(a) + vo : nullptr;
         for (int e = threadIdx.x; e < nr * rnew; e += NT) {
             int col = e / nr, i = e % nr;
-            V[(size_t)col * B.ncols + row0 + i] = X[(size_t)col * CH + i];
+            const cd x = X[(size_t)col * CH + i];
+            V[(size_t)col * B.ncols + row0 + i] = x;
+            if (V32) V32[(size_t)col * B.ncols + row0 + i] = from_cd<cf>(x);
         }
         return;
     }
@@ -501,7 +507,9 @@ __global__ void __launch_bounds__(NT) merge_down_kernel(MergeArgs a) {
     const int r_old = clamp_rank(m_rold(a)[pidx], a.RC);
     const int rnew = clamp_rank(m_rank(a)[fq], a.RC);
     const cd* UK = m_UK(a) + pidx * W * W;
-    cd* U = m_U(a) + B.Uoff + (size_t)q * a.RC * B.ldU;
+    const size_t uo = B.Uoff + (size_t)q * a.RC * B.ldU;
+    cd* U = m_U(a) + uo;
+    cf* U32 = a.U32 ? m_U32(a) + uo : nullptr;
     const int row = ut * NT + threadIdx.x;
     const int nrows = B.kb + a.pp;
     if (row >= nrows) return;
@@ -515,10 +523,15 @@ __global__ void __launch_bounds__(NT) merge_down_kernel(MergeArgs a) {
             for (int r = 0; r < W; ++r)
                 if (r < r_old) fma_(acc, u[r], UK[(size_t)col * W + r]);
             U[(size_t)col * B.ldU + row] = acc;
+            if (U32) U32[(size_t)col * B.ldU + row] = from_cd<cf>(acc);
         }
     } else {
         const int pr = r_old + (row - B.kb);
-        for (int col = 0; col < rnew; ++col) U[(size_t)col * B.ldU + row] = UK[(size_t)col * W + pr];
+        for (int col = 0; col < rnew; ++col) {
+            const cd x = UK[(size_t)col * W + pr];
+            U[(size_t)col * B.ldU + row] = x;
+            if (U32) U32[(size_t)col * B.ldU + row] = from_cd<cf>(x);
+        }
     }
 }
 
@@ -538,12 +551,11 @@ hipError_t launch_merge(const MergeArgs& a, int nk, hipStream_t st) {
 }
 
 hipError_t merge_init() {
-    hipError_t e = hipFuncSetAttribute((const void*)merge_up_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipError_t e = hipFuncSetAttribute((const void*)merge_up_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)merge_up_smem());
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)merge_down_kernel,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)merge_down_smem());
+    return hipFuncSetAttribute((const void*)merge_down_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)merge_down_smem());
 }
 
 }  // namespace hn
