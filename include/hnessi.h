@@ -135,6 +135,19 @@ int hnessi_history_R(hnessi_hodlr_t H, int n, const void* sigR_row, double h,
 int hnessi_history_lesser(hnessi_hodlr_t H, int n, const void* sigR_row,
                           const void* sigL_slice, double h, void* out, void* stream);
 
+/* Adjoint (vector-Jacobian product) of hnessi_history_R with respect to the
+ * Sigma^R row, for gradients of losses of I^R (adjoint form of the retarded
+ * equation's history term; the paper differentiates nothing, the operation is
+ * the transpose of the discrete sum of Eq. KBER's history integral):
+ *   out(j) = h sum_{m=0..j} w^{(n-m)}_{j-m} Ibar(n, m) G^R(t_j, t_m)^dagger,  j = 0..n,
+ * i.e. <Ibar, I^R> = <out, Sigma^R(n, .)> for the real inner product
+ * Re sum tr(A^dagger B).  ibar_row: device (n+1)*norb*norb complex128, the
+ * cotangent of I^R(n, m), m = 0..n; out: device, same size.  Needs the
+ * retarded row n appended (HNESSI_E_ORDER otherwise); reads only the
+ * retarded component. */
+int hnessi_history_R_adjoint(hnessi_hodlr_t H, int n, const void* ibar_row, double h, void* out,
+                             void* stream);
+
 /* Both integrals of step n in one pass over the stored data (each stored
  * factor is used for every product it enters).  outR / outL as above. */
 int hnessi_history_step(hnessi_hodlr_t H, int n, const void* sigR_row, const void* sigL_slice,

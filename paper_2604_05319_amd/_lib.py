@@ -50,6 +50,8 @@ _SIGS = {
     "hnessi_history_R": ([C.c_void_p, C.c_int, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p], C.c_int),
     "hnessi_history_lesser": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p,
                                C.c_void_p], C.c_int),
+    "hnessi_history_R_adjoint": ([C.c_void_p, C.c_int, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p],
+                                 C.c_int),
     "hnessi_history_step": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p,
                              C.c_void_p, C.c_void_p], C.c_int),
     "hnessi_sweep": ([C.c_void_p, C.c_int, C.c_int] + [C.c_void_p] * 4 + [C.c_double]
@@ -176,6 +178,10 @@ class Hodlr:
     def history_step(self, n, sigR, sigL, h, outR, outL):
         _check(lib().hnessi_history_step(self.h, n, _ptr(sigR), _ptr(sigL), h, _ptr(outR), _ptr(outL),
                                          _stream()))
+
+    def history_R_adjoint(self, n, ibar, h, out):
+        """out(j) = h sum_{m<=j} w^{(n-m)}_{j-m} ibar(m) G^R(j,m)^dagger, j = 0..n."""
+        _check(lib().hnessi_history_R_adjoint(self.h, n, _ptr(ibar), h, _ptr(out), _stream()))
 
     def sweep(self, n_begin, n_end, GR, GL, SR, SL, h, IR, IL):
         _check(lib().hnessi_sweep(self.h, n_begin, n_end, _ptr(GR), _ptr(GL), _ptr(SR), _ptr(SL), h,

@@ -522,13 +522,14 @@ bool panel_ends(hnessi_hodlr_t H, int c, int n) {
 
 int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, double h, void* outR,
                void* outL, bool wantR, bool wantL, hipStream_t st, long long in_stride = 0,
-               long long out_stride = 0) {
+               long long out_stride = 0, bool adj = false) {
     if (n < 0 || n >= H->nt) return fail(HNESSI_E_RANGE, "n outside the grid");
-    if (!sigR) return fail(HNESSI_E_ARG, "sigR_row is NULL");
+    if (!sigR && !adj) return fail(HNESSI_E_ARG, "sigR_row is NULL");
     if (wantR && !outR) return fail(HNESSI_E_ARG, "output is NULL");
-    if (wantL && (!outL || !sigL)) return fail(HNESSI_E_ARG, "lesser input or output is NULL");
+    if (wantL && (!outL || !sigL)) return fail(HNESSI_E_ARG, "input or output is NULL");
     if (H->last[0] != n) return fail(HNESSI_E_ORDER, "retarded row n has not been appended (or later rows have)");
-    if (wantL && H->last[1] != n) return fail(HNESSI_E_ORDER, "lesser row n has not been appended (or later rows have)");
+    if (wantL && !adj && H->last[1] != n)
+        return fail(HNESSI_E_ORDER, "lesser row n has not been appended (or later rows have)");
     const Geometry& g = H->g;
     HistArgs A{};
     A.n = n;
@@ -538,7 +539,7 @@ int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, doub
         A.ls[c] = 0;
         A.ntailchunk[c] = 0;
         A.nf[c] = 0;
-        bool use = (c == 0) || wantL;
+        bool use = (c == 0) || (wantL && !adj);
         if (!use) continue;
         A.nf[c] = (int)(std::lower_bound(H->ft_act[c].begin(), H->ft_act[c].end(), H->n0[c]) -
                         H->ft_act[c].begin());
@@ -556,6 +557,7 @@ int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, doub
     A.P = H->P;
     A.wantR = wantR;
     A.wantL = wantL;
+    A.adj = adj;
     A.h = h;
     A.W = H->W;
     A.sigR = static_cast<const cd*>(sigR);
@@ -710,6 +712,12 @@ int hnessi_history_step(hnessi_hodlr_t H, int n, const void* sigR_row, const voi
     int rc = single_only(H);
     if (rc != HNESSI_OK) return rc;
     return do_history(H, n, sigR_row, sigL_slice, h, outR, outL, true, true, (hipStream_t)stream);
+}
+
+int hnessi_history_R_adjoint(hnessi_hodlr_t H, int n, const void* ibar_row, double h, void* out, void* stream) {
+    int rc = single_only(H);
+    if (rc != HNESSI_OK) return rc;
+    return do_history(H, n, nullptr, ibar_row, h, nullptr, out, false, true, (hipStream_t)stream, 0, 0, true);
 }
 
 int hnessi_history_step_batched(hnessi_hodlr_t H, int n, const void* sigR_rows, const void* sigL_slices,

@@ -20,6 +20,7 @@ struct HistArgs {
     int nt, norb, npair, RC, nlvl, nb, P;
     int nk;         // objects in the batch (grid dimension y)
     int wantR, wantL;
+    int adj;        // adjoint of I^R: sigL holds Ibar(n, m) rows, outL receives dI/dSigma^R (see launch_history)
     double h;
     Weights W;
     const cd* sigR;   // Sigma^R(n, j), j = 0..n
@@ -63,6 +64,13 @@ struct HistArgs {
     long long kProj, kPart, kLeafOut, kTailcol, kTailpart, kTailrow;
 };
 
+// Adjoint mode (adj = 1, wantR = 0, wantL = 1): the comp-0 row-dot path of the
+// second lesser term is driven by x(m) = Ibar(n, m) instead of the folded
+// Sigma^< slice, which gives y(j) = sum_{m<=j} Ibar(n,m) G^R(j,m)^dagger; the
+// combine scales it by the end weight of j and adds the start / short-interval
+// corrections, so outL(j) = h sum_{m<=j} w^{(n-m)}_{j-m} Ibar(n,m) G^R(j,m)^dagger.
+// The lesser component is not touched.
+//
 // ev: nullptr, or four events recorded before hist_tasks, after it, after
 // proj_reduce and after hist_combine (per-kernel timing on the launch stream)
 hipError_t launch_history(const HistArgs& a, hipStream_t st, hipEvent_t* ev = nullptr);

@@ -54,7 +54,7 @@ __device__ inline void add_at(cd (&acc)[N], int idx, cd v) {
 // per-object data of object blockIdx.y of a batch (the kernel arguments
 // hold object 0 and the strides)
 #define OBJ ((long long)blockIdx.y)
-__device__ inline const cd* p_sigR(const HistArgs& A) { return A.sigR + OBJ * A.kIn; }
+__device__ inline const cd* p_sigR(const HistArgs& A) { return A.sigR ? A.sigR + OBJ * A.kIn : nullptr; }
 __device__ inline const cd* p_sigL(const HistArgs& A) { return A.sigL ? A.sigL + OBJ * A.kIn : nullptr; }
 __device__ inline cd* p_outR(const HistArgs& A) { return A.outR ? A.outR + OBJ * A.kOut : nullptr; }
 __device__ inline cd* p_outL(const HistArgs& A) { return A.outL ? A.outL + OBJ * A.kOut : nullptr; }
@@ -117,6 +117,7 @@ __device__ void fact_task(const HistArgs& A, const FactTask& t, unsigned char* s
     const int comp = t.comp, b = t.b, q = t.q, which = t.which;
     if (comp == 0 && which == 0 && !A.wantR) return;
     if ((comp == 1 || which == 1) && !A.wantL) return;
+    if (comp == 1 && A.adj) return;
     constexpr int npair = NORB * NORB;
     constexpr bool kStage = NORB <= 8;             // Sigma rows staged in LDS
     constexpr int RW = ProjRanks<NORB>::RW;
@@ -147,7 +148,10 @@ __device__ void fact_task(const HistArgs& A, const FactTask& t, unsigned char* s
     auto xval = [&](int i, int a) -> cd {
         const int j = base + i;
         if (comp == 0 && which == 0) return w_end(A.W, n, j) * p_sigR(A)[(size_t)j * npair + a * NORB + qr];
-        if (comp == 0) return -w_start(A.W, j) * conj(p_sigL(A)[(size_t)j * npair + qc * NORB + a]);
+        if (comp == 0) {
+            if (A.adj) return p_sigL(A)[(size_t)j * npair + a * NORB + qc];   // Ibar(n, j)[a][qc]
+            return -w_start(A.W, j) * conj(p_sigL(A)[(size_t)j * npair + qc * NORB + a]);
+        }
         return interval_w(A.W, n, j) * p_sigR(A)[(size_t)j * npair + a * NORB + (which == 0 ? qc : qr)];
     };
     const bool cj = (comp == 1);
@@ -216,7 +220,7 @@ __device__ void fact_task(const HistArgs& A, const FactTask& t, unsigned char* s
 // dot (columns s <= m) of lane m run in one loop over LDS.
 template <int NORB>
 __device__ void leaf_task(const HistArgs& A, int leaf, int comp, int ag, int pg, unsigned char* smem) {
-    if (comp == 1 && !A.wantL) return;
+    if (comp == 1 && (!A.wantL || A.adj)) return;
     constexpr int npair = NORB * NORB, AG = AGroups<NORB>::AG;
     constexpr int PPG = npair / LeafGroups<NORB>::LG;   // orbital pairs per group
     const int n = A.n;
@@ -243,8 +247,10 @@ __device__ void leaf_task(const HistArgs& A, int leaf, int comp, int ag, int pg,
         for (int e = threadIdx.x; e < nrow * AG; e += NT) {
             const int i = e / AG, aa = ag * AG + e % AG, j = s0 + i;
             if (comp == 0) {
-                xa[e] = w_end(A.W, n, j) * p_sigR(A)[(size_t)j * npair + aa * NORB + qr];
-                xb[e] = doL ? -w_start(A.W, j) * conj(p_sigL(A)[(size_t)j * npair + qc * NORB + aa]) : mk(0.0, 0.0);
+                xa[e] = doR ? w_end(A.W, n, j) * p_sigR(A)[(size_t)j * npair + aa * NORB + qr] : mk(0.0, 0.0);
+                xb[e] = !doL ? mk(0.0, 0.0)
+                        : A.adj ? p_sigL(A)[(size_t)j * npair + aa * NORB + qc]
+                                : -w_start(A.W, j) * conj(p_sigL(A)[(size_t)j * npair + qc * NORB + aa]);
             } else {
                 xa[e] = interval_w(A.W, n, j) * p_sigR(A)[(size_t)j * npair + aa * NORB + qr];
                 xb[e] = interval_w(A.W, n, j) * p_sigR(A)[(size_t)j * npair + aa * NORB + qc];
@@ -257,7 +263,8 @@ __device__ void leaf_task(const HistArgs& A, int leaf, int comp, int ag, int pg,
             const int w = wave;
             if (comp == 0) {
                 // column sum x(j) G^R(j, m), j = m..; row dot x2(s) G^R(m, s)^dagger, s <= m
-                const bool rowok = doL && (s0 + mo > 0);   // second lesser term is empty at m = 0
+                // the second lesser term is empty at m = 0; the adjoint row dot is not
+                const bool rowok = doL && (A.adj || s0 + mo > 0);
                 for (int t = 0; t < nrow; ++t) {
                     const int j = mo + t;
                     if (doR && j < nrow) fma_(colsum, xa[j * AG + w], T[tri(j) + mo]);
@@ -298,7 +305,7 @@ __device__ void leaf_task(const HistArgs& A, int leaf, int comp, int ag, int pg,
 // written per column chunk and summed by the combine.
 template <int NORB>
 __device__ void tail_task(const HistArgs& A, int comp, int ag, int chunk, unsigned char* smem) {
-    if (comp == 1 && !A.wantL) return;
+    if (comp == 1 && (!A.wantL || A.adj)) return;
     constexpr int npair = NORB * NORB, AG = AGroups<NORB>::AG;
     const int n = A.n;
     const int n0 = A.n0[comp], nrows = A.last[comp] - n0 + 1, ls = A.ls[comp];
@@ -324,7 +331,7 @@ __device__ void tail_task(const HistArgs& A, int comp, int ag, int chunk, unsign
         }
         for (int e = threadIdx.x; e < nrows * AG; e += NT) {
             const int i = e / AG, aa = ag * AG + e % AG, j = n0 + i;
-            xr[e] = comp == 0 ? w_end(A.W, n, j) * p_sigR(A)[(size_t)j * npair + aa * NORB + qr]
+            xr[e] = comp == 0 ? (doR ? w_end(A.W, n, j) * p_sigR(A)[(size_t)j * npair + aa * NORB + qr] : mk(0.0, 0.0))
                               : interval_w(A.W, n, j) * p_sigR(A)[(size_t)j * npair + aa * NORB + qc];
         }
         for (int e = threadIdx.x; e < kTailCH * AG; e += NT) {
@@ -332,7 +339,9 @@ __device__ void tail_task(const HistArgs& A, int comp, int ag, int chunk, unsign
             cd v = mk(0.0, 0.0);
             if (mm < ncol) {
                 if (comp == 0) {
-                    if (doL) v = -w_start(A.W, m) * conj(p_sigL(A)[(size_t)m * npair + qc * NORB + aa]);
+                    if (doL)
+                        v = A.adj ? p_sigL(A)[(size_t)m * npair + aa * NORB + qc]
+                                  : -w_start(A.W, m) * conj(p_sigL(A)[(size_t)m * npair + qc * NORB + aa]);
                 } else {
                     v = interval_w(A.W, n, m) * p_sigR(A)[(size_t)m * npair + aa * NORB + qr];
                 }
@@ -441,7 +450,7 @@ __global__ void __launch_bounds__(256) proj_reduce(HistArgs A) {
         const int q = (int)(w % npair);
         const int slot = (int)((w / npair) % A.P);
         const int comp = (int)(w / ((long long)npair * A.P));
-        if (comp > 1 || !A.wantL) return;
+        if (comp > 1 || !A.wantL || (comp == 1 && A.adj)) return;
         if (slot > A.last[comp] - A.n0[comp]) return;   // also: no tail rows at all
         const cd* tp = p_tailpart(A, comp) + (size_t)slot * npair + q;
         double re = 0.0, im = 0.0;
@@ -467,6 +476,7 @@ __global__ void __launch_bounds__(256) proj_reduce(HistArgs A) {
     const int comp = (int)(bq / ((long long)A.npair * A.nb));
     if (comp == 0 && which == 0 && !A.wantR) return;
     if ((comp == 1 || which == 1) && !A.wantL) return;
+    if (comp == 1 && A.adj) return;
     if (r >= rank_of(A, comp, b, q)) return;
     const int* bk = A.blk + 5 * b;
     const int r0 = bk[1];
@@ -551,7 +561,7 @@ __global__ void __launch_bounds__(64 * CombMap<NORB>::WAVES) hist_combine(HistAr
                             if (rk > 0) expand_ranks<NORB, true, false>(accR, Vq, ldV, z, RC, rk);
                         }
                     }
-                    if (A.wantL && A.n0[1] > r0) {
+                    if (A.wantL && !A.adj && A.n0[1] > r0) {
                         for (int o = g; o < NORB; o += G) {
                             const int q = c * NORB + o;
                             const int rk = rank_of(A, 1, b, q);
@@ -573,7 +583,7 @@ __global__ void __launch_bounds__(64 * CombMap<NORB>::WAVES) hist_combine(HistAr
                             if (rk > 0) expand_ranks<NORB, true, false>(accL, Uq, ldU, z, RC, rk);
                         }
                     }
-                    if (m < A.n0[1]) {
+                    if (!A.adj && m < A.n0[1]) {
                         for (int o = g; o < NORB; o += G) {
                             const int q = o * NORB + c;
                             const int rk = rank_of(A, 1, b, q);
@@ -598,6 +608,33 @@ __global__ void __launch_bounds__(64 * CombMap<NORB>::WAVES) hist_combine(HistAr
         }
         if (!live) continue;
         const size_t mo = (size_t)m * npair;
+        if (A.adj) {
+            // outL(j = m) = h [ w_end(n, j) y(j) + corrections ]; the corrections replace
+            // the bulk weight of the terms m' = j - i, i <= k, by the exact interval weight
+            const int j = m;
+            const double we = w_end(A.W, n, j);
+#pragma unroll
+            for (int a = 0; a < NORB; ++a) {
+                if (a % G != g) continue;
+                const size_t o = mo + a * NORB + c;
+                cd y = accL[a];
+                for (int pg = 0; pg < LG; ++pg) y = y + p_leafLR(A)[(size_t)pg * A.nt * npair + o];
+                if (A.last[0] >= A.n0[0] && j >= A.n0[0] && j <= A.last[0])
+                    y = y + p_tailrow(A, 0)[(size_t)(j - A.n0[0]) * npair + a * NORB + c];
+                cd out = we * y;
+                const int imax = j < k ? j : k;
+                for (int i = 0; i <= imax; ++i) {
+                    const int mp = j - i, L = n - mp;
+                    const double wc = L >= k ? A.W.om[i] - 1.0 : A.W.nc[L][i] - we;
+                    const cd* ib = p_sigL(A) + (size_t)mp * npair + a * NORB;       // Ibar(n, m')[a][b]
+                    const cd* bd = p_band(A) + ((size_t)mp * kb + i) * npair + c * NORB;  // G^R(j, m')[c][b]
+#pragma unroll
+                    for (int bb = 0; bb < NORB; ++bb) fmac_(out, bd[bb], wc * ib[bb]);
+                }
+                p_outL(A)[o] = A.h * out;
+            }
+            continue;
+        }
 #pragma unroll
         for (int a = 0; a < NORB; ++a) {
             if (a % G != g) continue;

@@ -1,0 +1,136 @@
+"""GPU parity of the adjoint of the retarded history sum (gradient of losses of
+I^R with respect to the Sigma^R rows) against the FP64 oracle, called through
+the C ABI and through the torch.autograd wrapper.
+
+Bar: per row n, max_j |Sbar_gpu(n,j) - Sbar_oracle(n,j)| / max_j |Sbar_oracle(n,j)| <= 1e-10.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import dense_from_packed, host_inputs, row, row_rel_err, say, to_dev
+from kbe_inputs import hermitian_terms, make_config_inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_05319_amd as P
+    return P
+
+
+@pytest.mark.parametrize("norb,N,nlvl,k", [(1, 96, 3, 3), (2, 128, 2, 5), (4, 160, 3, 5)])
+def test_adjoint_rows_match_oracle(P, norb, N, nlvl, k):
+    from oracle.adjoint import history_R_adjoint_row
+    from oracle.history import ArrayOperands
+    h = 0.03
+    G, S = hermitian_terms(61 + norb, 6, norb), hermitian_terms(71 + norb, 6, norb)
+    GR, GL, SR, SL = host_inputs(G, S, N, h)
+    rng = np.random.default_rng(norb)
+    tot = N * (N + 1) // 2
+    ibar = rng.standard_normal((tot, norb, norb)) + 1j * rng.standard_normal((tot, norb, norb))
+    H = P.Hodlr(N, nlvl, norb, k=k, tol=1e-12, panel=8, max_rank=16)
+    gGR, gib = to_dev(GR), to_dev(ibar)
+    out = torch.zeros_like(gib)
+    for n in range(N):
+        H.append_row(P.RET, n, row(gGR, n))
+        H.history_R_adjoint(n, row(gib, n), h, row(out, n))
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    ops = ArrayOperands(dense_from_packed(GR, N), dense_from_packed(GL, N), dense_from_packed(SR, N),
+                        dense_from_packed(SL, N))
+    worst = 0.0
+    for n in sorted(set([0, 1, 2, k, k + 1, 20, 31, 32, 47, 48, 63, 64, N // 2, N - 2, N - 1])):
+        ref = history_R_adjoint_row(ops, n, row(ibar, n), h, k)
+        e = row_rel_err(row(got, n), ref)
+        worst = max(worst, e)
+        assert e <= TOL, (n, e)
+    say(f"adjoint norb={norb} k={k} worst row relative error", worst)
+
+
+def test_autograd_gradient_of_weighted_loss(P):
+    """L = sum_{n,m} w_m |I^R(n,m)|_F^2; SR.grad against the oracle adjoint of 2 w I and
+    against central finite differences of the GPU loss."""
+    from oracle.adjoint import history_R_adjoint_row
+    from oracle.history import ArrayOperands
+    from paper_2604_05319_amd.autograd import history_R
+    norb, N, nlvl, k, h = 2, 96, 2, 5, 0.04
+    G, S = hermitian_terms(81, 5, norb), hermitian_terms(82, 5, norb)
+    GR, GL, SR, SL = host_inputs(G, S, N, h)
+    wm = np.random.default_rng(3).uniform(0.0, 1.0, N) + 1e-3
+    cols = np.concatenate([np.arange(n + 1) for n in range(N)])
+    wt = to_dev(wm[cols].reshape(-1, 1, 1).astype(np.complex128)).real
+    H = P.Hodlr(N, nlvl, norb, k=k, tol=1e-12, panel=8, max_rank=16)
+    gGR = to_dev(GR)
+    sr = to_dev(SR).requires_grad_(True)
+
+    def loss(x):
+        I = history_R(H, gGR, x, h)
+        return (wt * I.abs() ** 2).sum(), I
+
+    L, I = loss(sr)
+    L.backward()
+    grad = sr.grad.detach().cpu().numpy()
+    Ih = I.detach().cpu().numpy()
+    ops = ArrayOperands(dense_from_packed(GR, N), dense_from_packed(GL, N), dense_from_packed(SR, N),
+                        dense_from_packed(SL, N))
+    worst = 0.0
+    for n in (0, 1, 5, 6, 31, 47, 48, 70, 95):
+        ibar = 2.0 * wm[:n + 1, None, None] * row(Ih, n)
+        e = row_rel_err(row(grad, n), history_R_adjoint_row(ops, n, ibar, h, k))
+        worst = max(worst, e)
+        assert e <= TOL, (n, e)
+    say("autograd gradient worst row relative error", worst)
+    eps = 1e-5
+    with torch.no_grad():
+        for (n, j, a, b) in [(10, 3, 0, 1), (95, 60, 1, 1), (50, 50, 1, 0)]:
+            idx = n * (n + 1) // 2 + j
+            base = sr[idx, a, b].item()
+            vals = []
+            for d in (eps, -eps, 1j * eps, -1j * eps):
+                sr[idx, a, b] = base + d
+                vals.append(loss(sr)[0].item())
+            sr[idx, a, b] = base
+            fd = (vals[0] - vals[1]) / (2 * eps) + 1j * (vals[2] - vals[3]) / (2 * eps)
+            assert abs(fd - grad[idx, a, b]) <= 1e-6 * max(1.0, abs(fd)), (n, j, fd, grad[idx, a, b])
+
+
+def test_c5_full_size_sampled(P):
+    """C5 (norb = 2, N_t = 2048, leaf 64): autograd gradient of sum_m w_m |I^R|^2 on sampled rows."""
+    from kbe_inputs.packed import packed_torch
+    from oracle.adjoint import history_R_adjoint_entry
+    from oracle.history import GeneratorOperands
+    from paper_2604_05319_amd.autograd import history_R
+    cfg, G, S = make_config_inputs("c5")
+    N, h, k, norb = cfg["nt"], cfg["h"], cfg["k"], cfg["norb"]
+    nlvl = int(round(np.log2(N // cfg["leaf"])))
+    wm = np.random.default_rng(cfg["seed_w"]).uniform(0.0, 1.0, N) + 1e-12
+    dev = torch.device("cuda:0")
+    gGR = packed_torch(G, "ret", N, h, dev)
+    sr = packed_torch(S, "ret", N, h, dev).requires_grad_(True)
+    cols = torch.cat([torch.arange(n + 1, device=dev) for n in range(N)])
+    wt = torch.as_tensor(wm, device=dev)[cols].reshape(-1, 1, 1)
+    H = P.Hodlr(N, nlvl, norb, k=k, tol=cfg["tol"], panel=16, max_rank=16)
+    say("gpu: c5 autograd sweep", N)
+    I = history_R(H, gGR, sr, h)
+    ((wt * I.abs() ** 2).sum()).backward()
+    torch.cuda.synchronize()
+    assert H.status() == 0
+    ops = GeneratorOperands(G, S, h)
+    rng = np.random.default_rng(9)
+    worst = 0.0
+    for n in sorted(set([0, 5, 63, 64, 1023, 1024, N - 1] + list(rng.integers(0, N, 2)))):
+        a = n * (n + 1) // 2
+        g = sr.grad[a:a + n + 1].cpu().numpy()
+        ibar = 2.0 * wm[:n + 1, None, None] * I[a:a + n + 1].detach().cpu().numpy()
+        scale = np.abs(g).max()
+        for j in sorted(set(x for x in [0, 1, n - 5, n] + list(rng.integers(0, n + 1, 2)) if 0 <= x <= n)):
+            e = np.abs(g[j] - history_R_adjoint_entry(ops, n, j, ibar, h, k)).max() / max(scale, 1e-300)
+            worst = max(worst, e)
+            assert e <= TOL, (n, j, e)
+    say("c5 adjoint worst sampled relative error", worst)
