@@ -171,6 +171,42 @@ def lattice_bench(P, prof_stride):
     return out
 
 
+def adjoint_bench(P):
+    """Adjoint form at its workload (norb = 2, N_t = 2048, leaf 64): forward sweep of I^R and
+    the backward sweep that replays the appends and runs the adjoint kernel at every step."""
+    import numpy as np
+    import torch
+    from kbe_inputs import make_config_inputs
+    from kbe_inputs.packed import packed_torch
+    from paper_2604_05319_amd.autograd import history_R
+    cfg, G, S = make_config_inputs("c5")
+    N, h, k, norb = cfg["nt"], cfg["h"], cfg["k"], cfg["norb"]
+    nlvl = int(round(np.log2(N // cfg["leaf"])))
+    dev = torch.device("cuda:0")
+    wm = torch.as_tensor(np.random.default_rng(cfg["seed_w"]).uniform(0.0, 1.0, N), device=dev)
+    cols = torch.cat([torch.arange(n + 1, device=dev) for n in range(N)])
+    wt = wm[cols].reshape(-1, 1, 1)
+    GR = packed_torch(G, "ret", N, h, dev)
+    SR = packed_torch(S, "ret", N, h, dev).requires_grad_(True)
+    H = P.Hodlr(N, nlvl, norb, k=k, tol=cfg["tol"], panel=16, max_rank=16)
+
+    def run():
+        SR.grad = None
+        I = history_R(H, GR, SR, h)
+        ((wt * I.abs() ** 2).sum()).backward()
+
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = dict(value=round(N / dt, 2), unit="time steps/s (forward + backward sweep)", n_t=N, norb=norb,
+               seconds=round(dt, 3), status=H.status())
+    H.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -183,6 +219,7 @@ def main():
     ap.add_argument("--prof-stride", type=int, default=16)
     ap.add_argument("--nt", type=int, default=None, help="override N_t (testing only)")
     ap.add_argument("--no-lattice", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -307,6 +344,11 @@ def main():
         lattice = lattice_bench(P, args.prof_stride)
         log("lattice:", lattice)
 
+    adjoint = None
+    if not args.no_adjoint:
+        adjoint = adjoint_bench(P)
+        log("adjoint:", adjoint)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(cfg, G, S, args.cpu_budget)
@@ -326,6 +368,7 @@ def main():
         "kernels": kernels,
         "dense": dense,
         "lattice": lattice,
+        "adjoint": adjoint,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

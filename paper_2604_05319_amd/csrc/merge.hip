@@ -49,60 +49,103 @@ __device__ double block_sum(double v, double* red) {
 // nrows >= ncols.  On exit R is in the upper triangle, the reflector vectors
 // (v_j = 1 implicit) below it, and tau[j] holds the scalars: A = H_0..H_{n-1} R
 // with H_j = I - tau_j v_j v_j^dagger.
+//
+// One barrier per column: the thread group that updates column j+1 also sums
+// its squared entries below the diagonal (the next reflector's norm), and the
+// scaling of reflector j into v_j (with the diagonal beta_j) is written during
+// step j+1, when no thread reads column j any more.  Threads: groups of
+// TPC = NT / W per trailing column, group g updates column j + 1 + g.
+template <int W>
+__device__ void reflector(cd alpha, double sig2, cd& beta_out, cd& t, cd& scale) {
+    double beta = alpha.x;
+    t = mk(0.0, 0.0);
+    scale = mk(0.0, 0.0);
+    const double nrm0 = sqrt(norm2(alpha) + sig2);
+    // no reflection for an exactly zero column, or one so small (or not finite)
+    // that 1/(alpha - beta) would overflow: tau = 0, H_j = I
+    if (!(sig2 == 0.0 && alpha.y == 0.0) && nrm0 > 1e-150 && nrm0 < 1e150) {
+        beta = alpha.x >= 0.0 ? -nrm0 : nrm0;
+        t = mk((beta - alpha.x) / beta, -alpha.y / beta);
+        const cd d = alpha - mk(beta, 0.0);  // 1/(alpha - beta)
+        const double dn = norm2(d);
+        scale = mk(d.x / dn, -d.y / dn);
+    }
+    beta_out = mk(beta, 0.0);
+}
+
 template <int W>
 __device__ __attribute__((noinline)) void hh_qr(cd* A, int nrows, int ncols, cd* tau,
                                                 double* red) {
     constexpr int TPC = NT / W;  // threads per trailing column
     const int tid = threadIdx.x;
+    const int g = tid / TPC, l = tid % TPC;
+    // norm of column 0 below the diagonal
+    {
+        double part = 0.0;
+        for (int i = 1 + tid; i < nrows; i += NT) part += norm2(A[i]);
+        const double s0 = block_sum(part, red);
+        __syncthreads();
+        if (tid == 0) red[8] = s0;
+        __syncthreads();
+    }
+    cd pbeta = mk(0.0, 0.0), pt = mk(0.0, 0.0), pscale = mk(0.0, 0.0);   // reflector j - 1
     for (int j = 0; j < ncols; ++j) {
         cd* aj = A + (size_t)j * nrows;
-        double part = 0.0;
-        for (int i = j + 1 + tid; i < nrows; i += NT) part += norm2(aj[i]);
-        double sig2 = block_sum(part, red);
-        cd alpha = aj[j];
-        cd t = mk(0.0, 0.0), scale = mk(0.0, 0.0);
-        double beta = alpha.x;
-        const double nrm0 = sqrt(norm2(alpha) + sig2);
-        // no reflection for an exactly zero column, or one so small (or not
-        // finite) that 1/(alpha - beta) would overflow: tau = 0, H_j = I
-        if (!(sig2 == 0.0 && alpha.y == 0.0) && nrm0 > 1e-150 && nrm0 < 1e150) {
-            double nrm = nrm0;
-            beta = alpha.x >= 0.0 ? -nrm : nrm;
-            t = mk((beta - alpha.x) / beta, -alpha.y / beta);
-            cd d = alpha - mk(beta, 0.0);  // 1/(alpha - beta)
-            double dn = norm2(d);
-            scale = mk(d.x / dn, -d.y / dn);
+        const double sig2 = red[8 + (j & 1)];
+        const cd alpha = aj[j];
+        cd beta, t, scale;
+        reflector<W>(alpha, sig2, beta, t, scale);
+        // finish reflector j - 1 (nobody reads column j - 1 in this step)
+        if (j > 0) {
+            cd* ap = A + (size_t)(j - 1) * nrows;
+            for (int i = j + tid; i < nrows; i += NT) ap[i] = ap[i] * pscale;
+            if (tid == 0) {
+                ap[j - 1] = pbeta;
+                tau[j - 1] = pt;
+            }
         }
-        __syncthreads();
-        for (int i = j + 1 + tid; i < nrows; i += NT) aj[i] = aj[i] * scale;
-        if (tid == 0) {
-            aj[j] = mk(beta, 0.0);
-            tau[j] = t;
-        }
-        __syncthreads();
-        // apply H_j^dagger to the trailing columns: a_c -= conj(tau) v (v^dagger a_c)
-        const int g = tid / TPC, l = tid % TPC;
+        // apply H_j^dagger to the trailing columns: a_c -= conj(tau) v (v^dagger a_c),
+        // v_j = 1 and v_i = scale * a_ij below the diagonal
         const int c = j + 1 + g;
         cd dot = mk(0.0, 0.0);
         if (c < ncols) {
-            cd* ac = A + (size_t)c * nrows;
-            for (int i = j + l; i < nrows; i += TPC) {
-                cd v = (i == j) ? mk(1.0, 0.0) : aj[i];
-                fmac_(dot, v, ac[i]);
-            }
+            const cd* ac = A + (size_t)c * nrows;
+            cd d2 = mk(0.0, 0.0);
+            for (int i = j + 1 + l; i < nrows; i += TPC) fmac_(d2, aj[i], ac[i]);
+            dot = conj(scale) * d2;
+            if (l == 0) dot = dot + ac[j];
         }
         dot.x = warp_sum(dot.x, TPC);
         dot.y = warp_sum(dot.y, TPC);
+        double nrm_next = 0.0;
         if (c < ncols) {
             cd* ac = A + (size_t)c * nrows;
-            cd f = conj(t) * dot;
-            for (int i = j + l; i < nrows; i += TPC) {
-                cd v = (i == j) ? mk(1.0, 0.0) : aj[i];
-                ac[i] = ac[i] - v * f;
+            const cd f = conj(t) * dot;
+            if (l == 0) ac[j] = ac[j] - f;
+            const cd fs = scale * f;
+            for (int i = j + 1 + l; i < nrows; i += TPC) {
+                const cd v = ac[i] - aj[i] * fs;
+                ac[i] = v;
+                if (i > j + 1) nrm_next += norm2(v);
             }
         }
+        nrm_next = warp_sum(nrm_next, TPC);   // every lane takes part in the shuffles
+        if (g == 0 && l == 0) red[8 + ((j + 1) & 1)] = nrm_next;   // column j + 1's group
+        pbeta = beta;
+        pt = t;
+        pscale = scale;
         __syncthreads();
     }
+    if (ncols > 0) {
+        const int j = ncols;
+        cd* ap = A + (size_t)(j - 1) * nrows;
+        for (int i = j + tid; i < nrows; i += NT) ap[i] = ap[i] * pscale;
+        if (tid == 0) {
+            ap[j - 1] = pbeta;
+            tau[j - 1] = pt;
+        }
+    }
+    __syncthreads();
 }
 
 // X (nrows x nx, column-major, ldx = nrows) <- H_0 H_1 .. H_{nref-1} X
@@ -299,7 +342,7 @@ __global__ void __launch_bounds__(NT) merge_up_kernel(MergeArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cd* A = reinterpret_cast<cd*>(smem_raw);               // CH x W (also 2W x W, and M, J)
     cd* tau = A + (size_t)CH * W;                          // W
-    double* red = reinterpret_cast<double*>(tau + W);      // 8
+    double* red = reinterpret_cast<double*>(tau + W);      // 16
     __shared__ int sflag;
     __shared__ double s_old[W];
     __shared__ double ssig[W];
@@ -536,11 +579,11 @@ __global__ void __launch_bounds__(NT) merge_down_kernel(MergeArgs a) {
 }
 
 static size_t merge_up_smem() {
-    return (size_t)kMergeCH * kW * sizeof(cd) + (size_t)kW * sizeof(cd) + 8 * sizeof(double);
+    return (size_t)kMergeCH * kW * sizeof(cd) + (size_t)kW * sizeof(cd) + 16 * sizeof(double);
 }
 static size_t merge_down_smem() {
     return (size_t)2 * kMergeCH * kW * sizeof(cd) + (size_t)kW * kW * sizeof(cd) +
-           (size_t)kW * sizeof(cd) + 8 * sizeof(double);
+           (size_t)kW * sizeof(cd) + 16 * sizeof(double);
 }
 
 hipError_t launch_merge(const MergeArgs& a, int nk, hipStream_t st) {
