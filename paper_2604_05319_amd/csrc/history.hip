@@ -239,23 +239,46 @@ __device__ void leaf_task(const HistArgs& A, int leaf, int comp, int ag, int pg,
     cd accA[NORB], accB[NORB];
 #pragma unroll
     for (int c = 0; c < NORB; ++c) accA[c] = accB[c] = mk(0.0, 0.0);
-    for (int q = pg * PPG; q < (pg + 1) * PPG; ++q) {
+    // the next pair's triangle and Sigma entries are loaded into registers while
+    // the current pair is computed (one triangle element per thread and pass)
+    constexpr int TPT = (64 * 65 / 2 + NT - 1) / NT;   // triangle elements of a 64-row leaf per thread
+    cd pT[TPT], pxa = mk(0.0, 0.0), pxb = mk(0.0, 0.0);
+    auto fetch = [&](int q) {
         const int qr = q / NORB, qc = q % NORB;
         const cd* Lq = L + (size_t)q * tsz;
-        __syncthreads();
-        for (long long e = threadIdx.x; e < tnow; e += NT) T[e] = Lq[e];
-        for (int e = threadIdx.x; e < nrow * AG; e += NT) {
+#pragma unroll
+        for (int u = 0; u < TPT; ++u) {
+            const long long e = threadIdx.x + (long long)u * NT;
+            pT[u] = e < tnow ? Lq[e] : mk(0.0, 0.0);
+        }
+        const int e = threadIdx.x;   // nrow * AG <= NT
+        if (e < nrow * AG) {
             const int i = e / AG, aa = ag * AG + e % AG, j = s0 + i;
             if (comp == 0) {
-                xa[e] = doR ? w_end(A.W, n, j) * p_sigR(A)[(size_t)j * npair + aa * NORB + qr] : mk(0.0, 0.0);
-                xb[e] = !doL ? mk(0.0, 0.0)
-                        : A.adj ? p_sigL(A)[(size_t)j * npair + aa * NORB + qc]
-                                : -w_start(A.W, j) * conj(p_sigL(A)[(size_t)j * npair + qc * NORB + aa]);
+                pxa = doR ? w_end(A.W, n, j) * p_sigR(A)[(size_t)j * npair + aa * NORB + qr] : mk(0.0, 0.0);
+                pxb = !doL ? mk(0.0, 0.0)
+                      : A.adj ? p_sigL(A)[(size_t)j * npair + aa * NORB + qc]
+                              : -w_start(A.W, j) * conj(p_sigL(A)[(size_t)j * npair + qc * NORB + aa]);
             } else {
-                xa[e] = interval_w(A.W, n, j) * p_sigR(A)[(size_t)j * npair + aa * NORB + qr];
-                xb[e] = interval_w(A.W, n, j) * p_sigR(A)[(size_t)j * npair + aa * NORB + qc];
+                pxa = interval_w(A.W, n, j) * p_sigR(A)[(size_t)j * npair + aa * NORB + qr];
+                pxb = interval_w(A.W, n, j) * p_sigR(A)[(size_t)j * npair + aa * NORB + qc];
             }
         }
+    };
+    fetch(pg * PPG);
+    for (int q = pg * PPG; q < (pg + 1) * PPG; ++q) {
+        const int qr = q / NORB, qc = q % NORB;
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < TPT; ++u) {
+            const long long e = threadIdx.x + (long long)u * NT;
+            if (e < tnow) T[e] = pT[u];
+        }
+        if ((int)threadIdx.x < nrow * AG) {
+            xa[threadIdx.x] = pxa;
+            xb[threadIdx.x] = pxb;
+        }
+        if (q + 1 < (pg + 1) * PPG) fetch(q + 1);
         __syncthreads();
         if (act) {
             cd colsum = mk(0.0, 0.0), rowdot = mk(0.0, 0.0);
@@ -310,9 +333,9 @@ __device__ void tail_task(const HistArgs& A, int comp, int ag, int chunk, unsign
     const int n = A.n;
     const int n0 = A.n0[comp], nrows = A.last[comp] - n0 + 1, ls = A.ls[comp];
     const int cbeg = chunk * kTailCH, ncol = min(kTailCH, ls - cbeg);
-    cd* T = reinterpret_cast<cd*>(smem);       // P x 64
-    cd* xr = T + (size_t)A.P * kTailCH;        // P x AG   (row-side Sigma)
-    cd* xm = xr + (size_t)A.P * AG;            // 64 x AG  (column-side Sigma)
+    cd* T = reinterpret_cast<cd*>(smem);       // 16 x 64 (rows beyond the tail's are zero)
+    cd* xr = T + (size_t)16 * kTailCH;         // 16 x AG  (row-side Sigma)
+    cd* xm = xr + (size_t)16 * AG;             // 64 x AG  (column-side Sigma)
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int a = ag * AG + wave;
     const bool wok = wave < AG;
@@ -322,19 +345,24 @@ __device__ void tail_task(const HistArgs& A, int comp, int ag, int chunk, unsign
 #pragma unroll
     for (int c = 0; c < NORB; ++c) col[c] = row[c] = mk(0.0, 0.0);
     const int ri = lane & 15, part = lane >> 4;   // row-dot mapping: row ri, 16 columns per part
-    for (int q = 0; q < npair; ++q) {
+    // the next pair's tile and Sigma entries are loaded into registers while the
+    // current pair is computed
+    constexpr int EPT = 16 * kTailCH / NT;   // tile elements per thread (P <= 16 rows)
+    cd pT[EPT], pxr = mk(0.0, 0.0), pxm = mk(0.0, 0.0);
+    auto fetch = [&](int q) {
         const int qr = q / NORB, qc = q % NORB;
-        __syncthreads();
-        for (int e = threadIdx.x; e < nrows * kTailCH; e += NT) {
-            const int i = e / kTailCH, mm = e % kTailCH;
-            T[e] = mm < ncol ? Tg[((size_t)i * npair + q) * A.nt + cbeg + mm] : mk(0.0, 0.0);
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            const int e = threadIdx.x + u * NT, i = e / kTailCH, mm = e % kTailCH;
+            pT[u] = (i < nrows && mm < ncol) ? Tg[((size_t)i * npair + q) * A.nt + cbeg + mm] : mk(0.0, 0.0);
         }
-        for (int e = threadIdx.x; e < nrows * AG; e += NT) {
+        const int e = threadIdx.x;
+        if (e < nrows * AG) {     // row side, nrows * AG <= NT
             const int i = e / AG, aa = ag * AG + e % AG, j = n0 + i;
-            xr[e] = comp == 0 ? (doR ? w_end(A.W, n, j) * p_sigR(A)[(size_t)j * npair + aa * NORB + qr] : mk(0.0, 0.0))
-                              : interval_w(A.W, n, j) * p_sigR(A)[(size_t)j * npair + aa * NORB + qc];
+            pxr = comp == 0 ? (doR ? w_end(A.W, n, j) * p_sigR(A)[(size_t)j * npair + aa * NORB + qr] : mk(0.0, 0.0))
+                            : interval_w(A.W, n, j) * p_sigR(A)[(size_t)j * npair + aa * NORB + qc];
         }
-        for (int e = threadIdx.x; e < kTailCH * AG; e += NT) {
+        if (e < kTailCH * AG) {   // column side, 64 * AG <= NT
             const int mm = e / AG, aa = ag * AG + e % AG, m = cbeg + mm;
             cd v = mk(0.0, 0.0);
             if (mm < ncol) {
@@ -346,8 +374,18 @@ __device__ void tail_task(const HistArgs& A, int comp, int ag, int chunk, unsign
                     v = interval_w(A.W, n, m) * p_sigR(A)[(size_t)m * npair + aa * NORB + qr];
                 }
             }
-            xm[e] = v;
+            pxm = v;
         }
+    };
+    fetch(0);
+    for (int q = 0; q < npair; ++q) {
+        const int qr = q / NORB, qc = q % NORB;
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) T[threadIdx.x + u * NT] = pT[u];
+        if ((int)threadIdx.x < nrows * AG) xr[threadIdx.x] = pxr;
+        if ((int)threadIdx.x < kTailCH * AG) xm[threadIdx.x] = pxm;
+        if (q + 1 < npair) fetch(q + 1);
         __syncthreads();
         if (wok) {
             // column sums (lane = column)
