@@ -159,7 +159,21 @@ struct hnessi_hodlr_s {
     cd* tail[2] = {};
     cd* band = nullptr;
     int last[2] = {-1, -1};
-    int n0[2] = {0, 0};
+    int n0[2] = {0, 0};        // first row not in the current factor buffers
+    int fstart[2] = {0, 0};    // first row of the panel being formed
+    // Panel merges run on their own stream one panel behind: while panel [p0, p1) is
+    // merged into the blocks' other factor buffer, the history kernels keep reading
+    // the current buffer and treat the panel's rows as dense tail rows.
+    long long bU = 0, bV = 0, bS = 0, bRank = 0;   // buffer 1 offset (elements)
+    std::vector<int> cur[2];                        // per block: current buffer
+    int* d_cur[2] = {};
+    hipStream_t mstream = nullptr;
+    hipEvent_t ev_app[2] = {}, ev_merge[2] = {};
+    struct Pending {
+        bool on = false;
+        int p0 = 0, p1 = 0;
+        std::vector<int> blocks;
+    } pend[2];
     // projection tasks, sorted by activation row
     FactTask* d_ft[2] = {};
     std::vector<int> ft_act[2];
@@ -217,6 +231,17 @@ int hnessi_weights(int k, int L, double* w_host) {
 }  // extern "C"
 
 namespace {
+
+void release_streams(hnessi_hodlr_t H) {
+    if (H->mstream) hipStreamSynchronize(H->mstream);
+    for (int c = 0; c < 2; ++c) {
+        if (H->ev_app[c]) hipEventDestroy(H->ev_app[c]);
+        if (H->ev_merge[c]) hipEventDestroy(H->ev_merge[c]);
+        H->ev_app[c] = H->ev_merge[c] = nullptr;
+    }
+    if (H->mstream) hipStreamDestroy(H->mstream);
+    H->mstream = nullptr;
+}
 
 int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, double svd_tol, int panel,
                 int max_rank, int flags) {
@@ -308,16 +333,23 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
     HALLOC(H->d_Loff, g.nleaf, false);
     // factor and dense storage
     for (int c = 0; c < 2; ++c) {
-        HALLOC_K(H->U[c], uo, true, H->oU);
-        HALLOC_K(H->V[c], vo, true, H->oV);
+        // two buffers per object: [object][buffer][...]
+        H->bU = uo;
+        H->bV = vo;
+        H->bS = (long long)std::max(nb, 1) * npair * RC;
+        H->bRank = (long long)std::max(nb, 1) * npair;
+        HALLOC_K(H->U[c], 2 * uo, true, H->oU);
+        HALLOC_K(H->V[c], 2 * vo, true, H->oV);
         if (H->f32) {
-            HALLOC(H->U32[c], (size_t)uo * nk, true);
-            HALLOC(H->V32[c], (size_t)vo * nk, true);
+            HALLOC(H->U32[c], (size_t)2 * uo * nk, true);
+            HALLOC(H->V32[c], (size_t)2 * vo * nk, true);
         }
-        HALLOC_K(H->S[c], (size_t)std::max(nb, 1) * npair * RC, true, H->oS);
-        HALLOC_K(H->rank[c], (size_t)std::max(nb, 1) * npair, true, H->oRank);
+        HALLOC_K(H->S[c], 2 * H->bS, true, H->oS);
+        HALLOC_K(H->rank[c], 2 * H->bRank, true, H->oRank);
+        HALLOC(H->d_cur[c], (size_t)std::max(nb, 1), true);
+        H->cur[c].assign(std::max(nb, 1), 0);
         HALLOC_K(H->leaf[c], lo, true, H->oLeaf);
-        HALLOC_K(H->tail[c], (size_t)panel * npair * nt, true, H->oTail);
+        HALLOC_K(H->tail[c], (size_t)kTailRows * npair * nt, true, H->oTail);
     }
     HALLOC_K(H->band, (size_t)nt * (k + 1) * npair, true, H->oBand);
     HALLOC_K(H->proj, (size_t)2 * std::max(nb, 1) * npair * 2 * norb * RC, true, H->oProj);
@@ -340,8 +372,8 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
     H->ntailchunk_max = div_up(nt, kTailCH);
     for (int c = 0; c < 2; ++c) {
         HALLOC_K(H->tailcol[c], (size_t)nt * npair, true, H->oTailcol);
-        HALLOC_K(H->tailpart[c], (size_t)H->ntailchunk_max * panel * npair, true, H->oTailpart);
-        HALLOC_K(H->tailrow[c], (size_t)panel * npair, true, H->oTailrow);
+        HALLOC_K(H->tailpart[c], (size_t)H->ntailchunk_max * kTailRows * npair, true, H->oTailpart);
+        HALLOC_K(H->tailrow[c], (size_t)kTailRows * npair, true, H->oTailrow);
     }
     // merge scratch: one block per level per panel
     H->lvl_node_base.assign(nlvl + 1, 0);
@@ -391,6 +423,17 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
         hipMemcpy(H->d_Loff, H->Loff.data(), g.nleaf * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(H->d_partoff, partoff.data(), partoff.size() * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess)
         return bail(fail(HNESSI_E_DEVICE, "copy of geometry failed"));
+    // the merge stream (default priority) and its events
+    if (hipStreamCreateWithFlags(&H->mstream, hipStreamNonBlocking) != hipSuccess) {
+        H->mstream = nullptr;
+        return bail(fail(HNESSI_E_DEVICE, "stream creation failed"));
+    }
+    for (int c = 0; c < 2; ++c)
+        if (hipEventCreateWithFlags(&H->ev_app[c], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&H->ev_merge[c], hipEventDisableTiming) != hipSuccess) {
+            release_streams(H);
+            return bail(fail(HNESSI_E_DEVICE, "event creation failed"));
+        }
 #undef HALLOC_K
 #undef HALLOC
     *out = H;
@@ -418,6 +461,7 @@ int hnessi_hodlr_nk(hnessi_hodlr_t H) { return H ? H->nk : fail(HNESSI_E_ARG, "h
 int hnessi_hodlr_destroy(hnessi_hodlr_t H) {
     if (!H) return fail(HNESSI_E_ARG, "handle is NULL");
     hipDeviceSynchronize();
+    release_streams(H);
     H->prof.release();
     H->al.release();
     delete H;
@@ -428,9 +472,14 @@ int hnessi_hodlr_reset(hnessi_hodlr_t H, void* stream) {
     if (!H) return fail(HNESSI_E_ARG, "handle is NULL");
     hipStream_t st = (hipStream_t)stream;
     for (int c = 0; c < 2; ++c) {
+        if (H->pend[c].on) HIP_TRY(hipStreamWaitEvent(st, H->ev_merge[c], 0));   // merge done first
+        H->pend[c].on = false;
         HIP_TRY(hipMemsetAsync(H->rank[c], 0, sizeof(int) * H->oRank * H->nk, st));
+        HIP_TRY(hipMemsetAsync(H->d_cur[c], 0, sizeof(int) * H->cur[c].size(), st));
+        std::fill(H->cur[c].begin(), H->cur[c].end(), 0);
         H->last[c] = -1;
         H->n0[c] = 0;
+        H->fstart[c] = 0;
     }
     HIP_TRY(hipMemsetAsync(H->err, 0, sizeof(int), st));
     return HNESSI_OK;
@@ -440,9 +489,17 @@ int hnessi_hodlr_reset(hnessi_hodlr_t H, void* stream) {
 
 namespace {
 
-int merge_panel(hnessi_hodlr_t H, int c, int p0, int p1, hipStream_t st) {
+int merge_panel(hnessi_hodlr_t H, int c, int p0, int p1, hipStream_t st, std::vector<int>& blocks) {
     const Geometry& g = H->g;
+    blocks.clear();
     MergeArgs a{};
+    a.flip = 1;
+    a.bU = H->bU;
+    a.bV = H->bV;
+    a.bS = H->bS;
+    a.bRank = H->bRank;
+    a.src_first = p0 % kTailRows;
+    a.src_ring = kTailRows;
     a.pp = p1 - p0;
     a.npair = H->npair;
     a.RC = H->RC;
@@ -495,6 +552,8 @@ int merge_panel(hnessi_hodlr_t H, int c, int p0, int p1, hipStream_t st) {
         B.node_base = H->lvl_node_base[g.level[b]];
         B.Uoff = H->Uoff[b];
         B.Voff = H->Voff[b];
+        B.rd = H->cur[c][b];
+        blocks.push_back(b);
         nv += H->npair * B.nchunks;
         nu += H->npair * B.nutask;
         ++nblk;
@@ -516,8 +575,31 @@ int merge_panel(hnessi_hodlr_t H, int c, int p0, int p1, hipStream_t st) {
 
 bool panel_ends(hnessi_hodlr_t H, int c, int n) {
     if (n + 1 >= H->nt) return true;
-    if (n + 1 - H->n0[c] >= H->P) return true;
+    if (n + 1 - H->fstart[c] >= H->P) return true;
     return H->g.row_leaf[n + 1] != H->g.row_leaf[n];
+}
+
+// Make the in-flight merge of component c current for the work queued on st
+// after this call: st waits for the merge, the merged blocks switch buffers and
+// the panel's rows leave the dense tail.
+int finish_pending(hnessi_hodlr_t H, int c, hipStream_t st) {
+    auto& pd = H->pend[c];
+    if (!pd.on) return HNESSI_OK;
+    HIP_TRY(hipStreamWaitEvent(st, H->ev_merge[c], 0));
+    HIP_TRY(launch_flip(H->d_cur[c], pd.blocks.data(), (int)pd.blocks.size(), st));
+    for (int b : pd.blocks) H->cur[c][b] ^= 1;
+    H->n0[c] = pd.p1;
+    pd.on = false;
+    return HNESSI_OK;
+}
+
+// Finish every in-flight merge (queries of the stored state).
+int drain(hnessi_hodlr_t H, hipStream_t st) {
+    for (int c = 0; c < 2; ++c) {
+        int rc = finish_pending(H, c, st);
+        if (rc != HNESSI_OK) return rc;
+    }
+    return HNESSI_OK;
 }
 
 int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, double h, void* outR,
@@ -543,8 +625,12 @@ int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, doub
         if (!use) continue;
         A.nf[c] = (int)(std::lower_bound(H->ft_act[c].begin(), H->ft_act[c].end(), H->n0[c]) -
                         H->ft_act[c].begin());
+        // tail rows n0..last: those of the panel still being merged (before nsplit) hold
+        // columns [0, lslo), the later ones [0, ls)
+        A.nsplit[c] = H->pend[c].on ? H->pend[c].p1 : H->n0[c];
         if (H->last[c] >= H->n0[c]) {
-            A.ls[c] = g.s0[g.row_leaf[H->n0[c]]];
+            A.lslo[c] = g.s0[g.row_leaf[H->n0[c]]];
+            A.ls[c] = A.nsplit[c] <= H->last[c] ? g.s0[g.row_leaf[A.nsplit[c]]] : A.lslo[c];
             A.ntailchunk[c] = div_up(A.ls[c], kTailCH);
         }
     }
@@ -597,6 +683,13 @@ int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, doub
     A.outL = static_cast<cd*>(outL);
     A.nk = H->nk;
     A.f32 = H->f32;
+    A.ring = kTailRows;
+    A.bU = H->bU;
+    A.bV = H->bV;
+    A.bS = H->bS;
+    A.bRank = H->bRank;
+    A.cur[0] = H->d_cur[0];
+    A.cur[1] = H->d_cur[1];
     A.kIn = in_stride;
     A.kOut = out_stride;
     A.kU = H->oU;
@@ -647,7 +740,7 @@ int append_impl(hnessi_hodlr_t H, int c, int n, const void* row, long long k_str
     a.k = H->k;
     a.ls = g.s0[leaf];
     a.lw = g.s1[leaf] - g.s0[leaf];
-    a.slot = n - H->n0[c];
+    a.slot = n % kTailRows;
     a.leaf = H->leaf[c] + H->Loff[leaf];
     a.tail = H->tail[c];
     a.band = c == HNESSI_RET ? H->band : nullptr;
@@ -658,9 +751,23 @@ int append_impl(hnessi_hodlr_t H, int c, int n, const void* row, long long k_str
     HIP_TRY(launch_append_hodlr(a, H->nk, st));
     H->last[c] = n;
     if (panel_ends(H, c, n)) {
-        int rc = merge_panel(H, c, H->n0[c], n + 1, st);
+        const int p0 = H->fstart[c], p1 = n + 1;
+        // the previous panel's merge becomes current for everything queued from here on
+        int rc = finish_pending(H, c, st);
         if (rc != HNESSI_OK) return rc;
-        H->n0[c] = n + 1;
+        // this panel's merge runs on the merge stream after the work queued so far on st
+        // and writes the blocks' other buffers; until the next panel ends, the history
+        // kernels read the panel's rows from the dense tail
+        HIP_TRY(hipEventRecord(H->ev_app[c], st));
+        HIP_TRY(hipStreamWaitEvent(H->mstream, H->ev_app[c], 0));
+        auto& pd = H->pend[c];
+        rc = merge_panel(H, c, p0, p1, H->mstream, pd.blocks);
+        if (rc != HNESSI_OK) return rc;
+        HIP_TRY(hipEventRecord(H->ev_merge[c], H->mstream));
+        pd.on = true;
+        pd.p0 = p0;
+        pd.p1 = p1;
+        H->fstart[c] = p1;
     }
     return HNESSI_OK;
 }
@@ -775,6 +882,9 @@ int hnessi_sweep_batched(hnessi_hodlr_t H, int n_begin, int n_end, const void* G
 int hnessi_hodlr_status(hnessi_hodlr_t H, void* stream) {
     if (!H) return fail(HNESSI_E_ARG, "handle is NULL");
     HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    int rc = drain(H, H->mstream);
+    if (rc != HNESSI_OK) return rc;
+    HIP_TRY(hipDeviceSynchronize());
     int e = 0;
     HIP_TRY(hipMemcpy(&e, H->err, sizeof(int), hipMemcpyDeviceToHost));
     if (e & 2) return fail(HNESSI_E_VALUE, "a truncation met non-finite data (NaN or Inf in the rows)");
@@ -799,7 +909,7 @@ int hnessi_hodlr_get(hnessi_hodlr_t H, int c, int t1, int t2, void* out_host) {
             HIP_TRY(hipMemcpy(&out[q], H->leaf[c] + H->Loff[leaf] + (size_t)q * tri(lw) + tri(t1 - ls) + (t2 - ls),
                               sizeof(cd), hipMemcpyDeviceToHost));
     } else if (t1 >= H->n0[c]) {
-        const int slot = t1 - H->n0[c];
+        const int slot = t1 % kTailRows;
         for (int q = 0; q < npair; ++q)
             HIP_TRY(hipMemcpy(&out[q], H->tail[c] + ((size_t)slot * npair + q) * H->nt + t2, sizeof(cd),
                               hipMemcpyDeviceToHost));
@@ -812,18 +922,20 @@ int hnessi_hodlr_get(hnessi_hodlr_t H, int c, int t1, int t2, void* out_host) {
         if (b < 0) return fail(HNESSI_E_RANGE, "no block holds (t1, t2)");
         const int RC = H->RC;
         const int ldU = g.r1[b] - g.r0[b], ldV = g.c1[b] - g.c0[b];
+        const int bf = H->cur[c][b];   // the block's current buffer
         std::vector<int> rk(npair);
-        HIP_TRY(hipMemcpy(rk.data(), H->rank[c] + (size_t)b * npair, npair * sizeof(int), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(rk.data(), H->rank[c] + bf * H->bRank + (size_t)b * npair, npair * sizeof(int),
+                          hipMemcpyDeviceToHost));
         std::vector<double> S(RC);
         for (int q = 0; q < npair; ++q) {
             cd acc = mk(0.0, 0.0);
-            HIP_TRY(hipMemcpy(S.data(), H->S[c] + ((size_t)b * npair + q) * RC, RC * sizeof(double),
+            HIP_TRY(hipMemcpy(S.data(), H->S[c] + bf * H->bS + ((size_t)b * npair + q) * RC, RC * sizeof(double),
                               hipMemcpyDeviceToHost));
             for (int r = 0; r < rk[q]; ++r) {
                 cd u, v;
-                HIP_TRY(hipMemcpy(&u, H->U[c] + H->Uoff[b] + ((size_t)q * RC + r) * ldU + (t1 - g.r0[b]),
+                HIP_TRY(hipMemcpy(&u, H->U[c] + bf * H->bU + H->Uoff[b] + ((size_t)q * RC + r) * ldU + (t1 - g.r0[b]),
                                   sizeof(cd), hipMemcpyDeviceToHost));
-                HIP_TRY(hipMemcpy(&v, H->V[c] + H->Voff[b] + ((size_t)q * RC + r) * ldV + (t2 - g.c0[b]),
+                HIP_TRY(hipMemcpy(&v, H->V[c] + bf * H->bV + H->Voff[b] + ((size_t)q * RC + r) * ldV + (t2 - g.c0[b]),
                                   sizeof(cd), hipMemcpyDeviceToHost));
                 acc = acc + S[r] * (u * conj(v));
             }
@@ -840,10 +952,19 @@ int hnessi_hodlr_ranks(hnessi_hodlr_t H, int c, int* ranks_host, int capacity) {
     const int per = H->g.nb * H->npair;
     const long long total = (long long)per * H->nk;
     if (capacity < total) return fail(HNESSI_E_ARG, "capacity too small");
+    int rc = drain(H, H->mstream);
+    if (rc != HNESSI_OK) return rc;
     HIP_TRY(hipDeviceSynchronize());
-    for (int o = 0; o < H->nk && per > 0; ++o)
-        HIP_TRY(hipMemcpy(ranks_host + (size_t)o * per, H->rank[c] + (size_t)o * H->oRank, per * sizeof(int),
+    std::vector<int> both((size_t)2 * per);
+    for (int o = 0; o < H->nk && per > 0; ++o) {
+        HIP_TRY(hipMemcpy(both.data(), H->rank[c] + (size_t)o * H->oRank, per * sizeof(int), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(both.data() + per, H->rank[c] + (size_t)o * H->oRank + H->bRank, per * sizeof(int),
                           hipMemcpyDeviceToHost));
+        for (int b = 0; b < H->g.nb; ++b)
+            for (int q = 0; q < H->npair; ++q)
+                ranks_host[(size_t)o * per + (size_t)b * H->npair + q] =
+                    both[(size_t)H->cur[c][b] * per + (size_t)b * H->npair + q];
+    }
     return (int)total;
 }
 
@@ -924,6 +1045,8 @@ int hnessi_compress_block(const void* A, int rows, int cols, int lda, double tol
         a.src = static_cast<const cd*>(A) + (size_t)p0 * lda;
         a.src_row = lda;
         a.src_pair = 0;
+        a.src_first = 0;
+        a.src_ring = 1 << 30;   // rows of A in place: no wrap
         a.nodeR = nodeR;
         a.nodeQ = nodeQ;
         a.nodecnt = nodecnt;

@@ -100,5 +100,6 @@ bool interval_weights_exact(int k, int L, std::vector<double>& w, std::string& e
 // constants of the device kernels
 constexpr int kCH = 256;      // factor rows per projection task
 constexpr int kTailCH = 64;   // columns per tail task
+constexpr int kTailRows = 32; // tail rows at most: the panel being merged and the one being formed
 
 }  // namespace hn

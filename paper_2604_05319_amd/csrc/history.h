@@ -16,7 +16,10 @@ struct HistArgs {
     int n;          // current step
     int n0[2];      // first row not yet merged, per component
     int last[2];    // last appended row, per component
-    int ls[2];      // columns [0, ls) of the rows still held dense (tail), per component
+    int ls[2];      // tail rows (n0..last) hold columns [0, ls) for rows >= nsplit and
+    int lslo[2];    // [0, lslo) for rows < nsplit (the panel whose merge is still in flight)
+    int nsplit[2];
+    int ring;       // tail row r sits in slot r % ring
     int nt, norb, npair, RC, nlvl, nb, P;
     int nk;         // objects in the batch (grid dimension y)
     int wantR, wantL;
@@ -30,6 +33,10 @@ struct HistArgs {
     const void* V[2];
     const double* S[2];
     const int* rank[2];
+    // double-buffered factors: block b of component c is read from buffer cur[c][b];
+    // buffer 1 of U / V / S / rank lies bU / bV / bS / bRank elements after buffer 0
+    const int* cur[2];
+    long long bU, bV, bS, bRank;
     const cd* leaf[2];
     const cd* tail[2];
     const cd* band;   // retarded band: band[(m*(k+1) + i)*npair + q] = G^R(m+i, m)

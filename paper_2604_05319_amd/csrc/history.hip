@@ -58,12 +58,22 @@ __device__ inline const cd* p_sigR(const HistArgs& A) { return A.sigR ? A.sigR +
 __device__ inline const cd* p_sigL(const HistArgs& A) { return A.sigL ? A.sigL + OBJ * A.kIn : nullptr; }
 __device__ inline cd* p_outR(const HistArgs& A) { return A.outR ? A.outR + OBJ * A.kOut : nullptr; }
 __device__ inline cd* p_outL(const HistArgs& A) { return A.outL ? A.outL + OBJ * A.kOut : nullptr; }
+// factor buffer holding block b's current TSVD
+__device__ inline long long buf_of(const HistArgs& A, int c, int b) { return A.cur[c][b] & 1; }
 template <class FT>
-__device__ inline const FT* p_U(const HistArgs& A, int c) { return static_cast<const FT*>(A.U[c]) + OBJ * A.kU; }
+__device__ inline const FT* p_U(const HistArgs& A, int c, int b) {
+    return static_cast<const FT*>(A.U[c]) + OBJ * A.kU + buf_of(A, c, b) * A.bU;
+}
 template <class FT>
-__device__ inline const FT* p_V(const HistArgs& A, int c) { return static_cast<const FT*>(A.V[c]) + OBJ * A.kV; }
-__device__ inline const double* p_S(const HistArgs& A, int c) { return A.S[c] + OBJ * A.kS; }
-__device__ inline const int* p_rank(const HistArgs& A, int c) { return A.rank[c] + OBJ * A.kRank; }
+__device__ inline const FT* p_V(const HistArgs& A, int c, int b) {
+    return static_cast<const FT*>(A.V[c]) + OBJ * A.kV + buf_of(A, c, b) * A.bV;
+}
+__device__ inline const double* p_S(const HistArgs& A, int c, int b) {
+    return A.S[c] + OBJ * A.kS + buf_of(A, c, b) * A.bS;
+}
+__device__ inline const int* p_rank(const HistArgs& A, int c, int b) {
+    return A.rank[c] + OBJ * A.kRank + buf_of(A, c, b) * A.bRank;
+}
 __device__ inline const cd* p_leaf(const HistArgs& A, int c) { return A.leaf[c] + OBJ * A.kLeaf; }
 __device__ inline const cd* p_tail(const HistArgs& A, int c) { return A.tail[c] + OBJ * A.kTail; }
 __device__ inline cd* p_tailcol(const HistArgs& A, int c) { return A.tailcol[c] + OBJ * A.kTailcol; }
@@ -78,7 +88,7 @@ __device__ inline cd* p_leafLL(const HistArgs& A) { return A.leafLL + OBJ * A.kL
 
 // ranks come from device memory: clamp them to the allocated capacity
 __device__ inline int rank_of(const HistArgs& A, int comp, int b, int q) {
-    const int r = p_rank(A, comp)[(size_t)b * A.npair + q];
+    const int r = p_rank(A, comp, b)[(size_t)b * A.npair + q];
     return r < 0 ? 0 : (r > A.RC ? A.RC : r);
 }
 
@@ -134,12 +144,12 @@ __device__ void fact_task(const HistArgs& A, const FactTask& t, unsigned char* s
         len = min(A.n0[comp] - r0, r1 - r0);
         base = r0;
         ld = r1 - r0;
-        F = p_U<FT>(A, comp) + A.Uoff[b] + (size_t)q * RC * ld;
+        F = p_U<FT>(A, comp, b) + A.Uoff[b] + (size_t)q * RC * ld;
     } else {
         len = c1 - c0;
         base = c0;
         ld = c1 - c0;
-        F = p_V<FT>(A, comp) + A.Voff[b] + (size_t)q * RC * ld;
+        F = p_V<FT>(A, comp, b) + A.Voff[b] + (size_t)q * RC * ld;
     }
     const int i0 = t.chunk * kCH, i1 = min(len, i0 + kCH);
     if (i0 >= i1) return;
@@ -176,7 +186,7 @@ __device__ void fact_task(const HistArgs& A, const FactTask& t, unsigned char* s
         for (int e = threadIdx.x; e < (i1 - i0) * NORB; e += NT) xs[e] = xval(i0 + e / NORB, e % NORB);
         __syncthreads();
     }
-    const double* S = p_S(A, comp) + ((size_t)b * npair + q) * RC;
+    const double* S = p_S(A, comp, b) + ((size_t)b * npair + q) * RC;
     const size_t slot = proj_slot(A, comp, b, q, which);
     cd* out = p_part(A) + (size_t)(A.partoff[slot] + t.chunk) * NORB * RC;
     for (int rp = 0; rp < rk; rp += 4 * RW) {
@@ -333,9 +343,9 @@ __device__ void tail_task(const HistArgs& A, int comp, int ag, int chunk, unsign
     const int n = A.n;
     const int n0 = A.n0[comp], nrows = A.last[comp] - n0 + 1, ls = A.ls[comp];
     const int cbeg = chunk * kTailCH, ncol = min(kTailCH, ls - cbeg);
-    cd* T = reinterpret_cast<cd*>(smem);       // 16 x 64 (rows beyond the tail's are zero)
-    cd* xr = T + (size_t)16 * kTailCH;         // 16 x AG  (row-side Sigma)
-    cd* xm = xr + (size_t)16 * AG;             // 64 x AG  (column-side Sigma)
+    cd* T = reinterpret_cast<cd*>(smem);       // 32 x 64 (entries outside the tail rows are zero)
+    cd* xr = T + (size_t)kTailRows * kTailCH;  // 32 x AG  (row-side Sigma)
+    cd* xm = xr + (size_t)kTailRows * AG;      // 64 x AG  (column-side Sigma)
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int a = ag * AG + wave;
     const bool wok = wave < AG;
@@ -344,17 +354,20 @@ __device__ void tail_task(const HistArgs& A, int comp, int ag, int chunk, unsign
     cd col[NORB], row[NORB];
 #pragma unroll
     for (int c = 0; c < NORB; ++c) col[c] = row[c] = mk(0.0, 0.0);
-    const int ri = lane & 15, part = lane >> 4;   // row-dot mapping: row ri, 16 columns per part
+    const int ri = lane & 31, part = lane >> 5;   // row-dot mapping: row ri, 32 columns per part
     // the next pair's tile and Sigma entries are loaded into registers while the
     // current pair is computed
-    constexpr int EPT = 16 * kTailCH / NT;   // tile elements per thread (P <= 16 rows)
+    constexpr int EPT = kTailRows * kTailCH / NT;   // tile elements per thread
     cd pT[EPT], pxr = mk(0.0, 0.0), pxm = mk(0.0, 0.0);
     auto fetch = [&](int q) {
         const int qr = q / NORB, qc = q % NORB;
 #pragma unroll
         for (int u = 0; u < EPT; ++u) {
             const int e = threadIdx.x + u * NT, i = e / kTailCH, mm = e % kTailCH;
-            pT[u] = (i < nrows && mm < ncol) ? Tg[((size_t)i * npair + q) * A.nt + cbeg + mm] : mk(0.0, 0.0);
+            const int r = n0 + i;                                   // tail row
+            const int lsr = r < A.nsplit[comp] ? A.lslo[comp] : ls; // its dense columns
+            pT[u] = (i < nrows && cbeg + mm < lsr)
+                        ? Tg[((size_t)(r % A.ring) * npair + q) * A.nt + cbeg + mm] : mk(0.0, 0.0);
         }
         const int e = threadIdx.x;
         if (e < nrows * AG) {     // row side, nrows * AG <= NT
@@ -399,10 +412,10 @@ __device__ void tail_task(const HistArgs& A, int comp, int ag, int chunk, unsign
             } else {
                 add_at(col, qr, -cs);               // -x1(j) G^<(m, j)^dagger
             }
-            // row dots (lane = row ri, columns 16*part .. +16)
+            // row dots (lane = row ri, columns 32*part .. +32)
             cd rd = mk(0.0, 0.0);
             if (ri < nrows) {
-                for (int mm = part * 16; mm < part * 16 + 16; ++mm) {
+                for (int mm = part * 32; mm < part * 32 + 32; ++mm) {
                     if (comp == 0) fmac_(rd, T[ri * kTailCH + mm], xm[mm * AG + wave]);
                     else fma_(rd, xm[mm * AG + wave], T[ri * kTailCH + mm]);
                 }
@@ -411,12 +424,10 @@ __device__ void tail_task(const HistArgs& A, int comp, int ag, int chunk, unsign
             else add_at(row, qc, rd);               // x1(m) G^<(m, j)
         }
     }
-    // reduce the four column parts of each row dot (lanes ri, ri+16, ri+32, ri+48)
+    // add the two column parts of each row dot (lanes ri and ri + 32)
 #pragma unroll
     for (int c = 0; c < NORB; ++c) {
         double re = row[c].x, im = row[c].y;
-        re += __shfl_xor(re, 16, 64);
-        im += __shfl_xor(im, 16, 64);
         re += __shfl_xor(re, 32, 64);
         im += __shfl_xor(im, 32, 64);
         row[c] = mk(re, im);
@@ -428,7 +439,7 @@ __device__ void tail_task(const HistArgs& A, int comp, int ag, int chunk, unsign
                 p_tailcol(A, comp)[(size_t)(cbeg + lane) * npair + a * NORB + c] = col[c];
         }
         if (part == 0 && ri < nrows) {
-            cd* tp = p_tailpart(A, comp) + ((size_t)chunk * A.P + ri) * npair + a * NORB;
+            cd* tp = p_tailpart(A, comp) + ((size_t)chunk * A.ring + ri) * npair + a * NORB;
 #pragma unroll
             for (int c = 0; c < NORB; ++c) tp[c] = row[c];
         }
@@ -486,14 +497,14 @@ __global__ void __launch_bounds__(256) proj_reduce(HistArgs A) {
         const long long w = ((long long)blockIdx.x - nblk) * 4 + (threadIdx.x >> 6);
         const int lane = threadIdx.x & 63;
         const int q = (int)(w % npair);
-        const int slot = (int)((w / npair) % A.P);
-        const int comp = (int)(w / ((long long)npair * A.P));
+        const int slot = (int)((w / npair) % A.ring);
+        const int comp = (int)(w / ((long long)npair * A.ring));
         if (comp > 1 || !A.wantL || (comp == 1 && A.adj)) return;
         if (slot > A.last[comp] - A.n0[comp]) return;   // also: no tail rows at all
         const cd* tp = p_tailpart(A, comp) + (size_t)slot * npair + q;
         double re = 0.0, im = 0.0;
         for (int ch = lane; ch < A.ntailchunk[comp]; ch += 64) {
-            const cd v = tp[(size_t)ch * A.P * npair];
+            const cd v = tp[(size_t)ch * A.ring * npair];
             re += v.x;
             im += v.y;
         }
@@ -594,7 +605,7 @@ __global__ void __launch_bounds__(64 * CombMap<NORB>::WAVES) hist_combine(HistAr
                         for (int o = g; o < NORB; o += G) {
                             const int q = o * NORB + c;
                             const int rk = rank_of(A, 0, b, q);
-                            const FT* Vq = p_V<FT>(A, 0) + A.Voff[b] + (size_t)q * RC * ldV + (m - c0);
+                            const FT* Vq = p_V<FT>(A, 0, b) + A.Voff[b] + (size_t)q * RC * ldV + (m - c0);
                             const cd* z = p_proj(A) + proj_slot(A, 0, b, q, 0) * NORB * RC;
                             if (rk > 0) expand_ranks<NORB, true, false>(accR, Vq, ldV, z, RC, rk);
                         }
@@ -603,7 +614,7 @@ __global__ void __launch_bounds__(64 * CombMap<NORB>::WAVES) hist_combine(HistAr
                         for (int o = g; o < NORB; o += G) {
                             const int q = c * NORB + o;
                             const int rk = rank_of(A, 1, b, q);
-                            const FT* Vq = p_V<FT>(A, 1) + A.Voff[b] + (size_t)q * RC * ldV + (m - c0);
+                            const FT* Vq = p_V<FT>(A, 1, b) + A.Voff[b] + (size_t)q * RC * ldV + (m - c0);
                             const cd* z = p_proj(A) + proj_slot(A, 1, b, q, 0) * NORB * RC;
                             if (rk > 0) expand_ranks<NORB, false, true>(accL, Vq, ldV, z, RC, rk);
                         }
@@ -616,7 +627,7 @@ __global__ void __launch_bounds__(64 * CombMap<NORB>::WAVES) hist_combine(HistAr
                         for (int o = g; o < NORB; o += G) {
                             const int q = c * NORB + o;
                             const int rk = rank_of(A, 0, b, q);
-                            const FT* Uq = p_U<FT>(A, 0) + A.Uoff[b] + (size_t)q * RC * ldU + (m - r0);
+                            const FT* Uq = p_U<FT>(A, 0, b) + A.Uoff[b] + (size_t)q * RC * ldU + (m - r0);
                             const cd* z = p_proj(A) + proj_slot(A, 0, b, q, 1) * NORB * RC;
                             if (rk > 0) expand_ranks<NORB, true, false>(accL, Uq, ldU, z, RC, rk);
                         }
@@ -625,7 +636,7 @@ __global__ void __launch_bounds__(64 * CombMap<NORB>::WAVES) hist_combine(HistAr
                         for (int o = g; o < NORB; o += G) {
                             const int q = o * NORB + c;
                             const int rk = rank_of(A, 1, b, q);
-                            const FT* Uq = p_U<FT>(A, 1) + A.Uoff[b] + (size_t)q * RC * ldU + (m - r0);
+                            const FT* Uq = p_U<FT>(A, 1, b) + A.Uoff[b] + (size_t)q * RC * ldU + (m - r0);
                             const cd* z = p_proj(A) + proj_slot(A, 1, b, q, 1) * NORB * RC;
                             if (rk > 0) expand_ranks<NORB, false, false>(accL, Uq, ldU, z, RC, rk);
                         }
@@ -731,7 +742,7 @@ size_t tasks_smem(int norb) {
     const int ag = norb < 4 ? norb : 4;
     size_t fact = norb <= 8 ? (size_t)kCH * norb * sizeof(cd) : 0;
     size_t leaf = (size_t)(tri(64) + 2 * 64 * ag) * sizeof(cd);
-    size_t tail = (size_t)(16 * kTailCH + (16 + kTailCH) * ag) * sizeof(cd);
+    size_t tail = (size_t)(kTailRows * kTailCH + (kTailRows + kTailCH) * ag) * sizeof(cd);
     size_t s = fact > leaf ? fact : leaf;
     return s > tail ? s : tail;
 }
@@ -743,7 +754,7 @@ hipError_t launch_t(const HistArgs& a, hipStream_t st, hipEvent_t* ev) {
     if (ntask > 0) hist_tasks<NORB, FT><<<dim3(ntask, a.nk), NT, tasks_smem(NORB), st>>>(a);
     if (ev) hipEventRecord(ev[1], st);
     {
-        const long long nb1 = proj_reduce_blocks(a), nb2 = (2LL * a.P * NORB * NORB + 3) / 4;
+        const long long nb1 = proj_reduce_blocks(a), nb2 = (2LL * a.ring * NORB * NORB + 3) / 4;
         proj_reduce<NORB><<<dim3((unsigned)(nb1 + nb2), a.nk), 256, 0, st>>>(a);
     }
     if (ev) hipEventRecord(ev[2], st);

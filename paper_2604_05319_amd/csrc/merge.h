@@ -23,6 +23,8 @@ struct MergeBlk {
     int nnodes;     // tree nodes per pair (2 * nchunks)
     long long node_base;  // first node of pair 0 of this block in the scratch
     long long Uoff, Voff; // element offsets of the block in U / V (pair 0, rank 0)
+    int rd;               // factor buffer holding the block's current TSVD (read); the
+                          // update goes to buffer rd ^ flip
 };
 
 struct MergeArgs {
@@ -34,15 +36,17 @@ struct MergeArgs {
     MergeBlk blk[kMaxMergeBlk];
     int ntask_v;   // chunk tasks (merge_up grid; first part of merge_down grid)
     int ntask_u;   // U-row tasks (second part of merge_down grid)
-    cd* U;         // FP64 factors (the merge works on these)
+    cd* U;         // FP64 factors (the merge works on these), buffer 0
     cd* V;
     cf* U32;       // complex-float mirrors of U and V read by the history kernels, or nullptr
     cf* V32;
     double* S;
     int* rank;
-    // panel row i, pair q, absolute column s at src[i*src_row + q*src_pair + s]
+    // panel row i, pair q, absolute column s at src[slot*src_row + q*src_pair + s]
+    // with slot = (src_first + i) % src_ring
     const cd* src;
     long long src_row, src_pair;
+    int src_first, src_ring;
     // scratch
     cd* nodeR;     // [node][W*W]
     cd* nodeQ;     // [node][kNodeQ]
@@ -52,11 +56,19 @@ struct MergeArgs {
     double* Sold;  // [problem][W]
     int* rold;     // [problem]
     int* err;      // device error flags (bit 0: rank cap reached)
+    // double buffering: buffer 1 of U / V (and mirrors) / S / rank lies bU / bV / bS /
+    // bRank elements after buffer 0; flip = 1 writes the update into the other buffer,
+    // flip = 0 updates in place
+    int flip;
+    long long bU, bV, bS, bRank;
     // batched objects (grid dimension y): element strides from one object to the next
     long long kU, kV, kS, kRank, kSrc, kNodeR, kNodeQ, kNodeCnt, kProbW2, kProbW, kProb;
 };
 
 hipError_t launch_merge(const MergeArgs& a, int nk, hipStream_t st);
+// cur[b] ^= 1 for the n blocks listed (n <= kMaxMergeBlk): the merged blocks'
+// updated TSVDs become current
+hipError_t launch_flip(int* cur, const int* blocks, int n, hipStream_t st);
 hipError_t merge_init();
 
 }  // namespace hn

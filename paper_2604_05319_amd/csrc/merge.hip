@@ -270,6 +270,22 @@ __device__ inline cd* m_VR(const MergeArgs& a) { return a.VR + OBJ * a.kProbW2; 
 __device__ inline double* m_Sold(const MergeArgs& a) { return a.Sold + OBJ * a.kProbW; }
 __device__ inline int* m_rold(const MergeArgs& a) { return a.rold + OBJ * a.kProb; }
 
+// the block's current (read) and updated (write) factor buffers
+__device__ inline const cd* rd_U(const MergeArgs& a, const MergeBlk& B) { return m_U(a) + B.rd * a.bU; }
+__device__ inline const cd* rd_V(const MergeArgs& a, const MergeBlk& B) { return m_V(a) + B.rd * a.bV; }
+__device__ inline const double* rd_S(const MergeArgs& a, const MergeBlk& B) { return m_S(a) + B.rd * a.bS; }
+__device__ inline const int* rd_rank(const MergeArgs& a, const MergeBlk& B) { return m_rank(a) + B.rd * a.bRank; }
+__device__ inline cd* wr_U(const MergeArgs& a, const MergeBlk& B) { return m_U(a) + (B.rd ^ a.flip) * a.bU; }
+__device__ inline cd* wr_V(const MergeArgs& a, const MergeBlk& B) { return m_V(a) + (B.rd ^ a.flip) * a.bV; }
+__device__ inline double* wr_S(const MergeArgs& a, const MergeBlk& B) { return m_S(a) + (B.rd ^ a.flip) * a.bS; }
+__device__ inline int* wr_rank(const MergeArgs& a, const MergeBlk& B) { return m_rank(a) + (B.rd ^ a.flip) * a.bRank; }
+__device__ inline cf* wr_U32(const MergeArgs& a, const MergeBlk& B) {
+    return a.U32 ? m_U32(a) + (B.rd ^ a.flip) * a.bU : nullptr;
+}
+__device__ inline cf* wr_V32(const MergeArgs& a, const MergeBlk& B) {
+    return a.V32 ? m_V32(a) + (B.rd ^ a.flip) * a.bV : nullptr;
+}
+
 // ranks come from device memory; every index derived from them is kept
 // inside the capacity the host allocated, whatever the memory holds
 __device__ inline int clamp_rank(int r, int cap) { return r < 0 ? 0 : (r > cap ? cap : r); }
@@ -315,7 +331,7 @@ __device__ void chunk_qr(const MergeArgs& a, const Ctx& c, int r_old, const doub
     const int w = r_old + a.pp;
     const int row0 = c.chunk * kCH;
     const int nr = min(kCH, B.ncols - row0);
-    const cd* V = m_V(a) + B.Voff + (size_t)c.q * a.RC * B.ncols;
+    const cd* V = rd_V(a, B) + B.Voff + (size_t)c.q * a.RC * B.ncols;
     for (int idx = threadIdx.x; idx < kCH * w; idx += NT) {
         int col = idx / kCH, i = idx % kCH;
         cd z = mk(0.0, 0.0);
@@ -325,7 +341,8 @@ __device__ void chunk_qr(const MergeArgs& a, const Ctx& c, int r_old, const doub
                 z = s_old[col] * V[(size_t)col * B.ncols + s];
             } else {
                 int pr = col - r_old;
-                z = conj(m_src(a)[(size_t)pr * a.src_row + (size_t)c.q * a.src_pair + B.c0 + s]);
+                const size_t slot = (size_t)((a.src_first + pr) % a.src_ring);
+                z = conj(m_src(a)[slot * a.src_row + (size_t)c.q * a.src_pair + B.c0 + s]);
             }
         }
         A[idx] = z;
@@ -352,9 +369,9 @@ __global__ void __launch_bounds__(NT) merge_up_kernel(MergeArgs a) {
     const MergeBlk& B = *c.B;
     const size_t pidx = prob_index(a, c);
     const size_t fq = (size_t)B.b * a.npair + c.q;
-    const int r_old = clamp_rank(m_rank(a)[fq], a.RC);
+    const int r_old = clamp_rank(rd_rank(a, B)[fq], a.RC);
     const int w = r_old + a.pp;
-    for (int i = threadIdx.x; i < W; i += NT) s_old[i] = i < r_old ? m_S(a)[fq * a.RC + i] : 0.0;
+    for (int i = threadIdx.x; i < W; i += NT) s_old[i] = i < r_old ? rd_S(a, B)[fq * a.RC + i] : 0.0;
     __syncthreads();
 
     chunk_qr<W>(a, c, r_old, s_old, A, tau, red);
@@ -452,10 +469,10 @@ __global__ void __launch_bounds__(NT) merge_up_kernel(MergeArgs a) {
     }
     if (threadIdx.x == 0) {
         m_rold(a)[pidx] = r_old;
-        m_rank(a)[fq] = rnew;
+        wr_rank(a, B)[fq] = rnew;
     }
     for (int i = threadIdx.x; i < W; i += NT) m_Sold(a)[pidx * W + i] = s_old[i];
-    for (int i = threadIdx.x; i < a.RC; i += NT) m_S(a)[fq * a.RC + i] = i < rnew ? ssig[sperm[i]] : 0.0;
+    for (int i = threadIdx.x; i < a.RC; i += NT) wr_S(a, B)[fq * a.RC + i] = i < rnew ? ssig[sperm[i]] : 0.0;
     cd* UK = m_UK(a) + pidx * W * W;
     cd* VR = m_VR(a) + pidx * W * W;
     for (int e = threadIdx.x; e < w * rnew; e += NT) {
@@ -483,7 +500,7 @@ __global__ void __launch_bounds__(NT) merge_down_kernel(MergeArgs a) {
         const size_t pidx = prob_index(a, c);
         const size_t fq = (size_t)B.b * a.npair + c.q;
         const int r_old = clamp_rank(m_rold(a)[pidx], a.RC);
-        const int rnew = clamp_rank(m_rank(a)[fq], a.RC);
+        const int rnew = clamp_rank(wr_rank(a, B)[fq], a.RC);
         const int w = r_old + a.pp;
         for (int i = threadIdx.x; i < W; i += NT) s_old[i] = m_Sold(a)[pidx * W + i];
         __syncthreads();
@@ -528,8 +545,8 @@ __global__ void __launch_bounds__(NT) merge_down_kernel(MergeArgs a) {
         const int row0 = c.chunk * CH;
         const int nr = min(CH, B.ncols - row0);
         const size_t vo = B.Voff + (size_t)c.q * a.RC * B.ncols;
-        cd* V = m_V(a) + vo;
-        cf* V32 = a.V32 ? m_V32(a) + vo : nullptr;
+        cd* V = wr_V(a, B) + vo;
+        cf* V32 = a.V32 ? wr_V32(a, B) + vo : nullptr;
         for (int e = threadIdx.x; e < nr * rnew; e += NT) {
             int col = e / nr, i = e % nr;
             const cd x = X[(size_t)col * CH + i];
@@ -548,18 +565,19 @@ __global__ void __launch_bounds__(NT) merge_down_kernel(MergeArgs a) {
     const size_t pidx = (size_t)s * a.npair + q;
     const size_t fq = (size_t)B.b * a.npair + q;
     const int r_old = clamp_rank(m_rold(a)[pidx], a.RC);
-    const int rnew = clamp_rank(m_rank(a)[fq], a.RC);
+    const int rnew = clamp_rank(wr_rank(a, B)[fq], a.RC);
     const cd* UK = m_UK(a) + pidx * W * W;
     const size_t uo = B.Uoff + (size_t)q * a.RC * B.ldU;
-    cd* U = m_U(a) + uo;
-    cf* U32 = a.U32 ? m_U32(a) + uo : nullptr;
+    const cd* Uold = rd_U(a, B) + uo;
+    cd* U = wr_U(a, B) + uo;
+    cf* U32 = a.U32 ? wr_U32(a, B) + uo : nullptr;
     const int row = ut * NT + threadIdx.x;
     const int nrows = B.kb + a.pp;
     if (row >= nrows) return;
     if (row < B.kb) {
         cd u[W];
 #pragma unroll
-        for (int r = 0; r < W; ++r) u[r] = (r < r_old) ? U[(size_t)r * B.ldU + row] : mk(0.0, 0.0);
+        for (int r = 0; r < W; ++r) u[r] = (r < r_old) ? Uold[(size_t)r * B.ldU + row] : mk(0.0, 0.0);
         for (int col = 0; col < rnew; ++col) {
             cd acc = mk(0.0, 0.0);
 #pragma unroll
@@ -590,6 +608,26 @@ hipError_t launch_merge(const MergeArgs& a, int nk, hipStream_t st) {
     if (a.ntask_v == 0) return hipSuccess;
     merge_up_kernel<<<dim3(a.ntask_v, nk), NT, merge_up_smem(), st>>>(a);
     merge_down_kernel<<<dim3(a.ntask_v + a.ntask_u, nk), NT, merge_down_smem(), st>>>(a);
+    return hipGetLastError();
+}
+
+struct FlipList {
+    int n;
+    int b[kMaxMergeBlk];
+};
+
+__global__ void flip_kernel(int* cur, FlipList f) {
+    const int i = threadIdx.x;
+    if (i < f.n) cur[f.b[i]] ^= 1;
+}
+
+hipError_t launch_flip(int* cur, const int* blocks, int n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (n > kMaxMergeBlk) return hipErrorInvalidValue;
+    FlipList f{};
+    f.n = n;
+    for (int i = 0; i < n; ++i) f.b[i] = blocks[i];
+    flip_kernel<<<1, 64, 0, st>>>(cur, f);
     return hipGetLastError();
 }
 
