@@ -488,8 +488,8 @@ __global__ void __launch_bounds__(NT) merge_down_kernel(MergeArgs a) {
     constexpr int W = kW, CH = kMergeCH;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cd* A = reinterpret_cast<cd*>(smem_raw);       // CH x W
-    cd* X = A + (size_t)CH * W;                     // CH x W
-    cd* T = X + (size_t)CH * W;                     // W x W
+    cd* X = A + (size_t)CH * W;                     // CH x RC (the updated V rows, rank <= RC)
+    cd* T = X + (size_t)CH * a.RC;                  // W x W
     cd* tau = T + (size_t)W * W;                    // W
     double* red = reinterpret_cast<double*>(tau + W);
     __shared__ double s_old[W];
@@ -599,15 +599,17 @@ __global__ void __launch_bounds__(NT) merge_down_kernel(MergeArgs a) {
 static size_t merge_up_smem() {
     return (size_t)kMergeCH * kW * sizeof(cd) + (size_t)kW * sizeof(cd) + 16 * sizeof(double);
 }
-static size_t merge_down_smem() {
-    return (size_t)2 * kMergeCH * kW * sizeof(cd) + (size_t)kW * kW * sizeof(cd) +
+// sized by the rank capacity, so that a merge_down workgroup leaves room on its
+// compute unit for a history workgroup
+static size_t merge_down_smem(int RC) {
+    return (size_t)kMergeCH * kW * sizeof(cd) + (size_t)kMergeCH * RC * sizeof(cd) + (size_t)kW * kW * sizeof(cd) +
            (size_t)kW * sizeof(cd) + 16 * sizeof(double);
 }
 
 hipError_t launch_merge(const MergeArgs& a, int nk, hipStream_t st) {
     if (a.ntask_v == 0) return hipSuccess;
     merge_up_kernel<<<dim3(a.ntask_v, nk), NT, merge_up_smem(), st>>>(a);
-    merge_down_kernel<<<dim3(a.ntask_v + a.ntask_u, nk), NT, merge_down_smem(), st>>>(a);
+    merge_down_kernel<<<dim3(a.ntask_v + a.ntask_u, nk), NT, merge_down_smem(a.RC), st>>>(a);
     return hipGetLastError();
 }
 
@@ -636,7 +638,7 @@ hipError_t merge_init() {
                                        (int)merge_up_smem());
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void*)merge_down_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)merge_down_smem());
+                               (int)merge_down_smem(kW));
 }
 
 }  // namespace hn
