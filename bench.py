@@ -107,6 +107,29 @@ def cpu_baseline(cfg, G, S, budget_s):
                        f"{total:.3e} summands of a full N_t={N} sweep (single-threaded NumPy)")
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of the history tasks kernel from the committed counter summary,
+    or None if the kernel source changed since the counters were taken."""
+    import hashlib
+    if kernel != "hist_tasks":
+        return None
+    path = os.path.join(ROOT, "profiles", "hist_tasks_traffic_c2_norb4_nt8192.txt")
+    src = os.path.join(ROOT, "paper_2604_05319_amd", "csrc", "history.hip")
+    try:
+        txt = open(path).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    vals = {}
+    for line in txt.splitlines():
+        if "=" in line:
+            k, v = line.rsplit("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source history.hip sha256[:16]") != sha:
+        return None
+    return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
+
+
 def lattice_bench(P, prof_stride):
     """Batched form at the lattice workload: 32x32 momenta (nk = 1024), N_t = 2048, norb = 1,
     one handle for all momenta; one timed sweep (append both rows, merges, history step)."""
@@ -220,6 +243,8 @@ def main():
     ap.add_argument("--nt", type=int, default=None, help="override N_t (testing only)")
     ap.add_argument("--no-lattice", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one plain 1 GiB device copy first (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -232,6 +257,13 @@ def main():
     from kbe_inputs import make_config_inputs
     from kbe_inputs.packed import packed_torch
 
+    if args.copy_probe:
+        x = torch.ones(1 << 26, dtype=torch.complex128, device="cuda:0")   # 1 GiB
+        y = torch.empty_like(x)
+        torch.neg(x, out=y)          # one elementwise kernel: reads x once, writes y once
+        torch.cuda.synchronize()
+        log(f"copy probe: {x.numel() * 16} bytes read and written")
+        del x, y
     cfg, G, S = make_config_inputs("c2")
     if args.nt:
         cfg["nt"] = args.nt
@@ -285,8 +317,10 @@ def main():
     dominant = max(("hist_tasks", "hist_combine"), key=lambda nm: kern[nm][1].sum())
     bsel, msel = (b_tasks, ms0) if dominant == "hist_tasks" else (b_comb, ms1)
     achieved = float(bsel.sum() / (msel.sum() * 1e-3) / 1e9)
+    traffic = measured_traffic(dominant)
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                traffic_unit="bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)",
                 kernel=dominant, launches_timed=int(len(msel)),
                 avg_launch_us=round(float(msel.mean()) * 1e3, 2),
                 avg_alg_bytes_per_launch=float(bsel.mean()))
