@@ -42,11 +42,11 @@ def panel_schedule(N, P, leaves):
     return n0s, row_leaf
 
 
-def algorithmic_bytes(N, npair, P, blocks, leaves, ranks, steps, nk=1):
+def algorithmic_bytes(N, npair, P, blocks, leaves, ranks, steps, nk=1, zf=16):
     """Bytes each history kernel must move at the given steps (both components, all nk objects).
 
     tasks:   every stored factor row once (U rows merged so far, all V rows of
-             active blocks, at the blocks' ranks), the present part of every
+             active blocks, at the blocks' ranks; zf bytes per entry), the present part of every
              leaf triangle, the dense tail rows, and the two Sigma rows.
     combine: every stored factor row once (the expansions), and the two output rows.
     """
@@ -66,7 +66,7 @@ def algorithmic_bytes(N, npair, P, blocks, leaves, ranks, steps, nk=1):
         for c in (0, 1):
             for b, (lvl, r0, r1, c0, c1) in enumerate(blocks):
                 if n0 > r0:
-                    fac += rsum[c][b] * (min(n0 - r0, r1 - r0) + (c1 - c0)) * zb
+                    fac += rsum[c][b] * (min(n0 - r0, r1 - r0) + (c1 - c0)) * zf
         lf = 0
         for (s0, s1) in leaves:
             if s0 <= n:
@@ -128,6 +128,65 @@ def measured_traffic(kernel):
     if vals.get("kernel_source history.hip sha256[:16]") != sha:
         return None
     return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
+
+
+def fp32_bench(P, steps_timed=256):
+    """FP32-factor form at its workload (norb = 16, N_t = 8192, eps 1e-6).  Its packed inputs
+    (137 GB per triangle) do not fit, so rows come from the device generator: the first
+    N_t - steps_timed rows are appended untimed (with their merges; the history step reads the
+    stored state without changing it), then the last steps_timed full time steps are timed with
+    their rows already in HBM."""
+    import numpy as np
+    import torch
+    from kbe_inputs import make_config_inputs
+    from kbe_inputs.packed import RowSource
+    cfg, G, S = make_config_inputs("c4")
+    N, h, k, norb = cfg["nt"], cfg["h"], cfg["k"], cfg["norb"]
+    nlvl = int(round(np.log2(N // cfg["leaf"])))
+    dev = torch.device("cuda:0")
+    gs, ss = RowSource(G, N, h, dev), RowSource(S, N, h, dev)
+    n_first = N - steps_timed
+    offs = [0]
+    for n in range(n_first, N):
+        offs.append(offs[-1] + n + 1)
+    gl = torch.empty((offs[-1], norb, norb), dtype=torch.complex128, device=dev)
+    sl = torch.empty_like(gl)
+    for i, n in enumerate(range(n_first, N)):
+        gs.les(n, gl[offs[i]:offs[i + 1]])
+        ss.les(n, sl[offs[i]:offs[i + 1]])
+    outR = torch.empty((N, norb, norb), dtype=torch.complex128, device=dev)
+    outL = torch.empty_like(outR)
+    H = P.Hodlr(N, nlvl, norb, k=k, tol=cfg["tol"], panel=16, max_rank=16, flags=P.FLAG_FP32_FACTORS)
+    t = time.perf_counter()
+    for n in range(n_first):
+        H.append_row(P.RET, n, gs.ret(n))
+        H.append_row(P.LES, n, gs.les(n))
+    torch.cuda.synchronize()
+    log(f"fp32 form: {n_first} rows appended and merged in {time.perf_counter() - t:.1f} s")
+    H.profile(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, n in enumerate(range(n_first, N)):
+        H.append_row(P.RET, n, gs.ret(n))
+        H.append_row(P.LES, n, gl[offs[i]:offs[i + 1]])
+        H.history_step(n, ss.ret(n), sl[offs[i]:offs[i + 1]], h, outR[:n + 1], outL[:n + 1])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st0, ms0 = H.profile_read(0)
+    _, ms1 = H.profile_read(1)
+    ranks = [H.ranks(P.RET), H.ranks(P.LES)]
+    b_tasks, b_comb = algorithmic_bytes(N, norb * norb, 16, H.blocks(), H.leaves(), ranks, list(st0), zf=8)
+    out = dict(value=round(steps_timed / dt, 2),
+               unit=f"time steps/s over the last {steps_timed} steps (n = {n_first}..{N - 1})",
+               n_t=N, norb=norb, eps=cfg["tol"], status=H.status(), max_rank=int(max(r.max() for r in ranks)),
+               hist_tasks_gbs=round(float(b_tasks.sum() / (ms0.sum() * 1e-3) / 1e9), 1),
+               hist_combine_gbs=round(float(b_comb.sum() / (ms1.sum() * 1e-3) / 1e9), 1),
+               device_gib=round(H.nbytes() / 2**30, 2))
+    H.profile(0)
+    H.close()
+    del gl, sl
+    torch.cuda.empty_cache()
+    return out
 
 
 def lattice_bench(P, prof_stride):
@@ -243,6 +302,7 @@ def main():
     ap.add_argument("--nt", type=int, default=None, help="override N_t (testing only)")
     ap.add_argument("--no-lattice", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 1 GiB device copy first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -378,6 +438,11 @@ def main():
         lattice = lattice_bench(P, args.prof_stride)
         log("lattice:", lattice)
 
+    fp32 = None
+    if not args.no_fp32:
+        fp32 = fp32_bench(P)
+        log("fp32 form:", fp32)
+
     adjoint = None
     if not args.no_adjoint:
         adjoint = adjoint_bench(P)
@@ -403,6 +468,7 @@ def main():
         "dense": dense,
         "lattice": lattice,
         "adjoint": adjoint,
+        "fp32_factors": fp32,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -129,7 +129,7 @@ __device__ void fact_task(const HistArgs& A, const FactTask& t, unsigned char* s
     if ((comp == 1 || which == 1) && !A.wantL) return;
     if (comp == 1 && A.adj) return;
     constexpr int npair = NORB * NORB;
-    constexpr bool kStage = NORB <= 8;             // Sigma rows staged in LDS
+    constexpr bool kStage = true;                  // Sigma rows staged in LDS (kCH x NORB)
     constexpr int RW = ProjRanks<NORB>::RW;
     constexpr int RPL = kCH / 64;                  // rows per lane
     const int RC = A.RC;
@@ -740,7 +740,7 @@ __global__ void __launch_bounds__(64 * CombMap<NORB>::WAVES) hist_combine(HistAr
 
 size_t tasks_smem(int norb) {
     const int ag = norb < 4 ? norb : 4;
-    size_t fact = norb <= 8 ? (size_t)kCH * norb * sizeof(cd) : 0;
+    size_t fact = (size_t)kCH * norb * sizeof(cd);
     size_t leaf = (size_t)(tri(64) + 2 * 64 * ag) * sizeof(cd);
     size_t tail = (size_t)(kTailRows * kTailCH + (kTailRows + kTailCH) * ag) * sizeof(cd);
     size_t s = fact > leaf ? fact : leaf;
