@@ -134,7 +134,7 @@ struct hnessi_hodlr_s {
     // per-object element counts of the batched arrays (the stride between objects)
     long long oU = 0, oV = 0, oS = 0, oRank = 0, oLeaf = 0, oTail = 0, oBand = 0, oProj = 0, oPart = 0,
               oLeafOut = 0, oTailcol = 0, oTailpart = 0, oTailrow = 0, oNodeR = 0, oNodeQ = 0, oNodeCnt = 0, oProbW2 = 0,
-              oProbW = 0, oProb = 0;
+              oProbW = 0, oProb = 0, oChunkQ = 0;
     double tol = 0.0;
     Weights W{};
     Geometry g;
@@ -191,8 +191,10 @@ struct hnessi_hodlr_s {
     // merge scratch
     std::vector<long long> lvl_node_base;  // per level: first node of pair 0
     std::vector<int> lvl_nodes;            // per level: nodes per pair
+    std::vector<long long> lvl_chunk_base; // per level: first chunk slot of pair 0
     cd* nodeR = nullptr;
     cd* nodeQ = nullptr;
+    cd* chunkQ = nullptr;
     int* nodecnt = nullptr;
     cd* UK = nullptr;
     cd* VR = nullptr;
@@ -378,7 +380,8 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
     // merge scratch: one block per level per panel
     H->lvl_node_base.assign(nlvl + 1, 0);
     H->lvl_nodes.assign(nlvl + 1, 0);
-    long long nodes = 0;
+    H->lvl_chunk_base.assign(nlvl + 1, 0);
+    long long nodes = 0, chunks = 0;
     for (int l = 1; l <= nlvl; ++l) {
         int maxc = 0;
         for (int b = 0; b < nb; ++b)
@@ -386,10 +389,13 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
         H->lvl_nodes[l] = 2 * div_up(maxc, kMergeCH);
         H->lvl_node_base[l] = nodes;
         nodes += (long long)npair * H->lvl_nodes[l];
+        H->lvl_chunk_base[l] = chunks;
+        chunks += (long long)npair * div_up(maxc, kMergeCH);
     }
     const long long nprob = (long long)std::max(nlvl, 1) * npair;
     HALLOC_K(H->nodeR, (size_t)std::max(nodes, 1LL) * kW * kW, false, H->oNodeR);
     HALLOC_K(H->nodeQ, (size_t)std::max(nodes, 1LL) * kNodeQ, false, H->oNodeQ);
+    HALLOC_K(H->chunkQ, (size_t)std::max(chunks, 1LL) * kChunkQ, false, H->oChunkQ);
     HALLOC_K(H->nodecnt, (size_t)std::max(nodes, 1LL), true, H->oNodeCnt);
     HALLOC_K(H->UK, (size_t)nprob * kW * kW, false, H->oProbW2);
     HALLOC_K(H->VR, (size_t)nprob * kW * kW, false, H->oProbW2);
@@ -515,6 +521,8 @@ int merge_panel(hnessi_hodlr_t H, int c, int p0, int p1, hipStream_t st, std::ve
     a.src_pair = H->nt;
     a.nodeR = H->nodeR;
     a.nodeQ = H->nodeQ;
+    a.chunkQ = H->chunkQ;
+    a.kChunkQ = H->oChunkQ;
     a.nodecnt = H->nodecnt;
     a.UK = H->UK;
     a.VR = H->VR;
@@ -550,6 +558,7 @@ int merge_panel(hnessi_hodlr_t H, int c, int p0, int p1, hipStream_t st, std::ve
         B.nutask = div_up(B.kb + a.pp, 256);
         B.nnodes = H->lvl_nodes[g.level[b]];
         B.node_base = H->lvl_node_base[g.level[b]];
+        B.chunk_base = H->lvl_chunk_base[g.level[b]];
         B.Uoff = H->Uoff[b];
         B.Voff = H->Voff[b];
         B.rd = H->cur[c][b];
@@ -1020,11 +1029,12 @@ int hnessi_compress_block(const void* A, int rows, int cols, int lda, double tol
     const int P = std::max(1, std::min(16, kW - max_rank));
     const int nch = div_up(cols, kMergeCH);
     Allocs al;
-    cd *nodeR, *nodeQ, *UK, *VR;
+    cd *nodeR, *nodeQ, *chunkQ, *UK, *VR;
     int *nodecnt, *rold, *err;
     double* Sold;
     ALLOC(al, nodeR, (size_t)2 * nch * kW * kW, false);
     ALLOC(al, nodeQ, (size_t)2 * nch * kNodeQ, false);
+    ALLOC(al, chunkQ, (size_t)nch * kChunkQ, false);
     ALLOC(al, nodecnt, (size_t)2 * nch, true);
     ALLOC(al, UK, (size_t)kW * kW, false);
     ALLOC(al, VR, (size_t)kW * kW, false);
@@ -1049,6 +1059,7 @@ int hnessi_compress_block(const void* A, int rows, int cols, int lda, double tol
         a.src_ring = 1 << 30;   // rows of A in place: no wrap
         a.nodeR = nodeR;
         a.nodeQ = nodeQ;
+        a.chunkQ = chunkQ;
         a.nodecnt = nodecnt;
         a.UK = UK;
         a.VR = VR;
@@ -1067,6 +1078,7 @@ int hnessi_compress_block(const void* A, int rows, int cols, int lda, double tol
         B.nutask = div_up(p0 + a.pp, 256);
         B.nnodes = 2 * nch;
         B.node_base = 0;
+        B.chunk_base = 0;
         B.Uoff = 0;
         B.Voff = 0;
         a.nblk = 1;

@@ -9,6 +9,7 @@ constexpr int kW = 32;                  // max width r + panel of a merge (SVD s
 constexpr int kMergeCH = 128;           // rows of Z per chunk workgroup
 constexpr int kMaxMergeBlk = 24;        // blocks merged by one panel (<= nlvl)
 constexpr int kNodeQ = 2 * kW * kW + kW;  // reflectors (2W x W) + tau (W) of a tree node
+constexpr int kChunkQ = kMergeCH * kW + kW;  // reflectors (CH x W) + tau (W) of a chunk
 
 struct MergeBlk {
     int b;          // block index in the factor arrays (rank/S are [b][pair])
@@ -22,6 +23,7 @@ struct MergeBlk {
     int nutask;     // U tasks per pair
     int nnodes;     // tree nodes per pair (2 * nchunks)
     long long node_base;  // first node of pair 0 of this block in the scratch
+    long long chunk_base; // first chunk slot of pair 0 of this block in chunkQ
     long long Uoff, Voff; // element offsets of the block in U / V (pair 0, rank 0)
     int rd;               // factor buffer holding the block's current TSVD (read); the
                           // update goes to buffer rd ^ flip
@@ -50,6 +52,7 @@ struct MergeArgs {
     // scratch
     cd* nodeR;     // [node][W*W]
     cd* nodeQ;     // [node][kNodeQ]
+    cd* chunkQ;    // [chunk slot][kChunkQ]: chunk QR of merge_up, reused by merge_down
     int* nodecnt;  // [node]
     cd* UK;        // [problem][W*W]
     cd* VR;        // [problem][W*W]
@@ -62,7 +65,7 @@ struct MergeArgs {
     int flip;
     long long bU, bV, bS, bRank;
     // batched objects (grid dimension y): element strides from one object to the next
-    long long kU, kV, kS, kRank, kSrc, kNodeR, kNodeQ, kNodeCnt, kProbW2, kProbW, kProb;
+    long long kU, kV, kS, kRank, kSrc, kNodeR, kNodeQ, kNodeCnt, kProbW2, kProbW, kProb, kChunkQ;
 };
 
 hipError_t launch_merge(const MergeArgs& a, int nk, hipStream_t st);

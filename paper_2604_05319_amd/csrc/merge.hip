@@ -265,6 +265,7 @@ __device__ inline const cd* m_src(const MergeArgs& a) { return a.src + OBJ * a.k
 __device__ inline cd* m_nodeR(const MergeArgs& a) { return a.nodeR + OBJ * a.kNodeR; }
 __device__ inline cd* m_nodeQ(const MergeArgs& a) { return a.nodeQ + OBJ * a.kNodeQ; }
 __device__ inline int* m_nodecnt(const MergeArgs& a) { return a.nodecnt + OBJ * a.kNodeCnt; }
+__device__ inline cd* m_chunkQ(const MergeArgs& a) { return a.chunkQ + OBJ * a.kChunkQ; }
 __device__ inline cd* m_UK(const MergeArgs& a) { return a.UK + OBJ * a.kProbW2; }
 __device__ inline cd* m_VR(const MergeArgs& a) { return a.VR + OBJ * a.kProbW2; }
 __device__ inline double* m_Sold(const MergeArgs& a) { return a.Sold + OBJ * a.kProbW; }
@@ -375,6 +376,11 @@ __global__ void __launch_bounds__(NT) merge_up_kernel(MergeArgs a) {
     __syncthreads();
 
     chunk_qr<W>(a, c, r_old, s_old, A, tau, red);
+    {   // keep the chunk's reflectors for merge_down
+        cd* cq = m_chunkQ(a) + (size_t)(B.chunk_base + (long long)c.q * B.nchunks + c.chunk) * kChunkQ;
+        for (int e = threadIdx.x; e < CH * w; e += NT) cq[e] = A[e];
+        for (int e = threadIdx.x; e < w; e += NT) cq[CH * W + e] = tau[e];
+    }
 
     const long long nbase = B.node_base + (long long)c.q * B.nnodes;
     cd* nodeR = m_nodeR(a) + (size_t)nbase * W * W;
@@ -491,8 +497,6 @@ __global__ void __launch_bounds__(NT) merge_down_kernel(MergeArgs a) {
     cd* X = A + (size_t)CH * W;                     // CH x RC (the updated V rows, rank <= RC)
     cd* T = X + (size_t)CH * a.RC;                  // W x W
     cd* tau = T + (size_t)W * W;                    // W
-    double* red = reinterpret_cast<double*>(tau + W);
-    __shared__ double s_old[W];
 
     if ((int)blockIdx.x < a.ntask_v) {
         Ctx c = decode_task(a, blockIdx.x);
@@ -502,9 +506,12 @@ __global__ void __launch_bounds__(NT) merge_down_kernel(MergeArgs a) {
         const int r_old = clamp_rank(m_rold(a)[pidx], a.RC);
         const int rnew = clamp_rank(wr_rank(a, B)[fq], a.RC);
         const int w = r_old + a.pp;
-        for (int i = threadIdx.x; i < W; i += NT) s_old[i] = m_Sold(a)[pidx * W + i];
+        {   // the chunk's reflectors from merge_up
+            const cd* cq = m_chunkQ(a) + (size_t)(B.chunk_base + (long long)c.q * B.nchunks + c.chunk) * kChunkQ;
+            for (int e = threadIdx.x; e < CH * w; e += NT) A[e] = cq[e];
+            for (int e = threadIdx.x; e < w; e += NT) tau[e] = cq[CH * W + e];
+        }
         __syncthreads();
-        chunk_qr<W>(a, c, r_old, s_old, A, tau, red);
         const cd* VR = m_VR(a) + pidx * W * W;
         for (int e = threadIdx.x; e < W * W; e += NT) {
             int col = e / W, i = e % W;
