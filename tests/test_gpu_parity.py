@@ -158,6 +158,15 @@ def test_order_and_range_errors(P):
     assert e.value.code == -1
     with pytest.raises(P.HnessiError):
         P.Hodlr(64, 2, 1, panel=16, max_rank=20)  # rank + panel beyond the SVD width
+    with pytest.raises(P.HnessiError) as e:
+        P.Hodlr(64, 2, 1, flags=4)            # unknown flag
+    assert e.value.code == -1
+    with pytest.raises(P.HnessiError) as e:
+        P.HodlrBatch(0, 64, 2, 1)             # empty batch
+    assert e.value.code == -1
+    with pytest.raises(P.HnessiError) as e:
+        H.history_R_adjoint(0, r, 0.1, r)     # row 0 not appended
+    assert e.value.code == -2
 
 
 def test_reconstruction_exact_rank(P):
