@@ -450,15 +450,22 @@ template <int NORB, class FT>
 __global__ void __launch_bounds__(NT) hist_tasks(HistArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NG = AGroups<NORB>::NG;
-    const int id = blockIdx.x;
-    if (id < A.nfpad) {
-        if (id < A.nf[0]) fact_task<NORB, FT>(A, A.ft[0][id], smem);
-        else if (id - A.nf[0] < A.nf[1]) fact_task<NORB, FT>(A, A.ft[1][id - A.nf[0]], smem);
+    // longest tasks first: the tail tiles (all orbital pairs of a column chunk), then
+    // the leaf triangles, then the many short projection chunks that fill in behind
+    // them; every section starts at a multiple of 8, so workgroup id % 8 is the XCD
+    // that xcd_group assumes
+    int rel = blockIdx.x;
+    if (rel < A.ntailtask) {
+        int g, ag;
+        const int ng = A.ntailchunk[0] + A.ntailchunk[1];
+        if (!xcd_group(rel, ng, NG, g, ag)) return;
+        if (g < A.ntailchunk[0])
+            tail_task<NORB>(A, 0, ag, g, smem);
+        else
+            tail_task<NORB>(A, 1, ag, g - A.ntailchunk[0], smem);
         return;
     }
-    // leaf and tail sections start at multiples of 8, so workgroup id % 8 is
-    // the XCD that xcd_group assumes
-    int rel = id - A.nfpad;
+    rel -= A.ntailtask;
     if (rel < A.nleaftask) {
         constexpr int LG = LeafGroups<NORB>::LG;
         int g, mem;
@@ -467,13 +474,8 @@ __global__ void __launch_bounds__(NT) hist_tasks(HistArgs A) {
         return;
     }
     rel -= A.nleaftask;
-    int g, ag;
-    const int ng = A.ntailchunk[0] + A.ntailchunk[1];
-    if (!xcd_group(rel, ng, NG, g, ag)) return;
-    if (g < A.ntailchunk[0])
-        tail_task<NORB>(A, 0, ag, g, smem);
-    else
-        tail_task<NORB>(A, 1, ag, g - A.ntailchunk[0], smem);
+    if (rel < A.nf[0]) fact_task<NORB, FT>(A, A.ft[0][rel], smem);
+    else if (rel - A.nf[0] < A.nf[1]) fact_task<NORB, FT>(A, A.ft[1][rel - A.nf[0]], smem);
 }
 
 // ---------------------------------------------------------------------------

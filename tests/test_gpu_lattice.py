@@ -66,6 +66,35 @@ def test_batched_matches_oracle_and_single_objects(P):
         assert np.array_equal(H.ranks(P.RET), ranks[o])
 
 
+def test_batched_fp32_factors(P):
+    """Batched objects with complex-float factor mirrors: within 1e-5 of the oracle and within
+    1e-5 of the FP64-factor batch."""
+    cfg, G, S = make_config_inputs("c3")
+    sel = [3, 500, 1000]
+    N, h, k, nlvl = 128, cfg["h"], cfg["k"], 1
+    tot = N * (N + 1) // 2
+    inps = [host_inputs(G[i], S[i], N, h) for i in sel]
+    stacked = [to_dev(np.concatenate([inp[j] for inp in inps])) for j in range(4)]
+    out = {}
+    for flags in (0, P.FLAG_FP32_FACTORS):
+        IR, IL = _zeros(len(sel) * tot), _zeros(len(sel) * tot)
+        B = P.HodlrBatch(len(sel), N, nlvl, 1, k=k, tol=1e-8, panel=16, max_rank=16, flags=flags)
+        B.sweep(0, N, *stacked, h, IR, IL)
+        torch.cuda.synchronize()
+        assert B.status() == 0
+        out[flags] = (IR.cpu().numpy().reshape(len(sel), tot, 1, 1), IL.cpu().numpy().reshape(len(sel), tot, 1, 1))
+    rows = [0, 1, 63, 64, 65, 100, 127]
+    worst = 0.0
+    for o, inp in enumerate(inps):
+        oR, oL = oracle_rows(*inp, N, h, k, rows=rows)
+        for n in rows:
+            eR = row_rel_err(row(out[P.FLAG_FP32_FACTORS][0][o], n), oR[n])
+            eL = row_rel_err(row(out[P.FLAG_FP32_FACTORS][1][o], n), oL[n])
+            worst = max(worst, eR, eL)
+            assert eR <= 1e-5 and eL <= 1e-5, (o, n, eR, eL)
+    say("batched fp32 worst row relative error", worst)
+
+
 def test_batched_argument_errors(P):
     B = P.HodlrBatch(3, 128, 2, 1, k=5, tol=1e-10, panel=16, max_rank=16)
     row = _zeros(3 * 128)
