@@ -373,8 +373,9 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
     HALLOC_K(H->leafLL, (size_t)leaf_slots * nt * npair, true, H->oLeafOut);
     H->ntailchunk_max = div_up(nt, kTailCH);
     for (int c = 0; c < 2; ++c) {
-        HALLOC_K(H->tailcol[c], (size_t)nt * npair, true, H->oTailcol);
-        HALLOC_K(H->tailpart[c], (size_t)H->ntailchunk_max * kTailRows * npair, true, H->oTailpart);
+        HALLOC_K(H->tailcol[c], (size_t)tail_groups(norb) * nt * npair, true, H->oTailcol);
+        HALLOC_K(H->tailpart[c], (size_t)H->ntailchunk_max * tail_groups(norb) * kTailRows * npair, true,
+                 H->oTailpart);
         HALLOC_K(H->tailrow[c], (size_t)kTailRows * npair, true, H->oTailrow);
     }
     // merge scratch: one block per level per panel
@@ -682,7 +683,7 @@ int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, doub
     const int ngroups = H->norb <= 4 ? 1 : H->norb / 4;   // left-orbital groups of 4 waves
     const int leafgroups = H->norb == 1 ? 1 : 4;                   // orbital-pair groups per leaf
     A.nleaftask = div_up(2 * A.nleaf, 8) * 8 * ngroups * leafgroups;
-    A.ntailtask = div_up(A.ntailchunk[0] + A.ntailchunk[1], 8) * 8 * ngroups;
+    A.ntailtask = div_up(A.ntailchunk[0] + A.ntailchunk[1], 8) * 8 * ngroups * tail_groups(H->norb);
     A.part = H->part;
     A.proj = H->proj;
     A.leafR = H->leafR;

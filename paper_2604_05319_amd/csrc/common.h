@@ -101,5 +101,7 @@ bool interval_weights_exact(int k, int L, std::vector<double>& w, std::string& e
 constexpr int kCH = 256;      // factor rows per projection task
 constexpr int kTailCH = 64;   // columns per tail task
 constexpr int kTailRows = 32; // tail rows at most: the panel being merged and the one being formed
+// orbital-pair groups of the tail tasks (one workgroup and one partial slot each)
+__host__ __device__ constexpr int tail_groups(int norb) { return norb == 1 ? 1 : 4; }
 
 }  // namespace hn

@@ -337,9 +337,10 @@ __device__ void leaf_task(const HistArgs& A, int leaf, int comp, int ag, int pg,
 // [0, ls): the column sums over those rows are complete here; the row dots are
 // written per column chunk and summed by the combine.
 template <int NORB>
-__device__ void tail_task(const HistArgs& A, int comp, int ag, int chunk, unsigned char* smem) {
+__device__ void tail_task(const HistArgs& A, int comp, int ag, int chunk, int tg, unsigned char* smem) {
     if (comp == 1 && (!A.wantL || A.adj)) return;
     constexpr int npair = NORB * NORB, AG = AGroups<NORB>::AG;
+    constexpr int TG = tail_groups(NORB), PPG = npair / TG;   // orbital pairs of this group
     const int n = A.n;
     const int n0 = A.n0[comp], nrows = A.last[comp] - n0 + 1, ls = A.ls[comp];
     const int cbeg = chunk * kTailCH, ncol = min(kTailCH, ls - cbeg);
@@ -390,15 +391,15 @@ __device__ void tail_task(const HistArgs& A, int comp, int ag, int chunk, unsign
             pxm = v;
         }
     };
-    fetch(0);
-    for (int q = 0; q < npair; ++q) {
+    fetch(tg * PPG);
+    for (int q = tg * PPG; q < (tg + 1) * PPG; ++q) {
         const int qr = q / NORB, qc = q % NORB;
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < EPT; ++u) T[threadIdx.x + u * NT] = pT[u];
         if ((int)threadIdx.x < nrows * AG) xr[threadIdx.x] = pxr;
         if ((int)threadIdx.x < kTailCH * AG) xm[threadIdx.x] = pxm;
-        if (q + 1 < npair) fetch(q + 1);
+        if (q + 1 < (tg + 1) * PPG) fetch(q + 1);
         __syncthreads();
         if (wok) {
             // column sums (lane = column)
@@ -436,10 +437,10 @@ __device__ void tail_task(const HistArgs& A, int comp, int ag, int chunk, unsign
         if (lane < ncol) {
 #pragma unroll
             for (int c = 0; c < NORB; ++c)
-                p_tailcol(A, comp)[(size_t)(cbeg + lane) * npair + a * NORB + c] = col[c];
+                p_tailcol(A, comp)[((size_t)tg * A.nt + cbeg + lane) * npair + a * NORB + c] = col[c];
         }
         if (part == 0 && ri < nrows) {
-            cd* tp = p_tailpart(A, comp) + ((size_t)chunk * A.ring + ri) * npair + a * NORB;
+            cd* tp = p_tailpart(A, comp) + ((size_t)(chunk * TG + tg) * A.ring + ri) * npair + a * NORB;
 #pragma unroll
             for (int c = 0; c < NORB; ++c) tp[c] = row[c];
         }
@@ -456,13 +457,14 @@ __global__ void __launch_bounds__(NT) hist_tasks(HistArgs A) {
     // that xcd_group assumes
     int rel = blockIdx.x;
     if (rel < A.ntailtask) {
-        int g, ag;
+        constexpr int TG = tail_groups(NORB);
+        int g, mem;
         const int ng = A.ntailchunk[0] + A.ntailchunk[1];
-        if (!xcd_group(rel, ng, NG, g, ag)) return;
+        if (!xcd_group(rel, ng, NG * TG, g, mem)) return;
         if (g < A.ntailchunk[0])
-            tail_task<NORB>(A, 0, ag, g, smem);
+            tail_task<NORB>(A, 0, mem % NG, g, mem / NG, smem);
         else
-            tail_task<NORB>(A, 1, ag, g - A.ntailchunk[0], smem);
+            tail_task<NORB>(A, 1, mem % NG, g - A.ntailchunk[0], mem / NG, smem);
         return;
     }
     rel -= A.ntailtask;
@@ -505,7 +507,7 @@ __global__ void __launch_bounds__(256) proj_reduce(HistArgs A) {
         if (slot > A.last[comp] - A.n0[comp]) return;   // also: no tail rows at all
         const cd* tp = p_tailpart(A, comp) + (size_t)slot * npair + q;
         double re = 0.0, im = 0.0;
-        for (int ch = lane; ch < A.ntailchunk[comp]; ch += 64) {
+        for (int ch = lane; ch < A.ntailchunk[comp] * tail_groups(NORB); ch += 64) {   // chunks x pair groups
             const cd v = tp[(size_t)ch * A.ring * npair];
             re += v.x;
             im += v.y;
@@ -697,7 +699,8 @@ __global__ void __launch_bounds__(64 * CombMap<NORB>::WAVES) hist_combine(HistAr
                 if (A.wantL) sL = sL + p_leafLR(A)[op] + p_leafLL(A)[op];
             }
             if (A.wantR) {
-                if (A.last[0] >= A.n0[0] && m < A.ls[0]) sR = sR + p_tailcol(A, 0)[o];
+                if (A.last[0] >= A.n0[0] && m < A.ls[0])
+                    for (int tg = 0; tg < tail_groups(NORB); ++tg) sR = sR + p_tailcol(A, 0)[(size_t)tg * A.nt * npair + o];
                 // band correction: start weights (n-m >= k) or Newton-Cotes (n-m < k)
                 const int L = n - m;
                 if (L == 0) {
@@ -717,7 +720,8 @@ __global__ void __launch_bounds__(64 * CombMap<NORB>::WAVES) hist_combine(HistAr
             if (A.wantL) {
                 for (int comp = 0; comp < 2; ++comp) {
                     if (A.last[comp] < A.n0[comp]) continue;   // no tail rows
-                    if (comp == 1 && m < A.ls[1]) sL = sL + p_tailcol(A, 1)[o];
+                    if (comp == 1 && m < A.ls[1])
+                        for (int tg = 0; tg < tail_groups(NORB); ++tg) sL = sL + p_tailcol(A, 1)[(size_t)tg * A.nt * npair + o];
                     if (m >= A.n0[comp] && m <= A.last[comp])
                         sL = sL + p_tailrow(A, comp)[(size_t)(m - A.n0[comp]) * npair + a * NORB + c];
                 }
