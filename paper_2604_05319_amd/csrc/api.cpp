@@ -735,11 +735,8 @@ extern "C" {
 
 namespace {
 
-int append_impl(hnessi_hodlr_t H, int c, int n, const void* row, long long k_stride, hipStream_t st) {
-    if (c != HNESSI_RET && c != HNESSI_LES) return fail(HNESSI_E_ARG, "component must be RET or LES");
-    if (!row) return fail(HNESSI_E_ARG, "row is NULL");
-    if (n < 0 || n >= H->nt) return fail(HNESSI_E_RANGE, "n outside the grid");
-    if (n != H->last[c] + 1) return fail(HNESSI_E_ORDER, "rows must be appended in order");
+// the append arguments of row n of component c
+AppendArgs append_args(hnessi_hodlr_t H, int c, int n, const void* row, long long k_stride) {
     const Geometry& g = H->g;
     const int leaf = g.row_leaf[n];
     AppendArgs a{};
@@ -758,28 +755,59 @@ int append_impl(hnessi_hodlr_t H, int c, int n, const void* row, long long k_str
     a.kLeaf = H->oLeaf;
     a.kTail = H->oTail;
     a.kBand = H->oBand;
-    HIP_TRY(launch_append_hodlr(a, H->nk, st));
-    H->last[c] = n;
-    if (panel_ends(H, c, n)) {
-        const int p0 = H->fstart[c], p1 = n + 1;
-        // the previous panel's merge becomes current for everything queued from here on
-        int rc = finish_pending(H, c, st);
-        if (rc != HNESSI_OK) return rc;
-        // this panel's merge runs on the merge stream after the work queued so far on st
-        // and writes the blocks' other buffers; until the next panel ends, the history
-        // kernels read the panel's rows from the dense tail
-        HIP_TRY(hipEventRecord(H->ev_app[c], st));
-        HIP_TRY(hipStreamWaitEvent(H->mstream, H->ev_app[c], 0));
-        auto& pd = H->pend[c];
-        rc = merge_panel(H, c, p0, p1, H->mstream, pd.blocks);
-        if (rc != HNESSI_OK) return rc;
-        HIP_TRY(hipEventRecord(H->ev_merge[c], H->mstream));
-        pd.on = true;
-        pd.p0 = p0;
-        pd.p1 = p1;
-        H->fstart[c] = p1;
-    }
+    return a;
+}
+
+int check_append(hnessi_hodlr_t H, int c, int n, const void* row) {
+    if (c != HNESSI_RET && c != HNESSI_LES) return fail(HNESSI_E_ARG, "component must be RET or LES");
+    if (!row) return fail(HNESSI_E_ARG, "row is NULL");
+    if (n < 0 || n >= H->nt) return fail(HNESSI_E_RANGE, "n outside the grid");
+    if (n != H->last[c] + 1) return fail(HNESSI_E_ORDER, "rows must be appended in order");
     return HNESSI_OK;
+}
+
+// after row n of component c is appended: when it completes a panel, the previous
+// panel's merge becomes current and this panel's merge is launched
+int after_append(hnessi_hodlr_t H, int c, int n, hipStream_t st) {
+    H->last[c] = n;
+    if (!panel_ends(H, c, n)) return HNESSI_OK;
+    const int p0 = H->fstart[c], p1 = n + 1;
+    // the previous panel's merge becomes current for everything queued from here on
+    int rc = finish_pending(H, c, st);
+    if (rc != HNESSI_OK) return rc;
+    // this panel's merge runs on the merge stream after the work queued so far on st
+    // and writes the blocks' other buffers; until the next panel ends, the history
+    // kernels read the panel's rows from the dense tail
+    HIP_TRY(hipEventRecord(H->ev_app[c], st));
+    HIP_TRY(hipStreamWaitEvent(H->mstream, H->ev_app[c], 0));
+    auto& pd = H->pend[c];
+    rc = merge_panel(H, c, p0, p1, H->mstream, pd.blocks);
+    if (rc != HNESSI_OK) return rc;
+    HIP_TRY(hipEventRecord(H->ev_merge[c], H->mstream));
+    pd.on = true;
+    pd.p0 = p0;
+    pd.p1 = p1;
+    H->fstart[c] = p1;
+    return HNESSI_OK;
+}
+
+int append_impl(hnessi_hodlr_t H, int c, int n, const void* row, long long k_stride, hipStream_t st) {
+    int rc = check_append(H, c, n, row);
+    if (rc != HNESSI_OK) return rc;
+    HIP_TRY(launch_append_hodlr(append_args(H, c, n, row, k_stride), H->nk, st));
+    return after_append(H, c, n, st);
+}
+
+// rows n of both components in one launch
+int append2_impl(hnessi_hodlr_t H, int n, const void* rowR, const void* rowL, long long k_stride, hipStream_t st) {
+    int rc = check_append(H, HNESSI_RET, n, rowR);
+    if (rc == HNESSI_OK) rc = check_append(H, HNESSI_LES, n, rowL);
+    if (rc != HNESSI_OK) return rc;
+    HIP_TRY(launch_append_hodlr2(append_args(H, HNESSI_RET, n, rowR, k_stride),
+                                 append_args(H, HNESSI_LES, n, rowL, k_stride), H->nk, st));
+    rc = after_append(H, HNESSI_RET, n, st);
+    if (rc != HNESSI_OK) return rc;
+    return after_append(H, HNESSI_LES, n, st);
 }
 
 int single_only(hnessi_hodlr_t H) {
@@ -859,9 +887,7 @@ int sweep_impl(hnessi_hodlr_t H, int n_begin, int n_end, const void* GR, const v
     const size_t np = H->npair;
     for (int n = n_begin; n < n_end; ++n) {
         const size_t off = (size_t)tri(n) * np;
-        int rc = append_impl(H, HNESSI_RET, n, static_cast<const cd*>(GR) + off, k_stride, st);
-        if (rc != HNESSI_OK) return rc;
-        rc = append_impl(H, HNESSI_LES, n, static_cast<const cd*>(GL) + off, k_stride, st);
+        int rc = append2_impl(H, n, static_cast<const cd*>(GR) + off, static_cast<const cd*>(GL) + off, k_stride, st);
         if (rc != HNESSI_OK) return rc;
         rc = do_history(H, n, static_cast<const cd*>(SR) + off, static_cast<const cd*>(SL) + off, h,
                         static_cast<cd*>(IR) + off, static_cast<cd*>(IL) + off, true, true, st, k_stride, k_stride);

@@ -18,6 +18,8 @@ struct AppendArgs {
 };
 
 hipError_t launch_append_hodlr(const AppendArgs& a, int nk, hipStream_t st);
+// both components' rows n in one launch (grid dimension z = component)
+hipError_t launch_append_hodlr2(const AppendArgs& a0, const AppendArgs& a1, int nk, hipStream_t st);
 hipError_t launch_append_dense(cd* dst, const cd* row, int n, int npair, long long trin,
                                hipStream_t st);
 

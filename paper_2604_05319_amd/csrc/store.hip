@@ -14,7 +14,7 @@
 
 namespace hn {
 
-__global__ void append_hodlr_kernel(AppendArgs a) {
+__device__ inline void append_hodlr_row(const AppendArgs& a) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long total = (long long)(a.n + 1) * a.npair;
     if (e >= total) return;
@@ -29,6 +29,13 @@ __global__ void append_hodlr_kernel(AppendArgs a) {
     if (a.band && a.n - j <= a.k) a.band[o * a.kBand + ((size_t)j * (a.k + 1) + (a.n - j)) * a.npair + q] = v;
 }
 
+__global__ void append_hodlr_kernel(AppendArgs a) { append_hodlr_row(a); }
+
+__global__ void append_hodlr2_kernel(AppendArgs a0, AppendArgs a1) {
+    if (blockIdx.z == 0) append_hodlr_row(a0);
+    else append_hodlr_row(a1);
+}
+
 __global__ void append_dense_kernel(cd* dst, const cd* row, int n, int npair, long long trin) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long total = (long long)(n + 1) * npair;
@@ -41,6 +48,13 @@ hipError_t launch_append_hodlr(const AppendArgs& a, int nk, hipStream_t st) {
     const long long total = (long long)(a.n + 1) * a.npair;
     const int nb = (int)((total + 255) / 256);
     append_hodlr_kernel<<<dim3(nb, nk), 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_append_hodlr2(const AppendArgs& a0, const AppendArgs& a1, int nk, hipStream_t st) {
+    const long long total = (long long)(a0.n + 1) * a0.npair;
+    const int nb = (int)((total + 255) / 256);
+    append_hodlr2_kernel<<<dim3(nb, nk, 2), 256, 0, st>>>(a0, a1);
     return hipGetLastError();
 }
 
