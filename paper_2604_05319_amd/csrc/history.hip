@@ -599,8 +599,11 @@ __global__ void __launch_bounds__(64 * CombMap<NORB>::WAVES) hist_combine(HistAr
 #pragma unroll
         for (int a = 0; a < NORB; ++a) accR[a] = accL[a] = mk(0.0, 0.0);
         if (live) {
+            // the next level's block index is loaded while the current level is expanded
+            int cv_next = A.cover[m];
             for (int l = 0; l < A.nlvl; ++l) {
-                const int cv = A.cover[(size_t)l * A.nt + m];
+                const int cv = cv_next;
+                if (l + 1 < A.nlvl) cv_next = A.cover[(size_t)(l + 1) * A.nt + m];
                 if (cv >= 0) {  // m is a column of block b: expand through V
                     const int b = cv;
                     const int r0 = A.blk[5 * b + 1], c0 = A.blk[5 * b + 3], c1 = A.blk[5 * b + 4];
