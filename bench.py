@@ -308,7 +308,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              f"sharding is a design, not part of this build", file=sys.stderr)
+              f"sharding of the method is described but not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
