@@ -40,7 +40,12 @@
  *     hnessi_hodlr_status().
  *   - A handle is not thread-safe; use one host thread per handle.
  *   - The caller owns all inputs and outputs; a handle owns its own device
- *     storage (factors, leaves, tail rows, band, scratch).
+ *     storage (factors, leaves, tail rows, band, scratch), obtained through
+ *     the allocator hook (hnessi_set_allocator) on the stream of the call
+ *     that creates it.
+ *   - Calls that wait (destroy, get, ranks, status, profile) wait for the
+ *     work of their own handle only: the stream of the handle's last call and
+ *     its internal merge stream, never the whole device.
  */
 #ifndef HNESSI_H
 #define HNESSI_H
@@ -82,6 +87,28 @@ typedef enum {
 /* Message for the last failing call on this host thread (never NULL). */
 const char* hnessi_last_error(void);
 
+/* ---------------------------------------------------------------------------
+ * Device memory.  The paper's storage class owns the memory of its
+ * compressed representation (section "The herm_matrix_hodlr class"); here
+ * every device allocation of the library (handle storage and the scratch of
+ * hnessi_compress_block) goes through one process-wide hook, so that a
+ * caching allocator (e.g. PyTorch's) can serve it.
+ *   alloc(bytes, stream, ctx)  returns a device pointer usable in stream order
+ *                              on `stream`, or NULL on failure (the call that
+ *                              allocates then returns HNESSI_E_NOMEM);
+ *   free(ptr, stream, ctx)     returns ptr; `stream` is the allocating stream
+ *                              when the release is stream-ordered, or NULL
+ *                              after the library has waited for all work
+ *                              that uses ptr.
+ * hnessi_set_allocator(NULL, NULL, NULL) restores the default,
+ * hipMallocAsync / hipFreeAsync.  A handle keeps the hook it was created with
+ * and returns its memory through it.  Not thread-safe with respect to calls
+ * that allocate.  HNESSI_E_ARG if exactly one of the two functions is NULL.
+ * ------------------------------------------------------------------------- */
+typedef void* (*hnessi_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*hnessi_free_fn)(void* ptr, void* stream, void* ctx);
+int hnessi_set_allocator(hnessi_alloc_fn alloc, hnessi_free_fn free_fn, void* ctx);
+
 /* Interval quadrature weights w^{(L)}_i, i = 0..L, for Gregory order k (1..5),
  * written to w_host[0..L] (host).  Appendix "Integral and derivative
  * approximations".  Returns HNESSI_E_ARG for k outside 1..5 or L < 0. */
@@ -92,46 +119,66 @@ int hnessi_weights(int k, int L, double* w_host);
  * (the paper's herm_matrix_hodlr for its R and < parts).
  * ------------------------------------------------------------------------- */
 
-/* Create a handle for nt time steps.
+/* Create a handle for nt time steps (the constructor of the paper's
+ * herm_matrix_hodlr, section "The herm_matrix_hodlr class", with the
+ * partitioning parameters of section "Hierarchical decomposition").
  *   nlvl     number of hierarchical levels; level l holds 2^(l-1) off-diagonal
- *            blocks of about nt/2^l rows (section "Hierarchical decomposition");
- *            the 2^nlvl diagonal leaves are kept dense.  The smallest leaf must
- *            hold at least k+1 rows and the panel.
- *   norb     orbital dimension: 1, 2, 4, 8 or 16.
- *   k        Gregory order, 1..5.
+ *            blocks of about nt/2^l rows; the 2^nlvl diagonal leaves are kept
+ *            dense.  The smallest leaf must hold at least k+1 rows and the
+ *            panel; every leaf at most 64 rows.
+ *   norb     orbital dimension: 1, 2, 4, 8 or 16 (norb^2 separately
+ *            compressed orbital pairs, section "Multiorbital compression").
+ *   k        Gregory order, 1..5 (section "Numerical integration").
  *   svd_tol  absolute truncation threshold eps_SVD > 0: singular values
  *            sigma >= svd_tol are kept.
  *   panel    rows per compression panel P (1..16); a panel also ends at
  *            every leaf start, so it need not divide the leaf size.
- *   max_rank rank capacity per block and orbital pair; max_rank + panel <= 32
+ *   max_rank rank capacity per block and orbital pair; max_rank + panel <= 48
  *            (the width of the small SVD solved at each merge).
  *   flags    HNESSI_FLAG_NONE or HNESSI_FLAG_FP32_FACTORS.
- * Every leaf must hold at most 64 rows.
- * Allocates all device storage (synchronously).  On success *out is set. */
+ *   stream   every allocation, fill and copy of the handle is ordered on it;
+ *            the call returns once they are complete.
+ * On success *out is set.  HNESSI_E_ARG for an argument out of range,
+ * HNESSI_E_NOMEM when the allocator hook fails (nothing is leaked). */
 int hnessi_hodlr_create(hnessi_hodlr_t* out, int nt, int nlvl, int norb, int k,
                         double svd_tol, int panel, int max_rank, int flags, void* stream);
 
+/* Wait for the handle's work (its last call's stream and its merge stream),
+ * then return its memory through the hook it was created with. */
 int hnessi_hodlr_destroy(hnessi_hodlr_t H);
 
-/* Forget all rows (start a new sweep from n = 0); storage is kept. */
+/* Forget all rows and the device status flags (start a new sweep from
+ * n = 0); storage is kept.  Enqueued on stream. */
 int hnessi_hodlr_reset(hnessi_hodlr_t H, void* stream);
 
-/* Append row n of component c (device pointer, (n+1)*norb*norb complex128):
+/* Append row n of component c (device pointer, (n+1)*norb*norb complex128);
+ * the current-timestep set of Tab. getset followed by the once-per-step
+ * update_blocks of section "The herm_matrix_hodlr class":
  *   HNESSI_RET: G^R(t_n, t_j), j = 0..n
  *   HNESSI_LES: G^<(t_s, t_n), s = 0..n   (the paper's stored lesser slice)
- * n must equal the previous row of that component plus one (HNESSI_E_ORDER).
+ * n must equal the previous row of that component plus one (HNESSI_E_ORDER);
+ * n outside the grid: HNESSI_E_RANGE; NULL row: HNESSI_E_ARG.
  * When the row completes a panel, the panel is merged into the truncated SVDs
  * of the blocks it belongs to (incremental TSVD update, section "Hierarchical
  * decomposition").  The input may be reused once the stream reaches the call. */
 int hnessi_hodlr_append_row(hnessi_hodlr_t H, int c, int n, const void* row, void* stream);
 
-/* I^R(n, m), m = 0..n, into out (device, (n+1)*norb*norb complex128).
- * sigR_row: Sigma^R(t_n, t_j), j = 0..n (device).  Needs retarded rows 0..n. */
+/* I^R(n, m), m = 0..n, into out (device, (n+1)*norb*norb complex128): the
+ * history integral of the retarded Kadanoff-Baym equation (Eq. KBER, section
+ * "Kadanoff-Baym equations") in the form with the current Sigma^R row on the
+ * left, Gregory weights of the appendix "Integral and derivative
+ * approximations".  sigR_row: Sigma^R(t_n, t_j), j = 0..n (device).
+ * Needs retarded rows 0..n appended and no later row (HNESSI_E_ORDER);
+ * NULL pointers: HNESSI_E_ARG. */
 int hnessi_history_R(hnessi_hodlr_t H, int n, const void* sigR_row, double h,
                      void* out, void* stream);
 
-/* I^<(n, m), m = 0..n, into out (device).  sigL_slice: Sigma^<(t_s, t_n),
- * s = 0..n (device, stored orientation).  Needs both components up to row n. */
+/* I^<(n, m), m = 0..n, into out (device): the two history integrals of the
+ * lesser Kadanoff-Baym equation (Eq. KBEL, section "Kadanoff-Baym equations";
+ * the mixed imaginary-time term is not part of this call), Gregory weights as
+ * above.  sigL_slice: Sigma^<(t_s, t_n), s = 0..n (device, the stored
+ * orientation of the current lesser slice, Tab. getset).  Needs both
+ * components appended up to row n exactly (HNESSI_E_ORDER). */
 int hnessi_history_lesser(hnessi_hodlr_t H, int n, const void* sigR_row,
                           const void* sigL_slice, double h, void* out, void* stream);
 
@@ -148,14 +195,18 @@ int hnessi_history_lesser(hnessi_hodlr_t H, int n, const void* sigR_row,
 int hnessi_history_R_adjoint(hnessi_hodlr_t H, int n, const void* ibar_row, double h, void* out,
                              void* stream);
 
-/* Both integrals of step n in one pass over the stored data (each stored
- * factor is used for every product it enters).  outR / outL as above. */
+/* Both integrals of step n (Eqs. KBER and KBEL as for hnessi_history_R and
+ * hnessi_history_lesser) in one pass over the stored data: each stored
+ * factor is used for every product it enters.  outR / outL as above; errors
+ * as for the two calls. */
 int hnessi_history_step(hnessi_hodlr_t H, int n, const void* sigR_row, const void* sigL_slice,
                         double h, void* outR, void* outL, void* stream);
 
-/* A whole sweep n = n_begin..n_end-1 driven natively: for each n, append
- * G^R row n and G^< row n, then hnessi_history_step.  All arrays are device
- * packed lower triangles, row n at element offset n(n+1)/2 (times norb^2):
+/* A whole sweep n = n_begin..n_end-1 driven natively (the time-stepping loop
+ * of section "Timestepping and SVD updates" with the known rows of a
+ * synthetic G): for each n, append G^R row n and G^< row n, then
+ * hnessi_history_step.  All arrays are device packed lower triangles, row n
+ * at element offset n(n+1)/2 (times norb^2):
  *   GR, GL  rows of the two components as for append_row;
  *   SR, SL  Sigma^R rows and Sigma^< slices as for the history calls;
  *   IR, IL  outputs I^R(n, .), I^<(n, .).
@@ -163,7 +214,10 @@ int hnessi_history_step(hnessi_hodlr_t H, int n, const void* sigR_row, const voi
 int hnessi_sweep(hnessi_hodlr_t H, int n_begin, int n_end, const void* GR, const void* GL,
                  const void* SR, const void* SL, double h, void* IR, void* IL, void* stream);
 
-/* Device-side status, after synchronizing `stream`: HNESSI_OK; HNESSI_E_RANK
+/* Device-side status (the paper's library throws when a call cannot honour
+ * its contract, section "The herm_matrix_hodlr class"; here the device
+ * conditions are flags), after synchronizing `stream` and the handle's
+ * merges: HNESSI_OK; HNESSI_E_RANK
  * if any truncation needed more than max_rank singular values (the excess
  * ones were dropped and the eps_SVD guarantee does not hold); HNESSI_E_VALUE
  * if a truncation met non-finite data (those directions were dropped).  The
@@ -171,9 +225,10 @@ int hnessi_sweep(hnessi_hodlr_t H, int n_begin, int n_end, const void* GR, const
 int hnessi_hodlr_status(hnessi_hodlr_t H, void* stream);
 
 /* ---------------------------------------------------------------------------
- * Batched objects: the k-point lattice form (section on the 2D Hubbard model,
- * where every momentum k carries its own Green's function and self-energy and
- * the history integrals of different k are independent).
+ * Batched objects: the k-point lattice form (sections "Driven 2D Hubbard
+ * example" and "Implementation details", where every momentum k carries its
+ * own Green's function and self-energy, the Dyson steps of different k are
+ * independent and are distributed over threads and ranks).
  *
  * One handle holds nk objects of one geometry (nt, nlvl, norb, k, svd_tol,
  * panel, max_rank), advanced together: every call acts on all nk objects in
@@ -186,25 +241,29 @@ int hnessi_hodlr_status(hnessi_hodlr_t H, void* stream);
  * blocks, leaves, bytes and profiling work on both.
  * ------------------------------------------------------------------------- */
 
-/* nk in 1..65535; other arguments as for hnessi_hodlr_create. */
+/* nk objects (momenta) in 1..65535; other arguments and errors as for
+ * hnessi_hodlr_create. */
 int hnessi_hodlr_create_batched(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k,
                                 double svd_tol, int panel, int max_rank, int flags, void* stream);
 
-/* Number of objects of the handle (1 for hnessi_hodlr_create). */
+/* Number of objects (momenta) of the handle (1 for hnessi_hodlr_create). */
 int hnessi_hodlr_nk(hnessi_hodlr_t H);
 
-/* Row n of component c of every object: object o's row at rows + o*k_stride. */
+/* hnessi_hodlr_append_row for every object (Tab. getset and update_blocks
+ * per momentum): object o's row at rows + o*k_stride. */
 int hnessi_hodlr_append_row_batched(hnessi_hodlr_t H, int c, int n, const void* rows, long long k_stride,
                                     void* stream);
 
-/* hnessi_history_step for every object: inputs of object o at sigR_rows +
+/* hnessi_history_step for every object (Eqs. KBER and KBEL per momentum):
+ * inputs of object o at sigR_rows +
  * o*in_stride and sigL_slices + o*in_stride, outputs at outR + o*out_stride
  * and outL + o*out_stride. */
 int hnessi_history_step_batched(hnessi_hodlr_t H, int n, const void* sigR_rows, const void* sigL_slices,
                                 long long in_stride, double h, void* outR, void* outL, long long out_stride,
                                 void* stream);
 
-/* hnessi_sweep for every object: the six packed triangles of object o start
+/* hnessi_sweep for every object (the time-stepping loop per momentum):
+ * the six packed triangles of object o start
  * at o*k_stride elements (k_stride >= nt(nt+1)/2 * norb^2). */
 int hnessi_sweep_batched(hnessi_hodlr_t H, int n_begin, int n_end, const void* GR, const void* GL,
                          const void* SR, const void* SL, long long k_stride, double h, void* IR, void* IL,
@@ -212,29 +271,41 @@ int hnessi_sweep_batched(hnessi_hodlr_t H, int n_begin, int n_end, const void* G
 
 /* Value of component c at (t1, t2), t1 >= t2, t1 <= last appended row,
  * reconstructed from whichever storage holds it (dense leaf, dense row, or
- * truncated SVD), into out_host (norb*norb complex128).  Synchronous. */
+ * truncated SVD), into out_host (norb*norb complex128): the general get of
+ * Tab. getcompress, valid for any point up to the current timestep.
+ * Waits for the handle's work.  HNESSI_E_RANGE outside the stored region;
+ * HNESSI_E_ARG on a batched handle. */
 int hnessi_hodlr_get(hnessi_hodlr_t H, int c, int t1, int t2, void* out_host);
 
-/* Ranks of component c: ranks_host[b*norb*norb + q] for block b (in the
- * order of hnessi_hodlr_blocks) and orbital pair q.  Synchronous.  Returns the
- * number of entries written, or a negative status. */
+/* Ranks of component c (the eps-ranks of section "Hierarchical
+ * decomposition", one per orbital pair, section "Multiorbital compression"):
+ * ranks_host[b*norb*norb + q] for block b (in the order of
+ * hnessi_hodlr_blocks) and orbital pair q.  Waits for the handle's work and
+ * its pending merges.  Returns the number of entries written, or a negative
+ * status (HNESSI_E_ARG when capacity is too small). */
 int hnessi_hodlr_ranks(hnessi_hodlr_t H, int c, int* ranks_host, int capacity);
 
-/* Block table: for block b, rows [r0, r1) and columns [c0, c1), level in
- * 1..nlvl; tab_host[5*b + {0..4}] = level, r0, r1, c0, c1.  Host only.
+/* Block table of the partitioning (section "Hierarchical decomposition"):
+ * for block b, rows [r0, r1) and columns [c0, c1), level in 1..nlvl;
+ * tab_host[5*b + {0..4}] = level, r0, r1, c0, c1.  Host only.
  * Returns the number of blocks (or a negative status). */
 int hnessi_hodlr_blocks(hnessi_hodlr_t H, int* tab_host, int capacity);
 
-/* Leaf table: tab_host[2*i + {0,1}] = s0, s1.  Returns the number of leaves. */
+/* Leaf table (the dense diagonal triangles of section "Hierarchical
+ * decomposition"): tab_host[2*i + {0,1}] = s0, s1.  Returns the number of
+ * leaves. */
 int hnessi_hodlr_leaves(hnessi_hodlr_t H, int* tab_host, int capacity);
 
-/* Device bytes held by the handle (factor capacity, leaves, tail, band, scratch). */
+/* Device bytes held by the handle (factor capacity, leaves, tail, band,
+ * scratch): the memory footprint the paper compares with dense storage
+ * (section "Driven 2D Hubbard example"). */
 size_t hnessi_hodlr_bytes(hnessi_hodlr_t H);
 
-/* Kernel timing with HIP events recorded on the launch stream (measurement).
- * stride > 0: from now on time the three history kernels of every step n with
+/* Kernel timing with HIP events recorded on the launch stream (measurement,
+ * the per-part timings of section "Timing results").
+ * stride > 0: from now on time the history kernels of every step n with
  * n % stride == 0, and every panel merge; stride = 0 stops.  Clears earlier
- * records (synchronizes the device). */
+ * records (waits for the handle's work). */
 int hnessi_hodlr_profile(hnessi_hodlr_t H, int stride);
 
 /* Synchronizes the recorded events; for kernel kind 0 (projection / leaf /
@@ -246,36 +317,54 @@ int hnessi_hodlr_profile(hnessi_hodlr_t H, int stride);
 int hnessi_hodlr_profile_read(hnessi_hodlr_t H, int kind, int* steps_host, double* ms_host, int capacity);
 
 /* ---------------------------------------------------------------------------
- * Truncated SVD of one dense block (section "Hierarchical decomposition"):
+ * Truncated SVD of one dense block (section "Hierarchical decomposition":
+ * B ~ U S V^dagger keeping the singular values >= eps_SVD, so that
+ * |B - U S V^dagger|_2 < eps_SVD).
  * A (device, rows x cols complex128, row-major with leading dimension lda)
- * ~ U diag(S) V^dagger keeping singular values >= tol (absolute, > 0).
+ * ~ U diag(S) V^dagger with the absolute threshold tol > 0:
  *   U: device, column-major rows x max_rank (column r at U + r*rows)
- *   S: device, max_rank doubles, non-increasing
+ *   S: device, max_rank doubles, non-increasing (zero beyond the rank)
  *   V: device, column-major cols x max_rank
- *   rank_out: device int, the kept rank (<= max_rank)
- * Rows are merged in panels, exactly as the HODLR blocks are built.  If more
- * than max_rank values reach tol, the largest max_rank are kept and the call
- * still returns HNESSI_OK; compare *rank_out with max_rank to detect it.
- * max_rank + 16 <= 64.  Synchronous with respect to the host for its own
- * scratch allocation; the factorization itself runs on `stream`. */
+ *   rank_out: device int, the kept rank r; then S[r-1] >= tol and
+ *             |A - U S V^dagger|_2 < tol, except when a singular value of A
+ *             lies within 1e-3 * tol of tol (it may then be kept or dropped).
+ *             More than max_rank values >= tol: the largest max_rank are kept
+ *             and *rank_out == max_rank.  Negative values report a failure
+ *             found on the device: HNESSI_E_VALUE (non-finite entries in A) or
+ *             HNESSI_E_RANK (an intermediate merge needed more than 40 values).
+ * 1 <= max_rank <= 40.  The rows are merged 8 at a time; every merge but the
+ * last drops only values below 5e-4 * tol / (number of merges), the last
+ * truncates at tol.  Fully asynchronous on `stream`: the scratch comes from
+ * the allocator hook and is returned to it in stream order.  Argument errors:
+ * HNESSI_E_ARG; hook failure: HNESSI_E_NOMEM. */
 int hnessi_compress_block(const void* A, int rows, int cols, int lda, double tol, int max_rank,
                           void* U, double* S, void* V, int* rank_out, void* stream);
 
 /* ---------------------------------------------------------------------------
- * Dense storage (the uncompressed baseline on the same device): both
- * components as full packed lower triangles, the same history integrals by
- * direct summation (one read of every stored entry per step).
+ * Dense storage (the uncompressed baseline on the same device, the role of
+ * the NESSi solver in the paper's comparisons, sections "Timing results" and
+ * "Driven 2D Hubbard example"): both components as full packed lower
+ * triangles, the same history integrals (Eqs. KBER and KBEL) by direct
+ * summation, one read of every stored entry per step.  Arguments, layouts and
+ * errors as for the HODLR calls of the same name; norb is 1, 2 or 4.
  * ------------------------------------------------------------------------- */
+/* Allocates 2 * norb^2 * nt(nt+1)/2 complex128 through the hook on stream. */
 int hnessi_dense_create(hnessi_dense_t* out, int nt, int norb, int k, void* stream);
+/* Waits for the handle's last call, then frees. */
 int hnessi_dense_destroy(hnessi_dense_t D);
+/* Forget all rows. */
 int hnessi_dense_reset(hnessi_dense_t D, void* stream);
+/* Row n of component c, as hnessi_hodlr_append_row (stored, never compressed). */
 int hnessi_dense_append_row(hnessi_dense_t D, int c, int n, const void* row, void* stream);
+/* I^R(n, .) and I^<(n, .) as hnessi_history_step. */
 int hnessi_dense_history_step(hnessi_dense_t D, int n, const void* sigR_row,
                               const void* sigL_slice, double h, void* outR, void* outL,
                               void* stream);
+/* A sweep as hnessi_sweep. */
 int hnessi_dense_sweep(hnessi_dense_t D, int n_begin, int n_end, const void* GR, const void* GL,
                        const void* SR, const void* SL, double h, void* IR, void* IL,
                        void* stream);
+/* Device bytes held (the dense memory footprint of the paper's comparisons). */
 size_t hnessi_dense_bytes(hnessi_dense_t D);
 /* Event timing of the dense kernels as for the HODLR handle: kind 0 = tile
  * kernel, 1 = reduction. */

@@ -30,8 +30,12 @@ class HnessiError(RuntimeError):
 
 _lib = None
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
 _SIGS = {
     "hnessi_last_error": ([], C.c_char_p),
+    "hnessi_set_allocator": ([ALLOC_FN, FREE_FN, C.c_void_p], C.c_int),
     "hnessi_weights": ([C.c_int, C.c_int, C.c_void_p], C.c_int),
     "hnessi_hodlr_create": ([C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
                              C.c_int, C.c_int, C.c_int, C.c_void_p], C.c_int),
@@ -133,6 +137,51 @@ def _profile_read(fn, h, kind):
     ms = np.zeros(max(cnt, 1), dtype=np.float64)
     _check(fn(h, kind, steps.ctypes.data_as(C.c_void_p), ms.ctypes.data_as(C.c_void_p), cnt))
     return steps[:cnt], ms[:cnt]
+
+
+# ctypes callbacks of every hook ever installed: a handle returns its memory through the
+# hook it was created with, so none of them may be collected while the process runs
+_hooks = []
+
+
+def set_allocator(alloc=None, free=None):
+    """Route the library's device allocations through Python callables.
+
+    alloc(nbytes, stream_ptr) -> device pointer (int) or 0; free(ptr, stream_ptr).
+    With no arguments the library's default (hipMallocAsync / hipFreeAsync) is restored."""
+    if alloc is None and free is None:
+        _check(lib().hnessi_set_allocator(ALLOC_FN(), FREE_FN(), None))
+        return
+
+    def _a(nbytes, stream, ctx):
+        try:
+            return int(alloc(int(nbytes), int(stream or 0)) or 0) or None
+        except Exception:
+            return None
+
+    def _f(ptr, stream, ctx):
+        try:
+            free(int(ptr), int(stream or 0))
+        except Exception:
+            pass
+
+    hook = (ALLOC_FN(_a), FREE_FN(_f))
+    _hooks.append(hook)
+    _check(lib().hnessi_set_allocator(hook[0], hook[1], None))
+
+
+def use_torch_allocator():
+    """Serve the library's device memory from PyTorch's caching allocator
+    (stream-ordered on the stream of the allocating call)."""
+    import torch
+
+    def _alloc(nbytes, stream):
+        return torch.cuda.caching_allocator_alloc(nbytes, stream=stream)
+
+    def _free(ptr, stream):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    set_allocator(_alloc, _free)
 
 
 def weights(k: int, L: int) -> np.ndarray:
@@ -315,4 +364,6 @@ def compress_block(A, tol, max_rank):
     _check(lib().hnessi_compress_block(_ptr(A), rows, cols, cols, tol, max_rank, _ptr(U), _ptr(S),
                                        _ptr(V), _ptr(rk), _stream()))
     r = int(rk.item())
+    if r < 0:
+        raise HnessiError(r, "compress_block failed on the device (non-finite data or internal rank overflow)")
     return U[:r].T.contiguous(), S[:r].clone(), V[:r].T.contiguous(), r

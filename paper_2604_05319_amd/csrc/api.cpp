@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/hnessi.h"
+#include "alloc.h"
 #include "common.h"
 #include "dense.h"
 #include "history.h"
@@ -33,50 +34,23 @@ int fail(int code, const std::string& msg) {
     } while (0)
 
 bool g_init = false;
-int lib_init() {
-    if (g_init) return HNESSI_OK;
-    HIP_TRY(merge_init());
-    HIP_TRY(history_init());
-    HIP_TRY(dense_init());
-    g_init = true;
-    return HNESSI_OK;
+
+// the process-wide allocator hook (default: stream-ordered hipMallocAsync / hipFreeAsync)
+void* default_alloc(size_t bytes, void* stream, void*) {
+    void* p = nullptr;
+    if (hipMallocAsync(&p, bytes, (hipStream_t)stream) != hipSuccess) return nullptr;
+    return p;
 }
+void default_free(void* p, void* stream, void*) { (void)hipFreeAsync(p, (hipStream_t)stream); }
+hnessi_alloc_fn g_alloc = default_alloc;
+hnessi_free_fn g_free = default_free;
+void* g_alloc_ctx = nullptr;
 
-// device allocations owned by a handle
-struct Allocs {
-    std::vector<void*> ptrs;
-    size_t bytes = 0;
-    template <class T>
-    int alloc(T*& p, size_t count, bool zero = false) {
-        p = nullptr;
-        if (count == 0) count = 1;
-        size_t nb = count * sizeof(T);
-        void* q = nullptr;
-        hipError_t e = hipMalloc(&q, nb);
-        if (e != hipSuccess) return fail(HNESSI_E_NOMEM, "hipMalloc of " + std::to_string(nb) + " bytes failed");
-        if (zero) {
-            e = hipMemset(q, 0, nb);
-            if (e != hipSuccess) {
-                hipFree(q);
-                return fail(HNESSI_E_DEVICE, "hipMemset failed");
-            }
-        }
-        ptrs.push_back(q);
-        bytes += nb;
-        p = static_cast<T*>(q);
-        return HNESSI_OK;
-    }
-    void release() {
-        for (void* q : ptrs) hipFree(q);
-        ptrs.clear();
-        bytes = 0;
-    }
-};
-
-#define ALLOC(al, p, n, z)                       \
-    do {                                         \
-        int rc_ = (al).alloc((p), (n), (z));     \
-        if (rc_ != HNESSI_OK) return rc_;        \
+#define ALLOC(al, p, n, z)                                                                     \
+    do {                                                                                       \
+        if (dev_alloc((al), (p), (n), (z)) != HNESSI_OK)                                       \
+            return fail(HNESSI_E_NOMEM, "device allocation of " + std::to_string((size_t)(n)) + \
+                                            " elements failed");                              \
     } while (0)
 
 int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }
@@ -128,6 +102,48 @@ struct Prof {
 
 }  // namespace
 
+namespace hn {
+
+int set_error(int code, const std::string& msg) { return fail(code, msg); }
+
+int lib_init() {
+    if (g_init) return HNESSI_OK;
+    HIP_TRY(merge_init());
+    HIP_TRY(history_init());
+    HIP_TRY(dense_init());
+    g_init = true;
+    return HNESSI_OK;
+}
+
+DevAlloc DevAlloc::current(hipStream_t st) {
+    DevAlloc a;
+    a.fa = g_alloc;
+    a.ff = g_free;
+    a.ctx = g_alloc_ctx;
+    a.st = st;
+    return a;
+}
+
+void* DevAlloc::raw(size_t nbytes, bool zero) {
+    void* q = fa(nbytes, (void*)st, ctx);
+    if (!q) return nullptr;
+    ptrs.push_back(q);
+    bytes += nbytes;
+    if (zero) {
+        // zero fill by a kernel on the allocating stream
+        if (launch_fill_int(static_cast<int*>(q), (long long)((nbytes + 3) / 4), 0, st) != hipSuccess) return nullptr;
+    }
+    return q;
+}
+
+void DevAlloc::release(bool on_stream) {
+    for (void* q : ptrs) ff(q, on_stream ? (void*)st : nullptr, ctx);
+    ptrs.clear();
+    bytes = 0;
+}
+
+}  // namespace hn
+
 struct hnessi_hodlr_s {
     int nt = 0, nlvl = 0, norb = 0, npair = 0, k = 0, P = 0, RC = 0, flags = 0;
     int nk = 1;  // objects of a batch (same geometry, independent data)
@@ -138,7 +154,9 @@ struct hnessi_hodlr_s {
     double tol = 0.0;
     Weights W{};
     Geometry g;
-    Allocs al;
+    int MW = 0;           // merge width (kWSmall or kWLarge)
+    DevAlloc al;
+    hipEvent_t ev_last = nullptr;   // recorded after the work of every call on that call's stream
     // geometry on the device
     int* d_blk = nullptr;
     int* d_leaf = nullptr;
@@ -207,7 +225,8 @@ struct hnessi_hodlr_s {
 struct hnessi_dense_s {
     int nt = 0, norb = 0, npair = 0, k = 0;
     Weights W{};
-    Allocs al;
+    DevAlloc al;
+    hipEvent_t ev_last = nullptr;
     long long trin = 0;
     cd* L[2] = {};
     cd* colR = nullptr;
@@ -220,6 +239,21 @@ struct hnessi_dense_s {
 extern "C" {
 
 const char* hnessi_last_error(void) { return g_err.c_str(); }
+
+int hnessi_set_allocator(hnessi_alloc_fn alloc, hnessi_free_fn free_fn, void* ctx) {
+    if ((alloc == nullptr) != (free_fn == nullptr))
+        return fail(HNESSI_E_ARG, "allocator and free function must both be given or both be NULL");
+    if (alloc) {
+        g_alloc = alloc;
+        g_free = free_fn;
+        g_alloc_ctx = ctx;
+    } else {
+        g_alloc = default_alloc;
+        g_free = default_free;
+        g_alloc_ctx = nullptr;
+    }
+    return HNESSI_OK;
+}
 
 int hnessi_weights(int k, int L, double* w_host) {
     if (!w_host) return fail(HNESSI_E_ARG, "w_host is NULL");
@@ -234,6 +268,19 @@ int hnessi_weights(int k, int L, double* w_host) {
 
 namespace {
 
+// ev_last marks the end of the work a call enqueued on its stream
+int mark(hnessi_hodlr_t H, hipStream_t st) {
+    HIP_TRY(hipEventRecord(H->ev_last, st));
+    return HNESSI_OK;
+}
+
+// wait for the work of the handle: its last call's stream and its merge stream
+int wait_handle(hnessi_hodlr_t H) {
+    if (H->ev_last) HIP_TRY(hipEventSynchronize(H->ev_last));
+    if (H->mstream) HIP_TRY(hipStreamSynchronize(H->mstream));
+    return HNESSI_OK;
+}
+
 void release_streams(hnessi_hodlr_t H) {
     if (H->mstream) hipStreamSynchronize(H->mstream);
     for (int c = 0; c < 2; ++c) {
@@ -246,7 +293,7 @@ void release_streams(hnessi_hodlr_t H) {
 }
 
 int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, double svd_tol, int panel,
-                int max_rank, int flags) {
+                int max_rank, int flags, hipStream_t st) {
     if (!out) return fail(HNESSI_E_ARG, "out is NULL");
     *out = nullptr;
     if (nk < 1 || nk > 65535) return fail(HNESSI_E_ARG, "nk must be in 1..65535");
@@ -255,8 +302,8 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
         return fail(HNESSI_E_ARG, "norb must be 1, 2, 4, 8 or 16");
     if (!(svd_tol > 0.0)) return fail(HNESSI_E_ARG, "svd_tol must be > 0");
     if (panel < 1 || panel > 16) return fail(HNESSI_E_ARG, "panel must be in 1..16");
-    if (max_rank < 1 || max_rank + panel > kW)
-        return fail(HNESSI_E_ARG, "need 1 <= max_rank and max_rank + panel <= " + std::to_string(kW));
+    if (max_rank < 1 || max_rank + panel > kWLarge)
+        return fail(HNESSI_E_ARG, "need 1 <= max_rank and max_rank + panel <= " + std::to_string(kWLarge));
     int rc = lib_init();
     if (rc != HNESSI_OK) return rc;
     auto* H = new hnessi_hodlr_s();
@@ -285,17 +332,22 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
     H->flags = flags;
     H->f32 = (flags & HNESSI_FLAG_FP32_FACTORS) != 0;
     H->tol = svd_tol;
-    const int npair = H->npair, RC = H->RC, nb = g.nb;
-    Allocs& al = H->al;
+    H->MW = merge_width(max_rank, panel);
+    const int npair = H->npair, RC = H->RC, nb = g.nb, MW = H->MW;
+    H->al = DevAlloc::current(st);
+    DevAlloc& al = H->al;
     auto bail = [&](int code) {
-        al.release();
+        (void)hipStreamSynchronize(st);
+        al.release(true);
+        if (H->ev_last) hipEventDestroy(H->ev_last);
         delete H;
         return code;
     };
-#define HALLOC(p, n, z)                                  \
-    do {                                                 \
-        int rc_ = al.alloc((p), (n), (z));               \
-        if (rc_ != HNESSI_OK) return bail(rc_);          \
+#define HALLOC(p, n, z)                                                                           \
+    do {                                                                                          \
+        if (dev_alloc(al, (p), (n), (z)) != HNESSI_OK)                                            \
+            return bail(fail(HNESSI_E_NOMEM, "device allocation of " + std::to_string((size_t)(n)) + \
+                                                 " elements failed"));                           \
     } while (0)
     // one allocation holding nk objects; o receives the per-object count
 #define HALLOC_K(p, n, z, o)                             \
@@ -387,20 +439,20 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
         int maxc = 0;
         for (int b = 0; b < nb; ++b)
             if (g.level[b] == l) maxc = std::max(maxc, g.c1[b] - g.c0[b]);
-        H->lvl_nodes[l] = 2 * div_up(maxc, kMergeCH);
+        H->lvl_nodes[l] = 2 * div_up(maxc, merge_ch(MW));
         H->lvl_node_base[l] = nodes;
         nodes += (long long)npair * H->lvl_nodes[l];
         H->lvl_chunk_base[l] = chunks;
-        chunks += (long long)npair * div_up(maxc, kMergeCH);
+        chunks += (long long)npair * div_up(maxc, merge_ch(MW));
     }
     const long long nprob = (long long)std::max(nlvl, 1) * npair;
-    HALLOC_K(H->nodeR, (size_t)std::max(nodes, 1LL) * kW * kW, false, H->oNodeR);
-    HALLOC_K(H->nodeQ, (size_t)std::max(nodes, 1LL) * kNodeQ, false, H->oNodeQ);
-    HALLOC_K(H->chunkQ, (size_t)std::max(chunks, 1LL) * kChunkQ, false, H->oChunkQ);
+    HALLOC_K(H->nodeR, (size_t)std::max(nodes, 1LL) * MW * MW, false, H->oNodeR);
+    HALLOC_K(H->nodeQ, (size_t)std::max(nodes, 1LL) * node_q(MW), false, H->oNodeQ);
+    HALLOC_K(H->chunkQ, (size_t)std::max(chunks, 1LL) * chunk_q(MW), false, H->oChunkQ);
     HALLOC_K(H->nodecnt, (size_t)std::max(nodes, 1LL), true, H->oNodeCnt);
-    HALLOC_K(H->UK, (size_t)nprob * kW * kW, false, H->oProbW2);
-    HALLOC_K(H->VR, (size_t)nprob * kW * kW, false, H->oProbW2);
-    HALLOC_K(H->Sold, (size_t)nprob * kW, false, H->oProbW);
+    HALLOC_K(H->UK, (size_t)nprob * MW * MW, false, H->oProbW2);
+    HALLOC_K(H->VR, (size_t)nprob * MW * MW, false, H->oProbW2);
+    HALLOC_K(H->Sold, (size_t)nprob * MW, false, H->oProbW);
     HALLOC_K(H->rold, (size_t)nprob, false, H->oProb);
     HALLOC(H->err, 1, true);
     // projection task lists (sorted by the row that activates them)
@@ -418,18 +470,25 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
         H->ft_act[c].resize(ts.size());
         for (size_t i = 0; i < ts.size(); ++i) H->ft_act[c][i] = ts[i].act;
         HALLOC(H->d_ft[c], ts.size(), false);
-        if (!ts.empty() &&
-            hipMemcpy(H->d_ft[c], ts.data(), ts.size() * sizeof(FactTask), hipMemcpyHostToDevice) != hipSuccess)
+        if (!ts.empty() && hipMemcpyAsync(H->d_ft[c], ts.data(), ts.size() * sizeof(FactTask),
+                                          hipMemcpyHostToDevice, st) != hipSuccess)
             return bail(fail(HNESSI_E_DEVICE, "copy of task table failed"));
+        // the host tables are local: the copies complete before they go out of scope
+        if (hipStreamSynchronize(st) != hipSuccess) return bail(fail(HNESSI_E_DEVICE, "stream synchronization failed"));
     }
-    if (hipMemcpy(H->d_blk, blk.data(), blk.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(H->d_leaf, lf.data(), lf.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(H->d_cover, g.cover.data(), g.cover.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
-        (nb > 0 && hipMemcpy(H->d_Uoff, H->Uoff.data(), nb * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess) ||
-        (nb > 0 && hipMemcpy(H->d_Voff, H->Voff.data(), nb * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess) ||
-        hipMemcpy(H->d_Loff, H->Loff.data(), g.nleaf * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(H->d_partoff, partoff.data(), partoff.size() * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess)
+    auto h2d = [&](void* dst, const void* src, size_t bytes) {
+        return bytes == 0 || hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st) == hipSuccess;
+    };
+    if (!h2d(H->d_blk, blk.data(), blk.size() * sizeof(int)) || !h2d(H->d_leaf, lf.data(), lf.size() * sizeof(int)) ||
+        !h2d(H->d_cover, g.cover.data(), g.cover.size() * sizeof(int)) ||
+        !h2d(H->d_Uoff, H->Uoff.data(), nb * sizeof(long long)) ||
+        !h2d(H->d_Voff, H->Voff.data(), nb * sizeof(long long)) ||
+        !h2d(H->d_Loff, H->Loff.data(), g.nleaf * sizeof(long long)) ||
+        !h2d(H->d_partoff, partoff.data(), partoff.size() * sizeof(long long)))
         return bail(fail(HNESSI_E_DEVICE, "copy of geometry failed"));
+    // every allocation, fill and copy of this handle is ordered on st; the host tables
+    // above are local, so the copies complete before create returns
+    if (hipStreamSynchronize(st) != hipSuccess) return bail(fail(HNESSI_E_DEVICE, "stream synchronization failed"));
     // the merge stream (default priority) and its events
     if (hipStreamCreateWithFlags(&H->mstream, hipStreamNonBlocking) != hipSuccess) {
         H->mstream = nullptr;
@@ -441,6 +500,11 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
             release_streams(H);
             return bail(fail(HNESSI_E_DEVICE, "event creation failed"));
         }
+    if (hipEventCreateWithFlags(&H->ev_last, hipEventDisableTiming) != hipSuccess) {
+        H->ev_last = nullptr;
+        release_streams(H);
+        return bail(fail(HNESSI_E_DEVICE, "event creation failed"));
+    }
 #undef HALLOC_K
 #undef HALLOC
     *out = H;
@@ -453,26 +517,25 @@ extern "C" {
 
 int hnessi_hodlr_create(hnessi_hodlr_t* out, int nt, int nlvl, int norb, int k, double svd_tol,
                         int panel, int max_rank, int flags, void* stream) {
-    (void)stream;
-    return create_impl(out, 1, nt, nlvl, norb, k, svd_tol, panel, max_rank, flags);
+    return create_impl(out, 1, nt, nlvl, norb, k, svd_tol, panel, max_rank, flags, (hipStream_t)stream);
 }
 
 int hnessi_hodlr_create_batched(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k,
                                 double svd_tol, int panel, int max_rank, int flags, void* stream) {
-    (void)stream;
-    return create_impl(out, nk, nt, nlvl, norb, k, svd_tol, panel, max_rank, flags);
+    return create_impl(out, nk, nt, nlvl, norb, k, svd_tol, panel, max_rank, flags, (hipStream_t)stream);
 }
 
 int hnessi_hodlr_nk(hnessi_hodlr_t H) { return H ? H->nk : fail(HNESSI_E_ARG, "handle is NULL"); }
 
 int hnessi_hodlr_destroy(hnessi_hodlr_t H) {
     if (!H) return fail(HNESSI_E_ARG, "handle is NULL");
-    hipDeviceSynchronize();
+    const int rc = wait_handle(H);
     release_streams(H);
     H->prof.release();
-    H->al.release();
+    H->al.release(false);
+    if (H->ev_last) hipEventDestroy(H->ev_last);
     delete H;
-    return HNESSI_OK;
+    return rc;
 }
 
 int hnessi_hodlr_reset(hnessi_hodlr_t H, void* stream) {
@@ -481,15 +544,15 @@ int hnessi_hodlr_reset(hnessi_hodlr_t H, void* stream) {
     for (int c = 0; c < 2; ++c) {
         if (H->pend[c].on) HIP_TRY(hipStreamWaitEvent(st, H->ev_merge[c], 0));   // merge done first
         H->pend[c].on = false;
-        HIP_TRY(hipMemsetAsync(H->rank[c], 0, sizeof(int) * H->oRank * H->nk, st));
-        HIP_TRY(hipMemsetAsync(H->d_cur[c], 0, sizeof(int) * H->cur[c].size(), st));
+        HIP_TRY(launch_fill_int(H->rank[c], H->oRank * H->nk, 0, st));
+        HIP_TRY(launch_fill_int(H->d_cur[c], (long long)H->cur[c].size(), 0, st));
         std::fill(H->cur[c].begin(), H->cur[c].end(), 0);
         H->last[c] = -1;
         H->n0[c] = 0;
         H->fstart[c] = 0;
     }
-    HIP_TRY(hipMemsetAsync(H->err, 0, sizeof(int), st));
-    return HNESSI_OK;
+    HIP_TRY(launch_fill_int(H->err, 1, 0, st));
+    return mark(H, st);
 }
 
 }  // extern "C"
@@ -509,8 +572,14 @@ int merge_panel(hnessi_hodlr_t H, int c, int p0, int p1, hipStream_t st, std::ve
     a.src_ring = kTailRows;
     a.pp = p1 - p0;
     a.npair = H->npair;
+    a.W = H->MW;
     a.RC = H->RC;
+    a.RCr = H->RC;
     a.tol = H->tol;
+    a.Ur = H->U[c];
+    a.Vr = H->V[c];
+    a.Sr = H->S[c];
+    a.rankr = H->rank[c];
     a.U = H->U[c];
     a.V = H->V[c];
     a.U32 = H->U32[c];
@@ -553,7 +622,7 @@ int merge_panel(hnessi_hodlr_t H, int c, int p0, int p1, hipStream_t st, std::ve
         B.ncols = g.c1[b] - g.c0[b];
         B.ldU = g.r1[b] - g.r0[b];
         B.kb = p0 - g.r0[b];
-        B.nchunks = div_up(B.ncols, kMergeCH);
+        B.nchunks = div_up(B.ncols, merge_ch(H->MW));
         B.task_off = nv;
         B.utask_off = nu;
         B.nutask = div_up(B.kb + a.pp, 256);
@@ -829,40 +898,46 @@ extern "C" {
 int hnessi_hodlr_append_row(hnessi_hodlr_t H, int c, int n, const void* row, void* stream) {
     int rc = single_only(H);
     if (rc != HNESSI_OK) return rc;
-    return append_impl(H, c, n, row, 0, (hipStream_t)stream);
+    rc = append_impl(H, c, n, row, 0, (hipStream_t)stream);
+    return rc != HNESSI_OK ? rc : mark(H, (hipStream_t)stream);
 }
 
 int hnessi_hodlr_append_row_batched(hnessi_hodlr_t H, int c, int n, const void* rows, long long k_stride,
                                     void* stream) {
     int rc = batched_stride(H, k_stride, (long long)(n + 1) * (H ? H->npair : 0));
     if (rc != HNESSI_OK) return rc;
-    return append_impl(H, c, n, rows, k_stride, (hipStream_t)stream);
+    rc = append_impl(H, c, n, rows, k_stride, (hipStream_t)stream);
+    return rc != HNESSI_OK ? rc : mark(H, (hipStream_t)stream);
 }
 
 int hnessi_history_R(hnessi_hodlr_t H, int n, const void* sigR_row, double h, void* out, void* stream) {
     int rc = single_only(H);
     if (rc != HNESSI_OK) return rc;
-    return do_history(H, n, sigR_row, nullptr, h, out, nullptr, true, false, (hipStream_t)stream);
+    rc = do_history(H, n, sigR_row, nullptr, h, out, nullptr, true, false, (hipStream_t)stream);
+    return rc != HNESSI_OK ? rc : mark(H, (hipStream_t)stream);
 }
 
 int hnessi_history_lesser(hnessi_hodlr_t H, int n, const void* sigR_row, const void* sigL_slice,
                           double h, void* out, void* stream) {
     int rc = single_only(H);
     if (rc != HNESSI_OK) return rc;
-    return do_history(H, n, sigR_row, sigL_slice, h, nullptr, out, false, true, (hipStream_t)stream);
+    rc = do_history(H, n, sigR_row, sigL_slice, h, nullptr, out, false, true, (hipStream_t)stream);
+    return rc != HNESSI_OK ? rc : mark(H, (hipStream_t)stream);
 }
 
 int hnessi_history_step(hnessi_hodlr_t H, int n, const void* sigR_row, const void* sigL_slice,
                         double h, void* outR, void* outL, void* stream) {
     int rc = single_only(H);
     if (rc != HNESSI_OK) return rc;
-    return do_history(H, n, sigR_row, sigL_slice, h, outR, outL, true, true, (hipStream_t)stream);
+    rc = do_history(H, n, sigR_row, sigL_slice, h, outR, outL, true, true, (hipStream_t)stream);
+    return rc != HNESSI_OK ? rc : mark(H, (hipStream_t)stream);
 }
 
 int hnessi_history_R_adjoint(hnessi_hodlr_t H, int n, const void* ibar_row, double h, void* out, void* stream) {
     int rc = single_only(H);
     if (rc != HNESSI_OK) return rc;
-    return do_history(H, n, nullptr, ibar_row, h, nullptr, out, false, true, (hipStream_t)stream, 0, 0, true);
+    rc = do_history(H, n, nullptr, ibar_row, h, nullptr, out, false, true, (hipStream_t)stream, 0, 0, true);
+    return rc != HNESSI_OK ? rc : mark(H, (hipStream_t)stream);
 }
 
 int hnessi_history_step_batched(hnessi_hodlr_t H, int n, const void* sigR_rows, const void* sigL_slices,
@@ -872,8 +947,9 @@ int hnessi_history_step_batched(hnessi_hodlr_t H, int n, const void* sigR_rows, 
     int rc = batched_stride(H, in_stride, need);
     if (rc == HNESSI_OK) rc = batched_stride(H, out_stride, need);
     if (rc != HNESSI_OK) return rc;
-    return do_history(H, n, sigR_rows, sigL_slices, h, outR, outL, true, true, (hipStream_t)stream, in_stride,
-                      out_stride);
+    rc = do_history(H, n, sigR_rows, sigL_slices, h, outR, outL, true, true, (hipStream_t)stream, in_stride,
+                    out_stride);
+    return rc != HNESSI_OK ? rc : mark(H, (hipStream_t)stream);
 }
 
 }  // extern "C"
@@ -904,7 +980,8 @@ int hnessi_sweep(hnessi_hodlr_t H, int n_begin, int n_end, const void* GR, const
                  const void* SR, const void* SL, double h, void* IR, void* IL, void* stream) {
     int rc = single_only(H);
     if (rc != HNESSI_OK) return rc;
-    return sweep_impl(H, n_begin, n_end, GR, GL, SR, SL, 0, h, IR, IL, (hipStream_t)stream);
+    rc = sweep_impl(H, n_begin, n_end, GR, GL, SR, SL, 0, h, IR, IL, (hipStream_t)stream);
+    return rc != HNESSI_OK ? rc : mark(H, (hipStream_t)stream);
 }
 
 int hnessi_sweep_batched(hnessi_hodlr_t H, int n_begin, int n_end, const void* GR, const void* GL,
@@ -912,15 +989,16 @@ int hnessi_sweep_batched(hnessi_hodlr_t H, int n_begin, int n_end, const void* G
                          void* stream) {
     int rc = batched_stride(H, k_stride, tri(H ? H->nt : 0) * (H ? H->npair : 0));
     if (rc != HNESSI_OK) return rc;
-    return sweep_impl(H, n_begin, n_end, GR, GL, SR, SL, k_stride, h, IR, IL, (hipStream_t)stream);
+    rc = sweep_impl(H, n_begin, n_end, GR, GL, SR, SL, k_stride, h, IR, IL, (hipStream_t)stream);
+    return rc != HNESSI_OK ? rc : mark(H, (hipStream_t)stream);
 }
 
 int hnessi_hodlr_status(hnessi_hodlr_t H, void* stream) {
     if (!H) return fail(HNESSI_E_ARG, "handle is NULL");
     HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
     int rc = drain(H, H->mstream);
+    if (rc == HNESSI_OK) rc = wait_handle(H);
     if (rc != HNESSI_OK) return rc;
-    HIP_TRY(hipDeviceSynchronize());
     int e = 0;
     HIP_TRY(hipMemcpy(&e, H->err, sizeof(int), hipMemcpyDeviceToHost));
     if (e & 2) return fail(HNESSI_E_VALUE, "a truncation met non-finite data (NaN or Inf in the rows)");
@@ -933,7 +1011,8 @@ int hnessi_hodlr_get(hnessi_hodlr_t H, int c, int t1, int t2, void* out_host) {
     if (H->nk != 1) return fail(HNESSI_E_ARG, "batched handle: reconstruction is for single objects");
     if (c != HNESSI_RET && c != HNESSI_LES) return fail(HNESSI_E_ARG, "component must be RET or LES");
     if (t2 < 0 || t2 > t1 || t1 > H->last[c]) return fail(HNESSI_E_RANGE, "(t1, t2) outside the stored region");
-    HIP_TRY(hipDeviceSynchronize());
+    int rc = wait_handle(H);
+    if (rc != HNESSI_OK) return rc;
     const Geometry& g = H->g;
     const int npair = H->npair;
     std::vector<cd> out(npair);
@@ -989,8 +1068,8 @@ int hnessi_hodlr_ranks(hnessi_hodlr_t H, int c, int* ranks_host, int capacity) {
     const long long total = (long long)per * H->nk;
     if (capacity < total) return fail(HNESSI_E_ARG, "capacity too small");
     int rc = drain(H, H->mstream);
+    if (rc == HNESSI_OK) rc = wait_handle(H);
     if (rc != HNESSI_OK) return rc;
-    HIP_TRY(hipDeviceSynchronize());
     std::vector<int> both((size_t)2 * per);
     for (int o = 0; o < H->nk && per > 0; ++o) {
         HIP_TRY(hipMemcpy(both.data(), H->rank[c] + (size_t)o * H->oRank, per * sizeof(int), hipMemcpyDeviceToHost));
@@ -1033,7 +1112,8 @@ size_t hnessi_hodlr_bytes(hnessi_hodlr_t H) { return H ? H->al.bytes : 0; }
 
 int hnessi_hodlr_profile(hnessi_hodlr_t H, int stride) {
     if (!H || stride < 0) return fail(HNESSI_E_ARG, "bad argument");
-    HIP_TRY(hipDeviceSynchronize());
+    int rc = wait_handle(H);
+    if (rc != HNESSI_OK) return rc;
     H->prof.clear();
     H->prof.stride = stride;
     return HNESSI_OK;
@@ -1044,89 +1124,9 @@ int hnessi_hodlr_profile_read(hnessi_hodlr_t H, int kind, int* steps_host, doubl
     return H->prof.read(kind, steps_host, ms_host, capacity);
 }
 
-int hnessi_compress_block(const void* A, int rows, int cols, int lda, double tol, int max_rank, void* U,
-                          double* S, void* V, int* rank_out, void* stream) {
-    if (!A || !U || !S || !V || !rank_out) return fail(HNESSI_E_ARG, "NULL argument");
-    if (rows < 1 || cols < 1 || lda < cols) return fail(HNESSI_E_ARG, "bad matrix shape");
-    if (!(tol > 0.0)) return fail(HNESSI_E_ARG, "tol must be > 0");
-    if (max_rank < 1 || max_rank > kW - 1) return fail(HNESSI_E_ARG, "max_rank must be in 1..31");
-    int rc = lib_init();
-    if (rc != HNESSI_OK) return rc;
-    hipStream_t st = (hipStream_t)stream;
-    const int P = std::max(1, std::min(16, kW - max_rank));
-    const int nch = div_up(cols, kMergeCH);
-    Allocs al;
-    cd *nodeR, *nodeQ, *chunkQ, *UK, *VR;
-    int *nodecnt, *rold, *err;
-    double* Sold;
-    ALLOC(al, nodeR, (size_t)2 * nch * kW * kW, false);
-    ALLOC(al, nodeQ, (size_t)2 * nch * kNodeQ, false);
-    ALLOC(al, chunkQ, (size_t)nch * kChunkQ, false);
-    ALLOC(al, nodecnt, (size_t)2 * nch, true);
-    ALLOC(al, UK, (size_t)kW * kW, false);
-    ALLOC(al, VR, (size_t)kW * kW, false);
-    ALLOC(al, Sold, kW, false);
-    ALLOC(al, rold, 1, false);
-    ALLOC(al, err, 1, true);
-    HIP_TRY(hipMemsetAsync(rank_out, 0, sizeof(int), st));
-    for (int p0 = 0; p0 < rows; p0 += P) {
-        MergeArgs a{};
-        a.pp = std::min(P, rows - p0);
-        a.npair = 1;
-        a.RC = max_rank;
-        a.tol = tol;
-        a.U = static_cast<cd*>(U);
-        a.V = static_cast<cd*>(V);
-        a.S = S;
-        a.rank = rank_out;
-        a.src = static_cast<const cd*>(A) + (size_t)p0 * lda;
-        a.src_row = lda;
-        a.src_pair = 0;
-        a.src_first = 0;
-        a.src_ring = 1 << 30;   // rows of A in place: no wrap
-        a.nodeR = nodeR;
-        a.nodeQ = nodeQ;
-        a.chunkQ = chunkQ;
-        a.nodecnt = nodecnt;
-        a.UK = UK;
-        a.VR = VR;
-        a.Sold = Sold;
-        a.rold = rold;
-        a.err = err;
-        MergeBlk& B = a.blk[0];
-        B.b = 0;
-        B.c0 = 0;
-        B.ncols = cols;
-        B.ldU = rows;
-        B.kb = p0;
-        B.nchunks = nch;
-        B.task_off = 0;
-        B.utask_off = 0;
-        B.nutask = div_up(p0 + a.pp, 256);
-        B.nnodes = 2 * nch;
-        B.node_base = 0;
-        B.chunk_base = 0;
-        B.Uoff = 0;
-        B.Voff = 0;
-        a.nblk = 1;
-        a.ntask_v = nch;
-        a.ntask_u = B.nutask;
-        hipError_t e = launch_merge(a, 1, st);
-        if (e != hipSuccess) {
-            hipStreamSynchronize(st);
-            al.release();
-            return fail(HNESSI_E_DEVICE, std::string("merge launch: ") + hipGetErrorString(e));
-        }
-    }
-    hipError_t e = hipStreamSynchronize(st);
-    al.release();
-    if (e != hipSuccess) return fail(HNESSI_E_DEVICE, std::string("compress_block: ") + hipGetErrorString(e));
-    return HNESSI_OK;
-}
-
 // ---------------------------------------------------------------------------
 int hnessi_dense_create(hnessi_dense_t* out, int nt, int norb, int k, void* stream) {
-    (void)stream;
+    hipStream_t st = (hipStream_t)stream;
     if (!out) return fail(HNESSI_E_ARG, "out is NULL");
     *out = nullptr;
     if (!(norb == 1 || norb == 2 || norb == 4)) return fail(HNESSI_E_ARG, "dense storage supports norb 1, 2, 4");
@@ -1145,32 +1145,39 @@ int hnessi_dense_create(hnessi_dense_t* out, int nt, int norb, int k, void* stre
     D->k = k;
     D->trin = tri(nt);
     const int nbands = dense_band_count(nt);
+    D->al = DevAlloc::current(st);
     auto bail = [&](int code) {
-        D->al.release();
+        (void)hipStreamSynchronize(st);
+        D->al.release(true);
+        if (D->ev_last) hipEventDestroy(D->ev_last);
         delete D;
         return code;
     };
-    for (int c = 0; c < 2; ++c) {
-        int r = D->al.alloc(D->L[c], (size_t)D->npair * D->trin, false);
-        if (r != HNESSI_OK) return bail(r);
+    auto nomem = [&]() { return bail(fail(HNESSI_E_NOMEM, "device allocation failed")); };
+    for (int c = 0; c < 2; ++c)
+        if (dev_alloc(D->al, D->L[c], (size_t)D->npair * D->trin, false) != HNESSI_OK) return nomem();
+    if (dev_alloc(D->al, D->colR, (size_t)nbands * nt * D->npair, false) != HNESSI_OK ||
+        dev_alloc(D->al, D->colL, (size_t)nbands * nt * D->npair, false) != HNESSI_OK ||
+        dev_alloc(D->al, D->rowL, (size_t)nbands * nt * D->npair, false) != HNESSI_OK)
+        return nomem();
+    if (hipEventCreateWithFlags(&D->ev_last, hipEventDisableTiming) != hipSuccess) {
+        D->ev_last = nullptr;
+        return bail(fail(HNESSI_E_DEVICE, "event creation failed"));
     }
-    int r1 = D->al.alloc(D->colR, (size_t)nbands * nt * D->npair, false);
-    if (r1 != HNESSI_OK) return bail(r1);
-    r1 = D->al.alloc(D->colL, (size_t)nbands * nt * D->npair, false);
-    if (r1 != HNESSI_OK) return bail(r1);
-    r1 = D->al.alloc(D->rowL, (size_t)nbands * nt * D->npair, false);
-    if (r1 != HNESSI_OK) return bail(r1);
+    if (hipEventRecord(D->ev_last, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+        return bail(fail(HNESSI_E_DEVICE, "stream synchronization failed"));
     *out = D;
     return HNESSI_OK;
 }
 
 int hnessi_dense_destroy(hnessi_dense_t D) {
     if (!D) return fail(HNESSI_E_ARG, "handle is NULL");
-    hipDeviceSynchronize();
+    const hipError_t e = D->ev_last ? hipEventSynchronize(D->ev_last) : hipSuccess;
     D->prof.release();
-    D->al.release();
+    D->al.release(false);
+    if (D->ev_last) hipEventDestroy(D->ev_last);
     delete D;
-    return HNESSI_OK;
+    return e == hipSuccess ? HNESSI_OK : fail(HNESSI_E_DEVICE, "event synchronization failed");
 }
 
 int hnessi_dense_reset(hnessi_dense_t D, void* stream) {
@@ -1187,6 +1194,7 @@ int hnessi_dense_append_row(hnessi_dense_t D, int c, int n, const void* row, voi
     if (n != D->last[c] + 1) return fail(HNESSI_E_ORDER, "rows must be appended in order");
     HIP_TRY(launch_append_dense(D->L[c], static_cast<const cd*>(row), n, D->npair, D->trin, (hipStream_t)stream));
     D->last[c] = n;
+    HIP_TRY(hipEventRecord(D->ev_last, (hipStream_t)stream));
     return HNESSI_OK;
 }
 
@@ -1219,6 +1227,7 @@ int hnessi_dense_history_step(hnessi_dense_t D, int n, const void* sigR_row, con
     } else {
         HIP_TRY(launch_dense_history(a, (hipStream_t)stream));
     }
+    HIP_TRY(hipEventRecord(D->ev_last, (hipStream_t)stream));
     return HNESSI_OK;
 }
 
@@ -1245,7 +1254,7 @@ size_t hnessi_dense_bytes(hnessi_dense_t D) { return D ? D->al.bytes : 0; }
 
 int hnessi_dense_profile(hnessi_dense_t D, int stride) {
     if (!D || stride < 0) return fail(HNESSI_E_ARG, "bad argument");
-    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipEventSynchronize(D->ev_last));
     D->prof.clear();
     D->prof.stride = stride;
     return HNESSI_OK;

@@ -21,6 +21,7 @@
 //               the tree to its chunk, applies its reflectors and writes its
 //               rows of V'; further workgroups rewrite the rows of U'.
 #include "merge.h"
+#include "trunc.h"
 
 namespace hn {
 
@@ -73,10 +74,13 @@ __device__ void reflector(cd alpha, double sig2, cd& beta_out, cd& t, cd& scale)
     beta_out = mk(beta, 0.0);
 }
 
+// threads per column of a W-wide factorization: a power of two, at most NT / W
+__host__ __device__ constexpr int cols_tpc(int W) { return NT / W >= 8 ? 8 : (NT / W >= 4 ? 4 : 2); }
+
 template <int W>
 __device__ __attribute__((noinline)) void hh_qr(cd* A, int nrows, int ncols, cd* tau,
                                                 double* red) {
-    constexpr int TPC = NT / W;  // threads per trailing column
+    constexpr int TPC = cols_tpc(W);  // threads per trailing column
     const int tid = threadIdx.x;
     const int g = tid / TPC, l = tid % TPC;
     // norm of column 0 below the diagonal
@@ -152,7 +156,7 @@ __device__ __attribute__((noinline)) void hh_qr(cd* A, int nrows, int ncols, cd*
 template <int W>
 __device__ __attribute__((noinline)) void hh_apply_q(const cd* A, int nrows, int nref,
                                                      const cd* tau, cd* X, int nx) {
-    constexpr int TPC = NT / W;
+    constexpr int TPC = cols_tpc(W);
     const int tid = threadIdx.x;
     const int g = tid / TPC, l = tid % TPC;
     for (int j = nref - 1; j >= 0; --j) {
@@ -255,12 +259,8 @@ __device__ __attribute__((noinline)) void jacobi_svd(cd* M, cd* J, int n, int* f
 // per-object data of object blockIdx.y of a batch (the kernel arguments
 // hold object 0 and the strides)
 #define OBJ ((long long)blockIdx.y)
-__device__ inline cd* m_U(const MergeArgs& a) { return a.U + OBJ * a.kU; }
-__device__ inline cd* m_V(const MergeArgs& a) { return a.V + OBJ * a.kV; }
 __device__ inline cf* m_U32(const MergeArgs& a) { return a.U32 ? a.U32 + OBJ * a.kU : nullptr; }
 __device__ inline cf* m_V32(const MergeArgs& a) { return a.V32 ? a.V32 + OBJ * a.kV : nullptr; }
-__device__ inline double* m_S(const MergeArgs& a) { return a.S + OBJ * a.kS; }
-__device__ inline int* m_rank(const MergeArgs& a) { return a.rank + OBJ * a.kRank; }
 __device__ inline const cd* m_src(const MergeArgs& a) { return a.src + OBJ * a.kSrc; }
 __device__ inline cd* m_nodeR(const MergeArgs& a) { return a.nodeR + OBJ * a.kNodeR; }
 __device__ inline cd* m_nodeQ(const MergeArgs& a) { return a.nodeQ + OBJ * a.kNodeQ; }
@@ -272,19 +272,24 @@ __device__ inline double* m_Sold(const MergeArgs& a) { return a.Sold + OBJ * a.k
 __device__ inline int* m_rold(const MergeArgs& a) { return a.rold + OBJ * a.kProb; }
 
 // the block's current (read) and updated (write) factor buffers
-__device__ inline const cd* rd_U(const MergeArgs& a, const MergeBlk& B) { return m_U(a) + B.rd * a.bU; }
-__device__ inline const cd* rd_V(const MergeArgs& a, const MergeBlk& B) { return m_V(a) + B.rd * a.bV; }
-__device__ inline const double* rd_S(const MergeArgs& a, const MergeBlk& B) { return m_S(a) + B.rd * a.bS; }
-__device__ inline const int* rd_rank(const MergeArgs& a, const MergeBlk& B) { return m_rank(a) + B.rd * a.bRank; }
-__device__ inline cd* wr_U(const MergeArgs& a, const MergeBlk& B) { return m_U(a) + (B.rd ^ a.flip) * a.bU; }
-__device__ inline cd* wr_V(const MergeArgs& a, const MergeBlk& B) { return m_V(a) + (B.rd ^ a.flip) * a.bV; }
-__device__ inline double* wr_S(const MergeArgs& a, const MergeBlk& B) { return m_S(a) + (B.rd ^ a.flip) * a.bS; }
-__device__ inline int* wr_rank(const MergeArgs& a, const MergeBlk& B) { return m_rank(a) + (B.rd ^ a.flip) * a.bRank; }
+__device__ inline const cd* rd_U(const MergeArgs& a, const MergeBlk& B) { return a.Ur + OBJ * a.kU + B.rd * a.bU; }
+__device__ inline const cd* rd_V(const MergeArgs& a, const MergeBlk& B) { return a.Vr + OBJ * a.kV + B.rd * a.bV; }
+__device__ inline const double* rd_S(const MergeArgs& a, const MergeBlk& B) { return a.Sr + OBJ * a.kS + B.rd * a.bS; }
+__device__ inline const int* rd_rank(const MergeArgs& a, const MergeBlk& B) {
+    return a.rankr + OBJ * a.kRank + B.rd * a.bRank;
+}
+__device__ inline long long wr_buf(const MergeArgs& a, const MergeBlk& B) { return B.rd ^ a.flip; }
+__device__ inline cd* wr_U(const MergeArgs& a, const MergeBlk& B) { return a.U + OBJ * a.kU + wr_buf(a, B) * a.bU; }
+__device__ inline cd* wr_V(const MergeArgs& a, const MergeBlk& B) { return a.V + OBJ * a.kV + wr_buf(a, B) * a.bV; }
+__device__ inline double* wr_S(const MergeArgs& a, const MergeBlk& B) { return a.S + OBJ * a.kS + wr_buf(a, B) * a.bS; }
+__device__ inline int* wr_rank(const MergeArgs& a, const MergeBlk& B) {
+    return a.rank + OBJ * a.kRank + wr_buf(a, B) * a.bRank;
+}
 __device__ inline cf* wr_U32(const MergeArgs& a, const MergeBlk& B) {
-    return a.U32 ? m_U32(a) + (B.rd ^ a.flip) * a.bU : nullptr;
+    return a.U32 ? m_U32(a) + wr_buf(a, B) * a.bU : nullptr;
 }
 __device__ inline cf* wr_V32(const MergeArgs& a, const MergeBlk& B) {
-    return a.V32 ? m_V32(a) + (B.rd ^ a.flip) * a.bV : nullptr;
+    return a.V32 ? m_V32(a) + wr_buf(a, B) * a.bV : nullptr;
 }
 
 // ranks come from device memory; every index derived from them is kept
@@ -322,19 +327,19 @@ __device__ inline int tree_levoff(int nc, int L) {
     return off;
 }
 
-// Build the chunk of Z = [V S, A_p^dagger] into LDS (column-major, kCH rows,
+// Build the chunk of Z = [V S, A_p^dagger] into LDS (column-major, CH rows,
 // zero padded) and factor it.
 template <int W>
 __device__ void chunk_qr(const MergeArgs& a, const Ctx& c, int r_old, const double* s_old,
                          cd* A, cd* tau, double* red) {
-    constexpr int kCH = kMergeCH;
+    constexpr int CH = merge_ch(W);
     const MergeBlk& B = *c.B;
     const int w = r_old + a.pp;
-    const int row0 = c.chunk * kCH;
-    const int nr = min(kCH, B.ncols - row0);
-    const cd* V = rd_V(a, B) + B.Voff + (size_t)c.q * a.RC * B.ncols;
-    for (int idx = threadIdx.x; idx < kCH * w; idx += NT) {
-        int col = idx / kCH, i = idx % kCH;
+    const int row0 = c.chunk * CH;
+    const int nr = min(CH, B.ncols - row0);
+    const cd* V = rd_V(a, B) + B.Voff + (size_t)c.q * a.RCr * B.ncols;
+    for (int idx = threadIdx.x; idx < CH * w; idx += NT) {
+        int col = idx / CH, i = idx % CH;
         cd z = mk(0.0, 0.0);
         if (i < nr) {
             int s = row0 + i;  // column of the block (relative)
@@ -349,42 +354,42 @@ __device__ void chunk_qr(const MergeArgs& a, const Ctx& c, int r_old, const doub
         A[idx] = z;
     }
     __syncthreads();
-    hh_qr<W>(A, kCH, w, tau, red);
+    hh_qr<W>(A, CH, w, tau, red);
 }
 
-}  // namespace
-
-
+template <int W>
 __global__ void __launch_bounds__(NT) merge_up_kernel(MergeArgs a) {
-    constexpr int W = kW, CH = kMergeCH;
+    constexpr int CH = merge_ch(W), NQ = node_q(W), CQ = chunk_q(W);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cd* A = reinterpret_cast<cd*>(smem_raw);               // CH x W (also 2W x W, and M, J)
-    cd* tau = A + (size_t)CH * W;                          // W
+    cd* tau = A + (size_t)(CH > 2 * W ? CH : 2 * W) * W;   // W
     double* red = reinterpret_cast<double*>(tau + W);      // 16
     __shared__ int sflag;
     __shared__ double s_old[W];
     __shared__ double ssig[W];
     __shared__ int sperm[W];
+    __shared__ int sbad;
 
     Ctx c = decode_task(a, blockIdx.x);
     const MergeBlk& B = *c.B;
     const size_t pidx = prob_index(a, c);
     const size_t fq = (size_t)B.b * a.npair + c.q;
-    const int r_old = clamp_rank(rd_rank(a, B)[fq], a.RC);
+    const int r_old = clamp_rank(rd_rank(a, B)[fq], min(a.RCr, W - a.pp));
     const int w = r_old + a.pp;
-    for (int i = threadIdx.x; i < W; i += NT) s_old[i] = i < r_old ? rd_S(a, B)[fq * a.RC + i] : 0.0;
+    for (int i = threadIdx.x; i < W; i += NT) s_old[i] = i < r_old ? rd_S(a, B)[fq * a.RCr + i] : 0.0;
+    if (threadIdx.x == 0) sbad = 0;
     __syncthreads();
 
     chunk_qr<W>(a, c, r_old, s_old, A, tau, red);
     {   // keep the chunk's reflectors for merge_down
-        cd* cq = m_chunkQ(a) + (size_t)(B.chunk_base + (long long)c.q * B.nchunks + c.chunk) * kChunkQ;
+        cd* cq = m_chunkQ(a) + (size_t)(B.chunk_base + (long long)c.q * B.nchunks + c.chunk) * CQ;
         for (int e = threadIdx.x; e < CH * w; e += NT) cq[e] = A[e];
         for (int e = threadIdx.x; e < w; e += NT) cq[CH * W + e] = tau[e];
     }
 
     const long long nbase = B.node_base + (long long)c.q * B.nnodes;
     cd* nodeR = m_nodeR(a) + (size_t)nbase * W * W;
-    cd* nodeQ = m_nodeQ(a) + (size_t)nbase * kNodeQ;
+    cd* nodeQ = m_nodeQ(a) + (size_t)nbase * NQ;
     int* nodecnt = m_nodecnt(a) + nbase;
     {
         cd* dst = nodeR + (size_t)c.chunk * W * W;
@@ -420,7 +425,7 @@ __global__ void __launch_bounds__(NT) merge_up_kernel(MergeArgs a) {
                 int col = e / W, i = e % W;
                 dst[e] = (col < w && i <= col) ? A[(size_t)col * nr2 + i] : mk(0.0, 0.0);
             }
-            cd* qd = nodeQ + (size_t)(offP + parent) * kNodeQ;
+            cd* qd = nodeQ + (size_t)(offP + parent) * NQ;
             for (int e = threadIdx.x; e < nr2 * w; e += NT) qd[e] = A[e];
             for (int e = threadIdx.x; e < w; e += NT) qd[2 * W * W + e] = tau[e];
             __threadfence();
@@ -451,29 +456,19 @@ __global__ void __launch_bounds__(NT) merge_up_kernel(MergeArgs a) {
     for (int i = threadIdx.x; i < ne; i += NT) {
         double s = 0.0;
         for (int r = 0; r < ne; ++r) s += norm2(M[(size_t)i * ne + r]);
-        s = sqrt(s);
-        // a non-finite norm (non-finite input data) sorts last and is never kept
-        if (!(s <= 1e300)) {
-            if (s != s || s > 1e300) atomicOr(a.err, 2);
-            s = -1.0;
-        }
-        ssig[i] = s;
+        bool bad = false;
+        ssig[i] = trunc_key(sqrt(s), &bad);
+        if (bad) sbad = 1;
     }
     __syncthreads();
+    if (threadIdx.x == 0 && sbad) atomicOr(a.err, 2);
     // descending order; all keys are finite, so this is a permutation of 0..ne-1
-    for (int i = threadIdx.x; i < ne; i += NT) {
-        int pos = 0;
-        for (int j = 0; j < ne; ++j) pos += (ssig[j] > ssig[i]) || (ssig[j] == ssig[i] && j < i);
-        sperm[pos] = i;
-    }
+    for (int i = threadIdx.x; i < ne; i += NT) sperm[trunc_position(ssig, ne, i)] = i;
     __syncthreads();
-    int rnew = 0;
-    for (int i = 0; i < ne; ++i) rnew += (ssig[sperm[i]] >= a.tol) ? 1 : 0;
-    if (rnew > a.RC) {
-        if (threadIdx.x == 0) atomicOr(a.err, 1);
-        rnew = a.RC;
-    }
+    bool over = false;
+    const int rnew = trunc_rank(ssig, sperm, ne, a.tol, a.RC, &over);
     if (threadIdx.x == 0) {
+        if (over) atomicOr(a.err, 1);
         m_rold(a)[pidx] = r_old;
         wr_rank(a, B)[fq] = rnew;
     }
@@ -490,12 +485,14 @@ __global__ void __launch_bounds__(NT) merge_up_kernel(MergeArgs a) {
     }
 }
 
+template <int W>
 __global__ void __launch_bounds__(NT) merge_down_kernel(MergeArgs a) {
-    constexpr int W = kW, CH = kMergeCH;
+    constexpr int CH = merge_ch(W), NQ = node_q(W), CQ = chunk_q(W);
+    constexpr int XR = CH > 2 * W ? CH : 2 * W;      // rows of X (a chunk, or a tree node)
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cd* A = reinterpret_cast<cd*>(smem_raw);       // CH x W
-    cd* X = A + (size_t)CH * W;                     // CH x RC (the updated V rows, rank <= RC)
-    cd* T = X + (size_t)CH * a.RC;                  // W x W
+    cd* X = A + (size_t)CH * W;                     // XR x RC (the updated V rows, rank <= RC)
+    cd* T = X + (size_t)XR * a.RC;                  // W x W
     cd* tau = T + (size_t)W * W;                    // W
 
     if ((int)blockIdx.x < a.ntask_v) {
@@ -503,11 +500,11 @@ __global__ void __launch_bounds__(NT) merge_down_kernel(MergeArgs a) {
         const MergeBlk& B = *c.B;
         const size_t pidx = prob_index(a, c);
         const size_t fq = (size_t)B.b * a.npair + c.q;
-        const int r_old = clamp_rank(m_rold(a)[pidx], a.RC);
+        const int r_old = clamp_rank(m_rold(a)[pidx], min(a.RCr, W - a.pp));
         const int rnew = clamp_rank(wr_rank(a, B)[fq], a.RC);
         const int w = r_old + a.pp;
         {   // the chunk's reflectors from merge_up
-            const cd* cq = m_chunkQ(a) + (size_t)(B.chunk_base + (long long)c.q * B.nchunks + c.chunk) * kChunkQ;
+            const cd* cq = m_chunkQ(a) + (size_t)(B.chunk_base + (long long)c.q * B.nchunks + c.chunk) * CQ;
             for (int e = threadIdx.x; e < CH * w; e += NT) A[e] = cq[e];
             for (int e = threadIdx.x; e < w; e += NT) tau[e] = cq[CH * W + e];
         }
@@ -519,7 +516,7 @@ __global__ void __launch_bounds__(NT) merge_down_kernel(MergeArgs a) {
         }
         __syncthreads();
         const long long nbase = B.node_base + (long long)c.q * B.nnodes;
-        const cd* nodeQ = m_nodeQ(a) + (size_t)nbase * kNodeQ;
+        const cd* nodeQ = m_nodeQ(a) + (size_t)nbase * NQ;
         int depth = 0;
         for (int cnt = B.nchunks; cnt > 1; cnt = (cnt + 1) / 2) ++depth;
         for (int L = depth; L >= 1; --L) {
@@ -530,7 +527,7 @@ __global__ void __launch_bounds__(NT) merge_down_kernel(MergeArgs a) {
             if (2 * node + 1 >= cntBelow) continue;  // single child: Q = identity
             const int slot = child & 1;
             const int nr2 = 2 * w;
-            const cd* Qn = nodeQ + (size_t)(tree_levoff(B.nchunks, L) + node) * kNodeQ;
+            const cd* Qn = nodeQ + (size_t)(tree_levoff(B.nchunks, L) + node) * NQ;
             for (int e = threadIdx.x; e < nr2 * rnew; e += NT) {
                 int col = e / nr2, i = e % nr2;
                 X[e] = (i < w) ? T[(size_t)col * W + i] : mk(0.0, 0.0);
@@ -571,11 +568,11 @@ __global__ void __launch_bounds__(NT) merge_down_kernel(MergeArgs a) {
     const int q = local / B.nutask, ut = local % B.nutask;
     const size_t pidx = (size_t)s * a.npair + q;
     const size_t fq = (size_t)B.b * a.npair + q;
-    const int r_old = clamp_rank(m_rold(a)[pidx], a.RC);
+    const int r_old = clamp_rank(m_rold(a)[pidx], min(a.RCr, W - a.pp));
     const int rnew = clamp_rank(wr_rank(a, B)[fq], a.RC);
     const cd* UK = m_UK(a) + pidx * W * W;
+    const cd* Uold = rd_U(a, B) + B.Uoff + (size_t)q * a.RCr * B.ldU;
     const size_t uo = B.Uoff + (size_t)q * a.RC * B.ldU;
-    const cd* Uold = rd_U(a, B) + uo;
     cd* U = wr_U(a, B) + uo;
     cf* U32 = a.U32 ? wr_U32(a, B) + uo : nullptr;
     const int row = ut * NT + threadIdx.x;
@@ -603,20 +600,24 @@ __global__ void __launch_bounds__(NT) merge_down_kernel(MergeArgs a) {
     }
 }
 
-static size_t merge_up_smem() {
-    return (size_t)kMergeCH * kW * sizeof(cd) + (size_t)kW * sizeof(cd) + 16 * sizeof(double);
+template <int W>
+size_t merge_up_smem() {
+    constexpr int CH = merge_ch(W);
+    return (size_t)(CH > 2 * W ? CH : 2 * W) * W * sizeof(cd) + (size_t)W * sizeof(cd) + 16 * sizeof(double);
 }
 // sized by the rank capacity, so that a merge_down workgroup leaves room on its
 // compute unit for a history workgroup
-static size_t merge_down_smem(int RC) {
-    return (size_t)kMergeCH * kW * sizeof(cd) + (size_t)kMergeCH * RC * sizeof(cd) + (size_t)kW * kW * sizeof(cd) +
-           (size_t)kW * sizeof(cd) + 16 * sizeof(double);
+template <int W>
+size_t merge_down_smem(int RC) {
+    constexpr int CH = merge_ch(W), XR = CH > 2 * W ? CH : 2 * W;
+    return (size_t)CH * W * sizeof(cd) + (size_t)XR * RC * sizeof(cd) + (size_t)W * W * sizeof(cd) +
+           (size_t)W * sizeof(cd) + 16 * sizeof(double);
 }
 
-hipError_t launch_merge(const MergeArgs& a, int nk, hipStream_t st) {
-    if (a.ntask_v == 0) return hipSuccess;
-    merge_up_kernel<<<dim3(a.ntask_v, nk), NT, merge_up_smem(), st>>>(a);
-    merge_down_kernel<<<dim3(a.ntask_v + a.ntask_u, nk), NT, merge_down_smem(a.RC), st>>>(a);
+template <int W>
+hipError_t launch_merge_w(const MergeArgs& a, int nk, hipStream_t st) {
+    merge_up_kernel<W><<<dim3(a.ntask_v, nk), NT, merge_up_smem<W>(), st>>>(a);
+    merge_down_kernel<W><<<dim3(a.ntask_v + a.ntask_u, nk), NT, merge_down_smem<W>(a.RC), st>>>(a);
     return hipGetLastError();
 }
 
@@ -630,6 +631,21 @@ __global__ void flip_kernel(int* cur, FlipList f) {
     if (i < f.n) cur[f.b[i]] ^= 1;
 }
 
+__global__ void fill_int_kernel(int* p, long long n, int v) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+hipError_t launch_merge(const MergeArgs& a, int nk, hipStream_t st) {
+    if (a.ntask_v == 0) return hipSuccess;
+    if (a.RC < 1 || a.RC > a.W || a.pp < 1 || a.pp >= a.W) return hipErrorInvalidValue;
+    if (a.W == kWSmall) return launch_merge_w<kWSmall>(a, nk, st);
+    if (a.W == kWLarge) return launch_merge_w<kWLarge>(a, nk, st);
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_flip(int* cur, const int* blocks, int n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     if (n > kMaxMergeBlk) return hipErrorInvalidValue;
@@ -640,12 +656,22 @@ hipError_t launch_flip(int* cur, const int* blocks, int n, hipStream_t st) {
     return hipGetLastError();
 }
 
+hipError_t launch_fill_int(int* p, long long n, int v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    fill_int_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(p, n, v);
+    return hipGetLastError();
+}
+
 hipError_t merge_init() {
-    hipError_t e = hipFuncSetAttribute((const void*)merge_up_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)merge_up_smem());
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)merge_down_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)merge_down_smem(kW));
+    hipError_t e = hipSuccess;
+    auto set = [&](const void* f, size_t bytes) {
+        if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    };
+    set((const void*)merge_up_kernel<kWSmall>, merge_up_smem<kWSmall>());
+    set((const void*)merge_down_kernel<kWSmall>, merge_down_smem<kWSmall>(kWSmall));
+    set((const void*)merge_up_kernel<kWLarge>, merge_up_smem<kWLarge>());
+    set((const void*)merge_down_kernel<kWLarge>, merge_down_smem<kWLarge>(kWLarge));
+    return e;
 }
 
 }  // namespace hn
