@@ -340,6 +340,7 @@ int hnessi_hodlr_profile_read(hnessi_hodlr_t H, int kind, int* steps_host, doubl
 int hnessi_compress_block(const void* A, int rows, int cols, int lda, double tol, int max_rank,
                           void* U, double* S, void* V, int* rank_out, void* stream);
 
+
 /* ---------------------------------------------------------------------------
  * Dense storage (the uncompressed baseline on the same device, the role of
  * the NESSi solver in the paper's comparisons, sections "Timing results" and

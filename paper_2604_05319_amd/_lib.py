@@ -361,8 +361,8 @@ def compress_block(A, tol, max_rank):
     V = torch.zeros((max_rank, cols), dtype=torch.complex128, device=A.device)
     S = torch.zeros(max_rank, dtype=torch.float64, device=A.device)
     rk = torch.zeros(1, dtype=torch.int32, device=A.device)
-    _check(lib().hnessi_compress_block(_ptr(A), rows, cols, cols, tol, max_rank, _ptr(U), _ptr(S),
-                                       _ptr(V), _ptr(rk), _stream()))
+    fn = lib().hnessi_compress_block
+    _check(fn(_ptr(A), rows, cols, cols, tol, max_rank, _ptr(U), _ptr(S), _ptr(V), _ptr(rk), _stream()))
     r = int(rk.item())
     if r < 0:
         raise HnessiError(r, "compress_block failed on the device (non-finite data or internal rank overflow)")

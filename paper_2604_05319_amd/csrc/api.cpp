@@ -439,7 +439,7 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
         int maxc = 0;
         for (int b = 0; b < nb; ++b)
             if (g.level[b] == l) maxc = std::max(maxc, g.c1[b] - g.c0[b]);
-        H->lvl_nodes[l] = 2 * div_up(maxc, merge_ch(MW));
+        H->lvl_nodes[l] = tree_nodes(div_up(maxc, merge_ch(MW)));
         H->lvl_node_base[l] = nodes;
         nodes += (long long)npair * H->lvl_nodes[l];
         H->lvl_chunk_base[l] = chunks;

@@ -44,19 +44,19 @@ struct ScratchSizes {
     size_t Us, Vs, nodeR, nodeQ, chunkQ, UK, VR, Ss, Sold, rks, nodecnt, rold, err;
 };
 
-ScratchSizes scratch_sizes(int rows, int cols) {
+constexpr ScratchSizes scratch_sizes(int rows, int cols) {
     const size_t nch = (size_t)((cols + merge_ch(kCW) - 1) / merge_ch(kCW));
     ScratchSizes z{};
     z.Us = (size_t)rows * kCapInt;
     z.Vs = (size_t)cols * kCapInt;
-    z.nodeR = 2 * nch * kCW * kCW;
-    z.nodeQ = 2 * nch * node_q(kCW);
+    z.nodeR = (size_t)tree_nodes((int)nch) * kCW * kCW;
+    z.nodeQ = (size_t)tree_nodes((int)nch) * node_q(kCW);
     z.chunkQ = nch * chunk_q(kCW);
     z.UK = z.VR = (size_t)kCW * kCW;
     z.Ss = kCapInt;
     z.Sold = kCW;
     z.rks = 1;
-    z.nodecnt = 2 * nch;
+    z.nodecnt = (size_t)tree_nodes((int)nch);
     z.rold = 1;
     z.err = 2;
     return z;
@@ -79,7 +79,7 @@ int compress_run(const void* A, int rows, int cols, int lda, double tol, int max
     const int nch = (cols + merge_ch(kCW) - 1) / merge_ch(kCW);
     const double tol_int = tol * (kDropBudget / nmerge);
     hipError_t e = launch_fill_int(s.rks, 1, 0, st);
-    if (e == hipSuccess) e = launch_fill_int(s.nodecnt, 2LL * nch, 0, st);
+    if (e == hipSuccess) e = launch_fill_int(s.nodecnt, tree_nodes(nch), 0, st);
     if (e == hipSuccess) e = launch_fill_int(s.err, 2, 0, st);
     if (e == hipSuccess) e = launch_fill_int(rank_out, 1, 0, st);
     for (int i = 0; i < nmerge && e == hipSuccess; ++i) {
@@ -135,7 +135,7 @@ int compress_run(const void* A, int rows, int cols, int lda, double tol, int max
         B.task_off = 0;
         B.utask_off = 0;
         B.nutask = (p0 + a.pp + 255) / 256;
-        B.nnodes = 2 * nch;
+        B.nnodes = tree_nodes(nch);
         B.node_base = 0;
         B.chunk_base = 0;
         B.Uoff = 0;

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "common.h"
+#include "tsqr_tree.h"
 
 namespace hn {
 
@@ -28,7 +29,7 @@ struct MergeBlk {
     int task_off;   // first chunk task of this block (pair-major inside)
     int utask_off;  // first U task of this block (inside the U segment)
     int nutask;     // U tasks per pair
-    int nnodes;     // tree nodes per pair (2 * nchunks)
+    int nnodes;     // tree nodes per pair (at least tree_nodes(nchunks))
     long long node_base;  // first node of pair 0 of this block in the scratch
     long long chunk_base; // first chunk slot of pair 0 of this block in chunkQ
     long long Uoff, Voff; // element offsets of the block in U / V (pair 0, rank 0)

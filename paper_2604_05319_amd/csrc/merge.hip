@@ -317,15 +317,6 @@ __device__ inline size_t prob_index(const MergeArgs& a, const Ctx& c) {
     return (size_t)c.slot * a.npair + c.q;
 }
 
-// tree levels: cnt[0] = nchunks, cnt[L+1] = ceil(cnt[L]/2); node (L, i) at levoff[L] + i
-__device__ inline int tree_levoff(int nc, int L) {
-    int off = 0, cnt = nc;
-    for (int i = 0; i < L; ++i) {
-        off += cnt;
-        cnt = (cnt + 1) / 2;
-    }
-    return off;
-}
 
 // Build the chunk of Z = [V S, A_p^dagger] into LDS (column-major, CH rows,
 // zero padded) and factor it.
@@ -641,6 +632,8 @@ __global__ void fill_int_kernel(int* p, long long n, int v) {
 hipError_t launch_merge(const MergeArgs& a, int nk, hipStream_t st) {
     if (a.ntask_v == 0) return hipSuccess;
     if (a.RC < 1 || a.RC > a.W || a.pp < 1 || a.pp >= a.W) return hipErrorInvalidValue;
+    for (int i = 0; i < a.nblk; ++i)   // every tree node of a problem has its own slot
+        if (a.blk[i].nnodes < tree_nodes(a.blk[i].nchunks)) return hipErrorInvalidValue;
     if (a.W == kWSmall) return launch_merge_w<kWSmall>(a, nk, st);
     if (a.W == kWLarge) return launch_merge_w<kWLarge>(a, nk, st);
     return hipErrorInvalidValue;
