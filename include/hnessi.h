@@ -340,6 +340,17 @@ int hnessi_hodlr_profile_read(hnessi_hodlr_t H, int kind, int* steps_host, doubl
 int hnessi_compress_block(const void* A, int rows, int cols, int lda, double tol, int max_rank,
                           void* U, double* S, void* V, int* rank_out, void* stream);
 
+/* hnessi_compress_block for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same factorization and results, with the scratch taken from
+ * a static device array of about 23 MB that each GPU the library runs on
+ * holds until the process ends.  It calls no allocation routine and no
+ * allocator hook.  rows and cols must be at most 4096 (HNESSI_E_ARG beyond);
+ * other arguments and errors as for hnessi_compress_block.  Every call on one
+ * GPU shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other host threads) race and must be serialized by the caller. */
+int hnessi_compress_block_noalloc(const void* A, int rows, int cols, int lda, double tol, int max_rank,
+                                  void* U, double* S, void* V, int* rank_out, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Dense storage (the uncompressed baseline on the same device, the role of

@@ -68,6 +68,8 @@ _SIGS = {
     "hnessi_hodlr_bytes": ([C.c_void_p], C.c_size_t),
     "hnessi_compress_block": ([C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, C.c_void_p,
                                C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "hnessi_compress_block_noalloc": ([C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "hnessi_dense_create": ([C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_int, C.c_void_p], C.c_int),
     "hnessi_dense_destroy": ([C.c_void_p], C.c_int),
     "hnessi_dense_reset": ([C.c_void_p, C.c_void_p], C.c_int),
@@ -353,15 +355,16 @@ class Dense:
         return _profile_read(lib().hnessi_dense_profile_read, self.h, kind)
 
 
-def compress_block(A, tol, max_rank):
-    """TSVD of a dense device block A (rows x cols complex128).  Returns (U, S, V, rank)."""
+def compress_block(A, tol, max_rank, noalloc=False):
+    """TSVD of a dense device block A (rows x cols complex128).  Returns (U, S, V, rank).
+    noalloc: use the entry point whose scratch is the library's static device array."""
     import torch
     rows, cols = A.shape
     U = torch.zeros((max_rank, rows), dtype=torch.complex128, device=A.device)
     V = torch.zeros((max_rank, cols), dtype=torch.complex128, device=A.device)
     S = torch.zeros(max_rank, dtype=torch.float64, device=A.device)
     rk = torch.zeros(1, dtype=torch.int32, device=A.device)
-    fn = lib().hnessi_compress_block
+    fn = lib().hnessi_compress_block_noalloc if noalloc else lib().hnessi_compress_block
     _check(fn(_ptr(A), rows, cols, cols, tol, max_rank, _ptr(U), _ptr(S), _ptr(V), _ptr(rk), _stream()))
     r = int(rk.item())
     if r < 0:

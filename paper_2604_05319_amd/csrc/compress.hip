@@ -11,7 +11,9 @@
 // 5e-4 * eps: its rank is the eps-rank of the block except for a singular
 // value within 1e-3 * eps of eps, and the spectral error is below eps under
 // the same condition.
+#include <mutex>
 #include <string>
+#include <type_traits>
 
 #include "alloc.h"
 #include "merge.h"
@@ -154,8 +156,82 @@ int compress_run(const void* A, int rows, int cols, int lda, double tol, int max
     return HNESSI_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of the entry point that allocates nothing: one file-scope device
+// array, sized for blocks of at most kNoAllocRows x kNoAllocCols.  Host code
+// never uses the array's name as an address: the device address of each GPU's
+// copy comes from hipGetSymbolAddress on the first call with that device
+// current and is kept per device.
+constexpr int kNoAllocRows = 4096;
+constexpr int kNoAllocCols = 4096;
+constexpr size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t scratch_bytes(const ScratchSizes& z) {
+    return align256(z.Us * sizeof(cd)) + align256(z.Vs * sizeof(cd)) + align256(z.nodeR * sizeof(cd)) +
+           align256(z.nodeQ * sizeof(cd)) + align256(z.chunkQ * sizeof(cd)) + align256(z.UK * sizeof(cd)) +
+           align256(z.VR * sizeof(cd)) + align256(z.Ss * sizeof(double)) + align256(z.Sold * sizeof(double)) +
+           align256(z.rks * sizeof(int)) + align256(z.nodecnt * sizeof(int)) + align256(z.rold * sizeof(int)) +
+           align256(z.err * sizeof(int));
+}
+constexpr size_t kNoAllocBytes = scratch_bytes(scratch_sizes(kNoAllocRows, kNoAllocCols));
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_dev[kMaxDevices] = {};
+
+// carve the scratch of a rows x cols factorization out of base (256-byte aligned parts)
+CompressScratch carve(unsigned char* base, int rows, int cols) {
+    const ScratchSizes z = scratch_sizes(rows, cols);
+    CompressScratch s{};
+    size_t off = 0;
+    auto take = [&](auto*& p, size_t count) {
+        using T = std::remove_reference_t<decltype(*p)>;
+        p = reinterpret_cast<T*>(base + off);
+        off += align256(count * sizeof(T));
+    };
+    take(s.Us, z.Us);
+    take(s.Vs, z.Vs);
+    take(s.nodeR, z.nodeR);
+    take(s.nodeQ, z.nodeQ);
+    take(s.chunkQ, z.chunkQ);
+    take(s.UK, z.UK);
+    take(s.VR, z.VR);
+    take(s.Ss, z.Ss);
+    take(s.Sold, z.Sold);
+    take(s.rks, z.rks);
+    take(s.nodecnt, z.nodecnt);
+    take(s.rold, z.rold);
+    take(s.err, z.err);
+    return s;
+}
+
 }  // namespace
 
+}  // namespace hn
+
+static __device__ __align__(256) unsigned char scratch[hn::kNoAllocBytes];
+
+namespace hn {
+namespace {
+
+// device address of the current device's copy of `scratch`, looked up once per device
+int scratch_address(unsigned char** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return set_error(HNESSI_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return set_error(HNESSI_E_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(HNESSI_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_dev[dev] = static_cast<unsigned char*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return HNESSI_OK;
+}
+
+}  // namespace
 }  // namespace hn
 
 using namespace hn;
@@ -186,6 +262,22 @@ int hnessi_compress_block(const void* A, int rows, int cols, int lda, double tol
     // stream-ordered release: the memory returns to the hook after st reaches this point
     al.release(true);
     return rc;
+}
+
+int hnessi_compress_block_noalloc(const void* A, int rows, int cols, int lda, double tol, int max_rank, void* U,
+                                  double* S, void* V, int* rank_out, void* stream) {
+    int rc = check_args(A, rows, cols, lda, tol, max_rank, U, S, V, rank_out);
+    if (rc != HNESSI_OK) return rc;
+    if (rows > kNoAllocRows || cols > kNoAllocCols)
+        return set_error(HNESSI_E_ARG, "compress_block_noalloc: the block exceeds the static scratch (rows and "
+                                       "cols must be at most " + std::to_string(kNoAllocRows) + ")");
+    rc = lib_init();
+    if (rc != HNESSI_OK) return rc;
+    unsigned char* base = nullptr;
+    rc = scratch_address(&base);
+    if (rc != HNESSI_OK) return rc;
+    return compress_run(A, rows, cols, lda, tol, max_rank, U, S, V, rank_out, (hipStream_t)stream,
+                        carve(base, rows, cols));
 }
 
 }  // extern "C"
