@@ -149,7 +149,7 @@ struct hnessi_hodlr_s {
     int nk = 1;  // objects of a batch (same geometry, independent data)
     // per-object element counts of the batched arrays (the stride between objects)
     long long oU = 0, oV = 0, oS = 0, oRank = 0, oLeaf = 0, oTail = 0, oBand = 0, oProj = 0, oPart = 0,
-              oLeafOut = 0, oTailcol = 0, oTailpart = 0, oTailrow = 0, oNodeR = 0, oNodeQ = 0, oNodeCnt = 0, oProbW2 = 0,
+              oLeafOut = 0, oLeafOutLL = 0, oTailcol = 0, oTailpart = 0, oTailrow = 0, oNodeR = 0, oNodeQ = 0, oNodeCnt = 0, oProbW2 = 0,
               oProbW = 0, oProb = 0, oChunkQ = 0;
     double tol = 0.0;
     Weights W{};
@@ -185,7 +185,7 @@ struct hnessi_hodlr_s {
     long long bU = 0, bV = 0, bS = 0, bRank = 0;   // buffer 1 offset (elements)
     std::vector<int> cur[2];                        // per block: current buffer
     int* d_cur[2] = {};
-    hipStream_t mstream = nullptr;
+    hipStream_t mstream[2] = {};   // per component: the two components' merges run concurrently
     hipEvent_t ev_app[2] = {}, ev_merge[2] = {};
     struct Pending {
         bool on = false;
@@ -210,14 +210,15 @@ struct hnessi_hodlr_s {
     std::vector<long long> lvl_node_base;  // per level: first node of pair 0
     std::vector<int> lvl_nodes;            // per level: nodes per pair
     std::vector<long long> lvl_chunk_base; // per level: first chunk slot of pair 0
-    cd* nodeR = nullptr;
-    cd* nodeQ = nullptr;
-    cd* chunkQ = nullptr;
-    int* nodecnt = nullptr;
-    cd* UK = nullptr;
-    cd* VR = nullptr;
-    double* Sold = nullptr;
-    int* rold = nullptr;
+    // per component (the two components' merges run concurrently)
+    cd* nodeR[2] = {};
+    cd* nodeQ[2] = {};
+    cd* chunkQ[2] = {};
+    int* nodecnt[2] = {};
+    cd* UK[2] = {};
+    cd* VR[2] = {};
+    double* Sold[2] = {};
+    int* rold[2] = {};
     int* err = nullptr;
     Prof prof;
 };
@@ -277,19 +278,23 @@ int mark(hnessi_hodlr_t H, hipStream_t st) {
 // wait for the work of the handle: its last call's stream and its merge stream
 int wait_handle(hnessi_hodlr_t H) {
     if (H->ev_last) HIP_TRY(hipEventSynchronize(H->ev_last));
-    if (H->mstream) HIP_TRY(hipStreamSynchronize(H->mstream));
+    for (int c = 0; c < 2; ++c)
+        if (H->mstream[c]) HIP_TRY(hipStreamSynchronize(H->mstream[c]));
     return HNESSI_OK;
 }
 
 void release_streams(hnessi_hodlr_t H) {
-    if (H->mstream) hipStreamSynchronize(H->mstream);
+    for (int c = 0; c < 2; ++c)
+        if (H->mstream[c]) hipStreamSynchronize(H->mstream[c]);
     for (int c = 0; c < 2; ++c) {
         if (H->ev_app[c]) hipEventDestroy(H->ev_app[c]);
         if (H->ev_merge[c]) hipEventDestroy(H->ev_merge[c]);
         H->ev_app[c] = H->ev_merge[c] = nullptr;
     }
-    if (H->mstream) hipStreamDestroy(H->mstream);
-    H->mstream = nullptr;
+    for (int c = 0; c < 2; ++c) {
+        if (H->mstream[c]) hipStreamDestroy(H->mstream[c]);
+        H->mstream[c] = nullptr;
+    }
 }
 
 int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, double svd_tol, int panel,
@@ -407,7 +412,7 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
     }
     HALLOC_K(H->band, (size_t)nt * (k + 1) * npair, true, H->oBand);
     HALLOC_K(H->proj, (size_t)2 * std::max(nb, 1) * npair * 2 * norb * RC, true, H->oProj);
-    // chunk partials of the projections: one slot per kCH factor rows
+    // chunk partials of the projections: one slot per kch(norb) factor rows
     std::vector<long long> partoff((size_t)2 * std::max(nb, 1) * npair * 2, 0);
     long long ps = 0;
     for (int c = 0; c < 2; ++c)
@@ -415,14 +420,14 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
             for (int q = 0; q < npair; ++q)
                 for (int w = 0; w < 2; ++w) {
                     partoff[(((size_t)c * nb + b) * npair + q) * 2 + w] = ps;
-                    ps += div_up(w == 0 ? g.r1[b] - g.r0[b] : g.c1[b] - g.c0[b], kCH);
+                    ps += div_up(w == 0 ? g.r1[b] - g.r0[b] : g.c1[b] - g.c0[b], kch(norb));
                 }
     HALLOC(H->d_partoff, partoff.size(), false);
     HALLOC_K(H->part, (size_t)std::max(ps, 1LL) * norb * RC, true, H->oPart);
-    const int leaf_slots = norb == 1 ? 1 : 4;   // orbital-pair groups of the leaf tasks
+    const int leaf_slots = leaf_groups(norb);   // orbital-pair groups of the leaf tasks
     HALLOC_K(H->leafR, (size_t)leaf_slots * nt * npair, true, H->oLeafOut);
     HALLOC_K(H->leafLR, (size_t)leaf_slots * nt * npair, true, H->oLeafOut);
-    HALLOC_K(H->leafLL, (size_t)leaf_slots * nt * npair, true, H->oLeafOut);
+    HALLOC_K(H->leafLL, (size_t)leaf_ll_slots(norb) * nt * npair, true, H->oLeafOutLL);
     H->ntailchunk_max = div_up(nt, kTailCH);
     for (int c = 0; c < 2; ++c) {
         HALLOC_K(H->tailcol[c], (size_t)tail_groups(norb) * nt * npair, true, H->oTailcol);
@@ -446,23 +451,25 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
         chunks += (long long)npair * div_up(maxc, merge_ch(MW));
     }
     const long long nprob = (long long)std::max(nlvl, 1) * npair;
-    HALLOC_K(H->nodeR, (size_t)std::max(nodes, 1LL) * MW * MW, false, H->oNodeR);
-    HALLOC_K(H->nodeQ, (size_t)std::max(nodes, 1LL) * node_q(MW), false, H->oNodeQ);
-    HALLOC_K(H->chunkQ, (size_t)std::max(chunks, 1LL) * chunk_q(MW), false, H->oChunkQ);
-    HALLOC_K(H->nodecnt, (size_t)std::max(nodes, 1LL), true, H->oNodeCnt);
-    HALLOC_K(H->UK, (size_t)nprob * MW * MW, false, H->oProbW2);
-    HALLOC_K(H->VR, (size_t)nprob * MW * MW, false, H->oProbW2);
-    HALLOC_K(H->Sold, (size_t)nprob * MW, false, H->oProbW);
-    HALLOC_K(H->rold, (size_t)nprob, false, H->oProb);
+    for (int c = 0; c < 2; ++c) {
+        HALLOC_K(H->nodeR[c], (size_t)std::max(nodes, 1LL) * MW * MW, false, H->oNodeR);
+        HALLOC_K(H->nodeQ[c], (size_t)std::max(nodes, 1LL) * node_q(MW), false, H->oNodeQ);
+        HALLOC_K(H->chunkQ[c], (size_t)std::max(chunks, 1LL) * chunk_q(MW), false, H->oChunkQ);
+        HALLOC_K(H->nodecnt[c], (size_t)std::max(nodes, 1LL), true, H->oNodeCnt);
+        HALLOC_K(H->UK[c], (size_t)nprob * MW * MW, false, H->oProbW2);
+        HALLOC_K(H->VR[c], (size_t)nprob * MW * MW, false, H->oProbW2);
+        HALLOC_K(H->Sold[c], (size_t)nprob * MW, false, H->oProbW);
+        HALLOC_K(H->rold[c], (size_t)nprob, false, H->oProb);
+    }
     HALLOC(H->err, 1, true);
     // projection task lists (sorted by the row that activates them)
     for (int c = 0; c < 2; ++c) {
         std::vector<FactTask> ts;
         for (int b = 0; b < nb; ++b)
             for (int q = 0; q < npair; ++q) {
-                for (int ch = 0; ch < div_up(g.r1[b] - g.r0[b], kCH); ++ch)
-                    ts.push_back(FactTask{c, b, q, 0, ch, g.r0[b] + ch * kCH});
-                for (int ch = 0; ch < div_up(g.c1[b] - g.c0[b], kCH); ++ch)
+                for (int ch = 0; ch < div_up(g.r1[b] - g.r0[b], kch(norb)); ++ch)
+                    ts.push_back(FactTask{c, b, q, 0, ch, g.r0[b] + ch * kch(norb)});
+                for (int ch = 0; ch < div_up(g.c1[b] - g.c0[b], kch(norb)); ++ch)
                     ts.push_back(FactTask{c, b, q, 1, ch, g.r0[b]});
             }
         std::stable_sort(ts.begin(), ts.end(),
@@ -490,8 +497,9 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
     // above are local, so the copies complete before create returns
     if (hipStreamSynchronize(st) != hipSuccess) return bail(fail(HNESSI_E_DEVICE, "stream synchronization failed"));
     // the merge stream (default priority) and its events
-    if (hipStreamCreateWithFlags(&H->mstream, hipStreamNonBlocking) != hipSuccess) {
-        H->mstream = nullptr;
+    if (hipStreamCreateWithFlags(&H->mstream[0], hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&H->mstream[1], hipStreamNonBlocking) != hipSuccess) {
+        release_streams(H);
         return bail(fail(HNESSI_E_DEVICE, "stream creation failed"));
     }
     for (int c = 0; c < 2; ++c)
@@ -589,15 +597,15 @@ int merge_panel(hnessi_hodlr_t H, int c, int p0, int p1, hipStream_t st, std::ve
     a.src = H->tail[c];
     a.src_row = (long long)H->npair * H->nt;
     a.src_pair = H->nt;
-    a.nodeR = H->nodeR;
-    a.nodeQ = H->nodeQ;
-    a.chunkQ = H->chunkQ;
+    a.nodeR = H->nodeR[c];
+    a.nodeQ = H->nodeQ[c];
+    a.chunkQ = H->chunkQ[c];
     a.kChunkQ = H->oChunkQ;
-    a.nodecnt = H->nodecnt;
-    a.UK = H->UK;
-    a.VR = H->VR;
-    a.Sold = H->Sold;
-    a.rold = H->rold;
+    a.nodecnt = H->nodecnt[c];
+    a.UK = H->UK[c];
+    a.VR = H->VR[c];
+    a.Sold = H->Sold[c];
+    a.rold = H->rold[c];
     a.err = H->err;
     a.kU = H->oU;
     a.kV = H->oV;
@@ -672,10 +680,11 @@ int finish_pending(hnessi_hodlr_t H, int c, hipStream_t st) {
     return HNESSI_OK;
 }
 
-// Finish every in-flight merge (queries of the stored state).
-int drain(hnessi_hodlr_t H, hipStream_t st) {
+// Finish every in-flight merge (queries of the stored state): each component's
+// pending flip is enqueued on its own merge stream, which the caller then waits for.
+int drain(hnessi_hodlr_t H) {
     for (int c = 0; c < 2; ++c) {
-        int rc = finish_pending(H, c, st);
+        int rc = finish_pending(H, c, H->mstream[c]);
         if (rc != HNESSI_OK) return rc;
     }
     return HNESSI_OK;
@@ -750,9 +759,11 @@ int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, doub
     A.nfpad = div_up(A.nf[0] + A.nf[1], 8) * 8;
     A.nleaf = g.row_leaf[n] + 1;
     const int ngroups = H->norb <= 4 ? 1 : H->norb / 4;   // left-orbital groups of 4 waves
-    const int leafgroups = H->norb == 1 ? 1 : 4;                   // orbital-pair groups per leaf
-    A.nleaftask = div_up(2 * A.nleaf, 8) * 8 * ngroups * leafgroups;
-    A.ntailtask = div_up(A.ntailchunk[0] + A.ntailchunk[1], 8) * 8 * ngroups * tail_groups(H->norb);
+    // dense-piece tasks per leaf and per tail chunk: one per orbital pair for norb <= 4,
+    // left-orbital groups x pair groups for larger norb
+    const int per_piece = H->norb <= 4 ? H->npair : ngroups * 4;
+    A.nleaftask = div_up(2 * A.nleaf, 8) * 8 * per_piece;
+    A.ntailtask = div_up(A.ntailchunk[0] + A.ntailchunk[1], 8) * 8 * per_piece;
     A.part = H->part;
     A.proj = H->proj;
     A.leafR = H->leafR;
@@ -781,6 +792,7 @@ int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, doub
     A.kProj = H->oProj;
     A.kPart = H->oPart;
     A.kLeafOut = H->oLeafOut;
+    A.kLeafOutLL = H->oLeafOutLL;
     A.kTailcol = H->oTailcol;
     A.kTailpart = H->oTailpart;
     A.kTailrow = H->oTailrow;
@@ -848,11 +860,11 @@ int after_append(hnessi_hodlr_t H, int c, int n, hipStream_t st) {
     // and writes the blocks' other buffers; until the next panel ends, the history
     // kernels read the panel's rows from the dense tail
     HIP_TRY(hipEventRecord(H->ev_app[c], st));
-    HIP_TRY(hipStreamWaitEvent(H->mstream, H->ev_app[c], 0));
+    HIP_TRY(hipStreamWaitEvent(H->mstream[c], H->ev_app[c], 0));
     auto& pd = H->pend[c];
-    rc = merge_panel(H, c, p0, p1, H->mstream, pd.blocks);
+    rc = merge_panel(H, c, p0, p1, H->mstream[c], pd.blocks);
     if (rc != HNESSI_OK) return rc;
-    HIP_TRY(hipEventRecord(H->ev_merge[c], H->mstream));
+    HIP_TRY(hipEventRecord(H->ev_merge[c], H->mstream[c]));
     pd.on = true;
     pd.p0 = p0;
     pd.p1 = p1;
@@ -996,7 +1008,7 @@ int hnessi_sweep_batched(hnessi_hodlr_t H, int n_begin, int n_end, const void* G
 int hnessi_hodlr_status(hnessi_hodlr_t H, void* stream) {
     if (!H) return fail(HNESSI_E_ARG, "handle is NULL");
     HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
-    int rc = drain(H, H->mstream);
+    int rc = drain(H);
     if (rc == HNESSI_OK) rc = wait_handle(H);
     if (rc != HNESSI_OK) return rc;
     int e = 0;
@@ -1067,7 +1079,7 @@ int hnessi_hodlr_ranks(hnessi_hodlr_t H, int c, int* ranks_host, int capacity) {
     const int per = H->g.nb * H->npair;
     const long long total = (long long)per * H->nk;
     if (capacity < total) return fail(HNESSI_E_ARG, "capacity too small");
-    int rc = drain(H, H->mstream);
+    int rc = drain(H);
     if (rc == HNESSI_OK) rc = wait_handle(H);
     if (rc != HNESSI_OK) return rc;
     std::vector<int> both((size_t)2 * per);

@@ -98,10 +98,20 @@ bool interval_weights_exact(int k, int L, std::vector<double>& w, std::string& e
 
 // ---------------------------------------------------------------------------
 // constants of the device kernels
-constexpr int kCH = 256;      // factor rows per projection task
+// factor rows per projection task: more rows for small norb, whose tasks carry
+// fewer bytes per row (the Sigma rows of a task are staged in LDS, kch * norb entries)
+__host__ __device__ constexpr int kch(int norb) { return norb <= 2 ? 1024 : (norb == 4 ? 512 : 256); }
 constexpr int kTailCH = 64;   // columns per tail task
 constexpr int kTailRows = 32; // tail rows at most: the panel being merged and the one being formed
 // orbital-pair groups of the tail tasks (one workgroup and one partial slot each)
-__host__ __device__ constexpr int tail_groups(int norb) { return norb == 1 ? 1 : 4; }
+// Output slots of the dense pieces (leaf triangles and tail rows).  For norb <= 4
+// every orbital pair is a task of its own and writes one orbital entry of one
+// slot per output array (slot = the pair orbital summed over by the other
+// tasks), so that each slot entry has exactly one writer; for norb 8 and 16 a
+// task takes a group of pairs and the output has four slots.
+__host__ __device__ constexpr int tail_groups(int norb) { return norb <= 4 ? norb : 4; }
+__host__ __device__ constexpr int leaf_groups(int norb) { return norb <= 4 ? norb : 4; }
+// slots of the lesser leaf output (its two products sum over different orbitals)
+__host__ __device__ constexpr int leaf_ll_slots(int norb) { return norb <= 4 ? 2 * norb : 4; }
 
 }  // namespace hn

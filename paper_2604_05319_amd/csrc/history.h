@@ -5,7 +5,7 @@
 
 namespace hn {
 
-// A projection task: rows [chunk*kCH, +kCH) of U (which = 0) or V (which = 1)
+// A projection task: rows [chunk*kch, +kch) of U (which = 0) or V (which = 1)
 // of block b, orbital pair q, component comp.  Active once row `act` is merged
 // (U: the chunk's first row; V: the block's first row).
 struct FactTask {
@@ -68,7 +68,7 @@ struct HistArgs {
     // data to the next; the geometry and the task lists are shared
     long long kIn, kOut;   // Sigma rows, output rows
     long long kU, kV, kS, kRank, kLeaf, kTail, kBand;
-    long long kProj, kPart, kLeafOut, kTailcol, kTailpart, kTailrow;
+    long long kProj, kPart, kLeafOut, kLeafOutLL, kTailcol, kTailpart, kTailrow;
 };
 
 // Adjoint mode (adj = 1, wantR = 0, wantL = 1): the comp-0 row-dot path of the

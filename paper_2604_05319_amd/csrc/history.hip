@@ -84,7 +84,7 @@ __device__ inline cd* p_proj(const HistArgs& A) { return A.proj + OBJ * A.kProj;
 __device__ inline cd* p_part(const HistArgs& A) { return A.part + OBJ * A.kPart; }
 __device__ inline cd* p_leafR(const HistArgs& A) { return A.leafR + OBJ * A.kLeafOut; }
 __device__ inline cd* p_leafLR(const HistArgs& A) { return A.leafLR + OBJ * A.kLeafOut; }
-__device__ inline cd* p_leafLL(const HistArgs& A) { return A.leafLL + OBJ * A.kLeafOut; }
+__device__ inline cd* p_leafLL(const HistArgs& A) { return A.leafLL + OBJ * A.kLeafOutLL; }
 
 // ranks come from device memory: clamp them to the allocated capacity
 __device__ inline int rank_of(const HistArgs& A, int comp, int b, int q) {
@@ -106,22 +106,90 @@ struct AGroups {
 // orbital-pair groups of a leaf, each a workgroup with its own output slot
 template <int NORB>
 struct LeafGroups {
-    static constexpr int LG = NORB == 1 ? 1 : 4;
+    static constexpr int LG = leaf_groups(NORB);
 };
 
 // ---------------------------------------------------------------------------
-// Ranks per wave in one pass of a projection task (register budget of the
-// NORB accumulators per rank); a pass covers 4 * RW ranks.
-template <int NORB>
-struct ProjRanks {
-    static constexpr int RW = NORB <= 4 ? 4 : (NORB == 8 ? 2 : 1);
-};
+// Projection of rows [chunk*kch, +kch) of U (which = 0, rows merged so far) or
+// V (which = 1) of one block and orbital pair onto the folded Sigma row, scaled
+// by S; the chunk partials are summed by proj_reduce.
+// Lane layout: lane = g * RP + rl covers rank rp + rl of a pass of RP ranks and
+// row group g of LPR = 64 / RP groups; wave w takes the groups w*LPR .. +LPR, so
+// the 4 waves interleave 4*LPR row groups and a wave's load of one step reads RP
+// factor columns over LPR consecutive rows.  Each thread sums its rows for all
+// NORB left orbitals; the row groups are then summed by shuffles inside the wave
+// (log2(LPR) steps) and the waves through LDS.
+template <int NORB, class FT, int RP, class Stage>
+__device__ void fact_pass(const HistArgs& A, const FT* F, int ld, int i0, int i1, int rk, bool cj, const cd* xs,
+                          const double* S, cd* out, cd* red, Stage stage) {
+    constexpr int LPR = 64 / RP, G = 4 * LPR;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int rl = lane % RP, g = wave * LPR + lane / RP;
+    // the first four rows of the first pass are loaded while the Sigma rows are staged
+    cd f0[4];
+    {
+        const FT* Fr = F + (size_t)min(rl, rk - 1) * ld;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) f0[u] = to_cd(Fr[min(i0 + g + u * G, i1 - 1)]);
+    }
+    stage();
+    __syncthreads();
+    for (int rp = 0; rp < rk; rp += RP) {
+        const int r = rp + rl;
+        const bool rv = r < rk;
+        const FT* Fr = F + (size_t)min(r, rk - 1) * ld;
+        cd acc[NORB];
+#pragma unroll
+        for (int a = 0; a < NORB; ++a) acc[a] = mk(0.0, 0.0);
+        // four rows per step with their loads issued together; indices are clamped so
+        // that every load is in range and out-of-range terms are zeroed
+        for (int i = i0 + g; i < i1; i += 4 * G) {
+            cd f[4];
+            if (rp == 0 && i == i0 + g) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) f[u] = f0[u];
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) f[u] = to_cd(Fr[min(i + u * G, i1 - 1)]);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int iu = i + u * G;
+                if (iu < i1 && rv) {
+                    const cd fv = cj ? conj(f[u]) : f[u];
+                    const cd* x = xs + (size_t)(iu - i0) * NORB;
+#pragma unroll
+                    for (int a = 0; a < NORB; ++a) fma_(acc[a], x[a], fv);
+                }
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < NORB; ++a) {
+#pragma unroll
+            for (int off = RP; off < 64; off <<= 1) {
+                acc[a].x += __shfl_xor(acc[a].x, off, 64);
+                acc[a].y += __shfl_xor(acc[a].y, off, 64);
+            }
+        }
+        __syncthreads();   // red is free (previous pass consumed)
+        if (lane < RP)   // red[(a * 4 + wave) * RP + rl]: consecutive lanes, consecutive words
+#pragma unroll
+            for (int a = 0; a < NORB; ++a) red[((size_t)a * 4 + wave) * RP + rl] = acc[a];
+        __syncthreads();
+        if (wave == 0 && lane < RP && rv) {
+            cd sum[NORB];
+#pragma unroll
+            for (int a = 0; a < NORB; ++a) sum[a] = red[((size_t)a * 4) * RP + rl];
+            for (int ww = 1; ww < 4; ++ww)
+#pragma unroll
+                for (int a = 0; a < NORB; ++a) sum[a] = sum[a] + red[((size_t)a * 4 + ww) * RP + rl];
+            const double sr = S[r];
+#pragma unroll
+            for (int a = 0; a < NORB; ++a) out[(size_t)a * A.RC + r] = sr * sum[a];
+        }
+    }
+}
 
-// Projection of rows [chunk*kCH, +kCH) of U (which = 0, rows merged so far) or
-// V (which = 1) of one block and orbital pair onto the folded Sigma row,
-// scaled by S; the chunk partials are summed by proj_reduce.  Wave w takes the
-// ranks w, w+4, ... of a pass; its lanes run over the rows, kCH/64 rows each,
-// with every load of a pass independent of the others.
 template <int NORB, class FT>
 __device__ void fact_task(const HistArgs& A, const FactTask& t, unsigned char* smem) {
     const int comp = t.comp, b = t.b, q = t.q, which = t.which;
@@ -129,9 +197,6 @@ __device__ void fact_task(const HistArgs& A, const FactTask& t, unsigned char* s
     if ((comp == 1 || which == 1) && !A.wantL) return;
     if (comp == 1 && A.adj) return;
     constexpr int npair = NORB * NORB;
-    constexpr bool kStage = true;                  // Sigma rows staged in LDS (kCH x NORB)
-    constexpr int RW = ProjRanks<NORB>::RW;
-    constexpr int RPL = kCH / 64;                  // rows per lane
     const int RC = A.RC;
     const int qr = q / NORB, qc = q % NORB;
     const int rk = rank_of(A, comp, b, q);
@@ -151,6 +216,7 @@ __device__ void fact_task(const HistArgs& A, const FactTask& t, unsigned char* s
         ld = c1 - c0;
         F = p_V<FT>(A, comp, b) + A.Voff[b] + (size_t)q * RC * ld;
     }
+    constexpr int kCH = kch(NORB);
     const int i0 = t.chunk * kCH, i1 = min(len, i0 + kCH);
     if (i0 >= i1) return;
     const int n = A.n;
@@ -164,63 +230,19 @@ __device__ void fact_task(const HistArgs& A, const FactTask& t, unsigned char* s
         }
         return interval_w(A.W, n, j) * p_sigR(A)[(size_t)j * npair + a * NORB + (which == 0 ? qc : qr)];
     };
-    const bool cj = (comp == 1);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    // factor entries of one pass; indices clamped into range so that every
-    // load is issued unconditionally (out-of-range terms are zeroed)
-    cd fr[RPL][RW];
-    auto load_pass = [&](int rp) {
-#pragma unroll
-        for (int u = 0; u < RPL; ++u)
-#pragma unroll
-            for (int k = 0; k < RW; ++k) {
-                const int i = i0 + u * 64 + lane, r = rp + wave + 4 * k;
-                cd f = to_cd(F[(size_t)min(r, rk - 1) * ld + min(i, i1 - 1)]);
-                if (cj) f = conj(f);
-                fr[u][k] = (i < i1 && r < rk) ? f : mk(0.0, 0.0);
-            }
-    };
-    load_pass(0);   // in flight while the Sigma rows are staged
-    cd* xs = reinterpret_cast<cd*>(smem);  // kCH x NORB
-    if (kStage) {
+    cd* xs = reinterpret_cast<cd*>(smem);   // kCH x NORB
+    cd* red = xs + (size_t)kCH * NORB;       // 4 waves x 32 ranks x NORB
+    auto stage = [&]() {
         for (int e = threadIdx.x; e < (i1 - i0) * NORB; e += NT) xs[e] = xval(i0 + e / NORB, e % NORB);
-        __syncthreads();
-    }
+    };
     const double* S = p_S(A, comp, b) + ((size_t)b * npair + q) * RC;
     const size_t slot = proj_slot(A, comp, b, q, which);
     cd* out = p_part(A) + (size_t)(A.partoff[slot] + t.chunk) * NORB * RC;
-    for (int rp = 0; rp < rk; rp += 4 * RW) {
-        if (rp > 0) load_pass(rp);
-        cd acc[RW][NORB];
-#pragma unroll
-        for (int k = 0; k < RW; ++k)
-#pragma unroll
-            for (int a = 0; a < NORB; ++a) acc[k][a] = mk(0.0, 0.0);
-#pragma unroll
-        for (int u = 0; u < RPL; ++u) {
-            const int i = i0 + u * 64 + lane;
-            if (i < i1) {
-                cd xv[NORB];
-#pragma unroll
-                for (int a = 0; a < NORB; ++a) xv[a] = kStage ? xs[(size_t)(i - i0) * NORB + a] : xval(i, a);
-#pragma unroll
-                for (int k = 0; k < RW; ++k)
-#pragma unroll
-                    for (int a = 0; a < NORB; ++a) fma_(acc[k][a], xv[a], fr[u][k]);
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < RW; ++k) {
-            const int r = rp + wave + 4 * k;
-            if (r >= rk) continue;   // wave-uniform
-            const double sr = S[r];
-#pragma unroll
-            for (int a = 0; a < NORB; ++a) {
-                const double re = wsum64(acc[k][a].x), im = wsum64(acc[k][a].y);
-                if (lane == 0) out[(size_t)a * RC + r] = mk(sr * re, sr * im);
-            }
-        }
-    }
+    const bool cj = (comp == 1);
+    if (rk <= 4) fact_pass<NORB, FT, 4>(A, F, ld, i0, i1, rk, cj, xs, S, out, red, stage);
+    else if (rk <= 8) fact_pass<NORB, FT, 8>(A, F, ld, i0, i1, rk, cj, xs, S, out, red, stage);
+    else if (rk <= 16) fact_pass<NORB, FT, 16>(A, F, ld, i0, i1, rk, cj, xs, S, out, red, stage);
+    else fact_pass<NORB, FT, 32>(A, F, ld, i0, i1, rk, cj, xs, S, out, red, stage);
 }
 
 // ---------------------------------------------------------------------------
@@ -333,6 +355,265 @@ __device__ void leaf_task(const HistArgs& A, int leaf, int comp, int ag, int pg,
 }
 
 // ---------------------------------------------------------------------------
+// One leaf triangle, component and orbital pair (qr, qc) for NORB <= 4.  The
+// triangle is loaded in one round trip (every thread's loads issued together)
+// and staged in LDS as a packed triangle: a row is contiguous, and a column read
+// by an aligned group of 8 lanes hits 8 distinct 16-byte bank groups (tri(r) mod 8
+// runs through all residues over 8 aligned rows).  Lane m owns column and row m,
+// wave w the summation indices = w (mod 4), and every thread carries all NORB left
+// orbitals, so each staged element feeds NORB complex FMAs.  Outputs (slot, orbital
+// entry) have one writer each; the combine sums the slots:
+//   comp 0: column sum x(j)[a][qr] G^R(j,m), j >= m      -> leafR [qr][m][a][qc]
+//           row dot x2(s)[a][qc] G^R(m,s)^*, s <= m       -> leafLR[qc][m][a][qr]
+//   comp 1: row dot x1(s)[a][qr] G<(m,s), s <= m          -> leafLL[qr][m][a][qc]
+//           column sum -x1(j)[a][qc] G<(j,m)^*, j > m     -> leafLL[NORB + qc][m][a][qr]
+template <int NORB>
+__device__ void leaf_pair_task(const HistArgs& A, int leaf, int comp, int q, unsigned char* smem) {
+    static_assert(NORB <= 4, "one orbital pair per task");
+    if (comp == 1 && (!A.wantL || A.adj)) return;
+    constexpr int npair = NORB * NORB;
+    const int qr = q / NORB, qc = q % NORB;
+    const int n = A.n;
+    const int s0 = A.leafs[2 * leaf], s1 = A.leafs[2 * leaf + 1];
+    const int lw = s1 - s0;
+    const int nrow = min(s1, n + 1) - s0;
+    const cd* Lq = p_leaf(A, comp) + A.Loff[leaf] + (size_t)q * tri(lw);
+    const long long tnow = tri(nrow);
+    cd* T = reinterpret_cast<cd*>(smem);   // tri(64)
+    cd* xa = T + tri(64);                  // 64 x NORB: Sigma entries with orbital qr
+    cd* xb = xa + 64 * NORB;               // 64 x NORB: Sigma entries with orbital qc
+    const int w = threadIdx.x >> 6, m = threadIdx.x & 63;
+    const bool doR = A.wantR, doL = A.wantL;
+    const bool colOn = comp == 1 || doR;
+    const bool rowOn = (comp == 1 || doL) && (comp == 1 || A.adj || s0 + m > 0);
+    constexpr int TPT = (64 * 65 / 2 + NT - 1) / NT;   // triangle elements per thread
+    {
+        cd v[TPT];
+#pragma unroll
+        for (int u = 0; u < TPT; ++u) {
+            const long long e = threadIdx.x + (long long)u * NT;
+            v[u] = e < tnow ? Lq[e] : mk(0.0, 0.0);
+        }
+        if ((int)threadIdx.x < 64 * NORB) {   // rows beyond the leaf's present rows are zero
+            const int i = threadIdx.x / NORB, a = threadIdx.x % NORB, j = s0 + (i < nrow ? i : 0);
+            cd va, vb;
+            if (i >= nrow) {
+                va = vb = mk(0.0, 0.0);
+            } else if (comp == 0) {
+                va = doR ? w_end(A.W, n, j) * p_sigR(A)[(size_t)j * npair + a * NORB + qr] : mk(0.0, 0.0);
+                vb = !doL ? mk(0.0, 0.0)
+                     : A.adj ? p_sigL(A)[(size_t)j * npair + a * NORB + qc]
+                             : -w_start(A.W, j) * conj(p_sigL(A)[(size_t)j * npair + qc * NORB + a]);
+            } else {
+                const double wi = interval_w(A.W, n, j);
+                va = wi * p_sigR(A)[(size_t)j * npair + a * NORB + qr];
+                vb = wi * p_sigR(A)[(size_t)j * npair + a * NORB + qc];
+            }
+            xa[threadIdx.x] = va;
+            xb[threadIdx.x] = vb;
+        }
+#pragma unroll
+        for (int u = 0; u < TPT; ++u) {
+            const long long e = threadIdx.x + (long long)u * NT;
+            if (e < tnow) T[e] = v[u];
+        }
+    }
+    __syncthreads();
+    cd accC[NORB], accW[NORB];   // column sums, row dots
+#pragma unroll
+    for (int a = 0; a < NORB; ++a) accC[a] = accW[a] = mk(0.0, 0.0);
+    // Summation index j = w + 4t, t = 0..15: the column sum of column m takes row j and
+    // the row dot of row m takes column j.  Both LDS reads are in bounds for every
+    // j, m < 64 and are issued for every t; terms outside the triangle, the present rows
+    // or the requested products are zeroed by selects (the x entries of absent rows are
+    // zero), so the loop has a fixed trip count and no divergence.
+    const int trm = m * (m + 1) / 2;
+#pragma unroll 4
+    for (int t = 0; t < 16; ++t) {
+        const int j = w + 4 * t;
+        const bool vc = colOn && m < nrow && j < nrow && (comp == 0 ? j >= m : j > m);
+        const bool vr = rowOn && m < nrow && j <= m;
+        const cd tc0 = T[j * (j + 1) / 2 + m];
+        const cd tr0 = T[trm + j];
+        const cd tc = vc ? tc0 : mk(0.0, 0.0);
+        const cd tr = vr ? tr0 : mk(0.0, 0.0);
+#pragma unroll
+        for (int a = 0; a < NORB; ++a) {
+            if (comp == 0) {
+                fma_(accC[a], xa[j * NORB + a], tc);
+                fmac_(accW[a], tr, xb[j * NORB + a]);
+            } else {
+                fmac_(accC[a], tc, xb[j * NORB + a]);
+                fma_(accW[a], xa[j * NORB + a], tr);
+            }
+        }
+    }
+    // sum the four waves' partial sums through LDS (the triangle is no longer read);
+    // red[(k * 4 + wave) * 64 + lane]: consecutive lanes, consecutive 16-byte words
+    cd* red = T;   // 2 NORB x 4 x 64
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < NORB; ++a) {
+        red[((size_t)a * 4 + w) * 64 + m] = accC[a];
+        red[((size_t)(NORB + a) * 4 + w) * 64 + m] = accW[a];
+    }
+    __syncthreads();
+    if (w != 0 || m >= nrow) return;
+    for (int ww = 1; ww < 4; ++ww)
+#pragma unroll
+        for (int a = 0; a < NORB; ++a) {
+            accC[a] = accC[a] + red[((size_t)a * 4 + ww) * 64 + m];
+            accW[a] = accW[a] + red[((size_t)(NORB + a) * 4 + ww) * 64 + m];
+        }
+    const size_t mo = (size_t)(s0 + m) * npair;
+    const size_t sl = (size_t)A.nt * npair;   // one slot
+#pragma unroll
+    for (int a = 0; a < NORB; ++a) {
+        if (comp == 0) {
+            if (doR) p_leafR(A)[qr * sl + mo + a * NORB + qc] = accC[a];
+            if (doL) p_leafLR(A)[qc * sl + mo + a * NORB + qr] = accW[a];
+        } else {
+            p_leafLL(A)[qr * sl + mo + a * NORB + qc] = accW[a];
+            p_leafLL(A)[(NORB + qc) * sl + mo + a * NORB + qr] = -accC[a];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tail rows for NORB <= 4: one task per component, 64-column chunk and orbital
+// pair (qr, qc); the 32 x 64 tile (rows n0.. of the ring, columns of the chunk) is
+// loaded in one round trip and staged in LDS with its column index XORed by
+// (row & 15), so that lanes over columns and lanes over rows both spread over
+// distinct banks.  Column sums: lane = column, wave = rows = w (mod 4); row dots:
+// lane = (row, half of the columns), wave = 8 columns of that half.  Every thread
+// carries all NORB left orbitals.  Outputs (one writer per slot entry):
+//   comp 0: column sum x(j)[a][qr] G^R(j,m)        -> tailcol[qr][m][a][qc]
+//           row dot x2(m)[a][qc] G^R(r,m)^*         -> tailpart[chunk][qc][r][a][qr]
+//   comp 1: column sum -x1(j)[a][qc] G<(j,m)^*      -> tailcol[qc][m][a][qr]
+//           row dot x1(m)[a][qr] G<(r,m)            -> tailpart[chunk][qr][r][a][qc]
+template <int NORB>
+__device__ void tail_pair_task(const HistArgs& A, int comp, int chunk, int q, unsigned char* smem) {
+    static_assert(NORB <= 4, "one orbital pair per task");
+    if (comp == 1 && (!A.wantL || A.adj)) return;
+    constexpr int npair = NORB * NORB, TG = tail_groups(NORB);
+    const int qr = q / NORB, qc = q % NORB;
+    const int n = A.n;
+    const int n0 = A.n0[comp], nrows = A.last[comp] - n0 + 1, ls = A.ls[comp];
+    const int cbeg = chunk * kTailCH, ncol = min(kTailCH, ls - cbeg);
+    cd* T = reinterpret_cast<cd*>(smem);       // 32 x 64, swizzled
+    cd* xr = T + (size_t)kTailRows * kTailCH;  // 32 x NORB (row side)
+    cd* xm = xr + (size_t)kTailRows * NORB;    // 64 x NORB (column side)
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const bool doR = A.wantR, doL = A.wantL;
+    const cd* Tg = p_tail(A, comp);
+    constexpr int EPT = kTailRows * kTailCH / NT;   // tile elements per thread
+    {
+        cd v[EPT];
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            const int e = threadIdx.x + u * NT, i = e / kTailCH, mm = e % kTailCH;
+            const int r = n0 + i;                                   // tail row
+            const int lsr = r < A.nsplit[comp] ? A.lslo[comp] : ls; // its dense columns
+            v[u] = (i < nrows && cbeg + mm < lsr) ? Tg[((size_t)(r % A.ring) * npair + q) * A.nt + cbeg + mm]
+                                                 : mk(0.0, 0.0);
+        }
+        const int e = threadIdx.x;
+        if (e < kTailRows * NORB) {   // row side; rows beyond the tail are zero
+            const int i = e / NORB, a = e % NORB, j = n0 + i;
+            xr[e] = i >= nrows ? mk(0.0, 0.0)
+                    : comp == 0 ? (doR ? w_end(A.W, n, j) * p_sigR(A)[(size_t)j * npair + a * NORB + qr] : mk(0.0, 0.0))
+                                : interval_w(A.W, n, j) * p_sigR(A)[(size_t)j * npair + a * NORB + qc];
+        }
+        if (e < kTailCH * NORB) {   // column side
+            const int mm = e / NORB, a = e % NORB, m = cbeg + mm;
+            cd vv = mk(0.0, 0.0);
+            if (mm < ncol) {
+                if (comp == 0) {
+                    if (doL)
+                        vv = A.adj ? p_sigL(A)[(size_t)m * npair + a * NORB + qc]
+                                   : -w_start(A.W, m) * conj(p_sigL(A)[(size_t)m * npair + qc * NORB + a]);
+                } else {
+                    vv = interval_w(A.W, n, m) * p_sigR(A)[(size_t)m * npair + a * NORB + qr];
+                }
+            }
+            xm[e] = vv;
+        }
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            const int e = threadIdx.x + u * NT, i = e / kTailCH, mm = e % kTailCH;
+            T[i * kTailCH + (mm ^ (i & 15))] = v[u];
+        }
+    }
+    __syncthreads();
+    cd col[NORB], row[NORB];
+#pragma unroll
+    for (int a = 0; a < NORB; ++a) col[a] = row[a] = mk(0.0, 0.0);
+    // column sums (lane = column, rows = w mod 4; rows beyond the tail are zero in the
+    // tile and in xr, so the trip count is fixed)
+#pragma unroll 4
+    for (int i = w; i < kTailRows; i += 4) {
+        const cd v = T[i * kTailCH + (lane ^ (i & 15))];
+#pragma unroll
+        for (int a = 0; a < NORB; ++a) {
+            if (comp == 0) fma_(col[a], xr[i * NORB + a], v);
+            else fmac_(col[a], v, xr[i * NORB + a]);
+        }
+    }
+    // row dots (lane = row ri and column half part; wave = 8 columns of the half)
+    const int ri = lane & 31, part = lane >> 5;
+    {   // rows beyond the tail are zero in the tile
+        const int mb = part * 32 + w * 8;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int mm = mb + u;
+            const cd v = T[ri * kTailCH + (mm ^ (ri & 15))];
+#pragma unroll
+            for (int a = 0; a < NORB; ++a) {
+                if (comp == 0) fmac_(row[a], v, xm[mm * NORB + a]);
+                else fma_(row[a], xm[mm * NORB + a], v);
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < NORB; ++a) {   // the two column halves of each row dot
+        row[a].x += __shfl_xor(row[a].x, 32, 64);
+        row[a].y += __shfl_xor(row[a].y, 32, 64);
+    }
+    // sum over the waves through LDS (the tile is no longer read);
+    // red[(k * 4 + wave) * 64 + lane]: consecutive lanes, consecutive 16-byte words
+    cd* red = T;   // 2 NORB x 4 x 64
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < NORB; ++a) {
+        red[((size_t)a * 4 + w) * 64 + lane] = col[a];
+        red[((size_t)(NORB + a) * 4 + w) * 64 + lane] = row[a];
+    }
+    __syncthreads();
+    if (w != 0) return;
+    for (int ww = 1; ww < 4; ++ww)
+#pragma unroll
+        for (int a = 0; a < NORB; ++a) {
+            col[a] = col[a] + red[((size_t)a * 4 + ww) * 64 + lane];
+            row[a] = row[a] + red[((size_t)(NORB + a) * 4 + ww) * 64 + lane];
+        }
+    const size_t sl = (size_t)A.nt * npair;
+    if (lane < ncol) {
+        const size_t mo = (size_t)(cbeg + lane) * npair;
+#pragma unroll
+        for (int a = 0; a < NORB; ++a) {
+            if (comp == 0) p_tailcol(A, 0)[qr * sl + mo + a * NORB + qc] = col[a];
+            else p_tailcol(A, 1)[qc * sl + mo + a * NORB + qr] = -col[a];
+        }
+    }
+    if (part == 0 && ri < nrows) {
+        const int slot = comp == 0 ? qc : qr, c = comp == 0 ? qr : qc;
+        cd* tp = p_tailpart(A, comp) + ((size_t)(chunk * TG + slot) * A.ring + ri) * npair + c;
+#pragma unroll
+        for (int a = 0; a < NORB; ++a) tp[a * NORB] = row[a];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Rows appended since the last panel merge (dense), columns [chunk*64, +64) of
 // [0, ls): the column sums over those rows are complete here; the row dots are
 // written per column chunk and summed by the combine.
@@ -395,8 +676,14 @@ __device__ void tail_task(const HistArgs& A, int comp, int ag, int chunk, int tg
     for (int q = tg * PPG; q < (tg + 1) * PPG; ++q) {
         const int qr = q / NORB, qc = q % NORB;
         __syncthreads();
+        // the tile is stored with its column index XORed by (row & 15), so that the row
+        // dots (lanes over rows) and the column sums (lanes over columns) both spread
+        // over distinct LDS banks
 #pragma unroll
-        for (int u = 0; u < EPT; ++u) T[threadIdx.x + u * NT] = pT[u];
+        for (int u = 0; u < EPT; ++u) {
+            const int e = threadIdx.x + u * NT, i = e / kTailCH, mm = e % kTailCH;
+            T[i * kTailCH + (mm ^ (i & 15))] = pT[u];
+        }
         if ((int)threadIdx.x < nrows * AG) xr[threadIdx.x] = pxr;
         if ((int)threadIdx.x < kTailCH * AG) xm[threadIdx.x] = pxm;
         if (q + 1 < (tg + 1) * PPG) fetch(q + 1);
@@ -405,8 +692,9 @@ __device__ void tail_task(const HistArgs& A, int comp, int ag, int chunk, int tg
             // column sums (lane = column)
             cd cs = mk(0.0, 0.0);
             for (int i = 0; i < nrows; ++i) {
-                if (comp == 0) fma_(cs, xr[i * AG + wave], T[i * kTailCH + lane]);
-                else fmac_(cs, T[i * kTailCH + lane], xr[i * AG + wave]);
+                const cd v = T[i * kTailCH + (lane ^ (i & 15))];
+                if (comp == 0) fma_(cs, xr[i * AG + wave], v);
+                else fmac_(cs, v, xr[i * AG + wave]);
             }
             if (comp == 0) {
                 if (doR) add_at(col, qc, cs);       // x(j) G^R(j, m)
@@ -417,8 +705,9 @@ __device__ void tail_task(const HistArgs& A, int comp, int ag, int chunk, int tg
             cd rd = mk(0.0, 0.0);
             if (ri < nrows) {
                 for (int mm = part * 32; mm < part * 32 + 32; ++mm) {
-                    if (comp == 0) fmac_(rd, T[ri * kTailCH + mm], xm[mm * AG + wave]);
-                    else fma_(rd, xm[mm * AG + wave], T[ri * kTailCH + mm]);
+                    const cd v = T[ri * kTailCH + (mm ^ (ri & 15))];
+                    if (comp == 0) fmac_(rd, v, xm[mm * AG + wave]);
+                    else fma_(rd, xm[mm * AG + wave], v);
                 }
             }
             if (comp == 0) add_at(row, qr, rd);     // x2(m) G^R(j, m)^dagger
@@ -460,19 +749,30 @@ __global__ void __launch_bounds__(NT) hist_tasks(HistArgs A) {
         constexpr int TG = tail_groups(NORB);
         int g, mem;
         const int ng = A.ntailchunk[0] + A.ntailchunk[1];
-        if (!xcd_group(rel, ng, NG * TG, g, mem)) return;
-        if (g < A.ntailchunk[0])
-            tail_task<NORB>(A, 0, mem % NG, g, mem / NG, smem);
-        else
-            tail_task<NORB>(A, 1, mem % NG, g - A.ntailchunk[0], mem / NG, smem);
+        if constexpr (NORB <= 4) {
+            if (!xcd_group(rel, ng, NORB * NORB, g, mem)) return;
+            if (g < A.ntailchunk[0]) tail_pair_task<NORB>(A, 0, g, mem, smem);
+            else tail_pair_task<NORB>(A, 1, g - A.ntailchunk[0], mem, smem);
+        } else {
+            if (!xcd_group(rel, ng, NG * TG, g, mem)) return;
+            if (g < A.ntailchunk[0])
+                tail_task<NORB>(A, 0, mem % NG, g, mem / NG, smem);
+            else
+                tail_task<NORB>(A, 1, mem % NG, g - A.ntailchunk[0], mem / NG, smem);
+        }
         return;
     }
     rel -= A.ntailtask;
     if (rel < A.nleaftask) {
         constexpr int LG = LeafGroups<NORB>::LG;
         int g, mem;
-        if (!xcd_group(rel, 2 * A.nleaf, NG * LG, g, mem)) return;
-        leaf_task<NORB>(A, g >> 1, g & 1, mem % NG, mem / NG, smem);
+        if constexpr (NORB <= 4) {
+            if (!xcd_group(rel, 2 * A.nleaf, NORB * NORB, g, mem)) return;
+            leaf_pair_task<NORB>(A, g >> 1, g & 1, mem, smem);
+        } else {
+            if (!xcd_group(rel, 2 * A.nleaf, NG * LG, g, mem)) return;
+            leaf_task<NORB>(A, g >> 1, g & 1, mem % NG, mem / NG, smem);
+        }
         return;
     }
     rel -= A.nleaftask;
@@ -535,7 +835,7 @@ __global__ void __launch_bounds__(256) proj_reduce(HistArgs A) {
     const int r0 = bk[1];
     if (A.n0[comp] <= r0) return;
     const int len = which == 0 ? min(A.n0[comp] - r0, bk[2] - r0) : bk[4] - bk[3];
-    const int nch = (len + kCH - 1) / kCH;
+    const int nch = (len + kch(NORB) - 1) / kch(NORB);
     const cd* p = p_part(A) + (size_t)A.partoff[slot] * per + e;
     cd s = mk(0.0, 0.0);
     for (int ch = 0; ch < nch; ++ch) s = s + p[(size_t)ch * per];
@@ -543,38 +843,123 @@ __global__ void __launch_bounds__(256) proj_reduce(HistArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-// acc[a] (+|-)= op(F[r*ld]) z[a*RC + r] over r < rk, op = conj or identity.
-// The factor loads of a batch of eight ranks are issued together (indices
-// clamped to rk - 1, surplus terms skipped) so that they overlap in flight.
-template <int NORB, bool CONJ, bool NEG, class FT>
-__device__ inline void expand_ranks(cd (&acc)[NORB], const FT* F, int ld, const cd* z, int RC, int rk) {
+// acc[a] (+|-)= op(F[r*ld]) z[a*RC + r] over the ranks r = rs, rs + RS, ... < rk,
+// op = conj or identity.  The factor loads of a batch of eight ranks are issued
+// together (indices clamped to rk - 1, surplus terms skipped) so that they
+// overlap in flight.
+template <int NORB, bool CONJ, bool NEG, int RS, class FT>
+__device__ inline void expand_ranks(cd (&acc)[NORB], const FT* F, int ld, const cd* z, int RC, int rk, int rs) {
     constexpr int B = 8;
-    for (int r0 = 0; r0 < rk; r0 += B) {
+    for (int r0 = rs; r0 < rk; r0 += B * RS) {
         cd f[B];
 #pragma unroll
-        for (int u = 0; u < B; ++u) f[u] = to_cd(F[(size_t)min(r0 + u, rk - 1) * ld]);
+        for (int u = 0; u < B; ++u) f[u] = to_cd(F[(size_t)min(r0 + u * RS, rk - 1) * ld]);
 #pragma unroll
         for (int u = 0; u < B; ++u) {
-            if (r0 + u >= rk) break;
+            const int r = r0 + u * RS;
+            if (r >= rk) break;
             const cd fv = NEG ? -f[u] : f[u];
 #pragma unroll
             for (int a = 0; a < NORB; ++a) {
-                if (CONJ) fmac_(acc[a], fv, z[a * RC + r0 + u]);
-                else fma_(acc[a], fv, z[a * RC + r0 + u]);
+                if (CONJ) fmac_(acc[a], fv, z[a * RC + r]);
+                else fma_(acc[a], fv, z[a * RC + r]);
             }
         }
     }
 }
 
 // ---------------------------------------------------------------------------
+// Final sum of one output entry (column m, left orbital a, right orbital c) from
+// its expansion sum y: the leaf and tail slots, the tail row dots, the band
+// corrections of the Gregory weights, the factor h; part 0 writes I^R, part 1
+// writes I^< (or, in adjoint mode, dL/dSigma^R(n, j = m)).
+template <int NORB>
+__device__ void finish_entry(const HistArgs& A, int m, int a, int c, int part, cd y) {
+    constexpr int npair = NORB * NORB, LG = LeafGroups<NORB>::LG;
+    const int n = A.n, k = A.W.k, kb = k + 1;
+    const size_t sl = (size_t)A.nt * npair;
+    const size_t o = (size_t)m * npair + a * NORB + c;
+    if (A.adj) {
+        // outL(j = m) = h [ w_end(n, j) y(j) + corrections ]; the corrections replace
+        // the bulk weight of the terms m' = j - i, i <= k, by the exact interval weight
+        const int j = m;
+        const double we = w_end(A.W, n, j);
+        for (int pg = 0; pg < LG; ++pg) y = y + p_leafLR(A)[pg * sl + o];
+        if (A.last[0] >= A.n0[0] && j >= A.n0[0] && j <= A.last[0])
+            y = y + p_tailrow(A, 0)[(size_t)(j - A.n0[0]) * npair + a * NORB + c];
+        cd out = we * y;
+        const int imax = j < k ? j : k;
+        for (int i = 0; i <= imax; ++i) {
+            const int mp = j - i, L = n - mp;
+            const double wc = L >= k ? A.W.om[i] - 1.0 : A.W.nc[L][i] - we;
+            const cd* ib = p_sigL(A) + (size_t)mp * npair + a * NORB;            // Ibar(n, m')[a][b]
+            const cd* bd = p_band(A) + ((size_t)mp * kb + i) * npair + c * NORB;   // G^R(j, m')[c][b]
+#pragma unroll
+            for (int bb = 0; bb < NORB; ++bb) fmac_(out, bd[bb], wc * ib[bb]);
+        }
+        p_outL(A)[o] = A.h * out;
+        return;
+    }
+    if (part == 0) {
+        cd sR = y;
+        for (int pg = 0; pg < LG; ++pg) sR = sR + p_leafR(A)[pg * sl + o];
+        if (A.last[0] >= A.n0[0] && m < A.ls[0])
+            for (int tg = 0; tg < tail_groups(NORB); ++tg) sR = sR + p_tailcol(A, 0)[tg * sl + o];
+        // band correction: start weights (n-m >= k) or Newton-Cotes (n-m < k)
+        const int L = n - m;
+        if (L == 0) {
+            p_outR(A)[o] = mk(0.0, 0.0);
+            return;
+        }
+        const int imax = L < k ? L : k;
+        for (int i = 0; i <= imax; ++i) {
+            const double wc = L < k ? A.W.nc[L][i] - w_end(A.W, n, m + i) : A.W.om[i] - 1.0;
+            const cd* sg = p_sigR(A) + (size_t)(m + i) * npair + a * NORB;
+            const cd* bd = p_band(A) + ((size_t)m * kb + i) * npair + c;
+#pragma unroll
+            for (int bb = 0; bb < NORB; ++bb) fma_(sR, sg[bb], wc * bd[bb * NORB]);
+        }
+        p_outR(A)[o] = A.h * sR;
+        return;
+    }
+    cd sL = y;
+    for (int pg = 0; pg < LG; ++pg) sL = sL + p_leafLR(A)[pg * sl + o];
+    for (int pg = 0; pg < leaf_ll_slots(NORB); ++pg) sL = sL + p_leafLL(A)[pg * sl + o];
+    for (int comp = 0; comp < 2; ++comp) {
+        if (A.last[comp] < A.n0[comp]) continue;   // no tail rows
+        if (comp == 1 && m < A.ls[1])
+            for (int tg = 0; tg < tail_groups(NORB); ++tg) sL = sL + p_tailcol(A, 1)[tg * sl + o];
+        if (m >= A.n0[comp] && m <= A.last[comp])
+            sL = sL + p_tailrow(A, comp)[(size_t)(m - A.n0[comp]) * npair + a * NORB + c];
+    }
+    // second lesser term: end weights (m >= k) or Newton-Cotes (m < k); the
+    // interval is empty at m = 0 (no bulk term was added there either)
+    // Sigma^<(n,s)[a][b] = -conj(sigL[s][b][a]);  G^R(m,s)^dagger[b][c] = conj(G^R(m,s)[c][b])
+    const int imax = m == 0 ? -1 : (m < k ? m : k);
+    for (int i = 0; i <= imax; ++i) {
+        const int s = m - i;
+        const double wc = m < k ? A.W.nc[m][s] - w_start(A.W, s) : A.W.om[i] - 1.0;
+        const cd* slp = p_sigL(A) + (size_t)s * npair + a;
+        const cd* bd = p_band(A) + ((size_t)s * kb + i) * npair + c * NORB;
+#pragma unroll
+        for (int bb = 0; bb < NORB; ++bb) fmac_(sL, slp[bb * NORB], mk(-wc, 0.0) * conj(bd[bb]));
+    }
+    p_outL(A)[o] = A.h * sL;
+}
+
+// ---------------------------------------------------------------------------
 // Combine.  A wave handles MW consecutive columns m and one output orbital c
-// (c = wave, wave + 4, ...); its G = min(NORB, 4) lane groups split the summed
-// orbital index of the expansions (lane group g takes the orbitals g, g+G, ...)
-// and are summed by shuffles; lane group g then adds the leaf, tail and band
-// pieces of the outputs a = g, g+G, ... and writes them.
+// (c = wave, wave + 4, ...); its G = GO * RS lane groups split the summed
+// orbital index of the expansions (lane group g takes the orbitals g % GO,
+// + GO, ...) and the ranks (r = g / GO, + RS, ...), so that a wave's serial
+// chain of dependent factor loads is short and a step has many waves; the
+// groups are summed by shuffles, and lane group g then adds the leaf, tail and
+// band pieces of the outputs a = g, g+G, ... and writes them.
 template <int NORB>
 struct CombMap {
-    static constexpr int G = NORB < 4 ? NORB : 4;
+    static constexpr int GO = NORB < 4 ? NORB : 4;
+    static constexpr int RS = NORB <= 4 ? 8 / GO : 1;
+    static constexpr int G = GO * RS;
     static constexpr int MW = 64 / G;
     static constexpr int WAVES = NORB < 4 ? NORB : 4;
     static constexpr int NCI = NORB / WAVES;
@@ -583,16 +968,13 @@ struct CombMap {
 template <int NORB, class FT>
 __global__ void __launch_bounds__(64 * CombMap<NORB>::WAVES) hist_combine(HistArgs A) {
     using M = CombMap<NORB>;
-    constexpr int npair = NORB * NORB, G = M::G, MW = M::MW;
+    constexpr int npair = NORB * NORB, G = M::G, MW = M::MW, GO = M::GO, RS = M::RS;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int g = lane / MW;
+    const int g = lane / MW, og = g % GO, rs = g / GO;
     const int m = blockIdx.x * MW + lane % MW;
     const int n = A.n;
     const bool live = m <= n;
     const int RC = A.RC;
-    const int k = A.W.k;
-    const int kb = k + 1;
-    constexpr int LG = LeafGroups<NORB>::LG;
     for (int ci = 0; ci < M::NCI; ++ci) {
         const int c = wave + M::WAVES * ci;
         cd accR[NORB], accL[NORB];
@@ -609,21 +991,21 @@ __global__ void __launch_bounds__(64 * CombMap<NORB>::WAVES) hist_combine(HistAr
                     const int r0 = A.blk[5 * b + 1], c0 = A.blk[5 * b + 3], c1 = A.blk[5 * b + 4];
                     const int ldV = c1 - c0;
                     if (A.wantR && A.n0[0] > r0) {
-                        for (int o = g; o < NORB; o += G) {
+                        for (int o = og; o < NORB; o += GO) {
                             const int q = o * NORB + c;
                             const int rk = rank_of(A, 0, b, q);
                             const FT* Vq = p_V<FT>(A, 0, b) + A.Voff[b] + (size_t)q * RC * ldV + (m - c0);
                             const cd* z = p_proj(A) + proj_slot(A, 0, b, q, 0) * NORB * RC;
-                            if (rk > 0) expand_ranks<NORB, true, false>(accR, Vq, ldV, z, RC, rk);
+                            if (rk > 0) expand_ranks<NORB, true, false, RS>(accR, Vq, ldV, z, RC, rk, rs);
                         }
                     }
                     if (A.wantL && !A.adj && A.n0[1] > r0) {
-                        for (int o = g; o < NORB; o += G) {
+                        for (int o = og; o < NORB; o += GO) {
                             const int q = c * NORB + o;
                             const int rk = rank_of(A, 1, b, q);
                             const FT* Vq = p_V<FT>(A, 1, b) + A.Voff[b] + (size_t)q * RC * ldV + (m - c0);
                             const cd* z = p_proj(A) + proj_slot(A, 1, b, q, 0) * NORB * RC;
-                            if (rk > 0) expand_ranks<NORB, false, true>(accL, Vq, ldV, z, RC, rk);
+                            if (rk > 0) expand_ranks<NORB, false, true, RS>(accL, Vq, ldV, z, RC, rk, rs);
                         }
                     }
                 } else if (A.wantL) {  // m is a row of block b: expand through U
@@ -631,21 +1013,21 @@ __global__ void __launch_bounds__(64 * CombMap<NORB>::WAVES) hist_combine(HistAr
                     const int r0 = A.blk[5 * b + 1], r1 = A.blk[5 * b + 2];
                     const int ldU = r1 - r0;
                     if (m < A.n0[0]) {
-                        for (int o = g; o < NORB; o += G) {
+                        for (int o = og; o < NORB; o += GO) {
                             const int q = c * NORB + o;
                             const int rk = rank_of(A, 0, b, q);
                             const FT* Uq = p_U<FT>(A, 0, b) + A.Uoff[b] + (size_t)q * RC * ldU + (m - r0);
                             const cd* z = p_proj(A) + proj_slot(A, 0, b, q, 1) * NORB * RC;
-                            if (rk > 0) expand_ranks<NORB, true, false>(accL, Uq, ldU, z, RC, rk);
+                            if (rk > 0) expand_ranks<NORB, true, false, RS>(accL, Uq, ldU, z, RC, rk, rs);
                         }
                     }
                     if (!A.adj && m < A.n0[1]) {
-                        for (int o = g; o < NORB; o += G) {
+                        for (int o = og; o < NORB; o += GO) {
                             const int q = o * NORB + c;
                             const int rk = rank_of(A, 1, b, q);
                             const FT* Uq = p_U<FT>(A, 1, b) + A.Uoff[b] + (size_t)q * RC * ldU + (m - r0);
                             const cd* z = p_proj(A) + proj_slot(A, 1, b, q, 1) * NORB * RC;
-                            if (rk > 0) expand_ranks<NORB, false, false>(accL, Uq, ldU, z, RC, rk);
+                            if (rk > 0) expand_ranks<NORB, false, false, RS>(accL, Uq, ldU, z, RC, rk, rs);
                         }
                     }
                 }
@@ -663,85 +1045,14 @@ __global__ void __launch_bounds__(64 * CombMap<NORB>::WAVES) hist_combine(HistAr
             }
         }
         if (!live) continue;
-        const size_t mo = (size_t)m * npair;
-        if (A.adj) {
-            // outL(j = m) = h [ w_end(n, j) y(j) + corrections ]; the corrections replace
-            // the bulk weight of the terms m' = j - i, i <= k, by the exact interval weight
-            const int j = m;
-            const double we = w_end(A.W, n, j);
-#pragma unroll
-            for (int a = 0; a < NORB; ++a) {
-                if (a % G != g) continue;
-                const size_t o = mo + a * NORB + c;
-                cd y = accL[a];
-                for (int pg = 0; pg < LG; ++pg) y = y + p_leafLR(A)[(size_t)pg * A.nt * npair + o];
-                if (A.last[0] >= A.n0[0] && j >= A.n0[0] && j <= A.last[0])
-                    y = y + p_tailrow(A, 0)[(size_t)(j - A.n0[0]) * npair + a * NORB + c];
-                cd out = we * y;
-                const int imax = j < k ? j : k;
-                for (int i = 0; i <= imax; ++i) {
-                    const int mp = j - i, L = n - mp;
-                    const double wc = L >= k ? A.W.om[i] - 1.0 : A.W.nc[L][i] - we;
-                    const cd* ib = p_sigL(A) + (size_t)mp * npair + a * NORB;       // Ibar(n, m')[a][b]
-                    const cd* bd = p_band(A) + ((size_t)mp * kb + i) * npair + c * NORB;  // G^R(j, m')[c][b]
-#pragma unroll
-                    for (int bb = 0; bb < NORB; ++bb) fmac_(out, bd[bb], wc * ib[bb]);
-                }
-                p_outL(A)[o] = A.h * out;
-            }
-            continue;
-        }
 #pragma unroll
         for (int a = 0; a < NORB; ++a) {
             if (a % G != g) continue;
-            const size_t o = mo + a * NORB + c;
-            cd sR = accR[a], sL = accL[a];
-            for (int pg = 0; pg < LG; ++pg) {
-                const size_t op = (size_t)pg * A.nt * npair + o;
-                if (A.wantR) sR = sR + p_leafR(A)[op];
-                if (A.wantL) sL = sL + p_leafLR(A)[op] + p_leafLL(A)[op];
-            }
-            if (A.wantR) {
-                if (A.last[0] >= A.n0[0] && m < A.ls[0])
-                    for (int tg = 0; tg < tail_groups(NORB); ++tg) sR = sR + p_tailcol(A, 0)[(size_t)tg * A.nt * npair + o];
-                // band correction: start weights (n-m >= k) or Newton-Cotes (n-m < k)
-                const int L = n - m;
-                if (L == 0) {
-                    p_outR(A)[o] = mk(0.0, 0.0);
-                } else {
-                    const int imax = L < k ? L : k;
-                    for (int i = 0; i <= imax; ++i) {
-                        const double wc = L < k ? A.W.nc[L][i] - w_end(A.W, n, m + i) : A.W.om[i] - 1.0;
-                        const cd* sg = p_sigR(A) + (size_t)(m + i) * npair + a * NORB;
-                        const cd* bd = p_band(A) + ((size_t)m * kb + i) * npair + c;
-#pragma unroll
-                        for (int bb = 0; bb < NORB; ++bb) fma_(sR, sg[bb], wc * bd[bb * NORB]);
-                    }
-                    p_outR(A)[o] = A.h * sR;
-                }
-            }
-            if (A.wantL) {
-                for (int comp = 0; comp < 2; ++comp) {
-                    if (A.last[comp] < A.n0[comp]) continue;   // no tail rows
-                    if (comp == 1 && m < A.ls[1])
-                        for (int tg = 0; tg < tail_groups(NORB); ++tg) sL = sL + p_tailcol(A, 1)[(size_t)tg * A.nt * npair + o];
-                    if (m >= A.n0[comp] && m <= A.last[comp])
-                        sL = sL + p_tailrow(A, comp)[(size_t)(m - A.n0[comp]) * npair + a * NORB + c];
-                }
-                // second lesser term: end weights (m >= k) or Newton-Cotes (m < k); the
-                // interval is empty at m = 0 (no bulk term was added there either)
-                // Sigma^<(n,s)[a][b] = -conj(sigL[s][b][a]);  G^R(m,s)^dagger[b][c] = conj(G^R(m,s)[c][b])
-                const int imax = m == 0 ? -1 : (m < k ? m : k);
-                for (int i = 0; i <= imax; ++i) {
-                    const int s = m - i;
-                    const double wc = m < k ? A.W.nc[m][s] - w_start(A.W, s) : A.W.om[i] - 1.0;
-                    const cd* sl = p_sigL(A) + (size_t)s * npair + a;
-                    const cd* bd = p_band(A) + ((size_t)s * kb + i) * npair + c * NORB;
-#pragma unroll
-                    for (int bb = 0; bb < NORB; ++bb)
-                        fmac_(sL, sl[bb * NORB], mk(-wc, 0.0) * conj(bd[bb]));
-                }
-                p_outL(A)[o] = A.h * sL;
+            if (A.adj) {
+                finish_entry<NORB>(A, m, a, c, 1, accL[a]);
+            } else {
+                if (A.wantR) finish_entry<NORB>(A, m, a, c, 0, accR[a]);
+                if (A.wantL) finish_entry<NORB>(A, m, a, c, 1, accL[a]);
             }
         }
     }
@@ -749,7 +1060,7 @@ __global__ void __launch_bounds__(64 * CombMap<NORB>::WAVES) hist_combine(HistAr
 
 size_t tasks_smem(int norb) {
     const int ag = norb < 4 ? norb : 4;
-    size_t fact = (size_t)kCH * norb * sizeof(cd);
+    size_t fact = (size_t)(kch(norb) * norb + 4 * 32 * norb) * sizeof(cd);
     size_t leaf = (size_t)(tri(64) + 2 * 64 * ag) * sizeof(cd);
     size_t tail = (size_t)(kTailRows * kTailCH + (kTailRows + kTailCH) * ag) * sizeof(cd);
     size_t s = fact > leaf ? fact : leaf;

@@ -186,7 +186,12 @@ __device__ __attribute__((noinline)) void hh_apply_q(const cd* A, int nrows, int
 
 // one-sided (Hestenes) Jacobi on the columns of M (n x n, column-major, n even,
 // ld = n), accumulating the rotations in J (starts as identity).
-__device__ __attribute__((noinline)) void jacobi_svd(cd* M, cd* J, int n, int* flag) {
+// A pair (p, q) is rotated while its coupling |m_p^dagger m_q| exceeds both
+// 1e-15 |m_p| |m_q| (relative orthogonality) and 1e-30 |M|_F^2 (round-off of the
+// whole matrix): columns at round-off level, which exact-low-rank panels produce,
+// would otherwise keep the sweeps going without changing any singular value
+// above 1e-15 |M|_F.
+__device__ __attribute__((noinline)) void jacobi_svd(cd* M, cd* J, int n, int* flag, double* red) {
     const int tid = threadIdx.x;
     const int npairs = n / 2;
     int tpp = NT / npairs;
@@ -196,6 +201,9 @@ __device__ __attribute__((noinline)) void jacobi_svd(cd* M, cd* J, int n, int* f
     while (p2 * 2 <= tpp) p2 *= 2;
     tpp = p2;
     for (int i = tid; i < n * n; i += NT) J[i] = mk((i % (n + 1)) == 0 ? 1.0 : 0.0, 0.0);
+    double f2 = 0.0;
+    for (int i = tid; i < n * n; i += NT) f2 += norm2(M[i]);
+    const double floor2 = 1e-30 * block_sum(f2, red);   // |M|_F^2 is invariant under the rotations
     __syncthreads();
     for (int sweep = 0; sweep < 40; ++sweep) {
         if (tid == 0) *flag = 0;
@@ -227,7 +235,7 @@ __device__ __attribute__((noinline)) void jacobi_svd(cd* M, cd* J, int n, int* f
             gi = warp_sum(gi, tpp);
             if (pi < npairs) {
                 double ag = sqrt(gr * gr + gi * gi);
-                if (ag > 1e-15 * sqrt(al * be) && ag > 1e-300) {
+                if (ag > 1e-15 * sqrt(al * be) && ag > floor2 && ag > 1e-300) {
                     double zeta = (be - al) / (2.0 * ag);
                     double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                     double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
@@ -443,7 +451,7 @@ __global__ void __launch_bounds__(NT) merge_up_kernel(MergeArgs a) {
         M[e] = (i < w && col < w) ? conj(R[(size_t)i * W + col]) : mk(0.0, 0.0);
     }
     __syncthreads();
-    jacobi_svd(M, J, ne, &sflag);
+    jacobi_svd(M, J, ne, &sflag, red);
     for (int i = threadIdx.x; i < ne; i += NT) {
         double s = 0.0;
         for (int r = 0; r < ne; ++r) s += norm2(M[(size_t)i * ne + r]);
