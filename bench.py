@@ -7,7 +7,10 @@ merges that fall due), then evaluate I^R(n, .) and I^<(n, .).  The value is
 time steps per second over the timed sweeps (inputs already in HBM).  The same
 sweep on the dense (uncompressed) storage runs on the same GPU for comparison.
 Kernel durations for the roofline come from HIP events recorded by the library
-on its launch stream inside the timed sweeps (every `--prof-stride`-th step).
+on its launch stream around every launch of the timed sweeps (`--prof-stride 1`),
+so that their average agrees with a rocprofv3 kernel trace of the same command.
+`steps` in the JSON line counts the timed time steps (sweeps x N_t), so that
+steps x ms_per_step is the timed region.
 """
 from __future__ import annotations
 
@@ -83,28 +86,113 @@ def algorithmic_bytes(N, npair, P, blocks, leaves, ranks, steps, nk=1, zf=16):
     return np.array(tasks, dtype=np.float64), np.array(comb, dtype=np.float64)
 
 
-def cpu_baseline(cfg, G, S, budget_s):
-    """The FP64 oracle as it stands, timed on sampled entries (n, m) of the sweep."""
+def _oracle_worker(args):
+    """Entries I^R(n,m) and I^<(n,m) at sampled (n, m) for budget seconds (one core)."""
+    import os
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
     import numpy as np
     from oracle.history import GeneratorOperands, history_lesser_entry, history_R_entry
-    N, h, k = cfg["nt"], cfg["h"], cfg["k"]
+    G, S, N, h, k, seed, budget = args
     ops = GeneratorOperands(G, S, h)
-    rng = np.random.default_rng(12)
-    summands, t0, ne = 0, time.perf_counter(), 0
-    while time.perf_counter() - t0 < budget_s:
+    rng = np.random.default_rng(seed)
+    summands, ne, t0 = 0, 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget:
         n = int(rng.integers(N // 8, N))
         m = int(rng.integers(0, n + 1))
         history_R_entry(ops, n, m, h, k)
         history_lesser_entry(ops, n, m, h, k)
         summands += (n - m + 1) + (n + 1) + (m + 1)
         ne += 1
-    dt = time.perf_counter() - t0
+    return summands, ne, time.perf_counter() - t0
+
+
+def _entries_worker(args):
+    """Oracle I^R(n,m) and I^<(n,m) for a list of columns m of row n (one core)."""
+    import os
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    from oracle.history import GeneratorOperands, history_lesser_entry, history_R_entry
+    G, S, h, k, n, ms = args
+    ops = GeneratorOperands(G, S, h)
+    return [(history_R_entry(ops, n, m, h, k), history_lesser_entry(ops, n, m, h, k)) for m in ms]
+
+
+def fp32_oracle_error(sample, cores=None):
+    """Largest error of the FP32-factor form's sampled entries of its last row against the FP64
+    oracle, relative to the oracle's largest entry of that row sample (oracle leg of the bench)."""
+    import multiprocessing as mp
+    import numpy as np
+    G, S, h, k, n, ms, gR, gL = sample
+    cores = cores or min(os.cpu_count() or 1, 16)
+    jobs = [(G, S, h, k, n, list(ms[i::cores])) for i in range(cores) if len(ms[i::cores])]
+    t = time.perf_counter()
+    with mp.get_context("spawn").Pool(len(jobs)) as pool:
+        res = pool.map(_entries_worker, jobs)
+    oR, oL = np.zeros_like(gR), np.zeros_like(gL)
+    for (_, _, _, _, _, mj), vals in zip(jobs, res):
+        for m, (r, l) in zip(mj, vals):
+            i = int(np.flatnonzero(ms == m)[0])
+            oR[i], oL[i] = r, l
+    eR = float(np.abs(gR - oR).max() / np.abs(oR).max())
+    eL = float(np.abs(gL - oL).max() / np.abs(oL).max())
+    return dict(max_rel_err_R=eR, max_rel_err_L=eL, row=int(n), columns=int(len(ms)),
+                entries=int(gR.size + gL.size), oracle_s=round(time.perf_counter() - t, 1),
+                scale="oracle's largest |entry| over the sampled columns of the row")
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, G, S, budget_s, cores=None):
+    """The FP64 oracle as it stands, timed on sampled entries (n, m) of the sweep by one
+    single-threaded process per host core (a spawned pool; no GPU state is inherited)."""
+    import multiprocessing as mp
+    import os
+    N, h, k = cfg["nt"], cfg["h"], cfg["k"]
+    ncpu = os.cpu_count() or 1
+    cores = cores or min(ncpu, 16)
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_worker, [(G, S, N, h, k, 12 + i, budget_s) for i in range(cores)])
+    summands = sum(r[0] for r in res)
+    ne = sum(r[1] for r in res)
+    dt = max(r[2] for r in res)
     rate = summands / dt
     total = sum((n + 1) * (2 * n + 3) for n in range(N))   # summands of a full sweep
-    return dict(value=N / (total / rate), unit="steps/s", cores=1, kind="oracle",
-                sample=f"{ne} entries I^R(n,m) and I^<(n,m), n uniform in [{N // 8},{N}), m uniform "
-                       f"in [0,n], {dt:.1f} s; rate {rate:.3e} summands/s extrapolated to the "
-                       f"{total:.3e} summands of a full N_t={N} sweep (single-threaded NumPy)")
+    try:
+        from threadpoolctl import threadpool_info
+        blas = ",".join(f"{i.get('internal_api')}:{i.get('num_threads')}" for i in threadpool_info()) or "none"
+    except Exception:
+        blas = "unknown"
+    return dict(value=N / (total / rate), unit="steps/s", cores=cores, kind="oracle",
+                cpu_model=_cpu_model(), os_cpu_count=ncpu, blas_threads_per_process=1, blas_parent=blas,
+                sample=f"{ne} entries I^R(n,m) and I^<(n,m) on {cores} processes (one core each), n uniform "
+                       f"in [{N // 8},{N}), m uniform in [0,n], {dt:.1f} s; rate {rate:.3e} summands/s "
+                       f"extrapolated to the {total:.3e} summands of a full N_t={N} sweep")
+
+
+def hbm_copy_gbs():
+    """Measured device copy bandwidth (1 GiB read + 1 GiB written), best of 5, HIP events."""
+    import torch
+    x = torch.ones(1 << 26, dtype=torch.complex128, device="cuda:0")
+    y = torch.empty_like(x)
+    best = 0.0
+    for _ in range(6):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        y.copy_(x)
+        e1.record()
+        torch.cuda.synchronize()
+        best = max(best, 2 * x.numel() * 16 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del x, y
+    torch.cuda.empty_cache()
+    return round(best, 1)
 
 
 def measured_traffic(kernel):
@@ -182,11 +270,22 @@ def fp32_bench(P, steps_timed=256):
                hist_tasks_gbs=round(float(b_tasks.sum() / (ms0.sum() * 1e-3) / 1e9), 1),
                hist_combine_gbs=round(float(b_comb.sum() / (ms1.sum() * 1e-3) / 1e9), 1),
                device_gib=round(H.nbytes() / 2**30, 2))
+    # sampled columns of the last row for the oracle comparison: both ends, every level
+    # boundary leaf * 2^l with its neighbours, the rest spread uniformly
+    n = N - 1
+    ms = {0, 1, 2, n - 2, n - 1, n}
+    for l in range(nlvl + 1):
+        b = cfg["leaf"] * 2 ** l
+        ms |= {b - 1, b, b + 1}
+    ms |= set(int(x) for x in np.random.default_rng(5).integers(0, n + 1, 64 - len(ms) + 8))
+    ms = np.array(sorted(m for m in ms if 0 <= m <= n))
+    idx = torch.as_tensor(ms, device=dev)
+    sample = (G, S, h, k, n, ms, outR[idx].cpu().numpy(), outL[idx].cpu().numpy())
     H.profile(0)
     H.close()
     del gl, sl
     torch.cuda.empty_cache()
-    return out
+    return out, sample
 
 
 def lattice_bench(P, prof_stride):
@@ -292,13 +391,13 @@ def adjoint_bench(P):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2, help="timed sweeps of N_t time steps")
+    ap.add_argument("--steps", type=int, default=2, help="timed sweeps of N_t time steps each")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--dense-steps", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--prof-stride", type=int, default=16)
+    ap.add_argument("--prof-stride", type=int, default=1)
     ap.add_argument("--nt", type=int, default=None, help="override N_t (testing only)")
     ap.add_argument("--no-lattice", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -359,6 +458,7 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     value = args.steps * N / dt
+    timed_steps = args.steps * N
     status = H.status()
     log(f"HODLR: {args.steps} sweeps in {dt:.3f} s -> {value:.1f} steps/s (status {status})")
 
@@ -383,7 +483,9 @@ def main():
                 traffic_unit="bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)",
                 kernel=dominant, launches_timed=int(len(msel)),
                 avg_launch_us=round(float(msel.mean()) * 1e3, 2),
-                avg_alg_bytes_per_launch=float(bsel.mean()))
+                avg_alg_bytes_per_launch=float(bsel.mean()),
+                measured_copy_gbs=hbm_copy_gbs(),
+                copy_note="best of 5 device copies of 1 GiB (read + write), HIP events")
     other = "hist_combine" if dominant == "hist_tasks" else "hist_tasks"
     bo, mo = (b_comb, ms1) if other == "hist_combine" else (b_tasks, ms0)
     kernels = {
@@ -440,7 +542,7 @@ def main():
 
     fp32 = None
     if not args.no_fp32:
-        fp32 = fp32_bench(P)
+        fp32, fp32_sample = fp32_bench(P)
         log("fp32 form:", fp32)
 
     adjoint = None
@@ -452,16 +554,22 @@ def main():
     if not args.no_cpu:
         cpu = cpu_baseline(cfg, G, S, args.cpu_budget)
         log(f"cpu oracle: {cpu['value']:.3e} steps/s")
+        if fp32 is not None:
+            fp32["vs_oracle"] = fp32_oracle_error(fp32_sample)
+            log("fp32 form against the oracle:", fp32["vs_oracle"])
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 / value, 5),
+        "steps": timed_steps, "sweeps": args.steps, "warmup": args.warmup,
+        "warmup_steps": args.warmup * N, "ms_per_step": round(1e3 / value, 5),
+        "timed_region_s": round(dt, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c128",
         "data": "synthetic",
         "config": {"workload": f"norb{norb}-nt{N}: N_t={N}, norb={norb}, h={h}, Gregory k={k}, "
                                f"leaf {cfg['leaf']} ({nlvl} levels), eps_SVD={cfg['tol']}, panel {panel}, "
-                               f"8+8 Hermitian damped-exponential generators; one bench step = one sweep "
-                               f"of N_t time steps (append R and < rows, merges, I^R and I^<)",
+                               f"8+8 Hermitian damped-exponential generators; a step is one time step "
+                               f"(append the R and < rows, their merges, I^R and I^< of the row); "
+                               f"the timed region is `sweeps` sweeps of N_t steps",
                    "n_t": N, "norb": norb, "step_unit": "time step"},
         "roofline": roof,
         "kernels": kernels,
