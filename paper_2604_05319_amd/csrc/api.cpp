@@ -167,6 +167,9 @@ struct hnessi_hodlr_s {
     std::vector<long long> Uoff, Voff, Loff;
     // per component
     bool f32 = false;    // complex-float mirrors of the factors feed the history kernels
+    bool mfproj = false; // norb 16, complex-float factors, rank capacity <= 16: projections
+                         // on the matrix cores (task per block, factor, chunk, orbital beta)
+    bool mfcomb = false; // and leaves starting at multiples of 16: matrix-core expansions
     cd* U[2] = {};       // FP64 factors (merges, reconstruction)
     cd* V[2] = {};
     cf* U32[2] = {};     // mirrors, or nullptr
@@ -336,6 +339,9 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
     H->RC = max_rank;
     H->flags = flags;
     H->f32 = (flags & HNESSI_FLAG_FP32_FACTORS) != 0;
+    H->mfproj = H->f32 && norb == 16 && max_rank <= 16;
+    H->mfcomb = H->mfproj;
+    for (int i = 0; i < H->g.nleaf; ++i) H->mfcomb = H->mfcomb && H->g.s0[i] % 16 == 0;
     H->tol = svd_tol;
     H->MW = merge_width(max_rank, panel);
     const int npair = H->npair, RC = H->RC, nb = g.nb, MW = H->MW;
@@ -465,8 +471,10 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
     // projection task lists (sorted by the row that activates them)
     for (int c = 0; c < 2; ++c) {
         std::vector<FactTask> ts;
+        // matrix-core projections: one task per shared orbital index instead of per pair
+        const int ntq = H->mfproj ? norb : npair;
         for (int b = 0; b < nb; ++b)
-            for (int q = 0; q < npair; ++q) {
+            for (int q = 0; q < ntq; ++q) {
                 for (int ch = 0; ch < div_up(g.r1[b] - g.r0[b], kch(norb)); ++ch)
                     ts.push_back(FactTask{c, b, q, 0, ch, g.r0[b] + ch * kch(norb)});
                 for (int ch = 0; ch < div_up(g.c1[b] - g.c0[b], kch(norb)); ++ch)
@@ -773,6 +781,8 @@ int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, doub
     A.outL = static_cast<cd*>(outL);
     A.nk = H->nk;
     A.f32 = H->f32;
+    A.mfproj = H->mfproj;
+    A.mfcomb = H->mfcomb;
     A.ring = kTailRows;
     A.bU = H->bU;
     A.bV = H->bV;

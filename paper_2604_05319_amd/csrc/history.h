@@ -7,7 +7,8 @@ namespace hn {
 
 // A projection task: rows [chunk*kch, +kch) of U (which = 0) or V (which = 1)
 // of block b, orbital pair q, component comp.  Active once row `act` is merged
-// (U: the chunk's first row; V: the block's first row).
+// (U: the chunk's first row; V: the block's first row).  With matrix-core
+// projections (HistArgs::mfproj) q is the shared orbital index beta of 16 pairs.
 struct FactTask {
     int comp, b, q, which, chunk, act;
 };
@@ -29,6 +30,10 @@ struct HistArgs {
     const cd* sigR;   // Sigma^R(n, j), j = 0..n
     const cd* sigL;   // Sigma^<(s, n), s = 0..n
     int f32;          // factors stored as complex float (cf) instead of complex double
+    int mfproj;       // norb = 16 with cf factors and RC <= 16: projections on the matrix
+                      // cores, one task per (block, factor, chunk, orbital index beta)
+    int mfcomb;       // with mfproj and every leaf starting at a multiple of 16: the
+                      // expansions of the combine on the matrix cores, 16-column tiles
     const void* U[2]; // factor storage, element type cd or cf
     const void* V[2];
     const double* S[2];

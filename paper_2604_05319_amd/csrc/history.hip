@@ -23,6 +23,8 @@
 // and the band corrections for each output column m.
 #include "history.h"
 
+#include <type_traits>
+
 namespace hn {
 
 namespace {
@@ -243,6 +245,143 @@ __device__ void fact_task(const HistArgs& A, const FactTask& t, unsigned char* s
     else if (rk <= 8) fact_pass<NORB, FT, 8>(A, F, ld, i0, i1, rk, cj, xs, S, out, red, stage);
     else if (rk <= 16) fact_pass<NORB, FT, 16>(A, F, ld, i0, i1, rk, cj, xs, S, out, red, stage);
     else fact_pass<NORB, FT, 32>(A, F, ld, i0, i1, rk, cj, xs, S, out, red, stage);
+}
+
+// ---------------------------------------------------------------------------
+// Projections of the FP32-factor form at norb = 16 on the matrix cores.  For one
+// block, component, factor and chunk of kch rows, the 16 orbital pairs whose
+// folded Sigma entries carry the same orbital index beta share one folded row:
+// with X[i][a] = x_{a,beta}(row i) the projection of pair q is the product
+// Z_q = X^T F_q (16 left orbitals x rank), a complex 16 x 16 x rows product done
+// as four real v_mfma_f32_16x16x4f32 chains (re.re, im.im, re.im, im.re) with
+// FP32 inputs and FP32 accumulation.  X is staged once in LDS as complex float;
+// each wave takes four pairs and streams their factor columns, the next 32-row
+// tile's loads in flight while the current tile is multiplied.  Each tile's sum
+// is added to the running FP32 sum with TwoSum compensation, so the chunk sum
+// carries the rounding of one tile, not of the whole chunk.
+// Lane layout of the 16x16x4 products: A[i][k] in lane i + 16k, B[k][j] in lane
+// j + 16k, D[i][j] in lane j + 16 (i / 4), register i % 4.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ inline v4f mfma_16x16x4(float a, float b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// s += v, the rounding error of the addition added to e (TwoSum)
+__device__ inline void two_sum_acc(float& s, float& e, float v) {
+    const float t = s + v;
+    const float bp = t - s;
+    e += (s - (t - bp)) + (v - bp);
+    s = t;
+}
+
+constexpr int kXS = 18;   // LDS row stride of staged X in complex floats (16 orbitals + 2:
+                          // the rows 8 apart that one read touches fall in different banks)
+constexpr int kPT = 32;   // factor rows per tile
+
+// Z(a, r) = S_r sum_i X[i][a] op(F[r*ld + i]) over rows [i0, i1) for one pair, op =
+// conj for CONJ; written to out[a*RC + r] for r < rk.  The staged X rows past i1
+// are zero and every factor index is clamped into [i0, i1) x [0, rk), so all
+// loads are in range and the surplus terms vanish.
+template <bool CONJ>
+__device__ void fact_mfma_pair(const cf* F, int ld, int i0, int i1, int rk, const cf* xs, const double* S,
+                               cd* out, int RC) {
+    const int lane = threadIdx.x & 63, j = lane & 15, kk = lane >> 4;
+    const int ntile = (i1 - i0 + kPT - 1) / kPT;
+    const cf* Fj = F + (size_t)min(j, rk - 1) * ld;
+    float sr[4] = {0.f, 0.f, 0.f, 0.f}, er[4] = {0.f, 0.f, 0.f, 0.f};
+    float si[4] = {0.f, 0.f, 0.f, 0.f}, ei[4] = {0.f, 0.f, 0.f, 0.f};
+    cf bc[8], bn[8];
+    auto load = [&](cf (&bb)[8], int t) {
+        const int r = i0 + t * kPT + 8 * kk;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) bb[s] = Fj[min(r + s, i1 - 1)];
+    };
+    load(bc, 0);
+    for (int t = 0; t < ntile; ++t) {
+        if (t + 1 < ntile) load(bn, t + 1);
+        v4f rr = {0.f, 0.f, 0.f, 0.f}, ii = rr, ri = rr, ir = rr;
+        const cf* xt = xs + (size_t)(t * kPT + 8 * kk) * kXS + j;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const cf x = xt[s * kXS];
+            rr = mfma_16x16x4(x.x, bc[s].x, rr);
+            ii = mfma_16x16x4(x.y, bc[s].y, ii);
+            ri = mfma_16x16x4(x.x, bc[s].y, ri);
+            ir = mfma_16x16x4(x.y, bc[s].x, ir);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            two_sum_acc(sr[v], er[v], CONJ ? rr[v] + ii[v] : rr[v] - ii[v]);
+            two_sum_acc(si[v], ei[v], CONJ ? ir[v] - ri[v] : ri[v] + ir[v]);
+        }
+#pragma unroll
+        for (int s = 0; s < 8; ++s) bc[s] = bn[s];
+    }
+    if (j < rk) {
+        const double sj = S[j];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            out[(size_t)(4 * kk + v) * RC + j] =
+                sj * mk((double)sr[v] + (double)er[v], (double)si[v] + (double)ei[v]);
+    }
+}
+
+// One task: block b, component comp, factor `which`, chunk, orbital index beta = t.q.
+// The pairs sharing beta: q = beta*16 + o when the folded row takes the pair's row
+// orbital (retarded U, lesser V), q = o*16 + beta when it takes the column orbital.
+__device__ void fact_mfma_task(const HistArgs& A, const FactTask& t, unsigned char* smem) {
+    constexpr int NORB = 16, npair = 256;
+    const int comp = t.comp, b = t.b, beta = t.q, which = t.which;
+    if (comp == 0 && which == 0 && !A.wantR) return;
+    if ((comp == 1 || which == 1) && !A.wantL) return;
+    if (comp == 1 && A.adj) return;
+    const int RC = A.RC;
+    const int* bk = A.blk + 5 * b;
+    const int r0 = bk[1], r1 = bk[2], c0 = bk[3], c1 = bk[4];
+    int len, base, ld;
+    const cf* F;
+    if (which == 0) {
+        len = min(A.n0[comp] - r0, r1 - r0);
+        base = r0;
+        ld = r1 - r0;
+        F = p_U<cf>(A, comp, b) + A.Uoff[b];
+    } else {
+        len = c1 - c0;
+        base = c0;
+        ld = c1 - c0;
+        F = p_V<cf>(A, comp, b) + A.Voff[b];
+    }
+    constexpr int kCH = kch(NORB);
+    const int i0 = t.chunk * kCH, i1 = min(len, i0 + kCH);
+    if (i0 >= i1) return;
+    const int n = A.n, nrow = i1 - i0, nst = (nrow + kPT - 1) / kPT * kPT;
+    cf* xs = reinterpret_cast<cf*>(smem);   // nst x kXS
+    for (int e = threadIdx.x; e < nst * NORB; e += NT) {
+        const int i = e >> 4, a = e & 15, jj = base + i0 + i;
+        cd v = mk(0.0, 0.0);
+        if (i < nrow) {
+            if (comp == 0 && which == 0) v = w_end(A.W, n, jj) * p_sigR(A)[(size_t)jj * npair + a * NORB + beta];
+            else if (comp == 0) v = A.adj ? p_sigL(A)[(size_t)jj * npair + a * NORB + beta]
+                                          : -w_start(A.W, jj) * conj(p_sigL(A)[(size_t)jj * npair + beta * NORB + a]);
+            else v = interval_w(A.W, n, jj) * p_sigR(A)[(size_t)jj * npair + a * NORB + beta];
+        }
+        xs[(size_t)i * kXS + a] = cf{(float)v.x, (float)v.y};
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6;
+    const bool col_beta = (comp ^ which) != 0;
+    for (int p = 0; p < 4; ++p) {
+        const int o = 4 * wave + p;
+        const int q = col_beta ? o * NORB + beta : beta * NORB + o;
+        const int rk = rank_of(A, comp, b, q);
+        if (rk == 0) continue;
+        const cf* Fq = F + (size_t)q * RC * ld;
+        const double* S = p_S(A, comp, b) + ((size_t)b * npair + q) * RC;
+        cd* out = p_part(A) + (size_t)(A.partoff[proj_slot(A, comp, b, q, which)] + t.chunk) * NORB * RC;
+        if (comp == 1) fact_mfma_pair<true>(Fq, ld, i0, i1, rk, xs, S, out, RC);
+        else fact_mfma_pair<false>(Fq, ld, i0, i1, rk, xs, S, out, RC);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -776,8 +915,17 @@ __global__ void __launch_bounds__(NT) hist_tasks(HistArgs A) {
         return;
     }
     rel -= A.nleaftask;
-    if (rel < A.nf[0]) fact_task<NORB, FT>(A, A.ft[0][rel], smem);
-    else if (rel - A.nf[0] < A.nf[1]) fact_task<NORB, FT>(A, A.ft[1][rel - A.nf[0]], smem);
+    if (rel >= A.nf[0] + A.nf[1]) return;
+    fact_task<NORB, FT>(A, rel < A.nf[0] ? A.ft[0][rel] : A.ft[1][rel - A.nf[0]], smem);
+}
+
+// Matrix-core projections (norb 16, complex-float factors) in a kernel of their own, so
+// that their register budget is not that of the leaf and tail tasks.
+__global__ void __launch_bounds__(NT) proj_mfma(HistArgs A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int rel = blockIdx.x;
+    if (rel >= A.nf[0] + A.nf[1]) return;
+    fact_mfma_task(A, rel < A.nf[0] ? A.ft[0][rel] : A.ft[1][rel - A.nf[0]], smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -894,7 +1042,7 @@ __device__ void finish_entry(const HistArgs& A, int m, int a, int c, int part, c
             const double wc = L >= k ? A.W.om[i] - 1.0 : A.W.nc[L][i] - we;
             const cd* ib = p_sigL(A) + (size_t)mp * npair + a * NORB;            // Ibar(n, m')[a][b]
             const cd* bd = p_band(A) + ((size_t)mp * kb + i) * npair + c * NORB;   // G^R(j, m')[c][b]
-#pragma unroll
+#pragma unroll 4
             for (int bb = 0; bb < NORB; ++bb) fmac_(out, bd[bb], wc * ib[bb]);
         }
         p_outL(A)[o] = A.h * out;
@@ -916,7 +1064,7 @@ __device__ void finish_entry(const HistArgs& A, int m, int a, int c, int part, c
             const double wc = L < k ? A.W.nc[L][i] - w_end(A.W, n, m + i) : A.W.om[i] - 1.0;
             const cd* sg = p_sigR(A) + (size_t)(m + i) * npair + a * NORB;
             const cd* bd = p_band(A) + ((size_t)m * kb + i) * npair + c;
-#pragma unroll
+#pragma unroll 4
             for (int bb = 0; bb < NORB; ++bb) fma_(sR, sg[bb], wc * bd[bb * NORB]);
         }
         p_outR(A)[o] = A.h * sR;
@@ -941,7 +1089,7 @@ __device__ void finish_entry(const HistArgs& A, int m, int a, int c, int part, c
         const double wc = m < k ? A.W.nc[m][s] - w_start(A.W, s) : A.W.om[i] - 1.0;
         const cd* slp = p_sigL(A) + (size_t)s * npair + a;
         const cd* bd = p_band(A) + ((size_t)s * kb + i) * npair + c * NORB;
-#pragma unroll
+#pragma unroll 4
         for (int bb = 0; bb < NORB; ++bb) fmac_(sL, slp[bb * NORB], mk(-wc, 0.0) * conj(bd[bb]));
     }
     p_outL(A)[o] = A.h * sL;
@@ -1058,9 +1206,137 @@ __global__ void __launch_bounds__(64 * CombMap<NORB>::WAVES) hist_combine(HistAr
     }
 }
 
-size_t tasks_smem(int norb) {
+// ---------------------------------------------------------------------------
+// Combine of the FP32-factor form at norb = 16 on the matrix cores.  A workgroup
+// takes 16 consecutive columns m (a tile inside one leaf: every block boundary is
+// a multiple of 16), wave w the output orbitals c = w, w+4, w+8, w+12.  For each
+// level the tile's columns are columns (expansion through V) or rows (through U)
+// of one block, and each expansion is the product
+//   Y[a][m] (+|-)= sum over o, r of z_{q(o)}[a][r] op(F_{q(o)}[r][m])
+// with A = z (16 orbitals a x 4 ranks, FP32 from the FP64 projections) and B =
+// the factor rows of the tile's columns: four real 16x16x4 chains per 4 ranks.
+// Each expansion (one block and component) is a K tile whose FP32 sum is added to
+// the running sum with TwoSum compensation; the FP64 sum of the two then goes
+// through the same leaf, tail and band pieces as every other form.
+
+// one expansion into (s, e); rows of F whose column is not valid (colok) are zero
+template <bool CONJ, bool NEG>
+__device__ void expand_mfma(const HistArgs& A, int comp, int b, int which, bool q_row_c, int c, const cf* Fb,
+                            int ld, int col, bool colok, float (&sr)[4], float (&er)[4], float (&si)[4],
+                            float (&ei)[4]) {
+    constexpr int NORB = 16;
+    const int lane = threadIdx.x & 63, j = lane & 15, kk = lane >> 4;
+    const int RC = A.RC;
+    v4f rr = {0.f, 0.f, 0.f, 0.f}, ii = rr, ri = rr, ir = rr;
+    // operands of pair o: ranks 4u + kk, u < 4, indices clamped to the capacity (the
+    // rank mask is applied where they are used, so the loads do not wait for it)
+    cd zc[4], zn[4];
+    cf fc[4], fn[4];
+    int rkc = 0, rkn = 0;
+    auto fetch = [&](int o, cd (&z)[4], cf (&f)[4], int& rk) {
+        const int q = q_row_c ? c * NORB + o : o * NORB + c;
+        rk = rank_of(A, comp, b, q);
+        const cf* F = Fb + (size_t)q * RC * ld + col;
+        const cd* zq = p_proj(A) + proj_slot(A, comp, b, q, which) * NORB * RC + (size_t)j * RC;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int r = min(4 * u + kk, RC - 1);
+            z[u] = zq[r];
+            f[u] = F[(size_t)r * ld];
+        }
+    };
+    fetch(0, zc, fc, rkc);
+    for (int o = 0; o < NORB; ++o) {
+        if (o + 1 < NORB) fetch(o + 1, zn, fn, rkn);
+        const int nq = (rkc + 3) >> 2;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (u < nq) {
+                const bool ok = 4 * u + kk < rkc;
+                const float zr = ok ? (float)zc[u].x : 0.f, zi = ok ? (float)zc[u].y : 0.f;
+                const float fr = colok ? fc[u].x : 0.f, fi = colok ? fc[u].y : 0.f;
+                rr = mfma_16x16x4(zr, fr, rr);
+                ii = mfma_16x16x4(zi, fi, ii);
+                ri = mfma_16x16x4(zr, fi, ri);
+                ir = mfma_16x16x4(zi, fr, ir);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            zc[u] = zn[u];
+            fc[u] = fn[u];
+        }
+        rkc = rkn;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        float yr = CONJ ? rr[v] + ii[v] : rr[v] - ii[v];
+        float yi = CONJ ? ir[v] - ri[v] : ri[v] + ir[v];
+        if (NEG) {
+            yr = -yr;
+            yi = -yi;
+        }
+        two_sum_acc(sr[v], er[v], yr);
+        two_sum_acc(si[v], ei[v], yi);
+    }
+}
+
+__global__ void __launch_bounds__(256) combine_mfma(HistArgs A) {
+    constexpr int NORB = 16;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, j = lane & 15, kk = lane >> 4;
+    const int m0 = blockIdx.x * 16, m = m0 + j;
+    const int n = A.n;
+    if (m0 > n) return;
+    for (int ci = 0; ci < 4; ++ci) {
+        const int c = wave + 4 * ci;
+        float Rsr[4] = {0.f, 0.f, 0.f, 0.f}, Rer[4] = {0.f, 0.f, 0.f, 0.f};
+        float Rsi[4] = {0.f, 0.f, 0.f, 0.f}, Rei[4] = {0.f, 0.f, 0.f, 0.f};
+        float Lsr[4] = {0.f, 0.f, 0.f, 0.f}, Ler[4] = {0.f, 0.f, 0.f, 0.f};
+        float Lsi[4] = {0.f, 0.f, 0.f, 0.f}, Lei[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int l = 0; l < A.nlvl; ++l) {
+            const int cv = A.cover[(size_t)l * A.nt + m0];
+            if (cv >= 0) {   // the tile's columns are columns of block b: expand through V
+                const int b = cv;
+                const int r0 = A.blk[5 * b + 1], c0 = A.blk[5 * b + 3], c1 = A.blk[5 * b + 4];
+                const int ld = c1 - c0, col = min(m - c0, ld - 1);
+                if (A.wantR && A.n0[0] > r0)
+                    expand_mfma<true, false>(A, 0, b, 0, false, c, p_V<cf>(A, 0, b) + A.Voff[b], ld, col, true,
+                                             Rsr, Rer, Rsi, Rei);
+                if (A.wantL && !A.adj && A.n0[1] > r0)
+                    expand_mfma<false, true>(A, 1, b, 0, true, c, p_V<cf>(A, 1, b) + A.Voff[b], ld, col, true,
+                                             Lsr, Ler, Lsi, Lei);
+            } else if (A.wantL) {   // rows of block b: expand through U (merged rows only)
+                const int b = ~cv;
+                const int r0 = A.blk[5 * b + 1], r1 = A.blk[5 * b + 2];
+                const int ld = r1 - r0, col = min(m - r0, ld - 1);
+                if (m0 < A.n0[0])
+                    expand_mfma<true, false>(A, 0, b, 1, true, c, p_U<cf>(A, 0, b) + A.Uoff[b], ld, col,
+                                             m < A.n0[0], Lsr, Ler, Lsi, Lei);
+                if (!A.adj && m0 < A.n0[1])
+                    expand_mfma<false, false>(A, 1, b, 1, false, c, p_U<cf>(A, 1, b) + A.Uoff[b], ld, col,
+                                              m < A.n0[1], Lsr, Ler, Lsi, Lei);
+            }
+        }
+        if (m > n) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int a = 4 * kk + v;
+            const cd yL = mk((double)Lsr[v] + (double)Ler[v], (double)Lsi[v] + (double)Lei[v]);
+            if (A.adj) {
+                finish_entry<NORB>(A, m, a, c, 1, yL);
+            } else {
+                if (A.wantR)
+                    finish_entry<NORB>(A, m, a, c, 0,
+                                       mk((double)Rsr[v] + (double)Rer[v], (double)Rsi[v] + (double)Rei[v]));
+                if (A.wantL) finish_entry<NORB>(A, m, a, c, 1, yL);
+            }
+        }
+    }
+}
+
+size_t tasks_smem(int norb, bool mfproj) {
     const int ag = norb < 4 ? norb : 4;
-    size_t fact = (size_t)(kch(norb) * norb + 4 * 32 * norb) * sizeof(cd);
+    size_t fact = mfproj ? (size_t)kch(norb) * kXS * sizeof(cf) : (size_t)(kch(norb) * norb + 4 * 32 * norb) * sizeof(cd);
     size_t leaf = (size_t)(tri(64) + 2 * 64 * ag) * sizeof(cd);
     size_t tail = (size_t)(kTailRows * kTailCH + (kTailRows + kTailCH) * ag) * sizeof(cd);
     size_t s = fact > leaf ? fact : leaf;
@@ -1069,9 +1345,12 @@ size_t tasks_smem(int norb) {
 
 template <int NORB, class FT>
 hipError_t launch_t(const HistArgs& a, hipStream_t st, hipEvent_t* ev) {
-    const int ntask = a.nfpad + a.nleaftask + a.ntailtask;
+    const bool mf = NORB == 16 && std::is_same<FT, cf>::value && a.mfproj;
+    const int ntask = (mf ? 0 : a.nfpad) + a.nleaftask + a.ntailtask;
     if (ev) hipEventRecord(ev[0], st);
-    if (ntask > 0) hist_tasks<NORB, FT><<<dim3(ntask, a.nk), NT, tasks_smem(NORB), st>>>(a);
+    if (mf && a.nf[0] + a.nf[1] > 0)
+        proj_mfma<<<dim3(a.nf[0] + a.nf[1], a.nk), NT, (size_t)kch(16) * kXS * sizeof(cf), st>>>(a);
+    if (ntask > 0) hist_tasks<NORB, FT><<<dim3(ntask, a.nk), NT, tasks_smem(NORB, mf), st>>>(a);
     if (ev) hipEventRecord(ev[1], st);
     {
         const long long nb1 = proj_reduce_blocks(a), nb2 = (2LL * a.ring * NORB * NORB + 3) / 4;
@@ -1079,8 +1358,12 @@ hipError_t launch_t(const HistArgs& a, hipStream_t st, hipEvent_t* ev) {
     }
     if (ev) hipEventRecord(ev[2], st);
     using M = CombMap<NORB>;
-    const int nblk = (a.n + 1 + M::MW - 1) / M::MW;
-    hist_combine<NORB, FT><<<dim3(nblk, a.nk), 64 * M::WAVES, 0, st>>>(a);
+    if (mf && a.mfcomb) {
+        combine_mfma<<<dim3((a.n + 16) / 16, a.nk), 256, 0, st>>>(a);
+    } else {
+        const int nblk = (a.n + 1 + M::MW - 1) / M::MW;
+        hist_combine<NORB, FT><<<dim3(nblk, a.nk), 64 * M::WAVES, 0, st>>>(a);
+    }
     if (ev) hipEventRecord(ev[3], st);
     return hipGetLastError();
 }
@@ -1107,7 +1390,7 @@ hipError_t history_init() {
     hipError_t e = hipSuccess;
     auto set = [&](const void* f, int norb) {
         if (e == hipSuccess)
-            e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tasks_smem(norb));
+            e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tasks_smem(norb, false));
     };
     set((const void*)hist_tasks<1, cd>, 1);
     set((const void*)hist_tasks<1, cf>, 1);

@@ -35,12 +35,16 @@ def _sweep(obj, inp, N, h, norb):
     return IR.cpu().numpy(), IL.cpu().numpy()
 
 
-@pytest.mark.parametrize("norb", [4, 16])
-def test_fp32_factors_small(P, norb):
-    N, h, k, nlvl, tol = 160, 0.03, 5, 3, 1e-6
+# norb 16 runs the matrix-core projections; with leaves starting at multiples of 16
+# (N = 192, two levels: 48-row leaves) the matrix-core expansions of the combine too,
+# whose 16-column tiles end ragged at every step n not of the form 16 i + 15
+@pytest.mark.parametrize("norb,N,nlvl", [(4, 160, 3), (16, 160, 3), (16, 192, 2)])
+def test_fp32_factors_small(P, norb, N, nlvl):
+    h, k, tol = 0.03, 5, 1e-6
     G, S = hermitian_terms(41 + norb, 6, norb), hermitian_terms(51 + norb, 6, norb)
     inp = host_inputs(G, S, N, h)
-    rows = [0, 1, 2, 5, 19, 20, 39, 40, 79, 80, 100, 139, 159]
+    rows = sorted({0, 1, 2, 5, 15, 16, 17, 19, 20, 39, 40, 79, 80, 81, 100, 139, N // 2, N - 2, N - 1} |
+                  set(range(N - 20, N, 3)))
     IR, IL = oracle_rows(*inp, N, h, k, rows=rows)
     H32 = P.Hodlr(N, nlvl, norb, k=k, tol=tol, panel=8, max_rank=16, flags=P.FLAG_FP32_FACTORS)
     IRg, ILg = _sweep(H32, inp, N, h, norb)
@@ -54,8 +58,8 @@ def test_fp32_factors_small(P, norb):
         assert eR <= 1e-5 and eL <= 1e-5, (n, eR, eL)
     say(f"fp32 factors norb={norb} worst row relative error", worst)
     # factor reconstruction in FP32 storage: close to the stored rows
-    g = H32.get(P.RET, 150, 3)
-    a = 150 * 151 // 2
+    g = H32.get(P.RET, N - 10, 3)
+    a = (N - 10) * (N - 9) // 2
     assert np.abs(g - inp[0][a + 3]).max() <= 1e-5 * np.abs(inp[0]).max()
 
 
