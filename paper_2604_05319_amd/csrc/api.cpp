@@ -768,7 +768,7 @@ int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, doub
     A.nleaf = g.row_leaf[n] + 1;
     const int ngroups = H->norb <= 4 ? 1 : H->norb / 4;   // left-orbital groups of 4 waves
     // dense-piece tasks per leaf and per tail chunk: one per orbital pair for norb <= 4,
-    // left-orbital groups x pair groups for larger norb
+    // left-orbital groups x pair groups for norb 8, one per output orbital for norb 16
     const int per_piece = H->norb <= 4 ? H->npair : ngroups * 4;
     A.nleaftask = div_up(2 * A.nleaf, 8) * 8 * per_piece;
     A.ntailtask = div_up(A.ntailchunk[0] + A.ntailchunk[1], 8) * 8 * per_piece;

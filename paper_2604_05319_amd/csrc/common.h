@@ -107,11 +107,12 @@ constexpr int kTailRows = 32; // tail rows at most: the panel being merged and t
 // Output slots of the dense pieces (leaf triangles and tail rows).  For norb <= 4
 // every orbital pair is a task of its own and writes one orbital entry of one
 // slot per output array (slot = the pair orbital summed over by the other
-// tasks), so that each slot entry has exactly one writer; for norb 8 and 16 a
-// task takes a group of pairs and the output has four slots.
-__host__ __device__ constexpr int tail_groups(int norb) { return norb <= 4 ? norb : 4; }
-__host__ __device__ constexpr int leaf_groups(int norb) { return norb <= 4 ? norb : 4; }
-// slots of the lesser leaf output (its two products sum over different orbitals)
-__host__ __device__ constexpr int leaf_ll_slots(int norb) { return norb <= 4 ? 2 * norb : 4; }
+// tasks), so that each slot entry has exactly one writer; for norb 8 a task
+// takes a group of pairs and the output has four slots; for norb 16 a task
+// takes one output orbital and sums over all pairs that feed it (one slot, two
+// for the lesser leaf output, whose two products sum over different orbitals).
+__host__ __device__ constexpr int tail_groups(int norb) { return norb <= 4 ? norb : (norb == 16 ? 1 : 4); }
+__host__ __device__ constexpr int leaf_groups(int norb) { return norb <= 4 ? norb : (norb == 16 ? 1 : 4); }
+__host__ __device__ constexpr int leaf_ll_slots(int norb) { return norb <= 4 ? 2 * norb : (norb == 16 ? 2 : 4); }
 
 }  // namespace hn

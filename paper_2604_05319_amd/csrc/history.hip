@@ -884,6 +884,7 @@ __global__ void __launch_bounds__(NT) hist_tasks(HistArgs A) {
     // them; every section starts at a multiple of 8, so workgroup id % 8 is the XCD
     // that xcd_group assumes
     int rel = blockIdx.x;
+    if constexpr (NORB != 16) {   // norb 16: the dense pieces are the dense16 kernel's
     if (rel < A.ntailtask) {
         constexpr int TG = tail_groups(NORB);
         int g, mem;
@@ -915,6 +916,7 @@ __global__ void __launch_bounds__(NT) hist_tasks(HistArgs A) {
         return;
     }
     rel -= A.nleaftask;
+    }
     if (rel >= A.nf[0] + A.nf[1]) return;
     fact_task<NORB, FT>(A, rel < A.nf[0] ? A.ft[0][rel] : A.ft[1][rel - A.nf[0]], smem);
 }
@@ -1207,6 +1209,251 @@ __global__ void __launch_bounds__(64 * CombMap<NORB>::WAVES) hist_combine(HistAr
 }
 
 // ---------------------------------------------------------------------------
+// Dense pieces at norb = 16 on the FP64 matrix cores (both factor forms: the leaf
+// triangles and tail rows are FP64).  Every piece is, for one output orbital c, a
+// complex product Y[a][x] = sum over (b', k) of X[a][(b', k)] op(T_{q(b')}[k][x])
+// with the 16 left orbitals a as the M dimension: X is a folded Sigma entry at
+// the summation row or column k, T the stored triangle or tail row of the pair
+// q(b') = (b', c) or (c, b').  Each is done as four real v_mfma_f64_16x16x4f64
+// chains over K steps of 4 (re.re, im.im, re.im, im.re), both operands loaded
+// from memory by the lane that feeds them, out-of-range terms zeroed by selects
+// on clamped (in-range) loads.
+// Lane layout of the FP64 16x16x4 product: A[i][k] in lane i + 16k, B[k][j] in
+// lane j + 16k, D[i][j] in lane j + 16 (i % 4), register i / 4.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ inline v4d mfma64_16x16x4(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+struct CAcc {
+    v4d rr, ii, ri, ir;
+};
+__device__ inline void cacc_zero(CAcc& z) {
+    z.rr = v4d{0.0, 0.0, 0.0, 0.0};
+    z.ii = z.rr;
+    z.ri = z.rr;
+    z.ir = z.rr;
+}
+__device__ inline void cacc_step(CAcc& z, cd a, cd b) {
+    z.rr = mfma64_16x16x4(a.x, b.x, z.rr);
+    z.ii = mfma64_16x16x4(a.y, b.y, z.ii);
+    z.ri = mfma64_16x16x4(a.x, b.y, z.ri);
+    z.ir = mfma64_16x16x4(a.y, b.x, z.ir);
+}
+// register v of the product: sum a b, or sum a conj(b) for CONJ
+template <bool CONJ>
+__device__ inline cd cacc_get(const CAcc& z, int v) {
+    const double rr = z.rr[v], ii = z.ii[v], ri = z.ri[v], ir = z.ir[v];
+    return CONJ ? mk(rr + ii, ir - ri) : mk(rr - ii, ri + ir);
+}
+
+// One leaf triangle, component and output orbital c.  Wave w owns the columns m of
+// tile w (16w .. 16w + 15) for both products of the component, which balances
+// the waves (the column sums of tile w run over rows j >= 16w, the row dots over
+// columns t <= 16w + 15):
+//   comp 0: column sum x(j)[a][b'] G^R_{b'c}(j,m), j >= m     -> leafR [0][m][a][c]
+//           row dot x2(t)[a][b'] G^R_{cb'}(m,t)^*, t <= m     -> leafLR[0][m][a][c]
+//   comp 1: row dot x1(t)[a][b'] G<_{b'c}(m,t), t <= m        -> leafLL[0][m][a][c]
+//           column sum -x1(j)[a][b'] G<_{cb'}(j,m)^*, j > m   -> leafLL[1][m][a][c]
+__device__ void leaf16_task(const HistArgs& A, int leaf, int comp, int c) {
+    constexpr int NORB = 16, npair = 256;
+    if (comp == 1 && (!A.wantL || A.adj)) return;
+    const int n = A.n;
+    const int s0 = A.leafs[2 * leaf], s1 = A.leafs[2 * leaf + 1];
+    const int lw = s1 - s0, nrow = min(s1, n + 1) - s0;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, x = lane & 15, kk = lane >> 4;
+    if (16 * wave >= nrow) return;
+    const int m = 16 * wave + x;
+    const cd* L = p_leaf(A, comp) + A.Loff[leaf];
+    const cd* sR = p_sigR(A);
+    const cd* sL = p_sigL(A);
+    const bool colOn = comp == 1 || A.wantR;
+    const bool rowOn = comp == 1 || A.wantL;
+    CAcc col, row;
+    cacc_zero(col);
+    cacc_zero(row);
+    // column sums: rows j = 16w + 4st + kk < nrow
+    if (colOn) {
+        const int ncs = (nrow - 16 * wave + 3) >> 2;
+        for (int bp = 0; bp < NORB; ++bp) {
+            const cd* T = L + (size_t)(comp == 0 ? bp * NORB + c : c * NORB + bp) * tri(lw);
+#pragma unroll 4
+            for (int st = 0; st < ncs; ++st) {
+                const int j = 16 * wave + 4 * st + kk;
+                const bool jv = j < nrow;
+                const int jc = jv ? j : nrow - 1, jg = s0 + jc;
+                const cd sg = sR[(size_t)jg * npair + x * NORB + bp];
+                const cd tv = T[tri(jc) + min(m, jc)];
+                const double w = comp == 0 ? w_end(A.W, n, jg) : interval_w(A.W, n, jg);
+                const bool bv = jv && m < nrow && (comp == 0 ? jc >= m : jc > m);
+                cacc_step(col, jv ? w * sg : mk(0.0, 0.0), bv ? tv : mk(0.0, 0.0));
+            }
+        }
+    }
+    // row dots: columns t = 4st + kk <= min(16w + 15, nrow - 1)
+    if (rowOn) {
+        const int tend = min(16 * wave + 16, nrow);
+        const int nrs = (tend + 3) >> 2;
+        const bool mok = m < nrow && (comp == 1 || A.adj || s0 + m > 0);   // empty interval at m = 0
+        const int mc = m < nrow ? m : nrow - 1;
+        for (int bp = 0; bp < NORB; ++bp) {
+            const cd* T = L + (size_t)(comp == 0 ? c * NORB + bp : bp * NORB + c) * tri(lw);
+#pragma unroll 4
+            for (int st = 0; st < nrs; ++st) {
+                const int t = 4 * st + kk;
+                const bool tv_ = t < tend;
+                const int tc = tv_ ? t : tend - 1, tg = s0 + tc;
+                cd xv;
+                if (comp == 0) {
+                    xv = A.adj ? sL[(size_t)tg * npair + x * NORB + bp]
+                               : -w_start(A.W, tg) * conj(sL[(size_t)tg * npair + bp * NORB + x]);
+                } else {
+                    xv = interval_w(A.W, n, tg) * sR[(size_t)tg * npair + x * NORB + bp];
+                }
+                const cd tv = T[tri(mc) + min(tc, mc)];
+                const bool bv = tv_ && mok && tc <= m;
+                cacc_step(row, tv_ ? xv : mk(0.0, 0.0), bv ? tv : mk(0.0, 0.0));
+            }
+        }
+    }
+    if (m >= nrow) return;
+    const size_t sl = (size_t)A.nt * npair;
+    const size_t mo = (size_t)(s0 + m) * npair + c;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int a = 4 * v + kk;
+        if (comp == 0) {
+            if (A.wantR) p_leafR(A)[mo + a * NORB] = cacc_get<false>(col, v);
+            if (A.wantL) p_leafLR(A)[mo + a * NORB] = cacc_get<true>(row, v);
+        } else {
+            p_leafLL(A)[mo + a * NORB] = cacc_get<false>(row, v);
+            p_leafLL(A)[sl + mo + a * NORB] = -cacc_get<true>(col, v);
+        }
+    }
+}
+
+// Tail rows at norb 16: component comp, output orbital c, columns [chunk*64, +64) of
+// the dense tail.  Column sums: wave w owns column tile w, K over (b', tail row).
+// Row dots: wave w owns tail-row tile w & 1 and the column half w >> 1, K over
+// (b', column); the two halves are added through LDS.
+//   comp 0: column sum x(j)[a][b'] G^R_{b'c}(j,m)          -> tailcol[0][m][a][c]
+//           row dot x2(m)[a][b'] G^R_{cb'}(r,m)^*           -> tailpart[chunk][0][r][a][c]
+//   comp 1: column sum -x1(j)[a][b'] G<_{cb'}(j,m)^*        -> tailcol[0][m][a][c]
+//           row dot x1(m)[a][b'] G<_{b'c}(r,m)              -> tailpart[chunk][0][r][a][c]
+__device__ void tail16_task(const HistArgs& A, int comp, int c, int chunk, unsigned char* smem) {
+    constexpr int NORB = 16, npair = 256;
+    if (comp == 1 && (!A.wantL || A.adj)) return;
+    const int n = A.n, n0 = A.n0[comp], nrows = A.last[comp] - n0 + 1, ls = A.ls[comp];
+    const int cbeg = chunk * kTailCH, ncol = min(kTailCH, ls - cbeg);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, x = lane & 15, kk = lane >> 4;
+    const cd* Tg = p_tail(A, comp);
+    const cd* sR = p_sigR(A);
+    const cd* sL = p_sigL(A);
+    const int nt = A.nt, ring = A.ring;
+    const bool colOn = comp == 1 || A.wantR;
+    const bool rowOn = comp == 1 || A.wantL;
+    // dense columns of tail row i (relative to n0)
+    auto lsr = [&](int i) { return n0 + i < A.nsplit[comp] ? A.lslo[comp] : ls; };
+    // column sums
+    CAcc col;
+    cacc_zero(col);
+    const int mcol = cbeg + 16 * wave + x;
+    if (colOn && 16 * wave < ncol) {
+        const int ncs = (nrows + 3) >> 2;
+        const int mc = min(mcol, ls - 1);
+        for (int bp = 0; bp < NORB; ++bp) {
+            const int q = comp == 0 ? bp * NORB + c : c * NORB + bp;
+#pragma unroll 4
+            for (int st = 0; st < ncs; ++st) {
+                const int i = 4 * st + kk;
+                const bool iv = i < nrows;
+                const int ic = iv ? i : nrows - 1, j = n0 + ic;
+                const cd sg = sR[(size_t)j * npair + x * NORB + bp];
+                const double w = comp == 0 ? w_end(A.W, n, j) : interval_w(A.W, n, j);
+                const cd tv = Tg[((size_t)(j % ring) * npair + q) * nt + mc];
+                const bool bv = iv && mcol < cbeg + ncol && mcol < lsr(ic);
+                cacc_step(col, iv ? w * sg : mk(0.0, 0.0), bv ? tv : mk(0.0, 0.0));
+            }
+        }
+    }
+    // row dots
+    CAcc row;
+    cacc_zero(row);
+    const int rt = wave & 1, half = wave >> 1;
+    const int ir = 16 * rt + x;   // this lane's tail row (B operand column)
+    if (rowOn && 16 * rt < nrows) {
+        const int irc = ir < nrows ? ir : nrows - 1, jr = n0 + irc;
+        const int lim = min(cbeg + ncol, lsr(irc));
+        const cd* Trow = Tg + (size_t)(jr % ring) * npair * nt;
+        const int mb = cbeg + 32 * half;
+        for (int bp = 0; bp < NORB; ++bp) {
+            const int q = comp == 0 ? c * NORB + bp : bp * NORB + c;
+            const cd* Tq = Trow + (size_t)q * nt;
+#pragma unroll 4
+            for (int st = 0; st < 8; ++st) {
+                const int mm = mb + 4 * st + kk;
+                const bool mv = mm < cbeg + ncol;
+                const int mmc = mv ? mm : cbeg + ncol - 1;
+                cd xv;
+                if (comp == 0) {
+                    xv = A.adj ? sL[(size_t)mmc * npair + x * NORB + bp]
+                               : -w_start(A.W, mmc) * conj(sL[(size_t)mmc * npair + bp * NORB + x]);
+                } else {
+                    xv = interval_w(A.W, n, mmc) * sR[(size_t)mmc * npair + x * NORB + bp];
+                }
+                const cd tv = Tq[min(mmc, ls - 1)];
+                const bool bv = mv && ir < nrows && mmc < lim;
+                cacc_step(row, mv ? xv : mk(0.0, 0.0), bv ? tv : mk(0.0, 0.0));
+            }
+        }
+    }
+    const size_t sl = (size_t)nt * npair;
+    (void)sl;
+    if (colOn && mcol < cbeg + ncol) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int a = 4 * v + kk;
+            const size_t o = (size_t)mcol * npair + a * NORB + c;
+            if (comp == 0) p_tailcol(A, 0)[o] = cacc_get<false>(col, v);
+            else p_tailcol(A, 1)[o] = -cacc_get<true>(col, v);
+        }
+    }
+    // the two column halves of the row dots: the upper half's waves hand theirs over
+    cd* red = reinterpret_cast<cd*>(smem);   // [rt][v][lane]
+    cd rv[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) rv[v] = comp == 0 ? cacc_get<true>(row, v) : cacc_get<false>(row, v);
+    if (half == 1)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[((size_t)rt * 4 + v) * 64 + lane] = rv[v];
+    __syncthreads();
+    if (half == 0 && rowOn && ir < nrows) {
+        cd* tp = p_tailpart(A, comp) + ((size_t)chunk * ring + ir) * npair + c;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) tp[(4 * v + kk) * NORB] = rv[v] + red[((size_t)rt * 4 + v) * 64 + lane];
+    }
+}
+
+// Dense pieces at norb 16: tail tasks first (ntailtask: column chunks of both
+// components x 16 output orbitals), then the leaves (2 * nleaf x 16); the 16 tasks
+// of one chunk or leaf land on one XCD.
+__global__ void __launch_bounds__(256) dense16(HistArgs A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    int rel = blockIdx.x;
+    int g, mem;
+    if (rel < A.ntailtask) {
+        if (!xcd_group(rel, A.ntailchunk[0] + A.ntailchunk[1], 16, g, mem)) return;
+        if (g < A.ntailchunk[0]) tail16_task(A, 0, mem, g, smem);
+        else tail16_task(A, 1, mem, g - A.ntailchunk[0], smem);
+        return;
+    }
+    rel -= A.ntailtask;
+    if (!xcd_group(rel, 2 * A.nleaf, 16, g, mem)) return;
+    leaf16_task(A, g >> 1, g & 1, mem);
+}
+
+// ---------------------------------------------------------------------------
 // Combine of the FP32-factor form at norb = 16 on the matrix cores.  A workgroup
 // takes 16 consecutive columns m (a tile inside one leaf: every block boundary is
 // a multiple of 16), wave w the output orbitals c = w, w+4, w+8, w+12.  For each
@@ -1346,11 +1593,23 @@ size_t tasks_smem(int norb, bool mfproj) {
 template <int NORB, class FT>
 hipError_t launch_t(const HistArgs& a, hipStream_t st, hipEvent_t* ev) {
     const bool mf = NORB == 16 && std::is_same<FT, cf>::value && a.mfproj;
-    const int ntask = (mf ? 0 : a.nfpad) + a.nleaftask + a.ntailtask;
     if (ev) hipEventRecord(ev[0], st);
-    if (mf && a.nf[0] + a.nf[1] > 0)
-        proj_mfma<<<dim3(a.nf[0] + a.nf[1], a.nk), NT, (size_t)kch(16) * kXS * sizeof(cf), st>>>(a);
-    if (ntask > 0) hist_tasks<NORB, FT><<<dim3(ntask, a.nk), NT, tasks_smem(NORB, mf), st>>>(a);
+    if constexpr (NORB == 16) {
+        // projections (matrix-core kernel or the generic tasks), then the dense pieces
+        if (mf && a.nf[0] + a.nf[1] > 0)
+            proj_mfma<<<dim3(a.nf[0] + a.nf[1], a.nk), NT, (size_t)kch(16) * kXS * sizeof(cf), st>>>(a);
+        if (!mf && a.nfpad > 0) {
+            HistArgs b = a;
+            b.ntailtask = 0;
+            b.nleaftask = 0;
+            hist_tasks<NORB, FT><<<dim3(a.nfpad, a.nk), NT, tasks_smem(NORB, false), st>>>(b);
+        }
+        if (a.ntailtask + a.nleaftask > 0)
+            dense16<<<dim3(a.ntailtask + a.nleaftask, a.nk), 256, 8 * 64 * sizeof(cd), st>>>(a);
+    } else {
+        const int ntask = a.nfpad + a.nleaftask + a.ntailtask;
+        if (ntask > 0) hist_tasks<NORB, FT><<<dim3(ntask, a.nk), NT, tasks_smem(NORB, false), st>>>(a);
+    }
     if (ev) hipEventRecord(ev[1], st);
     {
         const long long nb1 = proj_reduce_blocks(a), nb2 = (2LL * a.ring * NORB * NORB + 3) / 4;

@@ -77,7 +77,7 @@ def test_c1_full_sweep_dense(P):
     _check_rows(IRg, ILg, d["IR"], d["IL"], "dense c1")
 
 
-@pytest.mark.parametrize("norb,k,panel", [(2, 5, 8), (4, 3, 16), (4, 1, 4), (8, 5, 8)])
+@pytest.mark.parametrize("norb,k,panel", [(2, 5, 8), (4, 3, 16), (4, 1, 4), (8, 5, 8), (16, 5, 8)])
 def test_multiorbital_sweep(P, norb, k, panel):
     N, h, nlvl = 160, 0.03, 3   # leaves of 20 rows: ragged panels, several blocks per level
     G = hermitian_terms(11 + norb, 6, norb)
