@@ -208,6 +208,8 @@ struct hnessi_hodlr_s {
     cd* tailcol[2] = {};
     cd* tailpart[2] = {};
     cd* tailrow[2] = {};
+    cd* sigRT = nullptr;   // norb 16: Sigma^R row with swapped orbital indices (per step)
+    long long oSigRT = 0;
     int ntailchunk_max = 0;
     // merge scratch
     std::vector<long long> lvl_node_base;  // per level: first node of pair 0
@@ -417,6 +419,7 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
         HALLOC_K(H->tail[c], (size_t)kTailRows * npair * nt, true, H->oTail);
     }
     HALLOC_K(H->band, (size_t)nt * (k + 1) * npair, true, H->oBand);
+    if (norb == 16) HALLOC_K(H->sigRT, (size_t)nt * npair, false, H->oSigRT);
     HALLOC_K(H->proj, (size_t)2 * std::max(nb, 1) * npair * 2 * norb * RC, true, H->oProj);
     // chunk partials of the projections: one slot per kch(norb) factor rows
     std::vector<long long> partoff((size_t)2 * std::max(nb, 1) * npair * 2, 0);
@@ -799,6 +802,8 @@ int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, doub
     A.kLeaf = H->oLeaf;
     A.kTail = H->oTail;
     A.kBand = H->oBand;
+    A.sigRT = H->sigRT;
+    A.kInT = H->oSigRT;
     A.kProj = H->oProj;
     A.kPart = H->oPart;
     A.kLeafOut = H->oLeafOut;

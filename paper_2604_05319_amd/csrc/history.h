@@ -29,6 +29,8 @@ struct HistArgs {
     Weights W;
     const cd* sigR;   // Sigma^R(n, j), j = 0..n
     const cd* sigL;   // Sigma^<(s, n), s = 0..n
+    cd* sigRT;        // norb 16: scratch for Sigma^R(n, j) with its orbital indices swapped
+    long long kInT;   // its object stride
     int f32;          // factors stored as complex float (cf) instead of complex double
     int mfproj;       // norb = 16 with cf factors and RC <= 16: projections on the matrix
                       // cores, one task per (block, factor, chunk, orbital index beta)

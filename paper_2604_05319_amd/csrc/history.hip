@@ -58,6 +58,8 @@ __device__ inline void add_at(cd (&acc)[N], int idx, cd v) {
 #define OBJ ((long long)blockIdx.y)
 __device__ inline const cd* p_sigR(const HistArgs& A) { return A.sigR ? A.sigR + OBJ * A.kIn : nullptr; }
 __device__ inline const cd* p_sigL(const HistArgs& A) { return A.sigL ? A.sigL + OBJ * A.kIn : nullptr; }
+// Sigma^R(n, j) with the orbital indices swapped ([j][b][a], norb 16 only)
+__device__ inline const cd* p_sigRT(const HistArgs& A) { return A.sigRT + OBJ * A.kInT; }
 __device__ inline cd* p_outR(const HistArgs& A) { return A.outR ? A.outR + OBJ * A.kOut : nullptr; }
 __device__ inline cd* p_outL(const HistArgs& A) { return A.outL ? A.outL + OBJ * A.kOut : nullptr; }
 // factor buffer holding block b's current TSVD
@@ -275,8 +277,8 @@ __device__ inline void two_sum_acc(float& s, float& e, float v) {
     s = t;
 }
 
-constexpr int kXS = 18;   // LDS row stride of staged X in complex floats (16 orbitals + 2:
-                          // the rows 8 apart that one read touches fall in different banks)
+constexpr int kXS = 16;   // LDS row stride of staged X in complex floats: the consecutive
+                          // rows that one read touches fall in alternate bank halves
 constexpr int kPT = 32;   // factor rows per tile
 
 // Z(a, r) = S_r sum_i X[i][a] op(F[r*ld + i]) over rows [i0, i1) for one pair, op =
@@ -292,19 +294,21 @@ __device__ void fact_mfma_pair(const cf* F, int ld, int i0, int i1, int rk, cons
     float sr[4] = {0.f, 0.f, 0.f, 0.f}, er[4] = {0.f, 0.f, 0.f, 0.f};
     float si[4] = {0.f, 0.f, 0.f, 0.f}, ei[4] = {0.f, 0.f, 0.f, 0.f};
     cf bc[8], bn[8];
+    // K step s of tile t takes rows t*kPT + 4s + kk: one load instruction reads four
+    // consecutive rows of each of the 16 columns
     auto load = [&](cf (&bb)[8], int t) {
-        const int r = i0 + t * kPT + 8 * kk;
+        const int r = i0 + t * kPT + kk;
 #pragma unroll
-        for (int s = 0; s < 8; ++s) bb[s] = Fj[min(r + s, i1 - 1)];
+        for (int s = 0; s < 8; ++s) bb[s] = Fj[min(r + 4 * s, i1 - 1)];
     };
     load(bc, 0);
     for (int t = 0; t < ntile; ++t) {
         if (t + 1 < ntile) load(bn, t + 1);
         v4f rr = {0.f, 0.f, 0.f, 0.f}, ii = rr, ri = rr, ir = rr;
-        const cf* xt = xs + (size_t)(t * kPT + 8 * kk) * kXS + j;
+        const cf* xt = xs + (size_t)(t * kPT + kk) * kXS + j;
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-            const cf x = xt[s * kXS];
+            const cf x = xt[4 * s * kXS];
             rr = mfma_16x16x4(x.x, bc[s].x, rr);
             ii = mfma_16x16x4(x.y, bc[s].y, ii);
             ri = mfma_16x16x4(x.x, bc[s].y, ri);
@@ -361,10 +365,10 @@ __device__ void fact_mfma_task(const HistArgs& A, const FactTask& t, unsigned ch
         const int i = e >> 4, a = e & 15, jj = base + i0 + i;
         cd v = mk(0.0, 0.0);
         if (i < nrow) {
-            if (comp == 0 && which == 0) v = w_end(A.W, n, jj) * p_sigR(A)[(size_t)jj * npair + a * NORB + beta];
+            if (comp == 0 && which == 0) v = w_end(A.W, n, jj) * p_sigRT(A)[(size_t)jj * npair + beta * NORB + a];
             else if (comp == 0) v = A.adj ? p_sigL(A)[(size_t)jj * npair + a * NORB + beta]
                                           : -w_start(A.W, jj) * conj(p_sigL(A)[(size_t)jj * npair + beta * NORB + a]);
-            else v = interval_w(A.W, n, jj) * p_sigR(A)[(size_t)jj * npair + a * NORB + beta];
+            else v = interval_w(A.W, n, jj) * p_sigRT(A)[(size_t)jj * npair + beta * NORB + a];
         }
         xs[(size_t)i * kXS + a] = cf{(float)v.x, (float)v.y};
     }
@@ -1266,7 +1270,7 @@ __device__ void leaf16_task(const HistArgs& A, int leaf, int comp, int c) {
     if (16 * wave >= nrow) return;
     const int m = 16 * wave + x;
     const cd* L = p_leaf(A, comp) + A.Loff[leaf];
-    const cd* sR = p_sigR(A);
+    const cd* sRT = p_sigRT(A);
     const cd* sL = p_sigL(A);
     const bool colOn = comp == 1 || A.wantR;
     const bool rowOn = comp == 1 || A.wantL;
@@ -1283,7 +1287,7 @@ __device__ void leaf16_task(const HistArgs& A, int leaf, int comp, int c) {
                 const int j = 16 * wave + 4 * st + kk;
                 const bool jv = j < nrow;
                 const int jc = jv ? j : nrow - 1, jg = s0 + jc;
-                const cd sg = sR[(size_t)jg * npair + x * NORB + bp];
+                const cd sg = sRT[(size_t)jg * npair + bp * NORB + x];
                 const cd tv = T[tri(jc) + min(m, jc)];
                 const double w = comp == 0 ? w_end(A.W, n, jg) : interval_w(A.W, n, jg);
                 const bool bv = jv && m < nrow && (comp == 0 ? jc >= m : jc > m);
@@ -1309,7 +1313,7 @@ __device__ void leaf16_task(const HistArgs& A, int leaf, int comp, int c) {
                     xv = A.adj ? sL[(size_t)tg * npair + x * NORB + bp]
                                : -w_start(A.W, tg) * conj(sL[(size_t)tg * npair + bp * NORB + x]);
                 } else {
-                    xv = interval_w(A.W, n, tg) * sR[(size_t)tg * npair + x * NORB + bp];
+                    xv = interval_w(A.W, n, tg) * sRT[(size_t)tg * npair + bp * NORB + x];
                 }
                 const cd tv = T[tri(mc) + min(tc, mc)];
                 const bool bv = tv_ && mok && tc <= m;
@@ -1348,7 +1352,7 @@ __device__ void tail16_task(const HistArgs& A, int comp, int c, int chunk, unsig
     const int cbeg = chunk * kTailCH, ncol = min(kTailCH, ls - cbeg);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, x = lane & 15, kk = lane >> 4;
     const cd* Tg = p_tail(A, comp);
-    const cd* sR = p_sigR(A);
+    const cd* sRT = p_sigRT(A);
     const cd* sL = p_sigL(A);
     const int nt = A.nt, ring = A.ring;
     const bool colOn = comp == 1 || A.wantR;
@@ -1369,7 +1373,7 @@ __device__ void tail16_task(const HistArgs& A, int comp, int c, int chunk, unsig
                 const int i = 4 * st + kk;
                 const bool iv = i < nrows;
                 const int ic = iv ? i : nrows - 1, j = n0 + ic;
-                const cd sg = sR[(size_t)j * npair + x * NORB + bp];
+                const cd sg = sRT[(size_t)j * npair + bp * NORB + x];
                 const double w = comp == 0 ? w_end(A.W, n, j) : interval_w(A.W, n, j);
                 const cd tv = Tg[((size_t)(j % ring) * npair + q) * nt + mc];
                 const bool bv = iv && mcol < cbeg + ncol && mcol < lsr(ic);
@@ -1400,7 +1404,7 @@ __device__ void tail16_task(const HistArgs& A, int comp, int c, int chunk, unsig
                     xv = A.adj ? sL[(size_t)mmc * npair + x * NORB + bp]
                                : -w_start(A.W, mmc) * conj(sL[(size_t)mmc * npair + bp * NORB + x]);
                 } else {
-                    xv = interval_w(A.W, n, mmc) * sR[(size_t)mmc * npair + x * NORB + bp];
+                    xv = interval_w(A.W, n, mmc) * sRT[(size_t)mmc * npair + bp * NORB + x];
                 }
                 const cd tv = Tq[min(mmc, ls - 1)];
                 const bool bv = mv && ir < nrows && mmc < lim;
@@ -1590,11 +1594,21 @@ size_t tasks_smem(int norb, bool mfproj) {
     return s > tail ? s : tail;
 }
 
+// sigRT[j][b][a] = sigR[j][a][b] for j <= n (norb 16): the matrix-core kernels read the
+// 16 left orbitals a of one (j, b) as consecutive words
+__global__ void __launch_bounds__(256) sig_transpose16(const cd* sigR, cd* sigRT, long long kIn, long long kInT) {
+    const long long j = blockIdx.x;
+    const int t = threadIdx.x;
+    const cd v = sigR[(long long)blockIdx.y * kIn + j * 256 + t];
+    sigRT[(long long)blockIdx.y * kInT + j * 256 + (t & 15) * 16 + (t >> 4)] = v;
+}
+
 template <int NORB, class FT>
 hipError_t launch_t(const HistArgs& a, hipStream_t st, hipEvent_t* ev) {
     const bool mf = NORB == 16 && std::is_same<FT, cf>::value && a.mfproj;
     if (ev) hipEventRecord(ev[0], st);
     if constexpr (NORB == 16) {
+        if (a.sigR) sig_transpose16<<<dim3(a.n + 1, a.nk), 256, 0, st>>>(a.sigR, a.sigRT, a.kIn, a.kInT);
         // projections (matrix-core kernel or the generic tasks), then the dense pieces
         if (mf && a.nf[0] + a.nf[1] > 0)
             proj_mfma<<<dim3(a.nf[0] + a.nf[1], a.nk), NT, (size_t)kch(16) * kXS * sizeof(cf), st>>>(a);
