@@ -168,8 +168,9 @@ int hnessi_hodlr_append_row(hnessi_hodlr_t H, int c, int n, const void* row, voi
  * "Kadanoff-Baym equations") in the form with the current Sigma^R row on the
  * left, Gregory weights of the appendix "Integral and derivative
  * approximations".  sigR_row: Sigma^R(t_n, t_j), j = 0..n (device).
- * Needs retarded rows 0..n appended and no later row (HNESSI_E_ORDER);
- * NULL pointers: HNESSI_E_ARG. */
+ * Needs retarded rows 0..n appended (HNESSI_E_ORDER otherwise); with later
+ * rows appended, step n is evaluated over the stored (frozen) state, see
+ * hnessi_history_R_adjoint.  NULL pointers: HNESSI_E_ARG. */
 int hnessi_history_R(hnessi_hodlr_t H, int n, const void* sigR_row, double h,
                      void* out, void* stream);
 
@@ -191,9 +192,59 @@ int hnessi_history_lesser(hnessi_hodlr_t H, int n, const void* sigR_row,
  * Re sum tr(A^dagger B).  ibar_row: device (n+1)*norb*norb complex128, the
  * cotangent of I^R(n, m), m = 0..n; out: device, same size.  Needs the
  * retarded row n appended (HNESSI_E_ORDER otherwise); reads only the
- * retarded component. */
+ * retarded component.
+ * Frozen state: like hnessi_history_R and hnessi_history_R_factor_grad, this call
+ * also takes any n below the last appended retarded row and then evaluates step
+ * n over the stored state (the compressed G^R of all rows appended so far, rows
+ * above n excluded), so a backward pass needs no replay of the appends and
+ * merges.  For n < last the call first completes the retarded component's
+ * in-flight panel merge on stream. */
 int hnessi_history_R_adjoint(hnessi_hodlr_t H, int n, const void* ibar_row, double h, void* out,
                              void* stream);
+
+/* Gradient of a real loss with respect to the retarded HODLR factors of the
+ * stored state, step n's contribution (the transpose of Eq. KBER's discrete
+ * history sum, section "Hierarchical decomposition" for G = U S V^H per block and
+ * orbital pair): with Gbar(j, m) = h sum_n w^{(n-m)}_{j-m} Sigma^R(n,j)^dagger
+ * Ibar(n, m) the gradient with respect to the entries of block b, pair
+ * q = (b', c), this call adds
+ *   dU += Gbar V S,   dV += Gbar^dagger U S,   dS += Re diag(U^dagger Gbar V)
+ * over the merged rows j <= n of every block (rows still in the dense tail carry
+ * no factor).  sigR_row: Sigma^R(n, j), j = 0..n; ibar_row: the cotangent of
+ * I^R(n, m), m = 0..n (device, (n+1)*norb*norb complex128 each).  The sums over
+ * n accumulate in device buffers of the handle, allocated (and cleared) by the
+ * first call; hnessi_factor_grad_reset clears them and hnessi_factor_grad_get
+ * reads them.  Gradients are taken in torch's convention for complex tensors
+ * (dL/dRe + i dL/dIm); S is real.  n may be below the last appended row
+ * (frozen state, see hnessi_history_R_adjoint), which is how a backward pass
+ * calls it: the factors are those of the handle when the call runs.  Single
+ * objects only (HNESSI_E_ARG for batched handles); HNESSI_E_NOMEM if the first
+ * call cannot allocate the buffers (one more copy of a buffer of U, V and S). */
+int hnessi_history_R_factor_grad(hnessi_hodlr_t H, int n, const void* sigR_row, const void* ibar_row,
+                                 double h, void* stream);
+
+/* Clear the factor-gradient buffers (no-op before the first
+ * hnessi_history_R_factor_grad), ordered on stream. */
+int hnessi_factor_grad_reset(hnessi_hodlr_t H, void* stream);
+
+/* Accumulated factor gradients of retarded block `block` (the row of
+ * hnessi_hodlr_blocks), orbital pair `pair` = b' * norb + c, to host memory:
+ * dU_host: rank columns of (r1 - r0) rows, column r at dU_host[r * (r1 - r0) + i]
+ * (complex128); dV_host likewise with c1 - c0 rows; dS_host: rank values.
+ * Returns the rank of the pair's current factors (the number of columns
+ * written), HNESSI_E_ORDER before any accumulation.  Synchronizes with the
+ * handle's work. */
+int hnessi_factor_grad_get(hnessi_hodlr_t H, int block, int pair, void* dU_host, double* dS_host,
+                           void* dV_host);
+
+/* The current TSVD factors U, S, V of block `block`, pair `pair` of component
+ * comp (section "Hierarchical decomposition": G = U S V^H on the block's rows
+ * and columns, Tab. getcompress for reading the compressed storage), to host
+ * memory in the layout of hnessi_factor_grad_get; rows of U at or above the
+ * merge frontier are not yet part of the factors.  Returns the rank.
+ * Completes in-flight merges and synchronizes with the handle's work. */
+int hnessi_hodlr_factors(hnessi_hodlr_t H, int comp, int block, int pair, void* U_host, double* S_host,
+                         void* V_host);
 
 /* Both integrals of step n (Eqs. KBER and KBEL as for hnessi_history_R and
  * hnessi_history_lesser) in one pass over the stored data: each stored

@@ -56,6 +56,12 @@ _SIGS = {
                                C.c_void_p], C.c_int),
     "hnessi_history_R_adjoint": ([C.c_void_p, C.c_int, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p],
                                  C.c_int),
+    "hnessi_history_R_factor_grad": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p],
+                                     C.c_int),
+    "hnessi_factor_grad_reset": ([C.c_void_p, C.c_void_p], C.c_int),
+    "hnessi_factor_grad_get": ([C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "hnessi_hodlr_factors": ([C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p],
+                             C.c_int),
     "hnessi_history_step": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p,
                              C.c_void_p, C.c_void_p], C.c_int),
     "hnessi_sweep": ([C.c_void_p, C.c_int, C.c_int] + [C.c_void_p] * 4 + [C.c_double]
@@ -201,7 +207,12 @@ class Hodlr:
                                          _stream()))
         self.h = h
         self.nt, self.nlvl, self.norb, self.k = nt, nlvl, norb, k
-        self.tol, self.panel, self.max_rank = tol, panel, max_rank
+        self.tol, self.panel, self.max_rank, self.flags = tol, panel, max_rank, flags
+
+    def spec(self):
+        """The creation parameters (a handle of the same geometry: Hodlr(**H.spec()))."""
+        return dict(nt=self.nt, nlvl=self.nlvl, norb=self.norb, k=self.k, tol=self.tol, panel=self.panel,
+                    max_rank=self.max_rank, flags=self.flags)
 
     def close(self):
         if self.h:
@@ -233,6 +244,30 @@ class Hodlr:
     def history_R_adjoint(self, n, ibar, h, out):
         """out(j) = h sum_{m<=j} w^{(n-m)}_{j-m} ibar(m) G^R(j,m)^dagger, j = 0..n."""
         _check(lib().hnessi_history_R_adjoint(self.h, n, _ptr(ibar), h, _ptr(out), _stream()))
+
+    def factor_grad(self, n, sigR, ibar, h):
+        _check(lib().hnessi_history_R_factor_grad(self.h, n, _ptr(sigR), _ptr(ibar), h, _stream()))
+
+    def factor_grad_reset(self):
+        _check(lib().hnessi_factor_grad_reset(self.h, _stream()))
+
+    def _block_arrays(self, b, fn, *lead):
+        lvl, r0, r1, c0, c1 = (int(x) for x in self.blocks()[b])
+        U = np.zeros((self.max_rank, r1 - r0), dtype=np.complex128)
+        V = np.zeros((self.max_rank, c1 - c0), dtype=np.complex128)
+        S = np.zeros(self.max_rank)
+        rk = _check(fn(self.h, *lead, U.ctypes.data_as(C.c_void_p), S.ctypes.data_as(C.c_void_p),
+                       V.ctypes.data_as(C.c_void_p)))
+        # rank columns, column r of U at U[:, r]
+        return U[:rk].T.copy(), S[:rk].copy(), V[:rk].T.copy()
+
+    def factor_grad_get(self, b, q):
+        """(dU, dS, dV) of retarded block b, pair q: dU (rows, rank), dS (rank,), dV (cols, rank)."""
+        return self._block_arrays(b, lib().hnessi_factor_grad_get, b, q)
+
+    def factors(self, comp, b, q):
+        """(U, S, V) of block b, pair q of component comp: U (rows, rank), S (rank,), V (cols, rank)."""
+        return self._block_arrays(b, lambda h, b_, q_, *a: lib().hnessi_hodlr_factors(h, comp, b_, q_, *a), b, q)
 
     def sweep(self, n_begin, n_end, GR, GL, SR, SL, h, IR, IL):
         _check(lib().hnessi_sweep(self.h, n_begin, n_end, _ptr(GR), _ptr(GL), _ptr(SR), _ptr(SL), h,

@@ -210,6 +210,11 @@ struct hnessi_hodlr_s {
     cd* tailrow[2] = {};
     cd* sigRT = nullptr;   // norb 16: Sigma^R row with swapped orbital indices (per step)
     long long oSigRT = 0;
+    // gradient of a loss with respect to the retarded factors (allocated on first use):
+    // dU, dV laid out like one buffer of U, V; dS like one buffer of S
+    cd* dU = nullptr;
+    cd* dV = nullptr;
+    double* dS = nullptr;
     int ntailchunk_max = 0;
     // merge scratch
     std::vector<long long> lvl_node_base;  // per level: first node of pair 0
@@ -701,35 +706,51 @@ int drain(hnessi_hodlr_t H) {
     return HNESSI_OK;
 }
 
+// Retarded-only calls (history_R, its adjoint, the factor gradient) also accept a
+// step n below the last appended row: they then evaluate step n over the stored
+// (frozen) state, which holds the compressed G^R of every row so far: the merged
+// rows at or below n through the factors, rows n0..n from the tail, no row above n.
 int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, double h, void* outR,
                void* outL, bool wantR, bool wantL, hipStream_t st, long long in_stride = 0,
-               long long out_stride = 0, bool adj = false) {
+               long long out_stride = 0, bool adj = false, bool fgrad = false) {
     if (n < 0 || n >= H->nt) return fail(HNESSI_E_RANGE, "n outside the grid");
-    if (!sigR && !adj) return fail(HNESSI_E_ARG, "sigR_row is NULL");
-    if (wantR && !outR) return fail(HNESSI_E_ARG, "output is NULL");
-    if (wantL && (!outL || !sigL)) return fail(HNESSI_E_ARG, "input or output is NULL");
-    if (H->last[0] != n) return fail(HNESSI_E_ORDER, "retarded row n has not been appended (or later rows have)");
+    if (!sigR && (!adj || fgrad)) return fail(HNESSI_E_ARG, "sigR_row is NULL");
+    if (wantR && !outR && !fgrad) return fail(HNESSI_E_ARG, "output is NULL");
+    if (wantL && (!sigL || (!outL && !fgrad))) return fail(HNESSI_E_ARG, "input or output is NULL");
+    const bool ronly = !wantL || adj;
+    if (n > H->last[0] || (n < H->last[0] && !ronly))
+        return fail(HNESSI_E_ORDER, "retarded row n has not been appended (or later rows have)");
     if (wantL && !adj && H->last[1] != n)
         return fail(HNESSI_E_ORDER, "lesser row n has not been appended (or later rows have)");
+    const bool frozen = n < H->last[0];
+    if (frozen) {
+        // the in-flight merge of the retarded component becomes current first
+        int rc = finish_pending(H, 0, st);
+        if (rc != HNESSI_OK) return rc;
+    }
     const Geometry& g = H->g;
     HistArgs A{};
     A.n = n;
     for (int c = 0; c < 2; ++c) {
         A.n0[c] = H->n0[c];
         A.last[c] = H->last[c];
+        if (frozen && c == 0) {
+            A.n0[0] = std::min(H->n0[0], n + 1);
+            A.last[0] = n;
+        }
         A.ls[c] = 0;
         A.ntailchunk[c] = 0;
         A.nf[c] = 0;
         bool use = (c == 0) || (wantL && !adj);
         if (!use) continue;
-        A.nf[c] = (int)(std::lower_bound(H->ft_act[c].begin(), H->ft_act[c].end(), H->n0[c]) -
+        A.nf[c] = (int)(std::lower_bound(H->ft_act[c].begin(), H->ft_act[c].end(), A.n0[c]) -
                         H->ft_act[c].begin());
         // tail rows n0..last: those of the panel still being merged (before nsplit) hold
         // columns [0, lslo), the later ones [0, ls)
-        A.nsplit[c] = H->pend[c].on ? H->pend[c].p1 : H->n0[c];
-        if (H->last[c] >= H->n0[c]) {
-            A.lslo[c] = g.s0[g.row_leaf[H->n0[c]]];
-            A.ls[c] = A.nsplit[c] <= H->last[c] ? g.s0[g.row_leaf[A.nsplit[c]]] : A.lslo[c];
+        A.nsplit[c] = H->pend[c].on ? H->pend[c].p1 : A.n0[c];
+        if (A.last[c] >= A.n0[c]) {
+            A.lslo[c] = g.s0[g.row_leaf[A.n0[c]]];
+            A.ls[c] = A.nsplit[c] <= A.last[c] ? g.s0[g.row_leaf[A.nsplit[c]]] : A.lslo[c];
             A.ntailchunk[c] = div_up(A.ls[c], kTailCH);
         }
     }
@@ -775,6 +796,16 @@ int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, doub
     const int per_piece = H->norb <= 4 ? H->npair : ngroups * 4;
     A.nleaftask = div_up(2 * A.nleaf, 8) * 8 * per_piece;
     A.ntailtask = div_up(A.ntailchunk[0] + A.ntailchunk[1], 8) * 8 * per_piece;
+    if (fgrad) {   // the projections only
+        A.nleaftask = 0;
+        A.ntailtask = 0;
+        A.fgrad = 1;
+        A.Ud = H->U[0];
+        A.Vd = H->V[0];
+        A.dU = H->dU;
+        A.dV = H->dV;
+        A.dS = H->dS;
+    }
     A.part = H->part;
     A.proj = H->proj;
     A.leafR = H->leafR;
@@ -967,6 +998,41 @@ int hnessi_history_R_adjoint(hnessi_hodlr_t H, int n, const void* ibar_row, doub
     return rc != HNESSI_OK ? rc : mark(H, (hipStream_t)stream);
 }
 
+int hnessi_factor_grad_reset(hnessi_hodlr_t H, void* stream);
+
+int hnessi_history_R_factor_grad(hnessi_hodlr_t H, int n, const void* sigR_row, const void* ibar_row, double h,
+                                 void* stream) {
+    int rc = single_only(H);
+    if (rc != HNESSI_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (!H->dU) {
+        // allocated on the handle's stream (ordered there), then cleared on st
+        DevAlloc& al = H->al;
+        if (dev_alloc(al, H->dU, (size_t)H->bU, false) != HNESSI_OK ||
+            dev_alloc(al, H->dV, (size_t)H->bV, false) != HNESSI_OK ||
+            dev_alloc(al, H->dS, (size_t)H->bS, false) != HNESSI_OK) {
+            H->dU = nullptr;
+            return fail(HNESSI_E_NOMEM, "device allocation of the factor gradients failed");
+        }
+        HIP_TRY(hipStreamSynchronize(al.st));
+        rc = hnessi_factor_grad_reset(H, stream);
+        if (rc != HNESSI_OK) return rc;
+    }
+    rc = do_history(H, n, sigR_row, ibar_row, h, nullptr, nullptr, true, true, st, 0, 0, true, true);
+    return rc != HNESSI_OK ? rc : mark(H, st);
+}
+
+int hnessi_factor_grad_reset(hnessi_hodlr_t H, void* stream) {
+    int rc = single_only(H);
+    if (rc != HNESSI_OK) return rc;
+    if (!H->dU) return HNESSI_OK;
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(launch_fill_int(reinterpret_cast<int*>(H->dU), 4 * H->bU, 0, st));
+    HIP_TRY(launch_fill_int(reinterpret_cast<int*>(H->dV), 4 * H->bV, 0, st));
+    HIP_TRY(launch_fill_int(reinterpret_cast<int*>(H->dS), 2 * H->bS, 0, st));
+    return mark(H, st);
+}
+
 int hnessi_history_step_batched(hnessi_hodlr_t H, int n, const void* sigR_rows, const void* sigL_slices,
                                 long long in_stride, double h, void* outR, void* outL, long long out_stride,
                                 void* stream) {
@@ -1086,6 +1152,46 @@ int hnessi_hodlr_get(hnessi_hodlr_t H, int c, int t1, int t2, void* out_host) {
     }
     std::memcpy(out_host, out.data(), npair * sizeof(cd));
     return HNESSI_OK;
+}
+
+// block b, pair q of component c (or, with grad, the factor gradients of the
+// retarded component) to the host; returns the rank
+static int factors_to_host(hnessi_hodlr_t H, int c, int b, int q, void* U_host, double* S_host, void* V_host,
+                           bool grad) {
+    if (!H || !U_host || !S_host || !V_host) return fail(HNESSI_E_ARG, "NULL argument");
+    if (H->nk != 1) return fail(HNESSI_E_ARG, "batched handle: factors are read for single objects");
+    if (c != HNESSI_RET && c != HNESSI_LES) return fail(HNESSI_E_ARG, "component must be RET or LES");
+    const Geometry& g = H->g;
+    if (b < 0 || b >= g.nb || q < 0 || q >= H->npair) return fail(HNESSI_E_RANGE, "block or pair out of range");
+    if (grad && !H->dU) return fail(HNESSI_E_ORDER, "no factor gradient has been accumulated");
+    int rc = drain(H);
+    if (rc == HNESSI_OK) rc = wait_handle(H);
+    if (rc != HNESSI_OK) return rc;
+    const int RC = H->RC, npair = H->npair;
+    const int ldU = g.r1[b] - g.r0[b], ldV = g.c1[b] - g.c0[b];
+    const long long bf = H->cur[c][b];
+    int rk = 0;
+    HIP_TRY(hipMemcpy(&rk, H->rank[c] + bf * H->bRank + (size_t)b * npair + q, sizeof(int), hipMemcpyDeviceToHost));
+    rk = std::max(0, std::min(rk, RC));
+    const size_t uo = (size_t)H->Uoff[b] + (size_t)q * RC * ldU, vo = (size_t)H->Voff[b] + (size_t)q * RC * ldV;
+    const size_t so = ((size_t)b * npair + q) * RC;
+    const cd* Us = grad ? H->dU + uo : H->U[c] + bf * H->bU + uo;
+    const cd* Vs = grad ? H->dV + vo : H->V[c] + bf * H->bV + vo;
+    const double* Ss = grad ? H->dS + so : H->S[c] + bf * H->bS + so;
+    if (rk > 0) {
+        HIP_TRY(hipMemcpy(U_host, Us, (size_t)rk * ldU * sizeof(cd), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(V_host, Vs, (size_t)rk * ldV * sizeof(cd), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(S_host, Ss, (size_t)rk * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    return rk;
+}
+
+int hnessi_hodlr_factors(hnessi_hodlr_t H, int c, int block, int pair, void* U_host, double* S_host, void* V_host) {
+    return factors_to_host(H, c, block, pair, U_host, S_host, V_host, false);
+}
+
+int hnessi_factor_grad_get(hnessi_hodlr_t H, int block, int pair, void* dU_host, double* dS_host, void* dV_host) {
+    return factors_to_host(H, HNESSI_RET, block, pair, dU_host, dS_host, dV_host, true);
 }
 
 int hnessi_hodlr_ranks(hnessi_hodlr_t H, int c, int* ranks_host, int capacity) {

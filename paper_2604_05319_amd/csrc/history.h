@@ -71,6 +71,16 @@ struct HistArgs {
     cd* tailrow[2];  // [slot][a][c]         row dots of the tail rows (sum over the chunks)
     cd* outR;
     cd* outL;
+    // factor-gradient mode (fgrad = 1, with wantR = wantL = adj = 1 and no dense
+    // pieces): the step's projections x_n U and Ibar_n V feed fgrad_kernel, which adds
+    // the step's contributions to dL/d(U, S, V) of the retarded factors (FP64 copies
+    // Ud, Vd) into dU, dV (laid out like one buffer of U, V) and dS ([b][pair][RC])
+    int fgrad;
+    const cd* Ud;
+    const cd* Vd;
+    cd* dU;
+    cd* dV;
+    double* dS;
     // batched objects (grid dimension y): element strides from one object's
     // data to the next; the geometry and the task lists are shared
     long long kIn, kOut;   // Sigma rows, output rows

@@ -1585,6 +1585,92 @@ __global__ void __launch_bounds__(256) combine_mfma(HistArgs A) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Gradient of a real loss with respect to the retarded factors of the current
+// (frozen) state: the contributions of step n.  With x_n(j) the folded Sigma^R row
+// and Ibar(n, m) the cotangent of I^R(n, m), the gradient of block b, pair
+// q = (b', c), with respect to its entries is
+//   Gbar(j, m) = h sum_n w^{(n-m)}_{j-m} sum_a conj(Sigma^R(n,j)[a][b']) Ibar(n,m)[a][c]
+// (the transpose of Eq. KBER's history sum), and through G = U S V^H
+//   Ubar = Gbar V S,   Vbar = Gbar^H U S,   Sbar = Re diag(U^H Gbar V).
+// The bulk weight w_end(n, j) is folded into x_n, so the bulk parts need only the
+// step's projections P0 = S_r (x_n U)[a][r] and P1 = S_r (Ibar_n V)[a][r]:
+//   Ubar(j, r) += h sum_a conj(x_n(j)[a][b']) P1[a][r]
+//   Vbar(m, r) += h sum_a conj(Ibar(n,m)[a][c]) P0[a][r]
+//   Sbar(r)    += h sum_a Re(conj(P0[a][r]) P1[a][r]) / S_r^2
+// The block entries within k of the diagonal (j - m <= k, the corner next to the
+// leaf boundary), whose exact weight w^{(n-m)}_{j-m} differs from w_end(n, j), are
+// added with the weight difference.  One thread per (pair, rank, U row | V row |
+// S), so every output entry has one writer; the block is blockIdx.x / xper (a single
+// object: grid.y = 1, which the accessors take as the object index).
+template <int NORB>
+__global__ void __launch_bounds__(256) fgrad_kernel(HistArgs A, int xper) {
+    constexpr int npair = NORB * NORB;
+    const int b = blockIdx.x / xper;
+    const int* bk = A.blk + 5 * b;
+    const int r0 = bk[1], r1 = bk[2], c0 = bk[3], c1 = bk[4];
+    const int n = A.n;
+    if (r0 > n || A.n0[0] <= r0) return;   // no merged row of the block at or below n
+    const int ldU = r1 - r0, ldV = c1 - c0, RC = A.RC, k = A.W.k;
+    const long long per = (long long)ldU + ldV + 1;
+    const long long t = (long long)(blockIdx.x % xper) * 256 + threadIdx.x;
+    if (t >= per * RC * npair) return;
+    const int row = (int)(t % per);
+    const int r = (int)((t / per) % RC);
+    const int q = (int)(t / (per * RC));
+    const int rk = rank_of(A, 0, b, q);
+    if (r >= rk) return;
+    const int qr = q / NORB, qc = q % NORB;
+    const int jend = min(A.n0[0], n + 1);   // merged rows at or below n
+    const long long buf = buf_of(A, 0, b);
+    const cd* Uq = A.Ud + buf * A.bU + A.Uoff[b] + (size_t)q * RC * ldU + (size_t)r * ldU;
+    const cd* Vq = A.Vd + buf * A.bV + A.Voff[b] + (size_t)q * RC * ldV + (size_t)r * ldV;
+    const double Sr = p_S(A, 0, b)[((size_t)b * npair + q) * RC + r];
+    const cd* P0 = p_proj(A) + proj_slot(A, 0, b, q, 0) * NORB * RC + r;
+    const cd* P1 = p_proj(A) + proj_slot(A, 0, b, q, 1) * NORB * RC + r;
+    const cd* sR = p_sigR(A);
+    const cd* ib = p_sigL(A);   // Ibar(n, m)
+    // corner term: h (w^{(n-m)}_{j-m} - w_end(n, j)) sum_a conj(Sigma(n,j)[a][b']) Ibar(n,m)[a][c]
+    auto gcorner = [&](int j, int m) -> cd {
+        const double dw = interval_w(A.W, n - m, j - m) - w_end(A.W, n, j);
+        cd g = mk(0.0, 0.0);
+        for (int a = 0; a < NORB; ++a) fmac_(g, sR[(size_t)j * npair + a * NORB + qr], ib[(size_t)m * npair + a * NORB + qc]);
+        return (A.h * dw) * g;
+    };
+    if (row < ldU) {
+        const int j = r0 + row;
+        if (j >= jend) return;
+        const double we = w_end(A.W, n, j);
+        cd acc = mk(0.0, 0.0);
+        for (int a = 0; a < NORB; ++a) fmac_(acc, sR[(size_t)j * npair + a * NORB + qr], P1[(size_t)a * RC]);
+        acc = (A.h * we) * acc;
+        for (int m = max(c0, j - k); m < c1; ++m) acc = acc + Sr * (gcorner(j, m) * Vq[m - c0]);
+        cd* d = A.dU + A.Uoff[b] + (size_t)q * RC * ldU + (size_t)r * ldU + row;
+        *d = *d + acc;
+    } else if (row < ldU + ldV) {
+        const int m = c0 + row - ldU;
+        cd acc = mk(0.0, 0.0);
+        for (int a = 0; a < NORB; ++a) fmac_(acc, ib[(size_t)m * npair + a * NORB + qc], P0[(size_t)a * RC]);
+        acc = A.h * acc;
+        for (int j = r0; j < min(m + k + 1, jend); ++j) acc = acc + Sr * (conj(gcorner(j, m)) * Uq[j - r0]);
+        cd* d = A.dV + A.Voff[b] + (size_t)q * RC * ldV + (size_t)r * ldV + (m - c0);
+        *d = *d + acc;
+    } else {
+        double acc = 0.0;
+        for (int a = 0; a < NORB; ++a) {
+            const cd p0 = P0[(size_t)a * RC], p1 = P1[(size_t)a * RC];
+            acc += p0.x * p1.x + p0.y * p1.y;
+        }
+        acc *= A.h / (Sr * Sr);
+        for (int j = r0; j < min(c1 + k, jend); ++j)
+            for (int m = max(c0, j - k); m < c1; ++m) {
+                const cd g = gcorner(j, m) * Vq[m - c0];
+                acc += Uq[j - r0].x * g.x + Uq[j - r0].y * g.y;   // Re(conj(U) g)
+            }
+        A.dS[((size_t)b * npair + q) * RC + r] += acc;
+    }
+}
+
 size_t tasks_smem(int norb, bool mfproj) {
     const int ag = norb < 4 ? norb : 4;
     size_t fact = mfproj ? (size_t)kch(norb) * kXS * sizeof(cf) : (size_t)(kch(norb) * norb + 4 * 32 * norb) * sizeof(cd);
@@ -1631,7 +1717,12 @@ hipError_t launch_t(const HistArgs& a, hipStream_t st, hipEvent_t* ev) {
     }
     if (ev) hipEventRecord(ev[2], st);
     using M = CombMap<NORB>;
-    if (mf && a.mfcomb) {
+    if (a.fgrad) {
+        // threads of the largest block: (U rows + V rows + 1) x RC x pairs
+        const long long mx = (long long)(a.nt + 1) * a.RC * NORB * NORB;
+        const int xper = (int)((mx + 255) / 256);
+        fgrad_kernel<NORB><<<dim3((unsigned)((long long)xper * a.nb), 1), 256, 0, st>>>(a, xper);
+    } else if (mf && a.mfcomb) {
         combine_mfma<<<dim3((a.n + 16) / 16, a.nk), 256, 0, st>>>(a);
     } else {
         const int nblk = (a.n + 1 + M::MW - 1) / M::MW;

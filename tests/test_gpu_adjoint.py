@@ -100,6 +100,106 @@ def test_autograd_gradient_of_weighted_loss(P):
             assert abs(fd - grad[idx, a, b]) <= 1e-6 * max(1.0, abs(fd)), (n, j, fd, grad[idx, a, b])
 
 
+def _dense_ibar(ops, wm, N, h, k):
+    """Oracle cotangents Ibar(n, m) = 2 w_m I^R(n, m) of L = sum w_m |I^R|^2, dense (N, N, norb, norb)."""
+    from oracle.history import history_R_row
+    norb = ops.sigR(0, 0).shape[-1]
+    ib = np.zeros((N, N, norb, norb), dtype=np.complex128)
+    for n in range(N):
+        ib[n, :n + 1] = 2.0 * wm[:n + 1, None, None] * history_R_row(ops, n, h, k)
+    return ib
+
+
+def _check_factor_grads(Hs, blocks, pairs, gbar_of, what):
+    """GPU factor gradients of the listed blocks against dU = Gbar V S, dV = Gbar^H U S,
+    dS = Re diag(U^H Gbar V) with the oracle's Gbar and the GPU's own factors (the factor
+    basis is not unique; the entry gradient Gbar is)."""
+    from oracle.adjoint import factor_gradients
+    import paper_2604_05319_amd as P
+    exp, got = [], []
+    for b in blocks:
+        gb = gbar_of(b)
+        for q in pairs:
+            bp, c = divmod(q, Hs.norb)
+            U, Sv, V = Hs.factors(P.RET, b, q)
+            if len(Sv) == 0:
+                continue
+            dU, dS, dV = Hs.factor_grad_get(b, q)
+            exp.append(factor_gradients(gb[:, :, bp, c], U, Sv, V))
+            got.append((dU, dS, dV))
+    assert exp, "no factors to check"
+    worst = 0.0
+    for i, name in enumerate(("dU", "dS", "dV")):
+        scale = max(np.abs(e[i]).max() for e in exp)
+        err = max(np.abs(g[i] - e[i]).max() for g, e in zip(got, exp)) / scale
+        say(f"{what}: {name} worst error / largest entry {err:.3e}")
+        worst = max(worst, err)
+    return worst
+
+
+def test_factor_gradients_match_oracle(P):
+    """dL/d(U, S, V) of every retarded block and pair for L = sum w_m |I^R|^2 over a sweep,
+    through the autograd wrapper (backward over the frozen final state), against the oracle's
+    entry gradient Gbar pushed through the GPU's factors; SR.grad against the oracle too."""
+    from oracle.adjoint import history_R_adjoint_row, history_R_G_gradient
+    from oracle.history import ArrayOperands
+    from paper_2604_05319_amd.autograd import history_R
+    norb, N, nlvl, k, h = 2, 192, 2, 5, 0.04
+    G, S = hermitian_terms(91, 5, norb), hermitian_terms(92, 5, norb)
+    GR, GL, SR, SL = host_inputs(G, S, N, h)
+    wm = np.random.default_rng(4).uniform(0.0, 1.0, N) + 1e-3
+    cols = np.concatenate([np.arange(n + 1) for n in range(N)])
+    wt = to_dev(wm[cols].reshape(-1, 1, 1).astype(np.complex128)).real
+    H = P.Hodlr(N, nlvl, norb, k=k, tol=1e-10, panel=8, max_rank=16)
+    sr = to_dev(SR).requires_grad_(True)
+    st = {}
+    I = history_R(H, to_dev(GR), sr, h, factor_grads=True, state=st)
+    ((wt * I.abs() ** 2).sum()).backward()
+    torch.cuda.synchronize()
+    Hs = st["handle"]
+    assert Hs.status() == 0 and st["factor_grads"]
+    ops = ArrayOperands(dense_from_packed(GR, N), dense_from_packed(GL, N), dense_from_packed(SR, N),
+                        dense_from_packed(SL, N))
+    say("oracle: dense cotangents and block gradients")
+    ib = _dense_ibar(ops, wm, N, h, k)
+    blocks = Hs.blocks()
+
+    def gbar_of(b):
+        _, r0, r1, c0, c1 = (int(x) for x in blocks[b])
+        return history_R_G_gradient(ops, lambda ns, m: ib[ns, m], N, h, k, range(r0, r1), range(c0, c1))
+
+    worst = _check_factor_grads(Hs, range(len(blocks)), range(norb * norb), gbar_of, "factor gradients")
+    assert worst <= 1e-9, worst
+    grad = sr.grad.detach().cpu().numpy()
+    for n in (0, 7, 47, 48, 95, 96, 150, N - 1):
+        e = row_rel_err(row(grad, n), history_R_adjoint_row(ops, n, ib[n, :n + 1], h, k))
+        assert e <= 1e-9, (n, e)
+
+
+def test_frozen_state_rows_match_oracle(P):
+    """history_R at steps below the last appended row evaluates the stored compressed
+    state (rows above n excluded) and matches the oracle's row n."""
+    from oracle.history import ArrayOperands, history_R_row
+    norb, N, nlvl, k, h = 2, 160, 3, 5, 0.03
+    G, S = hermitian_terms(93, 6, norb), hermitian_terms(94, 6, norb)
+    GR, GL, SR, SL = host_inputs(G, S, N, h)
+    H = P.Hodlr(N, nlvl, norb, k=k, tol=1e-12, panel=8, max_rank=16)
+    gGR, gSR = to_dev(GR), to_dev(SR)
+    for n in range(N - 3):   # the last rows stay unmerged (in the dense tail)
+        H.append_row(P.RET, n, row(gGR, n))
+    ops = ArrayOperands(dense_from_packed(GR, N), dense_from_packed(GL, N), dense_from_packed(SR, N),
+                        dense_from_packed(SL, N))
+    worst = 0.0
+    for n in (0, 1, 5, 19, 20, 21, 39, 40, 80, 100, 150, N - 5, N - 4):
+        out = torch.zeros((n + 1, norb, norb), dtype=torch.complex128, device="cuda")
+        H.history_R(n, row(gSR, n), h, out)
+        e = row_rel_err(out.cpu().numpy(), history_R_row(ops, n, h, k))
+        worst = max(worst, e)
+        assert e <= TOL, (n, e)
+    assert H.status() == 0
+    say("frozen-state rows worst relative error", worst)
+
+
 def test_c5_full_size_sampled(P):
     """C5 (norb = 2, N_t = 2048, leaf 64): autograd gradient of sum_m w_m |I^R|^2 on sampled rows."""
     from kbe_inputs.packed import packed_torch
@@ -117,10 +217,11 @@ def test_c5_full_size_sampled(P):
     wt = torch.as_tensor(wm, device=dev)[cols].reshape(-1, 1, 1)
     H = P.Hodlr(N, nlvl, norb, k=k, tol=cfg["tol"], panel=16, max_rank=16)
     say("gpu: c5 autograd sweep", N)
-    I = history_R(H, gGR, sr, h)
+    st = {}
+    I = history_R(H, gGR, sr, h, factor_grads=True, state=st)
     ((wt * I.abs() ** 2).sum()).backward()
     torch.cuda.synchronize()
-    assert H.status() == 0
+    assert st["handle"].status() == 0
     ops = GeneratorOperands(G, S, h)
     rng = np.random.default_rng(9)
     worst = 0.0
@@ -134,3 +235,23 @@ def test_c5_full_size_sampled(P):
             worst = max(worst, e)
             assert e <= TOL, (n, j, e)
     say("c5 adjoint worst sampled relative error", worst)
+    # factor gradients of the last block (rows N-64..N-1, columns N-128..N-65): its entry
+    # gradient needs the oracle cotangents of those steps and columns only
+    Hs = st["handle"]
+    blocks = Hs.blocks()
+    b = max(range(len(blocks)), key=lambda i: int(blocks[i][1]))   # the finest block at the end
+    _, r0, r1, c0, c1 = (int(x) for x in blocks[b])
+    say("oracle: c5 cotangents of block", b, (r0, r1, c0, c1))
+    from oracle.adjoint import history_R_G_gradient
+    from oracle.history import history_R_entry
+    ibc = {}
+    for n in range(r0, N):
+        for m in range(c0, c1):
+            ibc[n, m] = 2.0 * wm[m] * history_R_entry(ops, n, m, h, k)
+
+    def gbar_of(_b):
+        return history_R_G_gradient(ops, lambda ns, m: np.stack([ibc[int(n), m] for n in ns]), N, h, k,
+                                    range(r0, r1), range(c0, c1))
+
+    e = _check_factor_grads(Hs, [b], range(norb * norb), gbar_of, "c5 last block factor gradients")
+    assert e <= 1e-9, e
