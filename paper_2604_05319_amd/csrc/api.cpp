@@ -1291,7 +1291,7 @@ int hnessi_dense_create(hnessi_dense_t* out, int nt, int norb, int k, void* stre
         if (dev_alloc(D->al, D->L[c], (size_t)D->npair * D->trin, false) != HNESSI_OK) return nomem();
     if (dev_alloc(D->al, D->colR, (size_t)nbands * nt * D->npair, false) != HNESSI_OK ||
         dev_alloc(D->al, D->colL, (size_t)nbands * nt * D->npair, false) != HNESSI_OK ||
-        dev_alloc(D->al, D->rowL, (size_t)nbands * nt * D->npair, false) != HNESSI_OK)
+        dev_alloc(D->al, D->rowL, (size_t)dense_chunk_count(nt) * nt * D->npair, false) != HNESSI_OK)
         return nomem();
     if (hipEventCreateWithFlags(&D->ev_last, hipEventDisableTiming) != hipSuccess) {
         D->ev_last = nullptr;

@@ -15,12 +15,13 @@ struct DenseArgs {
     long long trin;      // nt(nt+1)/2
     cd* colR;            // [row band][m][npair] partial column sums (retarded)
     cd* colL;            // [row band][m][npair] partial column sums (lesser)
-    cd* rowL;            // [column band][j][npair] partial row dots (lesser output)
+    cd* rowL;            // [64-column chunk][j][npair] partial row dots (lesser output)
     cd* outR;
     cd* outL;
 };
 
-int dense_band_count(int nt);
+int dense_band_count(int nt);    // 128-row bands (column-sum partials)
+int dense_chunk_count(int nt);   // 64-column chunks (row-dot partials)
 hipError_t dense_init();
 hipError_t launch_dense_history(const DenseArgs& a, hipStream_t st, hipEvent_t* ev = nullptr);
 
