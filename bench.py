@@ -288,14 +288,29 @@ def fp32_bench(P, steps_timed=256):
     return out, sample
 
 
+def _lattice_inputs(G, S, sel, N, h, dev):
+    import torch
+    from kbe_inputs.packed import packed_torch
+    tot = N * (N + 1) // 2
+    arrs = []
+    for src, kind in ((G, "ret"), (G, "les"), (S, "ret"), (S, "les")):
+        a = torch.empty((len(sel) * tot,), dtype=torch.complex128, device=dev)
+        for o, i in enumerate(sel):
+            a[o * tot:(o + 1) * tot] = packed_torch(src[i], kind, N, h, dev).reshape(-1)
+        arrs.append(a)
+    return arrs
+
+
 def lattice_bench(P, prof_stride):
     """Batched form at the lattice workload: 32x32 momenta (nk = 1024), N_t = 2048, norb = 1,
-    one handle for all momenta; one timed sweep (append both rows, merges, history step)."""
+    one handle for all momenta, one timed launch-by-launch sweep (append both rows, merges,
+    history step) with the library's kernel events.  Graph replay (one HIP graph per window
+    between panel ends) is timed beside it on every eighth momentum (128 objects): a graph
+    sweep and a launch-by-launch sweep of the same handle geometry."""
     import ctypes as C
     import numpy as np
     import torch
     from kbe_inputs import make_config_inputs
-    from kbe_inputs.packed import packed_torch
     cfg, G, S = make_config_inputs("c3")
     N, h, k = cfg["nt"], cfg["h"], cfg["k"]
     nk = len(G)
@@ -303,12 +318,7 @@ def lattice_bench(P, prof_stride):
     tot = N * (N + 1) // 2
     dev = torch.device("cuda:0")
     t = time.perf_counter()
-    arrs = []
-    for src, kind in ((G, "ret"), (G, "les"), (S, "ret"), (S, "les")):
-        a = torch.empty((nk * tot,), dtype=torch.complex128, device=dev)
-        for o in range(nk):
-            a[o * tot:(o + 1) * tot] = packed_torch(src[o], kind, N, h, dev).reshape(-1)
-        arrs.append(a)
+    arrs = _lattice_inputs(G, S, range(nk), N, h, dev)
     torch.cuda.synchronize()
     log(f"lattice inputs: 4 x {nk} packed triangles ({4 * nk * tot * 16 / 2**30:.1f} GiB) in "
         f"{time.perf_counter() - t:.1f} s")
@@ -335,6 +345,7 @@ def lattice_bench(P, prof_stride):
     run(N)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    log(f"lattice: {N} steps of {nk} momenta in {dt:.2f} s")
     status = B.status()
     ranks = [B.ranks(P.RET), B.ranks(P.LES)]
     st0, ms0 = B.profile_read(0)
@@ -347,7 +358,33 @@ def lattice_bench(P, prof_stride):
                max_rank=int(max(r.max() for r in ranks)), device_gib=round(B.nbytes() / 2**30, 2))
     B.profile(0)
     B.close()
-    del arrs
+    del arrs, outR, outL
+    torch.cuda.empty_cache()
+    # graph replay on 128 momenta: fresh handles, one sweep each, on a side stream
+    sel = list(range(0, nk, 8))
+    arrs = _lattice_inputs(G, S, sel, N, h, dev)
+    IR = torch.empty((len(sel) * tot,), dtype=torch.complex128, device=dev)
+    IL = torch.empty_like(IR)
+    s = torch.cuda.Stream()
+    gr = {}
+    with torch.cuda.stream(s):
+        for mode, flags in (("graph", P.FLAG_GRAPHS), ("launches", 0)):
+            Bx = P.HodlrBatch(len(sel), N, nlvl, 1, k=k, tol=cfg["tol"], panel=16, max_rank=16, flags=flags)
+            s.synchronize()
+            t0 = time.perf_counter()
+            Bx.sweep(0, N, *arrs, h, IR, IL)
+            s.synchronize()
+            d = time.perf_counter() - t0
+            log(f"lattice ({len(sel)} momenta, {mode}): {N} steps in {d:.2f} s")
+            gr[mode] = round(N / d, 2)
+            if mode == "graph":
+                gr["status"] = Bx.status()
+                gr["windows"], gr["instantiations"] = Bx.graph_stats()
+            Bx.close()
+    out["graph_replay_128_momenta"] = dict(value=gr["graph"], unit="time steps/s (128 momenta)",
+                                           launch_by_launch=gr["launches"], windows=gr["windows"],
+                                           instantiations=gr["instantiations"], status=gr["status"])
+    del arrs, IR, IL
     torch.cuda.empty_cache()
     return out
 

@@ -83,6 +83,15 @@ typedef enum {
  * rows, band, singular values and all arithmetic stay FP64.  The added
  * relative error of I is about 1e-7, below 1e-5. */
 #define HNESSI_FLAG_FP32_FACTORS 1
+/* hnessi_sweep / hnessi_sweep_batched run as HIP graphs: the launches between two
+ * panel ends (appends, history kernels, the panel merges forked to and joined from
+ * their streams) are captured from the launch stream and replayed through one
+ * executable graph of the handle, updated in place window by window (instantiated
+ * anew when a window's shape differs).  The stream must not be the NULL stream.
+ * Results are identical to the launch-by-launch sweep.  (Section "Implementation
+ * details" runs one launch per k point and time step; here every momentum of a
+ * lattice is one object of a batched handle.) */
+#define HNESSI_FLAG_GRAPHS 2
 
 /* Message for the last failing call on this host thread (never NULL). */
 const char* hnessi_last_error(void);
@@ -135,7 +144,7 @@ int hnessi_weights(int k, int L, double* w_host);
  *            every leaf start, so it need not divide the leaf size.
  *   max_rank rank capacity per block and orbital pair; max_rank + panel <= 48
  *            (the width of the small SVD solved at each merge).
- *   flags    HNESSI_FLAG_NONE or HNESSI_FLAG_FP32_FACTORS.
+ *   flags    HNESSI_FLAG_NONE, or HNESSI_FLAG_FP32_FACTORS and/or HNESSI_FLAG_GRAPHS.
  *   stream   every allocation, fill and copy of the handle is ordered on it;
  *            the call returns once they are complete.
  * On success *out is set.  HNESSI_E_ARG for an argument out of range,
@@ -146,6 +155,10 @@ int hnessi_hodlr_create(hnessi_hodlr_t* out, int nt, int nlvl, int norb, int k,
 /* Wait for the handle's work (its last call's stream and its merge stream),
  * then return its memory through the hook it was created with. */
 int hnessi_hodlr_destroy(hnessi_hodlr_t H);
+
+/* Graph windows replayed by the handle's sweeps so far and how many of them needed a
+ * new instantiation (HNESSI_FLAG_GRAPHS; both zero otherwise). */
+int hnessi_hodlr_graph_stats(hnessi_hodlr_t H, long long* windows, long long* instantiations);
 
 /* Forget all rows and the device status flags (start a new sweep from
  * n = 0); storage is kept.  Enqueued on stream. */

@@ -3,5 +3,5 @@
 The compute path is the HIP library libhnessi.so (C ABI in include/hnessi.h);
 this package only marshals arguments to it.
 """
-from ._lib import (RET, LES, FLAG_FP32_FACTORS, Dense, Hodlr, HodlrBatch, HnessiError, compress_block,  # noqa: F401
+from ._lib import (RET, LES, FLAG_FP32_FACTORS, FLAG_GRAPHS, Dense, Hodlr, HodlrBatch, HnessiError, compress_block,  # noqa: F401
                    exported_names, lib, weights, LIB_PATH, set_allocator, use_torch_allocator)

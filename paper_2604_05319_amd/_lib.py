@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libhnessi.so")
 
 RET, LES = 0, 1
 FLAG_FP32_FACTORS = 1   # U, V stored as complex float
+FLAG_GRAPHS = 2         # sweeps replayed as HIP graphs, one per window between panel ends
 
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_ORDER", -3: "E_RANGE", -4: "E_NOMEM", -5: "E_DEVICE",
           -6: "E_RANK", -7: "E_VALUE"}
@@ -66,6 +67,7 @@ _SIGS = {
                              C.c_void_p, C.c_void_p], C.c_int),
     "hnessi_sweep": ([C.c_void_p, C.c_int, C.c_int] + [C.c_void_p] * 4 + [C.c_double]
                      + [C.c_void_p] * 3, C.c_int),
+    "hnessi_hodlr_graph_stats": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "hnessi_hodlr_status": ([C.c_void_p, C.c_void_p], C.c_int),
     "hnessi_hodlr_get": ([C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p], C.c_int),
     "hnessi_hodlr_ranks": ([C.c_void_p, C.c_int, C.c_void_p, C.c_int], C.c_int),
@@ -273,6 +275,12 @@ class Hodlr:
         _check(lib().hnessi_sweep(self.h, n_begin, n_end, _ptr(GR), _ptr(GL), _ptr(SR), _ptr(SL), h,
                                   _ptr(IR), _ptr(IL), _stream()))
 
+    def graph_stats(self):
+        """(windows replayed as graphs, instantiations) of this handle's sweeps."""
+        w, i = C.c_longlong(0), C.c_longlong(0)
+        _check(lib().hnessi_hodlr_graph_stats(self.h, C.byref(w), C.byref(i)))
+        return w.value, i.value
+
     def status(self):
         return _check(lib().hnessi_hodlr_status(self.h, _stream()))
 
@@ -326,7 +334,7 @@ class HodlrBatch(Hodlr):
         self.h = h
         self.nk = nk
         self.nt, self.nlvl, self.norb, self.k = nt, nlvl, norb, k
-        self.tol, self.panel, self.max_rank = tol, panel, max_rank
+        self.tol, self.panel, self.max_rank, self.flags = tol, panel, max_rank, flags
 
     def append_row(self, comp, n, rows, k_stride):
         _check(lib().hnessi_hodlr_append_row_batched(self.h, comp, n, _ptr(rows), k_stride, _stream()))

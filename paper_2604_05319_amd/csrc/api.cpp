@@ -73,7 +73,8 @@ struct Prof {
         }
         return pool[used++];
     }
-    bool want(int n) const { return stride > 0 && n % stride == 0; }
+    bool capturing = false;   // a graph capture is open: no timing events
+    bool want(int n) const { return !capturing && stride > 0 && n % stride == 0; }
     void clear() {
         recs.clear();
         used = 0;
@@ -215,6 +216,14 @@ struct hnessi_hodlr_s {
     cd* dU = nullptr;
     cd* dV = nullptr;
     double* dS = nullptr;
+    // sweeps as graphs (HNESSI_FLAG_GRAPHS): launches between two panel ends are captured
+    // from the launch stream (the merges fork to and join from their streams inside the
+    // window) and replayed through one executable graph, updated window by window
+    struct Graph {
+        bool on = false;       // a sweep in graph mode is running (a capture is open)
+        hipGraphExec_t exec = nullptr;
+        long long windows = 0, instantiations = 0;
+    } graph;
     int ntailchunk_max = 0;
     // merge scratch
     std::vector<long long> lvl_node_base;  // per level: first node of pair 0
@@ -312,7 +321,7 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
     if (!out) return fail(HNESSI_E_ARG, "out is NULL");
     *out = nullptr;
     if (nk < 1 || nk > 65535) return fail(HNESSI_E_ARG, "nk must be in 1..65535");
-    if (flags & ~HNESSI_FLAG_FP32_FACTORS) return fail(HNESSI_E_ARG, "unknown flags");
+    if (flags & ~(HNESSI_FLAG_FP32_FACTORS | HNESSI_FLAG_GRAPHS)) return fail(HNESSI_E_ARG, "unknown flags");
     if (!(norb == 1 || norb == 2 || norb == 4 || norb == 8 || norb == 16))
         return fail(HNESSI_E_ARG, "norb must be 1, 2, 4, 8 or 16");
     if (!(svd_tol > 0.0)) return fail(HNESSI_E_ARG, "svd_tol must be > 0");
@@ -556,10 +565,18 @@ int hnessi_hodlr_destroy(hnessi_hodlr_t H) {
     const int rc = wait_handle(H);
     release_streams(H);
     H->prof.release();
+    if (H->graph.exec) (void)hipGraphExecDestroy(H->graph.exec);
     H->al.release(false);
     if (H->ev_last) hipEventDestroy(H->ev_last);
     delete H;
     return rc;
+}
+
+int hnessi_hodlr_graph_stats(hnessi_hodlr_t H, long long* windows, long long* instantiations) {
+    if (!H || !windows || !instantiations) return fail(HNESSI_E_ARG, "NULL argument");
+    *windows = H->graph.windows;
+    *instantiations = H->graph.instantiations;
+    return HNESSI_OK;
 }
 
 int hnessi_hodlr_reset(hnessi_hodlr_t H, void* stream) {
@@ -665,7 +682,7 @@ int merge_panel(hnessi_hodlr_t H, int c, int p0, int p1, hipStream_t st, std::ve
     a.nblk = nblk;
     a.ntask_v = nv;
     a.ntask_u = nu;
-    const bool timed = H->prof.stride > 0;
+    const bool timed = H->prof.stride > 0 && !H->prof.capturing;
     hipEvent_t e0 = timed ? H->prof.ev() : nullptr, e1 = timed ? H->prof.ev() : nullptr;
     if (e0) hipEventRecord(e0, st);
     HIP_TRY(launch_merge(a, H->nk, st));
@@ -893,15 +910,10 @@ int check_append(hnessi_hodlr_t H, int c, int n, const void* row) {
     return HNESSI_OK;
 }
 
-// after row n of component c is appended: when it completes a panel, the previous
-// panel's merge becomes current and this panel's merge is launched
-int after_append(hnessi_hodlr_t H, int c, int n, hipStream_t st) {
-    H->last[c] = n;
-    if (!panel_ends(H, c, n)) return HNESSI_OK;
+// this panel's merge (rows fstart..n of component c) is launched on the merge stream
+int launch_panel(hnessi_hodlr_t H, int c, int n, hipStream_t st) {
     const int p0 = H->fstart[c], p1 = n + 1;
-    // the previous panel's merge becomes current for everything queued from here on
-    int rc = finish_pending(H, c, st);
-    if (rc != HNESSI_OK) return rc;
+    int rc = HNESSI_OK;
     // this panel's merge runs on the merge stream after the work queued so far on st
     // and writes the blocks' other buffers; until the next panel ends, the history
     // kernels read the panel's rows from the dense tail
@@ -915,6 +927,52 @@ int after_append(hnessi_hodlr_t H, int c, int n, hipStream_t st) {
     pd.p0 = p0;
     pd.p1 = p1;
     H->fstart[c] = p1;
+    return HNESSI_OK;
+}
+
+// after row n of component c is appended: when it completes a panel, the previous
+// panel's merge becomes current and this panel's merge is launched
+int after_append(hnessi_hodlr_t H, int c, int n, hipStream_t st) {
+    H->last[c] = n;
+    if (!panel_ends(H, c, n)) return HNESSI_OK;
+    // the previous panel's merge becomes current for everything queued from here on
+    int rc = finish_pending(H, c, st);
+    return rc != HNESSI_OK ? rc : launch_panel(H, c, n, st);
+}
+
+// Close the open capture on st, run it through the handle's executable graph (updated
+// in place when the window has the same shape as the last one, instantiated anew
+// otherwise) and, with reopen, open the next window.
+int graph_window(hnessi_hodlr_t H, hipStream_t st, bool reopen = true) {
+    hipGraph_t g = nullptr;
+    H->graph.on = false;
+    HIP_TRY(hipStreamEndCapture(st, &g));
+    bool ok = false;
+    if (H->graph.exec) {
+        hipGraphNode_t bad = nullptr;
+        hipGraphExecUpdateResult res;
+        ok = hipGraphExecUpdate(H->graph.exec, g, &bad, &res) == hipSuccess && res == hipGraphExecUpdateSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            (void)hipGraphExecDestroy(H->graph.exec);
+            H->graph.exec = nullptr;
+        }
+    }
+    if (!ok) {
+        if (hipGraphInstantiate(&H->graph.exec, g, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            H->graph.exec = nullptr;
+            return fail(HNESSI_E_DEVICE, "graph instantiation failed");
+        }
+        ++H->graph.instantiations;
+    }
+    (void)hipGraphDestroy(g);
+    HIP_TRY(hipGraphLaunch(H->graph.exec, st));
+    ++H->graph.windows;
+    if (reopen) {
+        HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        H->graph.on = true;
+    }
     return HNESSI_OK;
 }
 
@@ -932,9 +990,27 @@ int append2_impl(hnessi_hodlr_t H, int n, const void* rowR, const void* rowL, lo
     if (rc != HNESSI_OK) return rc;
     HIP_TRY(launch_append_hodlr2(append_args(H, HNESSI_RET, n, rowR, k_stride),
                                  append_args(H, HNESSI_LES, n, rowL, k_stride), H->nk, st));
-    rc = after_append(H, HNESSI_RET, n, st);
+    if (!H->graph.on) {
+        rc = after_append(H, HNESSI_RET, n, st);
+        if (rc != HNESSI_OK) return rc;
+        return after_append(H, HNESSI_LES, n, st);
+    }
+    // graph windows: both components' panels end at the same rows; the previous merges
+    // are joined, the window's graph is launched, and the next window opens with the
+    // new merges
+    H->last[0] = H->last[1] = n;
+    if (!panel_ends(H, HNESSI_RET, n)) return HNESSI_OK;
+    for (int c = 0; c < 2; ++c) {
+        rc = finish_pending(H, c, st);
+        if (rc != HNESSI_OK) return rc;
+    }
+    rc = graph_window(H, st);
     if (rc != HNESSI_OK) return rc;
-    return after_append(H, HNESSI_LES, n, st);
+    for (int c = 0; c < 2; ++c) {
+        rc = launch_panel(H, c, n, st);
+        if (rc != HNESSI_OK) return rc;
+    }
+    return HNESSI_OK;
 }
 
 int single_only(hnessi_hodlr_t H) {
@@ -1049,10 +1125,8 @@ int hnessi_history_step_batched(hnessi_hodlr_t H, int n, const void* sigR_rows, 
 
 namespace {
 
-int sweep_impl(hnessi_hodlr_t H, int n_begin, int n_end, const void* GR, const void* GL, const void* SR,
-               const void* SL, long long k_stride, double h, void* IR, void* IL, hipStream_t st) {
-    if (!GR || !GL || !SR || !SL || !IR || !IL) return fail(HNESSI_E_ARG, "NULL array");
-    if (n_begin < 0 || n_end > H->nt || n_begin > n_end) return fail(HNESSI_E_RANGE, "bad sweep range");
+int sweep_steps(hnessi_hodlr_t H, int n_begin, int n_end, const void* GR, const void* GL, const void* SR,
+                const void* SL, long long k_stride, double h, void* IR, void* IL, hipStream_t st) {
     const size_t np = H->npair;
     for (int n = n_begin; n < n_end; ++n) {
         const size_t off = (size_t)tri(n) * np;
@@ -1063,6 +1137,36 @@ int sweep_impl(hnessi_hodlr_t H, int n_begin, int n_end, const void* GR, const v
         if (rc != HNESSI_OK) return rc;
     }
     return HNESSI_OK;
+}
+
+int sweep_impl(hnessi_hodlr_t H, int n_begin, int n_end, const void* GR, const void* GL, const void* SR,
+               const void* SL, long long k_stride, double h, void* IR, void* IL, hipStream_t st) {
+    if (!GR || !GL || !SR || !SL || !IR || !IL) return fail(HNESSI_E_ARG, "NULL array");
+    if (n_begin < 0 || n_end > H->nt || n_begin > n_end) return fail(HNESSI_E_RANGE, "bad sweep range");
+    if (!(H->flags & HNESSI_FLAG_GRAPHS) || n_begin == n_end)
+        return sweep_steps(H, n_begin, n_end, GR, GL, SR, SL, k_stride, h, IR, IL, st);
+    if (!st) return fail(HNESSI_E_ARG, "graph sweeps need a stream other than the NULL stream");
+    // merges launched before the sweep are joined outside the capture
+    for (int c = 0; c < 2; ++c) {
+        int rc = finish_pending(H, c, st);
+        if (rc != HNESSI_OK) return rc;
+    }
+    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    H->graph.on = true;
+    H->prof.capturing = true;
+    int rc = sweep_steps(H, n_begin, n_end, GR, GL, SR, SL, k_stride, h, IR, IL, st);
+    // the last window joins its merges before the capture closes
+    for (int c = 0; c < 2 && rc == HNESSI_OK; ++c) rc = finish_pending(H, c, st);
+    if (rc == HNESSI_OK) rc = graph_window(H, st, false);
+    if (H->graph.on) {   // an error left the capture open: discard it
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(st, &g);
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+    }
+    H->graph.on = false;
+    H->prof.capturing = false;
+    return rc;
 }
 
 }  // namespace

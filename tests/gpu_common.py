@@ -116,3 +116,12 @@ def check_entries(label, got_R, got_L, ref, tol):
         assert eL <= tol, (label, "L", n, eL)
     say(label, "worst sampled relative error", worst)
     return worst
+
+
+def oracle_entries_multi(jobs, workers=16):
+    """Oracle I^R(n, m) and I^<(n, m) for a list of (G, S, h, k, n, [m, ...]) jobs of possibly
+    different objects, one spawned pool for all; returns one list of (R, L) per job."""
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers) as pool:
+        return pool.map(_entry_worker, jobs)

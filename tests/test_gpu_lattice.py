@@ -107,14 +107,64 @@ def test_batched_argument_errors(P):
     B.append_row(P.RET, 0, row, 128)
 
 
+def _graph_stream():
+    """Graph sweeps are captured from a stream other than the NULL stream."""
+    return torch.cuda.Stream()
+
+
+def test_graph_sweep_matches_launches(P):
+    """A sweep replayed as graphs (one window per panel, merges forked and joined inside)
+    gives the launch-by-launch results bit for bit, twice in a row with eager work and
+    synchronizations between the two, and from a partial sweep continued in graph mode."""
+    cfg, G, S = make_config_inputs("c3")
+    sel = [1, 200, 640, 1000]
+    N, h, k, nlvl = 192, cfg["h"], cfg["k"], 2
+    tot = N * (N + 1) // 2
+    inps = [host_inputs(G[i], S[i], N, h) for i in sel]
+    stacked = [to_dev(np.concatenate([inp[j] for inp in inps])) for j in range(4)]
+    ref = []
+    Be = P.HodlrBatch(len(sel), N, nlvl, 1, k=k, tol=cfg["tol"], panel=16, max_rank=16)
+    IR, IL = _zeros(len(sel) * tot), _zeros(len(sel) * tot)
+    Be.sweep(0, N, *stacked, h, IR, IL)
+    torch.cuda.synchronize()
+    ref = (IR.cpu().numpy(), IL.cpu().numpy(), Be.ranks(P.RET))
+    s = _graph_stream()
+    with torch.cuda.stream(s):
+        Bg = P.HodlrBatch(len(sel), N, nlvl, 1, k=k, tol=cfg["tol"], panel=16, max_rank=16, flags=P.FLAG_GRAPHS)
+        for rep in range(2):
+            IRg, ILg = _zeros(len(sel) * tot), _zeros(len(sel) * tot)
+            Bg.reset()
+            if rep == 0:
+                Bg.sweep(0, N, *stacked, h, IRg, ILg)
+            else:   # the first rows launch by launch through the single-step calls, then graphs
+                for n in range(40):
+                    off = n * (n + 1) // 2
+                    Bg.append_row(P.RET, n, stacked[0][off:], tot)
+                    Bg.append_row(P.LES, n, stacked[1][off:], tot)
+                    Bg.history_step(n, stacked[2][off:], stacked[3][off:], tot, h, IRg[off:], ILg[off:], tot)
+                Bg.sweep(40, N, *stacked, h, IRg, ILg)
+            s.synchronize()
+            junk = torch.randn(1 << 20, device="cuda").sum().item()   # eager work between replays
+            assert np.isfinite(junk)
+            assert np.array_equal(IRg.cpu().numpy(), ref[0]), rep
+            assert np.array_equal(ILg.cpu().numpy(), ref[1]), rep
+            assert np.array_equal(Bg.ranks(P.RET), ref[2]), rep
+        assert Bg.status() == 0
+    windows, inst = Bg.graph_stats()
+    say("graph windows", windows, "instantiations", inst)
+    assert windows >= 2 * (N // 16) - 2 and inst < windows
+
+
 def test_c3_full_size_sampled(P):
-    """C3 geometry (N_t = 2048, leaf 64, norb = 1) on 32 of the 1024 momenta, sampled entries."""
+    """C3 geometry (N_t = 2048, leaf 64, norb = 1) on 128 of the 1024 momenta (every eighth),
+    swept as graphs; sampled entries against the oracle, scaled by the oracle's largest
+    sampled entry of the row."""
     from kbe_inputs.packed import packed_torch
-    from oracle.history import GeneratorOperands, history_lesser_entry, history_R_entry
+    from gpu_common import oracle_entries_multi
     cfg, G, S = make_config_inputs("c3")
     N, h, k = cfg["nt"], cfg["h"], cfg["k"]
     nlvl = int(round(np.log2(N // cfg["leaf"])))
-    sel = list(range(0, 1024, 32))
+    sel = list(range(0, 1024, 8))
     tot = N * (N + 1) // 2
     dev = torch.device("cuda:0")
     arrs = []
@@ -124,23 +174,31 @@ def test_c3_full_size_sampled(P):
             a[o * tot:(o + 1) * tot] = packed_torch(src[i], kind, N, h, dev)
         arrs.append(a)
     IR, IL = torch.empty_like(arrs[0]), torch.empty_like(arrs[0])
-    B = P.HodlrBatch(len(sel), N, nlvl, 1, k=k, tol=cfg["tol"], panel=16, max_rank=16)
-    say("gpu: c3 batched sweep", len(sel), N)
-    B.sweep(0, N, *arrs, h, IR, IL)
     torch.cuda.synchronize()
-    assert B.status() == 0
+    s = _graph_stream()
+    with torch.cuda.stream(s):
+        B = P.HodlrBatch(len(sel), N, nlvl, 1, k=k, tol=cfg["tol"], panel=16, max_rank=16, flags=P.FLAG_GRAPHS)
+        say("gpu: c3 batched graph sweep", len(sel), N)
+        B.sweep(0, N, *arrs, h, IR, IL)
+        s.synchronize()
+        assert B.status() == 0
     rng = np.random.default_rng(77)
-    worst = 0.0
+    jobs, where = [], []
     for o, i in enumerate(sel):
-        ops = GeneratorOperands(G[i], S[i], h)
-        rows = sorted(set([0, 5, 63, 64, 1023, 1024, N - 1] + list(rng.integers(0, N, 2))))
-        for n in rows:
-            a = o * tot + n * (n + 1) // 2
-            gR, gL = IR[a:a + n + 1].cpu().numpy(), IL[a:a + n + 1].cpu().numpy()
-            sR, sL = np.abs(gR).max(), np.abs(gL).max()
-            for m in sorted(set(x for x in [0, 1, n - 5, n] + list(rng.integers(0, n + 1, 2)) if 0 <= x <= n)):
-                eR = np.abs(gR[m] - history_R_entry(ops, n, m, h, k)).max() / max(sR, 1e-300)
-                eL = np.abs(gL[m] - history_lesser_entry(ops, n, m, h, k)).max() / max(sL, 1e-300)
-                worst = max(worst, eR, eL)
-                assert eR <= TOL and eL <= TOL, (i, n, m, eR, eL)
-    say("c3 worst sampled relative error", worst)
+        for n in sorted(set([63, 1024, N - 1] + list(rng.integers(0, N, 1)))):
+            ms = sorted(set(x for x in [0, 1, 64, n - 5, n] + list(rng.integers(0, n + 1, 2)) if 0 <= x <= n))
+            jobs.append((G[i], S[i], h, k, int(n), ms))
+            where.append((o, int(n), ms))
+    say("oracle:", len(jobs), "rows of sampled entries")
+    res = oracle_entries_multi(jobs)
+    worst = 0.0
+    for (o, n, ms), vals in zip(where, res):
+        a = o * tot + n * (n + 1) // 2
+        gR, gL = IR[a:a + n + 1].cpu().numpy(), IL[a:a + n + 1].cpu().numpy()
+        oR, oL = np.stack([v[0] for v in vals]), np.stack([v[1] for v in vals])
+        sR, sL = np.abs(oR).max(), np.abs(oL).max()
+        eR = np.abs(gR[ms] - oR).max() / max(sR, 1e-300)
+        eL = np.abs(gL[ms] - oL).max() / max(sL, 1e-300)
+        worst = max(worst, eR, eL)
+        assert eR <= TOL and eL <= TOL, (sel[o], n, eR, eL)
+    say("c3 worst sampled relative error (128 momenta)", worst)
