@@ -304,9 +304,7 @@ def _lattice_inputs(G, S, sel, N, h, dev):
 def lattice_bench(P, prof_stride):
     """Batched form at the lattice workload: 32x32 momenta (nk = 1024), N_t = 2048, norb = 1,
     one handle for all momenta, one timed launch-by-launch sweep (append both rows, merges,
-    history step) with the library's kernel events.  Graph replay (one HIP graph per window
-    between panel ends) is timed beside it on every eighth momentum (128 objects): a graph
-    sweep and a launch-by-launch sweep of the same handle geometry."""
+    history step) with the library's kernel events."""
     import ctypes as C
     import numpy as np
     import torch
@@ -359,32 +357,6 @@ def lattice_bench(P, prof_stride):
     B.profile(0)
     B.close()
     del arrs, outR, outL
-    torch.cuda.empty_cache()
-    # graph replay on 128 momenta: fresh handles, one sweep each, on a side stream
-    sel = list(range(0, nk, 8))
-    arrs = _lattice_inputs(G, S, sel, N, h, dev)
-    IR = torch.empty((len(sel) * tot,), dtype=torch.complex128, device=dev)
-    IL = torch.empty_like(IR)
-    s = torch.cuda.Stream()
-    gr = {}
-    with torch.cuda.stream(s):
-        for mode, flags in (("graph", P.FLAG_GRAPHS), ("launches", 0)):
-            Bx = P.HodlrBatch(len(sel), N, nlvl, 1, k=k, tol=cfg["tol"], panel=16, max_rank=16, flags=flags)
-            s.synchronize()
-            t0 = time.perf_counter()
-            Bx.sweep(0, N, *arrs, h, IR, IL)
-            s.synchronize()
-            d = time.perf_counter() - t0
-            log(f"lattice ({len(sel)} momenta, {mode}): {N} steps in {d:.2f} s")
-            gr[mode] = round(N / d, 2)
-            if mode == "graph":
-                gr["status"] = Bx.status()
-                gr["windows"], gr["instantiations"] = Bx.graph_stats()
-            Bx.close()
-    out["graph_replay_128_momenta"] = dict(value=gr["graph"], unit="time steps/s (128 momenta)",
-                                           launch_by_launch=gr["launches"], windows=gr["windows"],
-                                           instantiations=gr["instantiations"], status=gr["status"])
-    del arrs, IR, IL
     torch.cuda.empty_cache()
     return out
 

@@ -112,6 +112,12 @@ def _graph_stream():
     return torch.cuda.Stream()
 
 
+GRAPH_SKIP = ("graph sweeps passed this test and the 128-momentum C3 test once, but a graph sweep run "
+              "inside the lattice benchmark stopped producing output for 180 s (twice, at 1024 and at 128 "
+              "momenta) without a cause found; kept off the GPU until one is")
+
+
+@pytest.mark.skip(reason=GRAPH_SKIP)
 def test_graph_sweep_matches_launches(P):
     """A sweep replayed as graphs (one window per panel, merges forked and joined inside)
     gives the launch-by-launch results bit for bit, twice in a row with eager work and
@@ -155,10 +161,11 @@ def test_graph_sweep_matches_launches(P):
     assert windows >= 2 * (N // 16) - 2 and inst < windows
 
 
-def test_c3_full_size_sampled(P):
+@pytest.mark.parametrize("graphs", [False, pytest.param(True, marks=pytest.mark.skip(reason=GRAPH_SKIP))])
+def test_c3_full_size_sampled(P, graphs):
     """C3 geometry (N_t = 2048, leaf 64, norb = 1) on 128 of the 1024 momenta (every eighth),
-    swept as graphs; sampled entries against the oracle, scaled by the oracle's largest
-    sampled entry of the row."""
+    launch by launch or swept as graphs; sampled entries against the oracle, scaled by the
+    oracle's largest sampled entry of the row."""
     from kbe_inputs.packed import packed_torch
     from gpu_common import oracle_entries_multi
     cfg, G, S = make_config_inputs("c3")
@@ -177,8 +184,9 @@ def test_c3_full_size_sampled(P):
     torch.cuda.synchronize()
     s = _graph_stream()
     with torch.cuda.stream(s):
-        B = P.HodlrBatch(len(sel), N, nlvl, 1, k=k, tol=cfg["tol"], panel=16, max_rank=16, flags=P.FLAG_GRAPHS)
-        say("gpu: c3 batched graph sweep", len(sel), N)
+        B = P.HodlrBatch(len(sel), N, nlvl, 1, k=k, tol=cfg["tol"], panel=16, max_rank=16,
+                         flags=P.FLAG_GRAPHS if graphs else 0)
+        say("gpu: c3 batched sweep", len(sel), N, "graphs" if graphs else "launches")
         B.sweep(0, N, *arrs, h, IR, IL)
         s.synchronize()
         assert B.status() == 0
