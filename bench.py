@@ -322,7 +322,15 @@ def lattice_bench(P, prof_stride):
         f"{time.perf_counter() - t:.1f} s")
     outR = torch.empty((nk, N), dtype=torch.complex128, device=dev)
     outL = torch.empty_like(outR)
-    B = P.HodlrBatch(nk, N, nlvl, 1, k=k, tol=cfg["tol"], panel=16, max_rank=16)
+    from paper_2604_05319_amd.autotune import load as load_tuning
+    tun = load_tuning().get("c3")
+    lpanel = int(tun["panel"]) if tun else 16
+    if tun:
+        P.set_tile_shape(1, int(tun["proj_rows"]))
+    B = P.HodlrBatch(nk, N, nlvl, 1, k=k, tol=cfg["tol"], panel=lpanel, max_rank=16)
+    P.set_tile_shape(1, 0)
+    ltuning = dict(panel=lpanel, proj_rows=B.tile_shape(),
+                   source="autotuner (paper_2604_05319_amd/tuning.json)" if tun else "built-in defaults")
     L, chk, st = P.lib(), P._lib._check, P._lib._stream()
     ptr = [a.data_ptr() for a in arrs]
     oR, oL = C.c_void_p(outR.data_ptr()), C.c_void_p(outL.data_ptr())
@@ -353,7 +361,8 @@ def lattice_bench(P, prof_stride):
                sweep_s=round(dt, 3), status=status,
                hist_tasks_gbs=round(float(b_tasks.sum() / (ms0.sum() * 1e-3) / 1e9), 1),
                hist_combine_gbs=round(float(b_comb.sum() / (ms1.sum() * 1e-3) / 1e9), 1),
-               max_rank=int(max(r.max() for r in ranks)), device_gib=round(B.nbytes() / 2**30, 2))
+               max_rank=int(max(r.max() for r in ranks)), device_gib=round(B.nbytes() / 2**30, 2),
+               tuning=ltuning)
     B.profile(0)
     B.close()
     del arrs, outR, outL
@@ -454,7 +463,17 @@ def main():
     torch.cuda.synchronize()
     log(f"inputs: 4 packed triangles of {GR.numel() * 16 / 2**30:.1f} GiB in {time.perf_counter() - t:.1f} s")
 
+    # tile shape and panel height chosen by the project's autotuner for this workload, if it
+    # has been run (paper_2604_05319_amd/tuning.json); the built-in defaults otherwise
+    from paper_2604_05319_amd.autotune import load as load_tuning
+    tun = load_tuning().get("c2")
+    if tun:
+        panel = int(tun["panel"])
+        P.set_tile_shape(norb, int(tun["proj_rows"]))
     H = P.Hodlr(N, nlvl, norb, k=k, tol=cfg["tol"], panel=panel, max_rank=max_rank)
+    P.set_tile_shape(norb, 0)
+    tuning = dict(panel=panel, proj_rows=H.tile_shape(),
+                  source="autotuner (paper_2604_05319_amd/tuning.json)" if tun else "built-in defaults")
 
     def sweep(obj):
         obj.reset()
@@ -583,7 +602,7 @@ def main():
                                f"8+8 Hermitian damped-exponential generators; a step is one time step "
                                f"(append the R and < rows, their merges, I^R and I^< of the row); "
                                f"the timed region is `sweeps` sweeps of N_t steps",
-                   "n_t": N, "norb": norb, "step_unit": "time step"},
+                   "n_t": N, "norb": norb, "step_unit": "time step", "tuning": tuning},
         "roofline": roof,
         "kernels": kernels,
         "dense": dense,

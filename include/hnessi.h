@@ -118,6 +118,18 @@ typedef void* (*hnessi_alloc_fn)(size_t bytes, void* stream, void* ctx);
 typedef void (*hnessi_free_fn)(void* ptr, void* stream, void* ctx);
 int hnessi_set_allocator(hnessi_alloc_fn alloc, hnessi_free_fn free_fn, void* ctx);
 
+/* Tile shape of handles created after this call, for one norb: the factor rows
+ * of one projection task of the history kernels (and of one partial slot), 0 for
+ * the built-in default (1024 for norb <= 2, 512 for norb 4, 256 above).  Allowed:
+ * 256, 512, 1024 for norb <= 4; 128, 256 for norb 8 and 16; other values give
+ * HNESSI_E_ARG.  Results do not depend on it beyond the order of floating-point
+ * sums; it exists for the project's autotuner, which times the candidates on the
+ * target workload and records its choice.  Process-wide, thread-safe. */
+int hnessi_set_tile_shape(int norb, int proj_rows);
+
+/* The projection chunk rows a handle was created with. */
+int hnessi_get_tile_shape(hnessi_hodlr_t H);
+
 /* Interval quadrature weights w^{(L)}_i, i = 0..L, for Gregory order k (1..5),
  * written to w_host[0..L] (host).  Appendix "Integral and derivative
  * approximations".  Returns HNESSI_E_ARG for k outside 1..5 or L < 0. */

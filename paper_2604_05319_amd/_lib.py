@@ -67,6 +67,8 @@ _SIGS = {
                              C.c_void_p, C.c_void_p], C.c_int),
     "hnessi_sweep": ([C.c_void_p, C.c_int, C.c_int] + [C.c_void_p] * 4 + [C.c_double]
                      + [C.c_void_p] * 3, C.c_int),
+    "hnessi_set_tile_shape": ([C.c_int, C.c_int], C.c_int),
+    "hnessi_get_tile_shape": ([C.c_void_p], C.c_int),
     "hnessi_hodlr_graph_stats": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "hnessi_hodlr_status": ([C.c_void_p, C.c_void_p], C.c_int),
     "hnessi_hodlr_get": ([C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p], C.c_int),
@@ -194,6 +196,11 @@ def use_torch_allocator():
     set_allocator(_alloc, _free)
 
 
+def set_tile_shape(norb, proj_rows):
+    """Projection chunk rows of handles created from now on (0: default)."""
+    _check(lib().hnessi_set_tile_shape(norb, proj_rows))
+
+
 def weights(k: int, L: int) -> np.ndarray:
     w = np.zeros(L + 1, dtype=np.float64)
     _check(lib().hnessi_weights(k, L, w.ctypes.data_as(C.c_void_p)))
@@ -274,6 +281,10 @@ class Hodlr:
     def sweep(self, n_begin, n_end, GR, GL, SR, SL, h, IR, IL):
         _check(lib().hnessi_sweep(self.h, n_begin, n_end, _ptr(GR), _ptr(GL), _ptr(SR), _ptr(SL), h,
                                   _ptr(IR), _ptr(IL), _stream()))
+
+    def tile_shape(self):
+        """Projection chunk rows of this handle."""
+        return _check(lib().hnessi_get_tile_shape(self.h))
 
     def graph_stats(self):
         """(windows replayed as graphs, instantiations) of this handle's sweeps."""

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -45,6 +46,9 @@ void default_free(void* p, void* stream, void*) { (void)hipFreeAsync(p, (hipStre
 hnessi_alloc_fn g_alloc = default_alloc;
 hnessi_free_fn g_free = default_free;
 void* g_alloc_ctx = nullptr;
+// projection chunk rows of handles created from now on, by norb (0: the built-in default)
+std::mutex g_tile_mu;
+int g_proj_rows[17] = {};
 
 #define ALLOC(al, p, n, z)                                                                     \
     do {                                                                                       \
@@ -171,6 +175,7 @@ struct hnessi_hodlr_s {
     bool mfproj = false; // norb 16, complex-float factors, rank capacity <= 16: projections
                          // on the matrix cores (task per block, factor, chunk, orbital beta)
     bool mfcomb = false; // and leaves starting at multiples of 16: matrix-core expansions
+    int kch = 0;         // factor rows per projection chunk
     cd* U[2] = {};       // FP64 factors (merges, reconstruction)
     cd* V[2] = {};
     cf* U32[2] = {};     // mirrors, or nullptr
@@ -259,6 +264,21 @@ struct hnessi_dense_s {
 extern "C" {
 
 const char* hnessi_last_error(void) { return g_err.c_str(); }
+
+int hnessi_set_tile_shape(int norb, int proj_rows) {
+    if (!(norb == 1 || norb == 2 || norb == 4 || norb == 8 || norb == 16))
+        return fail(HNESSI_E_ARG, "norb must be 1, 2, 4, 8 or 16");
+    if (!kch_allowed(norb, proj_rows))
+        return fail(HNESSI_E_ARG, "projection chunk rows: 0, 256, 512 or 1024 for norb <= 4; 0, 128 or 256 above");
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    g_proj_rows[norb] = proj_rows;
+    return HNESSI_OK;
+}
+
+int hnessi_get_tile_shape(hnessi_hodlr_t H) {
+    if (!H) return fail(HNESSI_E_ARG, "handle is NULL");
+    return H->kch;
+}
 
 int hnessi_set_allocator(hnessi_alloc_fn alloc, hnessi_free_fn free_fn, void* ctx) {
     if ((alloc == nullptr) != (free_fn == nullptr))
@@ -356,6 +376,10 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
     H->flags = flags;
     H->f32 = (flags & HNESSI_FLAG_FP32_FACTORS) != 0;
     H->mfproj = H->f32 && norb == 16 && max_rank <= 16;
+    {
+        std::lock_guard<std::mutex> lk(g_tile_mu);
+        H->kch = g_proj_rows[norb] ? g_proj_rows[norb] : kch(norb);
+    }
     H->mfcomb = H->mfproj;
     for (int i = 0; i < H->g.nleaf; ++i) H->mfcomb = H->mfcomb && H->g.s0[i] % 16 == 0;
     H->tol = svd_tol;
@@ -443,7 +467,7 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
             for (int q = 0; q < npair; ++q)
                 for (int w = 0; w < 2; ++w) {
                     partoff[(((size_t)c * nb + b) * npair + q) * 2 + w] = ps;
-                    ps += div_up(w == 0 ? g.r1[b] - g.r0[b] : g.c1[b] - g.c0[b], kch(norb));
+                    ps += div_up(w == 0 ? g.r1[b] - g.r0[b] : g.c1[b] - g.c0[b], H->kch);
                 }
     HALLOC(H->d_partoff, partoff.size(), false);
     HALLOC_K(H->part, (size_t)std::max(ps, 1LL) * norb * RC, true, H->oPart);
@@ -492,9 +516,9 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
         const int ntq = H->mfproj ? norb : npair;
         for (int b = 0; b < nb; ++b)
             for (int q = 0; q < ntq; ++q) {
-                for (int ch = 0; ch < div_up(g.r1[b] - g.r0[b], kch(norb)); ++ch)
-                    ts.push_back(FactTask{c, b, q, 0, ch, g.r0[b] + ch * kch(norb)});
-                for (int ch = 0; ch < div_up(g.c1[b] - g.c0[b], kch(norb)); ++ch)
+                for (int ch = 0; ch < div_up(g.r1[b] - g.r0[b], H->kch); ++ch)
+                    ts.push_back(FactTask{c, b, q, 0, ch, g.r0[b] + ch * H->kch});
+                for (int ch = 0; ch < div_up(g.c1[b] - g.c0[b], H->kch); ++ch)
                     ts.push_back(FactTask{c, b, q, 1, ch, g.r0[b]});
             }
         std::stable_sort(ts.begin(), ts.end(),
@@ -832,6 +856,7 @@ int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, doub
     A.outL = static_cast<cd*>(outL);
     A.nk = H->nk;
     A.f32 = H->f32;
+    A.kch = H->kch;
     A.mfproj = H->mfproj;
     A.mfcomb = H->mfcomb;
     A.ring = kTailRows;

@@ -101,6 +101,13 @@ bool interval_weights_exact(int k, int L, std::vector<double>& w, std::string& e
 // factor rows per projection task: more rows for small norb, whose tasks carry
 // fewer bytes per row (the Sigma rows of a task are staged in LDS, kch * norb entries)
 __host__ __device__ constexpr int kch(int norb) { return norb <= 2 ? 1024 : (norb == 4 ? 512 : 256); }
+// projection chunk rows a handle may be created with (hnessi_set_tile_shape), by norb:
+// 256..1024 for norb <= 4, 128..256 for norb 8 and 16 (the staged Sigma rows of a
+// chunk and the rank reduction share the task's LDS)
+__host__ __device__ constexpr int kch_max(int norb) { return norb <= 4 ? 1024 : 256; }
+inline bool kch_allowed(int norb, int rows) {
+    return rows == 0 || (norb <= 4 ? (rows == 256 || rows == 512 || rows == 1024) : (rows == 128 || rows == 256));
+}
 constexpr int kTailCH = 64;   // columns per tail task
 constexpr int kTailRows = 32; // tail rows at most: the panel being merged and the one being formed
 // orbital-pair groups of the tail tasks (one workgroup and one partial slot each)

@@ -6,6 +6,7 @@
 namespace hn {
 
 // A projection task: rows [chunk*kch, +kch) of U (which = 0) or V (which = 1)
+// (kch: HistArgs::kch, the handle's chunk rows)
 // of block b, orbital pair q, component comp.  Active once row `act` is merged
 // (U: the chunk's first row; V: the block's first row).  With matrix-core
 // projections (HistArgs::mfproj) q is the shared orbital index beta of 16 pairs.
@@ -31,6 +32,7 @@ struct HistArgs {
     const cd* sigL;   // Sigma^<(s, n), s = 0..n
     cd* sigRT;        // norb 16: scratch for Sigma^R(n, j) with its orbital indices swapped
     long long kInT;   // its object stride
+    int kch;          // factor rows per projection chunk (task and partial slot)
     int f32;          // factors stored as complex float (cf) instead of complex double
     int mfproj;       // norb = 16 with cf factors and RC <= 16: projections on the matrix
                       // cores, one task per (block, factor, chunk, orbital index beta)

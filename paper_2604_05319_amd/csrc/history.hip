@@ -220,7 +220,7 @@ __device__ void fact_task(const HistArgs& A, const FactTask& t, unsigned char* s
         ld = c1 - c0;
         F = p_V<FT>(A, comp, b) + A.Voff[b] + (size_t)q * RC * ld;
     }
-    constexpr int kCH = kch(NORB);
+    const int kCH = A.kch;
     const int i0 = t.chunk * kCH, i1 = min(len, i0 + kCH);
     if (i0 >= i1) return;
     const int n = A.n;
@@ -356,7 +356,7 @@ __device__ void fact_mfma_task(const HistArgs& A, const FactTask& t, unsigned ch
         ld = c1 - c0;
         F = p_V<cf>(A, comp, b) + A.Voff[b];
     }
-    constexpr int kCH = kch(NORB);
+    const int kCH = A.kch;
     const int i0 = t.chunk * kCH, i1 = min(len, i0 + kCH);
     if (i0 >= i1) return;
     const int n = A.n, nrow = i1 - i0, nst = (nrow + kPT - 1) / kPT * kPT;
@@ -989,7 +989,7 @@ __global__ void __launch_bounds__(256) proj_reduce(HistArgs A) {
     const int r0 = bk[1];
     if (A.n0[comp] <= r0) return;
     const int len = which == 0 ? min(A.n0[comp] - r0, bk[2] - r0) : bk[4] - bk[3];
-    const int nch = (len + kch(NORB) - 1) / kch(NORB);
+    const int nch = (len + A.kch - 1) / A.kch;
     const cd* p = p_part(A) + (size_t)A.partoff[slot] * per + e;
     cd s = mk(0.0, 0.0);
     for (int ch = 0; ch < nch; ++ch) s = s + p[(size_t)ch * per];
@@ -1671,9 +1671,9 @@ __global__ void __launch_bounds__(256) fgrad_kernel(HistArgs A, int xper) {
     }
 }
 
-size_t tasks_smem(int norb, bool mfproj) {
+size_t tasks_smem(int norb, bool mfproj, int kc) {
     const int ag = norb < 4 ? norb : 4;
-    size_t fact = mfproj ? (size_t)kch(norb) * kXS * sizeof(cf) : (size_t)(kch(norb) * norb + 4 * 32 * norb) * sizeof(cd);
+    size_t fact = mfproj ? (size_t)kc * kXS * sizeof(cf) : (size_t)(kc * norb + 4 * 32 * norb) * sizeof(cd);
     size_t leaf = (size_t)(tri(64) + 2 * 64 * ag) * sizeof(cd);
     size_t tail = (size_t)(kTailRows * kTailCH + (kTailRows + kTailCH) * ag) * sizeof(cd);
     size_t s = fact > leaf ? fact : leaf;
@@ -1697,18 +1697,18 @@ hipError_t launch_t(const HistArgs& a, hipStream_t st, hipEvent_t* ev) {
         if (a.sigR) sig_transpose16<<<dim3(a.n + 1, a.nk), 256, 0, st>>>(a.sigR, a.sigRT, a.kIn, a.kInT);
         // projections (matrix-core kernel or the generic tasks), then the dense pieces
         if (mf && a.nf[0] + a.nf[1] > 0)
-            proj_mfma<<<dim3(a.nf[0] + a.nf[1], a.nk), NT, (size_t)kch(16) * kXS * sizeof(cf), st>>>(a);
+            proj_mfma<<<dim3(a.nf[0] + a.nf[1], a.nk), NT, (size_t)a.kch * kXS * sizeof(cf), st>>>(a);
         if (!mf && a.nfpad > 0) {
             HistArgs b = a;
             b.ntailtask = 0;
             b.nleaftask = 0;
-            hist_tasks<NORB, FT><<<dim3(a.nfpad, a.nk), NT, tasks_smem(NORB, false), st>>>(b);
+            hist_tasks<NORB, FT><<<dim3(a.nfpad, a.nk), NT, tasks_smem(NORB, false, a.kch), st>>>(b);
         }
         if (a.ntailtask + a.nleaftask > 0)
             dense16<<<dim3(a.ntailtask + a.nleaftask, a.nk), 256, 8 * 64 * sizeof(cd), st>>>(a);
     } else {
         const int ntask = a.nfpad + a.nleaftask + a.ntailtask;
-        if (ntask > 0) hist_tasks<NORB, FT><<<dim3(ntask, a.nk), NT, tasks_smem(NORB, false), st>>>(a);
+        if (ntask > 0) hist_tasks<NORB, FT><<<dim3(ntask, a.nk), NT, tasks_smem(NORB, false, a.kch), st>>>(a);
     }
     if (ev) hipEventRecord(ev[1], st);
     {
@@ -1754,7 +1754,8 @@ hipError_t history_init() {
     hipError_t e = hipSuccess;
     auto set = [&](const void* f, int norb) {
         if (e == hipSuccess)
-            e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tasks_smem(norb, false));
+            e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)tasks_smem(norb, false, kch_max(norb)));
     };
     set((const void*)hist_tasks<1, cd>, 1);
     set((const void*)hist_tasks<1, cf>, 1);

@@ -49,3 +49,14 @@ def test_no_host_fallback_without_gpu():
     # creating a handle must fail loudly (no CPU path exists)
     with pytest.raises(Exception):
         P.Hodlr(64, 3, 1)
+
+
+def test_tile_shape_validation():
+    """hnessi_set_tile_shape checks norb and the chunk rows before anything else (no GPU)."""
+    import paper_2604_05319_amd as P
+    for norb, rows in ((3, 256), (4, 300), (4, 128), (16, 512), (8, 1024)):
+        with pytest.raises(P.HnessiError):
+            P.set_tile_shape(norb, rows)
+    for norb, rows in ((1, 1024), (4, 256), (16, 128), (8, 0)):
+        P.set_tile_shape(norb, rows)
+        P.set_tile_shape(norb, 0)

@@ -98,6 +98,27 @@ def test_multiorbital_sweep(P, norb, k, panel):
         _check_rows(IRg, ILg, IR, IL, f"dense norb={norb} k={k}")
 
 
+@pytest.mark.parametrize("norb,rows", [(4, 256), (4, 1024), (1, 256), (16, 128)])
+def test_tile_shapes(P, norb, rows):
+    """Handles created with another projection chunk height (the autotuner's knob) give the
+    oracle's rows (ragged chunks: blocks of 20 to 80 rows against 128..1024-row chunks)."""
+    N, h, nlvl, k = 160, 0.03, 3, 5
+    G = hermitian_terms(31 + norb, 6, norb)
+    S = hermitian_terms(41 + norb, 6, norb)
+    inp = host_inputs(G, S, N, h)
+    rows_ = [0, 1, 19, 20, 39, 40, 79, 80, 100, 159]
+    IR, IL = oracle_rows(*inp, N, h, k, rows=rows_)
+    P.set_tile_shape(norb, rows)
+    try:
+        H = P.Hodlr(N, nlvl, norb, k=k, tol=1e-12, panel=8, max_rank=16)
+    finally:
+        P.set_tile_shape(norb, 0)
+    assert H.tile_shape() == rows
+    IRg, ILg = _sweep(H, inp, N, h, norb)
+    assert H.status() == 0
+    _check_rows(IRg, ILg, IR, IL, f"tile shape norb={norb} rows={rows}")
+
+
 def test_ranks_above_sixteen(P):
     """Blocks whose rank exceeds 16 (a projection pass covers 16 ranks)."""
     from kbe_inputs import scalar_terms
