@@ -512,8 +512,9 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
     // projection task lists (sorted by the row that activates them)
     for (int c = 0; c < 2; ++c) {
         std::vector<FactTask> ts;
-        // matrix-core projections: one task per shared orbital index instead of per pair
-        const int ntq = H->mfproj ? norb : npair;
+        // one task per shared orbital index instead of per pair: the matrix-core
+        // projections of norb 16 and the wave-per-pair projections of norb 4
+        const int ntq = (H->mfproj || norb == 4) ? norb : npair;
         for (int b = 0; b < nb; ++b)
             for (int q = 0; q < ntq; ++q) {
                 for (int ch = 0; ch < div_up(g.r1[b] - g.r0[b], H->kch); ++ch)

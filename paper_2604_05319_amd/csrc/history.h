@@ -8,8 +8,9 @@ namespace hn {
 // A projection task: rows [chunk*kch, +kch) of U (which = 0) or V (which = 1)
 // (kch: HistArgs::kch, the handle's chunk rows)
 // of block b, orbital pair q, component comp.  Active once row `act` is merged
-// (U: the chunk's first row; V: the block's first row).  With matrix-core
-// projections (HistArgs::mfproj) q is the shared orbital index beta of 16 pairs.
+// (U: the chunk's first row; V: the block's first row).  At norb 4, and with
+// matrix-core projections (HistArgs::mfproj) at norb 16, q is the shared orbital
+// index beta of the norb pairs the task takes.
 struct FactTask {
     int comp, b, q, which, chunk, act;
 };

@@ -250,6 +250,110 @@ __device__ void fact_task(const HistArgs& A, const FactTask& t, unsigned char* s
 }
 
 // ---------------------------------------------------------------------------
+// Projections at norb = 4: one task per (block, factor, chunk, orbital index beta)
+// takes the 4 orbital pairs whose folded Sigma entries carry the same beta: their
+// common folded row X is staged once in LDS and wave w projects pair o = w alone.
+// Lane layout of a wave: lane = g * RP + rl covers rank rp + rl of a pass of RP
+// ranks and row group g of LPR = 64 / RP; a step takes four rows per lane with
+// their loads issued together; the row groups are summed by shuffles, so a wave
+// needs no barrier after the staging.  Surplus rank lanes compute on clamped
+// (in-range) loads and are never written.
+template <int NORB, class FT, int RP>
+__device__ void fact_wave(const FT* F, int ld, int i0, int i1, int rk, bool cj, const cd* xs, const double* S,
+                          cd* out, int RC) {
+    constexpr int LPR = 64 / RP;
+    const int lane = threadIdx.x & 63, rl = lane % RP, g = lane / RP;
+    for (int rp = 0; rp < rk; rp += RP) {
+        const int r = rp + rl;
+        const FT* Fr = F + (size_t)min(r, rk - 1) * ld;
+        cd acc[NORB];
+#pragma unroll
+        for (int a = 0; a < NORB; ++a) acc[a] = mk(0.0, 0.0);
+        for (int i = i0 + g; i < i1; i += 4 * LPR) {
+            cd f[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) f[u] = to_cd(Fr[min(i + u * LPR, i1 - 1)]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int iu = i + u * LPR;
+                if (iu < i1) {
+                    const cd fv = cj ? conj(f[u]) : f[u];
+                    const cd* x = xs + (size_t)(iu - i0) * NORB;
+#pragma unroll
+                    for (int a = 0; a < NORB; ++a) fma_(acc[a], x[a], fv);
+                }
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < NORB; ++a) {
+#pragma unroll
+            for (int off = RP; off < 64; off <<= 1) {
+                acc[a].x += __shfl_xor(acc[a].x, off, 64);
+                acc[a].y += __shfl_xor(acc[a].y, off, 64);
+            }
+        }
+        if (g == 0 && r < rk) {
+            const double sr = S[r];
+#pragma unroll
+            for (int a = 0; a < NORB; ++a) out[(size_t)a * RC + r] = sr * acc[a];
+        }
+    }
+}
+
+template <int NORB, class FT>
+__device__ void fact_task_beta(const HistArgs& A, const FactTask& t, unsigned char* smem) {
+    static_assert(NORB == 4, "one wave per orbital pair of a shared index");
+    const int comp = t.comp, b = t.b, beta = t.q, which = t.which;
+    if (comp == 0 && which == 0 && !A.wantR) return;
+    if ((comp == 1 || which == 1) && !A.wantL) return;
+    if (comp == 1 && A.adj) return;
+    constexpr int npair = NORB * NORB;
+    const int RC = A.RC;
+    const int* bk = A.blk + 5 * b;
+    const int r0 = bk[1], r1 = bk[2], c0 = bk[3], c1 = bk[4];
+    int len, base, ld;
+    const FT* F;
+    if (which == 0) {
+        len = min(A.n0[comp] - r0, r1 - r0);
+        base = r0;
+        ld = r1 - r0;
+        F = p_U<FT>(A, comp, b) + A.Uoff[b];
+    } else {
+        len = c1 - c0;
+        base = c0;
+        ld = c1 - c0;
+        F = p_V<FT>(A, comp, b) + A.Voff[b];
+    }
+    const int kCH = A.kch;
+    const int i0 = t.chunk * kCH, i1 = min(len, i0 + kCH);
+    if (i0 >= i1) return;
+    const int n = A.n;
+    cd* xs = reinterpret_cast<cd*>(smem);   // kCH x NORB
+    for (int e = threadIdx.x; e < (i1 - i0) * NORB; e += NT) {
+        const int i = e / NORB, a = e % NORB, j = base + i0 + i;
+        cd v;
+        if (comp == 0 && which == 0) v = w_end(A.W, n, j) * p_sigR(A)[(size_t)j * npair + a * NORB + beta];
+        else if (comp == 0) v = A.adj ? p_sigL(A)[(size_t)j * npair + a * NORB + beta]
+                                      : -w_start(A.W, j) * conj(p_sigL(A)[(size_t)j * npair + beta * NORB + a]);
+        else v = interval_w(A.W, n, j) * p_sigR(A)[(size_t)j * npair + a * NORB + beta];
+        xs[e] = v;
+    }
+    __syncthreads();
+    const int o = threadIdx.x >> 6;
+    const int q = (comp ^ which) ? o * NORB + beta : beta * NORB + o;
+    const int rk = rank_of(A, comp, b, q);
+    if (rk == 0) return;
+    const FT* Fq = F + (size_t)q * RC * ld;
+    const double* S = p_S(A, comp, b) + ((size_t)b * npair + q) * RC;
+    cd* out = p_part(A) + (size_t)(A.partoff[proj_slot(A, comp, b, q, which)] + t.chunk) * NORB * RC;
+    const bool cj = (comp == 1);
+    if (rk <= 4) fact_wave<NORB, FT, 4>(Fq, ld, i0, i1, rk, cj, xs, S, out, RC);
+    else if (rk <= 8) fact_wave<NORB, FT, 8>(Fq, ld, i0, i1, rk, cj, xs, S, out, RC);
+    else if (rk <= 16) fact_wave<NORB, FT, 16>(Fq, ld, i0, i1, rk, cj, xs, S, out, RC);
+    else fact_wave<NORB, FT, 32>(Fq, ld, i0, i1, rk, cj, xs, S, out, RC);
+}
+
+// ---------------------------------------------------------------------------
 // Projections of the FP32-factor form at norb = 16 on the matrix cores.  For one
 // block, component, factor and chunk of kch rows, the 16 orbital pairs whose
 // folded Sigma entries carry the same orbital index beta share one folded row:
@@ -922,7 +1026,9 @@ __global__ void __launch_bounds__(NT) hist_tasks(HistArgs A) {
     rel -= A.nleaftask;
     }
     if (rel >= A.nf[0] + A.nf[1]) return;
-    fact_task<NORB, FT>(A, rel < A.nf[0] ? A.ft[0][rel] : A.ft[1][rel - A.nf[0]], smem);
+    const FactTask& t = rel < A.nf[0] ? A.ft[0][rel] : A.ft[1][rel - A.nf[0]];
+    if constexpr (NORB == 4) fact_task_beta<NORB, FT>(A, t, smem);   // tasks per shared index
+    else fact_task<NORB, FT>(A, t, smem);
 }
 
 // Matrix-core projections (norb 16, complex-float factors) in a kernel of their own, so
