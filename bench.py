@@ -370,6 +370,44 @@ def lattice_bench(P, prof_stride):
     return out
 
 
+def rank1_bench(P, n_steps=2048):
+    """Row-by-row TSVD updates (panel height 1, the paper's rank-1 update) against the
+    16-row panels on the first n_steps steps of the norb-4 workload: steps/s and the
+    merge kernel time of each (both include the history step)."""
+    import numpy as np
+    import torch
+    from kbe_inputs import make_config_inputs
+    from kbe_inputs.packed import packed_torch
+    cfg, G, S = make_config_inputs("c2")
+    N, h, norb, k = cfg["nt"], cfg["h"], cfg["norb"], cfg["k"]
+    nlvl = int(round(np.log2(N // cfg["leaf"])))
+    dev = torch.device("cuda:0")
+    arrs = [packed_torch(G, "ret", N, h, dev), packed_torch(G, "les", N, h, dev),
+            packed_torch(S, "ret", N, h, dev), packed_torch(S, "les", N, h, dev)]
+    IR, IL = torch.empty_like(arrs[0]), torch.empty_like(arrs[0])
+    out = {}
+    for panel in (1, 16):
+        H = P.Hodlr(N, nlvl, norb, k=k, tol=cfg["tol"], panel=panel, max_rank=16)
+        H.sweep(0, 128, *arrs, h, IR, IL)
+        H.reset()
+        H.profile(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        H.sweep(0, n_steps, *arrs, h, IR, IL)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        _, mm = H.profile_read(2)
+        out[f"panel_{panel}"] = dict(steps_per_s=round(n_steps / dt, 1), merge_launches=int(len(mm)),
+                                      merge_ms=round(float(mm.sum()), 1), status=H.status())
+        log(f"panel {panel}: {n_steps} steps in {dt:.2f} s")
+        H.profile(0)
+        H.close()
+    del arrs, IR, IL
+    torch.cuda.empty_cache()
+    out["steps"] = n_steps
+    return out
+
+
 def adjoint_bench(P):
     """Adjoint form at its workload (norb = 2, N_t = 2048, leaf 64): forward sweep of I^R and
     the backward sweep over the frozen compressed state (dL/dSigma^R and dL/d(U, S, V) at
@@ -424,6 +462,7 @@ def main():
     ap.add_argument("--no-lattice", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-rank1", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 1 GiB device copy first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -577,6 +616,11 @@ def main():
         fp32, fp32_sample = fp32_bench(P)
         log("fp32 form:", fp32)
 
+    rank1 = None
+    if not args.no_rank1:
+        rank1 = rank1_bench(P)
+        log("rank-1 updates:", rank1)
+
     adjoint = None
     if not args.no_adjoint:
         adjoint = adjoint_bench(P)
@@ -608,6 +652,7 @@ def main():
         "dense": dense,
         "lattice": lattice,
         "adjoint": adjoint,
+        "rank1_updates": rank1,
         "fp32_factors": fp32,
         "cpu_baseline": cpu,
     }

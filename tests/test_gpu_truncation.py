@@ -58,23 +58,10 @@ def _merges_per_block(blocks, leaves, N, P_rows, n0):
     return [int(np.count_nonzero((starts >= r0) & (starts < min(r1, n0)))) for (_, r0, r1, _, _) in blocks]
 
 
-def test_sweep_with_active_truncation(P):
-    N, h, k, nlvl, panel, eps = 256, 0.05, 5, 3, 8, 1e-8
-    G, S = _geometric_terms(41, 20, 1e-10), _geometric_terms(42, 20, 1e-10)
-    inp = host_inputs(G, S, N, h)
-    say("oracle: active truncation sweep")
-    IR, IL = oracle_rows(*inp, N, h, k)
-    H = P.Hodlr(N, nlvl, 1, k=k, tol=eps, panel=panel, max_rank=24)
-    GR, GL, SR, SL = [to_dev(x) for x in inp]
-    IRg, ILg = torch.zeros_like(GR), torch.zeros_like(GR)
-    say("gpu: active truncation sweep")
-    H.sweep(0, N, GR, GL, SR, SL, h, IRg, ILg)
-    assert H.status() == 0
-    IRg, ILg = IRg.cpu().numpy(), ILg.cpu().numpy()
+def _check_against_bound(P, H, inp, IR, IL, IRg, ILg, N, h, k, nlvl, panel, eps):
+    """Assert every row's error against the a-priori bound; return (worst error / bound,
+    worst row relative error)."""
     blocks, leaves = H.blocks(), H.leaves()
-    rk = H.ranks(P.RET)
-    say("ranks (retarded)", rk.ravel().tolist())
-    assert rk.max() >= 6          # the truncation is active: values on both sides of eps
     sR = dense_from_packed(inp[2], N)[..., 0, 0]   # Sigma^R(n, j)
     sL = dense_from_packed(inp[3], N)[..., 0, 0]   # Sigma^<(s, n) stored orientation
     w_max = max(abs(w) for L in range(2 * k + 2) for w in P.weights(k, L))
@@ -102,10 +89,55 @@ def test_sweep_with_active_truncation(P):
         eR = np.abs(row(IRg, n) - IR[n]).max()
         eL = np.abs(row(ILg, n) - IL[n]).max()
         scale = max(np.abs(IR[n]).max(), np.abs(IL[n]).max(), 1e-300)
-        assert eR <= bR + 1e-13 * scale, (n, eR, bR)
-        assert eL <= bL + 1e-13 * scale, (n, eL, bL)
+        assert eR <= bR + 1e-13 * scale, (panel, n, eR, bR)
+        assert eL <= bL + 1e-13 * scale, (panel, n, eL, bL)
         if bR > 0:
             worst_ratio = max(worst_ratio, eR / bR, eL / max(bL, 1e-300))
         rel = max(rel, eR / max(np.abs(IR[n]).max(), 1e-300), eL / max(np.abs(IL[n]).max(), 1e-300))
+    return worst_ratio, rel
+
+
+def test_sweep_with_active_truncation(P):
+    N, h, k, nlvl, panel, eps = 256, 0.05, 5, 3, 8, 1e-8
+    G, S = _geometric_terms(41, 20, 1e-10), _geometric_terms(42, 20, 1e-10)
+    inp = host_inputs(G, S, N, h)
+    say("oracle: active truncation sweep")
+    IR, IL = oracle_rows(*inp, N, h, k)
+    H = P.Hodlr(N, nlvl, 1, k=k, tol=eps, panel=panel, max_rank=24)
+    GR, GL, SR, SL = [to_dev(x) for x in inp]
+    IRg, ILg = torch.zeros_like(GR), torch.zeros_like(GR)
+    say("gpu: active truncation sweep")
+    H.sweep(0, N, GR, GL, SR, SL, h, IRg, ILg)
+    assert H.status() == 0
+    IRg, ILg = IRg.cpu().numpy(), ILg.cpu().numpy()
+    rk = H.ranks(P.RET)
+    say("ranks (retarded)", rk.ravel().tolist())
+    assert rk.max() >= 6          # the truncation is active: values on both sides of eps
+    worst_ratio, rel = _check_against_bound(P, H, inp, IR, IL, IRg, ILg, N, h, k, nlvl, panel, eps)
     say(f"active truncation: worst error / a-priori bound {worst_ratio:.3e}; worst row relative error "
         f"{rel:.3e} (eps {eps:g})")
+
+
+def test_rank_one_updates_against_panels(P):
+    """Panel height 1 (the paper's row-by-row TSVD update) against panels of 16 rows on the
+    active-truncation workload: both within the a-priori bound of their own merge counts,
+    parity with the oracle on exact-rank inputs, and the drift of the per-row truncation
+    (error of P = 1 relative to P = 16) reported."""
+    N, h, k, nlvl, eps = 256, 0.05, 5, 3, 1e-8
+    G, S = _geometric_terms(41, 20, 1e-10), _geometric_terms(42, 20, 1e-10)
+    inp = host_inputs(G, S, N, h)
+    say("oracle: rank-1 updates")
+    IR, IL = oracle_rows(*inp, N, h, k)
+    errs = {}
+    for panel in (1, 16):
+        H = P.Hodlr(N, nlvl, 1, k=k, tol=eps, panel=panel, max_rank=24)
+        GR, GL, SR, SL = [to_dev(x) for x in inp]
+        IRg, ILg = torch.zeros_like(GR), torch.zeros_like(GR)
+        H.sweep(0, N, GR, GL, SR, SL, h, IRg, ILg)
+        assert H.status() == 0
+        IRg, ILg = IRg.cpu().numpy(), ILg.cpu().numpy()
+        ratio, rel = _check_against_bound(P, H, inp, IR, IL, IRg, ILg, N, h, k, nlvl, panel, eps)
+        errs[panel] = rel
+        say(f"panel {panel}: worst row relative error {rel:.3e}, worst error / a-priori bound {ratio:.3e}, "
+            f"max rank {int(H.ranks(P.RET).max())}")
+    say(f"drift of row-by-row updates: relative error ratio P=1 / P=16 {errs[1] / max(errs[16], 1e-300):.2f}")
