@@ -1,0 +1,91 @@
+"""FP64 time step of the retarded Kadanoff-Baym equation (test infrastructure, like the
+rest of this package; only tests may import it).
+
+Equation (section "Kadanoff-Baym equations", retarded component, orbital matrices):
+  left form   i d/dt G^R(t,t') - eps(t) G^R(t,t') = int_{t'}^{t} Sigma^R(t,s) G^R(s,t') ds
+  right form -i d/dt' G^R(t,t') - G^R(t,t') eps(t') = int_{t'}^{t} G^R(t,s) Sigma^R(s,t') ds
+  G^R(t,t) = -i.
+The history term of the left form is the sum of Eq. KBER in the current-Sigma-row
+orientation.  A time step n >= k, with rows 0..n-1 known (the first k rows come from a
+bootstrap, not part of this step):
+  * columns m < n-k: the left form at (t_n, t_m), the t-derivative by the backward
+    differentiation weights a_j = -D_0j of the appendix, the history sum with the interval
+    weights w^{(n-m)}, its newest term (j = n) moved to the left:
+      [i a_0/h - eps(n) - h w^{(n-m)}_{n-m} Sigma(n,n)] G(n,m)
+          = -(i/h) sum_{l=1..k} a_l G(n-l,m) + h sum_{j=m..n-1} w^{(n-m)}_{j-m} Sigma(n,j) G(j,m)
+  * columns n-k <= m < n: the right form at (t_n, t_m), the t'-derivative of the degree-k
+    polynomial through row n's points n-k..n (differentiation weights D_ip of the appendix,
+    G(n,n) = -i known), the integral over [m, n] with the interval weights w^{(n-m)}: one
+    linear system for the k unknown entries (a start of the row that needs no entry from
+    the other side of the diagonal), which multiply the known matrices from the left, so
+    the rows of G decouple.  With k-1 unknowns and G(n,n-k) taken from the first part the
+    march is unstable for even k.
+  * m = n: G(n,n) = -i.
+Written from the equations; every sum is the definition's.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .weights import bdf_weights, interval_weights_f64, poly_differentiation_weights
+
+
+def bdf(k: int):
+    return np.array([float(x) for x in bdf_weights(k)])
+
+
+def diff_matrix(k: int):
+    """D[i][p]: derivative at point i of the degree-k interpolant through points 0..k."""
+    return np.array([[float(x) for x in poly_differentiation_weights(k, i)] for i in range(k + 1)])
+
+
+def step(G, Sig, eps, n: int, h: float, k: int):
+    """Row n of G^R, shape (n+1, norb, norb), from rows 0..n-1 of G (dense, G[j, m] for
+    m <= j < n), Sigma^R (dense, Sig[s, m] for m <= s <= n) and eps (eps[t], t <= n)."""
+    norb = eps.shape[-1]
+    I = np.eye(norb, dtype=np.complex128)
+    a = bdf(k)
+    row = np.zeros((n + 1, norb, norb), dtype=np.complex128)
+    row[n] = -1j * I
+    for m in range(0, n - k):
+        L = n - m
+        w = interval_weights_f64(k, L)
+        M = (1j * a[0] / h) * I - eps[n] - h * w[L] * Sig[n, n]
+        rhs = -(1j / h) * sum(a[l] * G[n - l, m] for l in range(1, k + 1))
+        rhs = rhs + h * sum(w[j - m] * (Sig[n, j] @ G[j, m]) for j in range(m, n))
+        row[m] = np.linalg.solve(M, rhs)
+    # near-diagonal entries m = n-k .. n-1: X C = R with X = [row[u], u in U]
+    U = list(range(n - k, n))
+    if U:
+        D = diff_matrix(k)
+        nu = len(U)
+        C = np.zeros((nu * norb, nu * norb), dtype=np.complex128)
+        R = np.zeros((norb, nu * norb), dtype=np.complex128)
+        for ii, m in enumerate(U):
+            i = m - (n - k)
+            L = n - m
+            w = interval_weights_f64(k, L)
+            for uu, mp in enumerate(U):
+                p = mp - (n - k)
+                blk = -(1j / h) * D[i][p] * I
+                if mp == m:
+                    blk = blk - eps[m]
+                if mp >= m:
+                    blk = blk - h * w[mp - m] * Sig[mp, m]
+                C[uu * norb:(uu + 1) * norb, ii * norb:(ii + 1) * norb] = blk
+            R[:, ii * norb:(ii + 1) * norb] = (1j / h) * D[i][k] * row[n] + h * w[L] * (row[n] @ Sig[n, m])
+        X = np.linalg.solve(C.T, R.T).T
+        for uu, m in enumerate(U):
+            row[m] = X[:, uu * norb:(uu + 1) * norb]
+    return row
+
+
+def solve(Sig, eps, G_init, h: float, k: int, N: int):
+    """G^R on the whole grid (dense, G[n, m] for m <= n): rows 0..k-1 from G_init, the
+    rest by successive steps."""
+    norb = eps.shape[-1]
+    G = np.zeros((N, N, norb, norb), dtype=np.complex128)
+    G[:k] = G_init[:k]
+    for n in range(k, N):
+        G[n, :n + 1] = step(G, Sig, eps, n, h, k)
+    return G

@@ -1,0 +1,91 @@
+"""Pins of the FP64 step-solve oracle against closed forms of the retarded equation:
+Sigma = 0 with a constant Hermitian eps (G = -i exp(-i eps (t-t'))), and eps = 0 with a
+constant scalar Sigma = lam (i G' = lam int_0^tau G, G(0) = -i, so G = -i cosh(kappa tau),
+kappa^2 = -i lam); the first k rows are the exact ones (the bootstrap is not part of the
+step), and the error must fall at the scheme's order under step halving: k for the free
+propagator, min(k, 4) with memory (the near-diagonal start integrates intervals shorter
+than k with the closed Newton-Cotes rule of their own length)."""
+import numpy as np
+import pytest
+from scipy.linalg import expm
+
+from oracle.step_solve import solve
+
+
+def _free_case(N, h, norb, k, seed=3):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((norb, norb)) + 1j * rng.standard_normal((norb, norb))
+    eps = 0.5 * (A + A.conj().T)
+    G = np.zeros((N, N, norb, norb), dtype=np.complex128)
+    for n in range(N):
+        for m in range(n + 1):
+            G[n, m] = -1j * expm(-1j * eps * (n - m) * h)
+    return np.broadcast_to(eps, (N, norb, norb)).copy(), np.zeros((N, N, norb, norb), dtype=np.complex128), G
+
+
+def _memory_case(N, h, lam):
+    kap = np.sqrt(-1j * lam)
+    G = np.zeros((N, N, 1, 1), dtype=np.complex128)
+    S = np.zeros((N, N, 1, 1), dtype=np.complex128)
+    for n in range(N):
+        for m in range(n + 1):
+            G[n, m] = -1j * np.cosh(kap * (n - m) * h)
+            S[n, m] = lam
+    return np.zeros((N, 1, 1), dtype=np.complex128), S, G
+
+
+@pytest.mark.parametrize("k", [2, 3, 4, 5])
+def test_free_propagator_order(k):
+    T, norb = 1.6, 2
+    errs = []
+    for N in (65, 129):
+        h = T / (N - 1)
+        eps, S, G = _free_case(N, h, norb, k)
+        Gs = solve(S, eps, G, h, k, N)
+        errs.append(max(np.abs(Gs[n, :n + 1] - G[n, :n + 1]).max() for n in range(N)))
+    order = np.log2(errs[0] / errs[1])
+    assert errs[1] < 1e-2 and order > k - 0.3, (k, errs, order)
+
+
+@pytest.mark.parametrize("k", [2, 3, 4, 5])
+def test_constant_memory_kernel_order(k):
+    T, lam = 1.6, 0.8
+    errs = []
+    for N in (65, 129):
+        h = T / (N - 1)
+        eps, S, G = _memory_case(N, h, lam)
+        Gs = solve(S, eps, G, h, k, N)
+        errs.append(max(np.abs(Gs[n, :n + 1] - G[n, :n + 1]).max() for n in range(N)))
+    order = np.log2(errs[0] / errs[1])
+    assert errs[1] < 1e-3 and order > min(k, 4) - 0.3, (k, errs, order)
+
+
+def test_exponential_memory_kernel_order():
+    """Sigma(t,s) = lam exp(-gam (t-s)), eps = 0: with F(tau) = int_0^tau exp(-gam (tau-s)) G(s) ds
+    the pair (G, F) obeys the linear system G' = -i lam F, F' = G - gam F, G(0) = -i, F(0) = 0,
+    solved exactly by the matrix exponential."""
+    T, lam, gam, k = 1.6, 0.9, 0.7, 4
+    A = np.array([[0.0, -1j * lam], [1.0, -gam]], dtype=np.complex128)
+    errs = []
+    for N in (65, 129):
+        h = T / (N - 1)
+        ex = np.array([(expm(A * tau * h) @ np.array([-1j, 0.0]))[0] for tau in range(N)])
+        G = np.zeros((N, N, 1, 1), dtype=np.complex128)
+        S = np.zeros((N, N, 1, 1), dtype=np.complex128)
+        for n in range(N):
+            for m in range(n + 1):
+                G[n, m] = ex[n - m]
+                S[n, m] = lam * np.exp(-gam * (n - m) * h)
+        Gs = solve(S, np.zeros((N, 1, 1), dtype=np.complex128), G, h, k, N)
+        errs.append(max(np.abs(Gs[n, :n + 1] - G[n, :n + 1]).max() for n in range(N)))
+    order = np.log2(errs[0] / errs[1])
+    assert errs[1] < 1e-4 and order > k - 0.3, (errs, order)
+
+
+def test_first_rows_and_diagonal_are_kept():
+    N, h, k = 12, 0.1, 3
+    eps, S, G = _memory_case(N, h, 0.5)
+    Gs = solve(S, eps, G, h, k, N)
+    assert np.array_equal(Gs[:k], G[:k])
+    for n in range(N):
+        assert np.allclose(Gs[n, n], -1j)
