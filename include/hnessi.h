@@ -135,6 +135,14 @@ int hnessi_get_tile_shape(hnessi_hodlr_t H);
  * approximations".  Returns HNESSI_E_ARG for k outside 1..5 or L < 0. */
 int hnessi_weights(int k, int L, double* w_host);
 
+/* Weights of the retarded time step (hnessi_step_R) for order k (1..5), host
+ * outputs: a_host[0..k] the backward differentiation weights a_l = -D_{0l}
+ * (f'(t_n) h ~ sum_l a_l f(t_{n-l})) and D_host[i*(k+1) + p], i, p = 0..k, the
+ * derivative at point i of the degree-k interpolant through the equispaced
+ * points 0..k (unit spacing), appendix "Integral and derivative
+ * approximations".  Returns HNESSI_E_ARG for k outside 1..5 or a NULL output. */
+int hnessi_step_weights(int k, double* a_host, double* D_host);
+
 /* ---------------------------------------------------------------------------
  * HODLR-compressed storage of the retarded and lesser components
  * (the paper's herm_matrix_hodlr for its R and < parts).
@@ -198,6 +206,39 @@ int hnessi_hodlr_append_row(hnessi_hodlr_t H, int c, int n, const void* row, voi
  * hnessi_history_R_adjoint.  NULL pointers: HNESSI_E_ARG. */
 int hnessi_history_R(hnessi_hodlr_t H, int n, const void* sigR_row, double h,
                      void* out, void* stream);
+
+/* One time step of the retarded Kadanoff-Baym equation (section "Kadanoff-Baym
+ * equations", Eq. KBER and its left form, G^R(t,t) = -i): row n of G^R from the
+ * stored rows 0..n-1, written to row_out (device, (n+1)*norb*norb complex128,
+ * G^R(t_n, t_m) at [m][a][b]).  The row is not appended: the caller appends it
+ * (hnessi_hodlr_append_row), or calls again with a new Sigma^R first (a
+ * self-consistent iteration at fixed n).
+ *   columns m < n-k: the left form, the t-derivative by the backward
+ *     differentiation weights a_l = -D_{0l} of the appendix "Integral and
+ *     derivative approximations", the history sum over the stored rows with the
+ *     Gregory interval weights (the hnessi_history_R sum without its newest term,
+ *     which is taken to the left side): one norb x norb solve per column;
+ *   columns n-k..n-1: the right form at (t_n, t_m), its t'-derivative by the
+ *     polynomial differentiation weights D_{ip} of the same appendix on the points
+ *     n-k..n and its integral over [t_m, t_n] on the same points: one linear system
+ *     for those k entries.
+ * Arguments (device pointers, complex128, orbital matrices row-major [a][b]):
+ *   eps        k+1 matrices eps(t_{n-k+i}), i = 0..k
+ *   sigR_row   Sigma^R(t_n, t_j), j = 0..n
+ *   sig_near   k*k matrices at [u*k + i]: Sigma^R(t_{n-k+u}, t_{n-k+i}) for
+ *              0 <= i <= u < k (the entries with u < i are not read)
+ *   prev_rows  host array of k device pointers: prev_rows[l-1] holds row n-l of
+ *              G^R, G^R(t_{n-l}, t_m) at [m][a][b] (columns m < n-k are read)
+ *   h          time step (> 0)
+ * The first k rows (the start-up of the paper's bootstrapping) are the caller's:
+ * n < k gives HNESSI_E_RANGE.  Needs retarded rows 0..n-1 appended and row n not
+ * (HNESSI_E_ORDER), a handle of one object (HNESSI_E_ARG for a batch), no NULL
+ * pointer and h > 0 (HNESSI_E_ARG).  A singular system (a zero pivot) leaves
+ * non-finite entries in row_out; the call does not wait for the device.
+ * row_out must not overlap the inputs. */
+int hnessi_step_R(hnessi_hodlr_t H, int n, const void* eps, const void* sigR_row,
+                  const void* sig_near, const void* const* prev_rows, double h,
+                  void* row_out, void* stream);
 
 /* I^<(n, m), m = 0..n, into out (device): the two history integrals of the
  * lesser Kadanoff-Baym equation (Eq. KBEL, section "Kadanoff-Baym equations";
@@ -385,8 +426,9 @@ size_t hnessi_hodlr_bytes(hnessi_hodlr_t H);
 int hnessi_hodlr_profile(hnessi_hodlr_t H, int stride);
 
 /* Synchronizes the recorded events; for kernel kind 0 (projection / leaf /
- * tail tasks), 1 (combine), 2 (panel merge, both of its kernels) or 3 (sum of
- * the projection chunk partials) returns the
+ * tail tasks), 1 (combine), 2 (panel merge, both of its kernels), 3 (sum of
+ * the projection chunk partials), 4 (time step: near-diagonal system) or 5
+ * (time step: columns m < n-k) returns the
  * number of timed launches and writes, for the first `capacity` of them, the
  * step n (host int) and the duration in ms (host double).  Either output
  * pointer may be NULL. */

@@ -140,3 +140,17 @@ def les_row(p: DampedExpSum, n: int, h: float) -> np.ndarray:
 def packed_offset(n: int) -> int:
     """Offset (in elements of norb x norb) of row n in a packed lower triangle."""
     return n * (n + 1) // 2
+
+
+def hermitian_drive(seed: int, norb: int, nt: int, h: float, scale: float = 1.0,
+                    amp: float = 0.5, freq: float = 2.0) -> np.ndarray:
+    """One-body term eps(t_n) = E0 + cos(freq t_n) amp E1, n = 0..nt-1, shape
+    (nt, norb, norb): E0, E1 Hermitian with N(0, scale^2 / norb) entries (GUE-like),
+    seeded."""
+    rng = np.random.default_rng(seed)
+    es = []
+    for _ in range(2):
+        z = (rng.standard_normal((norb, norb)) + 1j * rng.standard_normal((norb, norb))) * (scale / np.sqrt(2.0 * norb))
+        es.append(0.5 * (z + np.conj(z.T)))
+    t = np.arange(nt) * h
+    return es[0][None] + (amp * np.cos(freq * t))[:, None, None] * es[1][None]

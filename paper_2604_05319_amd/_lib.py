@@ -38,6 +38,7 @@ _SIGS = {
     "hnessi_last_error": ([], C.c_char_p),
     "hnessi_set_allocator": ([ALLOC_FN, FREE_FN, C.c_void_p], C.c_int),
     "hnessi_weights": ([C.c_int, C.c_int, C.c_void_p], C.c_int),
+    "hnessi_step_weights": ([C.c_int, C.c_void_p, C.c_void_p], C.c_int),
     "hnessi_hodlr_create": ([C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
                              C.c_int, C.c_int, C.c_int, C.c_void_p], C.c_int),
     "hnessi_hodlr_create_batched": ([C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
@@ -53,6 +54,8 @@ _SIGS = {
     "hnessi_hodlr_reset": ([C.c_void_p, C.c_void_p], C.c_int),
     "hnessi_hodlr_append_row": ([C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p], C.c_int),
     "hnessi_history_R": ([C.c_void_p, C.c_int, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p], C.c_int),
+    "hnessi_step_R": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                       C.c_void_p, C.c_void_p], C.c_int),
     "hnessi_history_lesser": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p,
                                C.c_void_p], C.c_int),
     "hnessi_history_R_adjoint": ([C.c_void_p, C.c_int, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p],
@@ -207,6 +210,15 @@ def weights(k: int, L: int) -> np.ndarray:
     return w
 
 
+def step_weights(k: int):
+    """(a, D): backward differentiation weights a_l and the differentiation matrix D[i][p]."""
+    n = max(k + 1, 1)
+    a = np.zeros(n, dtype=np.float64)
+    D = np.zeros((n, n), dtype=np.float64)
+    _check(lib().hnessi_step_weights(k, a.ctypes.data_as(C.c_void_p), D.ctypes.data_as(C.c_void_p)))
+    return a, D
+
+
 class Hodlr:
     """HODLR-compressed retarded and lesser components (one handle, one stream)."""
 
@@ -242,6 +254,17 @@ class Hodlr:
 
     def history_R(self, n, sigR, h, out):
         _check(lib().hnessi_history_R(self.h, n, _ptr(sigR), h, _ptr(out), _stream()))
+
+    def step_R(self, n, eps, sigR, sig_near, prev_rows, h, out):
+        """Row n of G^R into out from the stored rows 0..n-1 (the row is not appended):
+        eps (k+1, norb, norb) = eps(t_{n-k+i}); sigR (n+1, norb, norb) = Sigma^R(n, j);
+        sig_near (k, k, norb, norb) = Sigma^R(t_{n-k+u}, t_{n-k+i}); prev_rows: k device
+        rows, prev_rows[l-1] = row n-l of G^R."""
+        if len(prev_rows) != self.k:
+            raise ValueError(f"prev_rows must hold the k = {self.k} previous rows")
+        ptrs = (C.c_void_p * self.k)(*[_ptr(r).value for r in prev_rows])
+        _check(lib().hnessi_step_R(self.h, n, _ptr(eps), _ptr(sigR), _ptr(sig_near), ptrs, h, _ptr(out),
+                                   _stream()))
 
     def history_lesser(self, n, sigR, sigL, h, out):
         _check(lib().hnessi_history_lesser(self.h, n, _ptr(sigR), _ptr(sigL), h, _ptr(out), _stream()))

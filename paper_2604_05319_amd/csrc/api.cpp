@@ -14,6 +14,7 @@
 #include "dense.h"
 #include "history.h"
 #include "merge.h"
+#include "step.h"
 #include "store.h"
 
 using namespace hn;
@@ -158,6 +159,7 @@ struct hnessi_hodlr_s {
               oProbW = 0, oProb = 0, oChunkQ = 0;
     double tol = 0.0;
     Weights W{};
+    StepWeights SW{};   // weights of the retarded time step
     Geometry g;
     int MW = 0;           // merge width (kWSmall or kWLarge)
     DevAlloc al;
@@ -304,6 +306,18 @@ int hnessi_weights(int k, int L, double* w_host) {
     return HNESSI_OK;
 }
 
+int hnessi_step_weights(int k, double* a_host, double* D_host) {
+    if (!a_host || !D_host) return fail(HNESSI_E_ARG, "an output is NULL");
+    StepWeights S;
+    std::string err;
+    if (!make_step_weights(k, S, err)) return fail(HNESSI_E_ARG, err);
+    for (int i = 0; i <= k; ++i) {
+        a_host[i] = S.a[i];
+        for (int p = 0; p <= k; ++p) D_host[i * (k + 1) + p] = S.D[i][p];
+    }
+    return HNESSI_OK;
+}
+
 }  // extern "C"
 
 namespace {
@@ -352,7 +366,7 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
     if (rc != HNESSI_OK) return rc;
     auto* H = new hnessi_hodlr_s();
     std::string err;
-    if (!make_weights(k, H->W, err) || !build_geometry(nt, nlvl, H->g, err)) {
+    if (!make_weights(k, H->W, err) || !make_step_weights(k, H->SW, err) || !build_geometry(nt, nlvl, H->g, err)) {
         delete H;
         return fail(HNESSI_E_ARG, err);
     }
@@ -752,16 +766,22 @@ int drain(hnessi_hodlr_t H) {
 // step n below the last appended row: they then evaluate step n over the stored
 // (frozen) state, which holds the compressed G^R of every row so far: the merged
 // rows at or below n through the factors, rows n0..n from the tail, no row above n.
+// implicit (retarded history only): step n = last appended row + 1, whose row is not
+// stored, so the sum runs over j = m..n-1 (the history term of a step solve).
 int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, double h, void* outR,
                void* outL, bool wantR, bool wantL, hipStream_t st, long long in_stride = 0,
-               long long out_stride = 0, bool adj = false, bool fgrad = false) {
+               long long out_stride = 0, bool adj = false, bool fgrad = false, bool implicit = false) {
     if (n < 0 || n >= H->nt) return fail(HNESSI_E_RANGE, "n outside the grid");
     if (!sigR && (!adj || fgrad)) return fail(HNESSI_E_ARG, "sigR_row is NULL");
     if (wantR && !outR && !fgrad) return fail(HNESSI_E_ARG, "output is NULL");
     if (wantL && (!sigL || (!outL && !fgrad))) return fail(HNESSI_E_ARG, "input or output is NULL");
     const bool ronly = !wantL || adj;
-    if (n > H->last[0] || (n < H->last[0] && !ronly))
+    if (implicit) {
+        if (wantL || adj || fgrad || n != H->last[0] + 1)
+            return fail(HNESSI_E_ORDER, "the step solve needs rows 0..n-1 appended and row n not");
+    } else if (n > H->last[0] || (n < H->last[0] && !ronly)) {
         return fail(HNESSI_E_ORDER, "retarded row n has not been appended (or later rows have)");
+    }
     if (wantL && !adj && H->last[1] != n)
         return fail(HNESSI_E_ORDER, "lesser row n has not been appended (or later rows have)");
     const bool frozen = n < H->last[0];
@@ -1077,6 +1097,45 @@ int hnessi_history_R(hnessi_hodlr_t H, int n, const void* sigR_row, double h, vo
     return rc != HNESSI_OK ? rc : mark(H, (hipStream_t)stream);
 }
 
+int hnessi_step_R(hnessi_hodlr_t H, int n, const void* eps, const void* sigR_row, const void* sig_near,
+                  const void* const* prev_rows, double h, void* row_out, void* stream) {
+    int rc = single_only(H);
+    if (rc != HNESSI_OK) return rc;
+    const int k = H->k;
+    if (n < 0 || n >= H->nt) return fail(HNESSI_E_RANGE, "n outside the grid");
+    if (n < k) return fail(HNESSI_E_RANGE, "the step needs n >= k (the first k rows are a start-up)");
+    if (!eps || !sigR_row || !sig_near || !prev_rows || !row_out) return fail(HNESSI_E_ARG, "a pointer is NULL");
+    if (!(h > 0.0)) return fail(HNESSI_E_ARG, "h must be > 0");
+    StepArgs a{};
+    for (int l = 0; l < k; ++l) {
+        if (!prev_rows[l]) return fail(HNESSI_E_ARG, "a previous row is NULL");
+        a.prev[l] = static_cast<const cd*>(prev_rows[l]);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    // the history sum over the stored rows, into the output row
+    rc = do_history(H, n, sigR_row, nullptr, h, row_out, nullptr, true, false, st, 0, 0, false, false, true);
+    if (rc != HNESSI_OK) return rc;
+    a.n = n;
+    a.k = k;
+    a.norb = H->norb;
+    a.h = h;
+    a.W = H->W;
+    a.S = H->SW;
+    a.eps = static_cast<const cd*>(eps);
+    a.sigR = static_cast<const cd*>(sigR_row);
+    a.sigNear = static_cast<const cd*>(sig_near);
+    a.row = static_cast<cd*>(row_out);
+    if (H->prof.want(n)) {
+        hipEvent_t ev[3] = {H->prof.ev(), H->prof.ev(), H->prof.ev()};
+        HIP_TRY(launch_step(a, st, ev));
+        H->prof.recs.push_back({4, n, ev[0], ev[1]});
+        H->prof.recs.push_back({5, n, ev[1], ev[2]});
+    } else {
+        HIP_TRY(launch_step(a, st));
+    }
+    return mark(H, st);
+}
+
 int hnessi_history_lesser(hnessi_hodlr_t H, int n, const void* sigR_row, const void* sigL_slice,
                           double h, void* out, void* stream) {
     int rc = single_only(H);
@@ -1383,7 +1442,7 @@ int hnessi_hodlr_profile(hnessi_hodlr_t H, int stride) {
 }
 
 int hnessi_hodlr_profile_read(hnessi_hodlr_t H, int kind, int* steps_host, double* ms_host, int capacity) {
-    if (!H || kind < 0 || kind > 3) return fail(HNESSI_E_ARG, "bad argument");
+    if (!H || kind < 0 || kind > 5) return fail(HNESSI_E_ARG, "bad argument");
     return H->prof.read(kind, steps_host, ms_host, capacity);
 }
 

@@ -91,6 +91,16 @@ struct Geometry {
     int max_leaf = 0, min_leaf = 0;
 };
 
+// weights of the retarded time step: backward differentiation a_l (f'(t_n) h ~
+// sum_l a_l f(t_{n-l})) and the differentiation matrix D[i][p] of the degree-k
+// interpolant through k+1 equispaced points (derivative at point i)
+struct StepWeights {
+    int k;
+    double a[6];
+    double D[6][6];
+};
+bool make_step_weights(int k, StepWeights& S, std::string& err);
+
 bool build_geometry(int nt, int nlvl, Geometry& g, std::string& err);
 bool make_weights(int k, Weights& W, std::string& err);
 // exact-rational interval weights, for the public hnessi_weights

@@ -505,7 +505,7 @@ __device__ void leaf_task(const HistArgs& A, int leaf, int comp, int ag, int pg,
     const int n = A.n;
     const int s0 = A.leafs[2 * leaf], s1 = A.leafs[2 * leaf + 1];
     const int lw = s1 - s0;
-    const int nrow = min(s1, n + 1) - s0;
+    const int nrow = min(s1, A.last[comp] + 1) - s0;   // stored rows (row n, or up to n-1 for a step solve)
     const cd* L = p_leaf(A, comp) + A.Loff[leaf];
     const long long tsz = tri(lw), tnow = tri(nrow);
     cd* T = reinterpret_cast<cd*>(smem);   // tri(64)
@@ -623,7 +623,7 @@ __device__ void leaf_pair_task(const HistArgs& A, int leaf, int comp, int q, uns
     const int n = A.n;
     const int s0 = A.leafs[2 * leaf], s1 = A.leafs[2 * leaf + 1];
     const int lw = s1 - s0;
-    const int nrow = min(s1, n + 1) - s0;
+    const int nrow = min(s1, A.last[comp] + 1) - s0;   // stored rows (row n, or up to n-1 for a step solve)
     const cd* Lq = p_leaf(A, comp) + A.Loff[leaf] + (size_t)q * tri(lw);
     const long long tnow = tri(nrow);
     cd* T = reinterpret_cast<cd*>(smem);   // tri(64)
@@ -1171,7 +1171,8 @@ __device__ void finish_entry(const HistArgs& A, int m, int a, int c, int part, c
             p_outR(A)[o] = mk(0.0, 0.0);
             return;
         }
-        const int imax = L < k ? L : k;
+        // the newest term (j = n) is absent when row n is not stored (step solve)
+        const int imax = min(L < k ? L : k, A.last[0] - m);
         for (int i = 0; i <= imax; ++i) {
             const double wc = L < k ? A.W.nc[L][i] - w_end(A.W, n, m + i) : A.W.om[i] - 1.0;
             const cd* sg = p_sigR(A) + (size_t)(m + i) * npair + a * NORB;
@@ -1371,7 +1372,7 @@ __device__ void leaf16_task(const HistArgs& A, int leaf, int comp, int c) {
     if (comp == 1 && (!A.wantL || A.adj)) return;
     const int n = A.n;
     const int s0 = A.leafs[2 * leaf], s1 = A.leafs[2 * leaf + 1];
-    const int lw = s1 - s0, nrow = min(s1, n + 1) - s0;
+    const int lw = s1 - s0, nrow = min(s1, A.last[comp] + 1) - s0;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, x = lane & 15, kk = lane >> 4;
     if (16 * wave >= nrow) return;
     const int m = 16 * wave + x;

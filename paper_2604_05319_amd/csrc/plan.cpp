@@ -122,6 +122,31 @@ std::vector<Q> interval_q(int k, int L) {
 
 }  // namespace
 
+// D_{m l} = sum_{a >= 1} P_{a l} a m^{a-1}: derivative at point m of the degree-deg
+// interpolant through points 0..deg (unit spacing)
+std::vector<Q> poly_diff(int deg, int m) {
+    auto P = vandermonde_inverse(deg);
+    std::vector<Q> d(deg + 1);
+    for (int l = 0; l <= deg; ++l) {
+        Q s(0);
+        for (int a = 1; a <= deg; ++a) s = s + P[a][l] * Q(a) * qpow(m, a - 1);
+        d[l] = s;
+    }
+    return d;
+}
+
+bool make_step_weights(int k, StepWeights& S, std::string& err) {
+    if (k < 1 || k > 5) { err = "order k must be in 1..5"; return false; }
+    S = StepWeights{};
+    S.k = k;
+    for (int i = 0; i <= k; ++i) {
+        auto d = poly_diff(k, i);
+        for (int l = 0; l <= k; ++l) S.D[i][l] = d[l].to_double();
+    }
+    for (int l = 0; l <= k; ++l) S.a[l] = -S.D[0][l];   // backward differentiation: a_l = -D_{0 l}
+    return true;
+}
+
 bool interval_weights_exact(int k, int L, std::vector<double>& w, std::string& err) {
     if (k < 1 || k > 5) { err = "Gregory order k must be in 1..5"; return false; }
     if (L < 0) { err = "interval length must be >= 0"; return false; }

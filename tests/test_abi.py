@@ -60,3 +60,19 @@ def test_tile_shape_validation():
     for norb, rows in ((1, 1024), (4, 256), (16, 128), (8, 0)):
         P.set_tile_shape(norb, rows)
         P.set_tile_shape(norb, 0)
+
+
+@pytest.mark.parametrize("k", range(1, 6))
+def test_host_step_weights_match_oracle(k):
+    """The step solve's backward differentiation and differentiation-matrix tables
+    (host, exact rationals rounded once) against the oracle's exact rationals."""
+    a, D = P.step_weights(k)
+    np.testing.assert_array_equal(a, [float(x) for x in OW.bdf_weights(k)])
+    for i in range(k + 1):
+        np.testing.assert_array_equal(D[i], [float(x) for x in OW.poly_differentiation_weights(k, i)])
+
+
+def test_step_weights_argument_errors():
+    for k in (0, 6):
+        with pytest.raises(P.HnessiError):
+            P.step_weights(k)

@@ -1,0 +1,137 @@
+"""GPU parity of the retarded time step (hnessi_step_R) against the FP64 step oracle.
+
+Rows k..N-1 are marched on the GPU: each row is solved from the compressed rows
+0..n-1, then appended.  Every step is checked against the oracle's step applied to
+the GPU's own rows 0..n-1 (one-step parity: max_m |G_gpu(n,m) - G_oracle(n,m)| over
+max_m |G_oracle(n,m)| <= 1e-10 with FP64 factors at SVD tolerance 1e-12, <= 1e-5
+with FP32 factors), and the whole march against the oracle's own march (the one-step
+differences carried through the remaining steps: 1e-8, FP32 factors 1e-4).
+Inputs: Sigma^R from the damped-exponential generator, eps(t) a seeded Hermitian
+drive, rows 0..k-1 the free propagator of eps(0) (the start-up is not part of the
+step).  Grids span several leaves, panel merges and a ragged last leaf.
+"""
+import numpy as np
+import pytest
+from scipy.linalg import expm
+
+from gpu_common import say, to_dev
+from kbe_inputs import hermitian_drive, hermitian_terms, retarded, scalar_terms
+from oracle.step_solve import solve, step
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_05319_amd as P
+    return P
+
+
+def _inputs(N, norb, h, k, seed):
+    pS = scalar_terms(seed, 8) if norb == 1 else hermitian_terms(seed, 8, norb)
+    t = np.arange(N) * h
+    S = np.zeros((N, N, norb, norb), dtype=np.complex128)
+    for n in range(N):
+        S[n, :n + 1] = retarded(pS, t[n], t[:n + 1])
+    eps = hermitian_drive(seed + 1, norb, N, h)
+    G0 = np.zeros((N, N, norb, norb), dtype=np.complex128)
+    for n in range(k):
+        for m in range(n + 1):
+            G0[n, m] = -1j * expm(-1j * eps[0] * (n - m) * h)
+    return S, eps, G0
+
+
+def _near(S, n, k):
+    norb = S.shape[-1]
+    out = np.zeros((k, k, norb, norb), dtype=np.complex128)
+    for u in range(k):
+        for i in range(u + 1):
+            out[u, i] = S[n - k + u, n - k + i]
+    return out
+
+
+def _march(P, S, eps, G0, N, nlvl, norb, k, h, tol, flags):
+    H = P.Hodlr(N, nlvl, norb, k=k, tol=tol, panel=16, max_rank=16, flags=flags)
+    rows = []
+    for n in range(k):
+        r = to_dev(G0[n, :n + 1])
+        H.append_row(P.RET, n, r)
+        rows.append(r)
+    for n in range(k, N):
+        out = torch.empty((n + 1, norb, norb), dtype=torch.complex128, device="cuda")
+        H.step_R(n, to_dev(eps[n - k:n + 1]), to_dev(S[n, :n + 1]), to_dev(_near(S, n, k)),
+                 rows[n - k:n][::-1], h, out)
+        H.append_row(P.RET, n, out)
+        rows.append(out)
+    torch.cuda.synchronize()
+    G = np.zeros((N, N, norb, norb), dtype=np.complex128)
+    for n in range(N):
+        G[n, :n + 1] = rows[n].cpu().numpy()
+    return H, G
+
+
+CASES = [  # norb, k, N, nlvl, fp32 factors
+    (1, 5, 150, 2, False),
+    (2, 3, 150, 2, False),
+    (4, 5, 150, 2, False),
+    (4, 2, 131, 2, False),
+    (8, 4, 120, 2, False),
+    (16, 5, 100, 1, False),
+    (16, 5, 128, 1, True),
+]
+
+
+@pytest.mark.parametrize("norb,k,N,nlvl,f32", CASES)
+def test_step_march_against_oracle(P, norb, k, N, nlvl, f32):
+    h = 0.02
+    say(f"step march: norb {norb} k {k} N {N} nlvl {nlvl} fp32 factors {f32}")
+    S, eps, G0 = _inputs(N, norb, h, k, seed=40 + norb + k)
+    tol_svd = 1e-6 if f32 else 1e-12
+    _, G = _march(P, S, eps, G0, N, nlvl, norb, k, h, tol_svd, P.FLAG_FP32_FACTORS if f32 else 0)
+    assert np.all(np.isfinite(G))
+    bar1, barN = (1e-5, 1e-4) if f32 else (1e-10, 1e-8)
+    worst = 0.0
+    for n in range(k, N):
+        ref = step(G, S, eps, n, h, k)
+        err = np.abs(G[n, :n + 1] - ref).max() / np.abs(ref).max()
+        worst = max(worst, err)
+        assert err <= bar1, (n, err)
+    ref = solve(S, eps, G0, h, k, N)
+    errN = max(np.abs(G[n, :n + 1] - ref[n, :n + 1]).max() / np.abs(ref[n, :n + 1]).max() for n in range(N))
+    say(f"  one-step worst {worst:.2e}, march {errN:.2e}")
+    assert errN <= barN, errN
+
+
+def test_step_argument_errors(P):
+    norb, k, N, h = 2, 5, 64, 0.02
+    S, eps, G0 = _inputs(N, norb, h, k, seed=7)
+    H = P.Hodlr(N, 1, norb, k=k, tol=1e-12, panel=16, max_rank=16)
+    rows = [to_dev(G0[n, :n + 1]) for n in range(k)]
+    out = torch.empty((N, norb, norb), dtype=torch.complex128, device="cuda")
+    e, near = to_dev(eps[:k + 1]), to_dev(_near(S, k, k))
+    # rows 0..k-1 not appended yet: order error
+    with pytest.raises(P.HnessiError):
+        H.step_R(k, e, to_dev(S[k, :k + 1]), near, rows[::-1], h, out)
+    for n in range(k):
+        H.append_row(P.RET, n, rows[n])
+    # n < k: the start-up is not a step
+    with pytest.raises(P.HnessiError):
+        H.step_R(k - 1, e, to_dev(S[k - 1, :k]), near, rows[::-1], h, out)
+    # n beyond the next row
+    with pytest.raises(P.HnessiError):
+        H.step_R(k + 1, e, to_dev(S[k + 1, :k + 2]), near, rows[::-1], h, out)
+    # h <= 0
+    with pytest.raises(P.HnessiError):
+        H.step_R(k, e, to_dev(S[k, :k + 1]), near, rows[::-1], 0.0, out)
+    # wrong number of previous rows (caught by the binding)
+    with pytest.raises(ValueError):
+        H.step_R(k, e, to_dev(S[k, :k + 1]), near, rows[:2], h, out)
+    # a valid call after the errors
+    H.step_R(k, e, to_dev(S[k, :k + 1]), near, rows[::-1], h, out)
+    torch.cuda.synchronize()
+    ref = step(G0, S, eps, k, h, k)
+    got = out[:k + 1].cpu().numpy()
+    assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
