@@ -408,6 +408,80 @@ def rank1_bench(P, n_steps=2048):
     return out
 
 
+def step_solve_bench(P, prof_stride=8):
+    """The retarded time step (hnessi_step_R) marched over the norb-4 N_t = 8192 grid:
+    each step the history sum over the stored rows, the two FP64 solves and the append of
+    the new row (with the merges that fall due).  Sigma^R a 2-term damped-exponential
+    generator, eps a constant seeded Hermitian matrix, rows 0..k-1 the free propagator."""
+    import numpy as np
+    import torch
+    from scipy.linalg import expm
+    from kbe_inputs import hermitian_drive, hermitian_terms, make_config_inputs, retarded
+    from kbe_inputs.packed import RowSource
+    cfg = make_config_inputs("c2")[0]
+    N, h, norb, k = cfg["nt"], cfg["h"], cfg["norb"], cfg["k"]
+    npair = norb * norb
+    nlvl = int(round(np.log2(N // cfg["leaf"])))
+    dev = torch.device("cuda:0")
+    # a constant Hermitian eps and a 2-term Sigma^R: the marched G^R then has
+    # norb (1 + 2) = 12 poles (plus the decaying parasitic modes of the multistep scheme),
+    # within the rank capacity of 32 at tolerance 1e-10
+    S = hermitian_terms(cfg["seed_s"], 2, norb)
+    src = RowSource(S, N, h, dev)
+    eps_h = hermitian_drive(cfg["seed_s"] + 100, norb, N, h, amp=0.0)
+    eps_d = torch.as_tensor(eps_h, device=dev)
+    near = np.zeros((k, k, norb, norb), dtype=np.complex128)
+    for u in range(k):
+        for i in range(u + 1):
+            near[u, i] = retarded(S, (u - i) * h, 0.0)
+    near_d = torch.as_tensor(near, device=dev)
+    start = [torch.as_tensor(np.stack([-1j * expm(-1j * eps_h[0] * (n - m) * h) for m in range(n + 1)]),
+                             device=dev) for n in range(k)]
+    H = P.Hodlr(N, nlvl, norb, k=k, tol=cfg["tol"], panel=16, max_rank=32)
+
+    def march(n_end):
+        H.reset()
+        ring = []
+        for n in range(n_end):
+            if n < k:
+                row = start[n]
+            else:
+                row = torch.empty((n + 1, norb, norb), dtype=torch.complex128, device=dev)
+                H.step_R(n, eps_d[n - k:n + 1], src.ret(n), near_d, ring[::-1], h, row)
+            H.append_row(P.RET, n, row)
+            ring = (ring + [row])[-k:]
+        return ring[-1]
+
+    march(512)
+    torch.cuda.synchronize()
+    H.profile(prof_stride)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = march(N)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    fin = bool(torch.isfinite(torch.view_as_real(last)).all())
+    times = {}
+    for kind, name in ((0, "hist_tasks"), (3, "proj_reduce"), (1, "hist_combine"), (4, "step_near"),
+                       (5, "step_bulk"), (2, "merge")):
+        st, ms = H.profile_read(kind)
+        times[name] = (st, ms)
+    sb, mb = times["step_bulk"]
+    # algorithmic bytes of one bulk launch: k previous rows and the history row read, the
+    # solution written, over the n-k columns (the norb x norb inverse is recomputed in LDS)
+    bb = np.array([(k + 2) * (int(n) - k) * npair * 16 for n in sb], dtype=np.float64)
+    per_step_us = {name: round(1e3 * float(ms.mean()), 2) for name, (st, ms) in times.items() if name != "merge"}
+    out = dict(value=round(N / dt, 1), unit="time steps/s (history sum + FP64 step solve + append, retarded)",
+               n_t=N, norb=norb, k=k, seconds=round(dt, 3), finite=fin,
+               kernel_us_per_step=per_step_us,
+               step_bulk_gbs=round(float(bb.sum() / (mb.sum() * 1e-3) / 1e9), 1),
+               merge_ms=round(float(times["merge"][1].sum()), 1),
+               max_rank=int(H.ranks(P.RET).max()), status=H.status())
+    H.profile(0)
+    H.close()
+    return out
+
+
 def adjoint_bench(P):
     """Adjoint form at its workload (norb = 2, N_t = 2048, leaf 64): forward sweep of I^R and
     the backward sweep over the frozen compressed state (dL/dSigma^R and dL/d(U, S, V) at
@@ -463,6 +537,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-rank1", action="store_true")
+    ap.add_argument("--no-step", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 1 GiB device copy first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -621,6 +696,11 @@ def main():
         rank1 = rank1_bench(P)
         log("rank-1 updates:", rank1)
 
+    step_solve = None
+    if not args.no_step:
+        step_solve = step_solve_bench(P, args.prof_stride)
+        log("step solve:", step_solve)
+
     adjoint = None
     if not args.no_adjoint:
         adjoint = adjoint_bench(P)
@@ -653,6 +733,7 @@ def main():
         "lattice": lattice,
         "adjoint": adjoint,
         "rank1_updates": rank1,
+        "step_solve": step_solve,
         "fp32_factors": fp32,
         "cpu_baseline": cpu,
     }

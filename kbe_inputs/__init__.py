@@ -23,6 +23,6 @@ innermost and row-major, so a row is (n+1) x norb x norb complex128.
 """
 from .generators import (  # noqa: F401
     DampedExpSum, scalar_terms, hermitian_terms, lattice_terms,
-    retarded, lesser, ret_row, les_row, packed_offset, hermitian_drive,
+    retarded, lesser, ret_row, les_row, packed_offset, hermitian_drive, channel_terms,
 )
 from .configs import CONFIGS, make_config_inputs  # noqa: F401

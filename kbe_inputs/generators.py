@@ -154,3 +154,25 @@ def hermitian_drive(seed: int, norb: int, nt: int, h: float, scale: float = 1.0,
         es.append(0.5 * (z + np.conj(z.T)))
     t = np.arange(nt) * h
     return es[0][None] + (amp * np.cos(freq * t))[:, None, None] * es[1][None]
+
+
+def channel_terms(seed: int, norb: int, nchan: int, nterms: int = 1, omega_range=(-2.0, 2.0),
+                  gamma_range=(0.05, 0.2), e_range=(-1.5, 1.5), d_range=(0.2, 0.6)):
+    """A one-body term and a retarded self-energy that share one Haar eigenbasis U:
+    eps0 = U diag(e) U^H and Sigma amplitudes A_p = a_p U diag(d_p) U^H, where e and d_p
+    take nchan distinct values (each on norb / nchan orbitals).  Every orbital pair then
+    couples the same nchan channels, which keeps the solution's block ranks bounded by
+    nchan (1 + nterms) on long grids.  Returns (eps0 (norb, norb), DampedExpSum)."""
+    rng = np.random.default_rng(seed)
+    u = _haar_unitary(rng, norb)
+    chan = np.arange(norb) % nchan
+    e = rng.uniform(*e_range, size=nchan)[chan]
+    omega = rng.uniform(*omega_range, size=nterms)
+    gamma = rng.uniform(*gamma_range, size=nterms)
+    a = rng.dirichlet(np.ones(nterms))
+    amp = np.empty((nterms, norb, norb), dtype=np.complex128)
+    for p in range(nterms):
+        d = rng.uniform(*d_range, size=nchan)[chan]
+        amp[p] = a[p] * (u * d[None, :]) @ np.conj(u.T)
+    eps0 = (u * e[None, :]) @ np.conj(u.T)
+    return eps0, DampedExpSum(omega, gamma, amp, _fermi(omega, 1.0), dict(kind="channels", seed=seed))

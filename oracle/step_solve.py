@@ -39,44 +39,57 @@ def diff_matrix(k: int):
     return np.array([[float(x) for x in poly_differentiation_weights(k, i)] for i in range(k + 1)])
 
 
+def bulk_column(Gcol, Sig_row, eps_n, n: int, m: int, h: float, k: int):
+    """G(n, m) for a column m < n-k from the left form: Gcol[j - m] = G(j, m) for
+    j = m..n-1, Sig_row[j] = Sigma^R(n, j) for j = 0..n, eps_n = eps(t_n)."""
+    norb = eps_n.shape[-1]
+    I = np.eye(norb, dtype=np.complex128)
+    a = bdf(k)
+    L = n - m
+    w = interval_weights_f64(k, L)
+    M = (1j * a[0] / h) * I - eps_n - h * w[L] * Sig_row[n]
+    rhs = -(1j / h) * sum(a[l] * Gcol[n - l - m] for l in range(1, k + 1))
+    rhs = rhs + h * sum(w[j - m] * (Sig_row[j] @ Gcol[j - m]) for j in range(m, n))
+    return np.linalg.solve(M, rhs)
+
+
+def near_block(Sig_near, Sig_row, eps, n: int, h: float, k: int):
+    """G(n, m) for m = n-k..n-1 (shape (k, norb, norb)) from the right form with
+    G(n, n) = -i: Sig_near[u][i] = Sigma^R(t_{n-k+u}, t_{n-k+i}) (i <= u < k),
+    Sig_row[j] = Sigma^R(n, j), eps[t] = eps(t) (t = n-k..n-1 read)."""
+    norb = Sig_row.shape[-1]
+    I = np.eye(norb, dtype=np.complex128)
+    Gnn = -1j * I
+    D = diff_matrix(k)
+    C = np.zeros((k * norb, k * norb), dtype=np.complex128)
+    R = np.zeros((norb, k * norb), dtype=np.complex128)
+    for i in range(k):       # the equation at column m = n-k+i
+        m = n - k + i
+        L = n - m
+        w = interval_weights_f64(k, L)
+        for u in range(k):   # the unknown G(n, n-k+u)
+            blk = -(1j / h) * D[i][u] * I
+            if u == i:
+                blk = blk - eps[m]
+            if u >= i:
+                blk = blk - h * w[u - i] * Sig_near[u][i]
+            C[u * norb:(u + 1) * norb, i * norb:(i + 1) * norb] = blk
+        R[:, i * norb:(i + 1) * norb] = (1j / h) * D[i][k] * Gnn + h * w[L] * (Gnn @ Sig_row[m])
+    X = np.linalg.solve(C.T, R.T).T          # X C = R, X = [G(n, n-k+u)]_u
+    return np.stack([X[:, u * norb:(u + 1) * norb] for u in range(k)])
+
+
 def step(G, Sig, eps, n: int, h: float, k: int):
     """Row n of G^R, shape (n+1, norb, norb), from rows 0..n-1 of G (dense, G[j, m] for
     m <= j < n), Sigma^R (dense, Sig[s, m] for m <= s <= n) and eps (eps[t], t <= n)."""
     norb = eps.shape[-1]
-    I = np.eye(norb, dtype=np.complex128)
-    a = bdf(k)
     row = np.zeros((n + 1, norb, norb), dtype=np.complex128)
-    row[n] = -1j * I
+    row[n] = -1j * np.eye(norb, dtype=np.complex128)
     for m in range(0, n - k):
-        L = n - m
-        w = interval_weights_f64(k, L)
-        M = (1j * a[0] / h) * I - eps[n] - h * w[L] * Sig[n, n]
-        rhs = -(1j / h) * sum(a[l] * G[n - l, m] for l in range(1, k + 1))
-        rhs = rhs + h * sum(w[j - m] * (Sig[n, j] @ G[j, m]) for j in range(m, n))
-        row[m] = np.linalg.solve(M, rhs)
-    # near-diagonal entries m = n-k .. n-1: X C = R with X = [row[u], u in U]
-    U = list(range(n - k, n))
-    if U:
-        D = diff_matrix(k)
-        nu = len(U)
-        C = np.zeros((nu * norb, nu * norb), dtype=np.complex128)
-        R = np.zeros((norb, nu * norb), dtype=np.complex128)
-        for ii, m in enumerate(U):
-            i = m - (n - k)
-            L = n - m
-            w = interval_weights_f64(k, L)
-            for uu, mp in enumerate(U):
-                p = mp - (n - k)
-                blk = -(1j / h) * D[i][p] * I
-                if mp == m:
-                    blk = blk - eps[m]
-                if mp >= m:
-                    blk = blk - h * w[mp - m] * Sig[mp, m]
-                C[uu * norb:(uu + 1) * norb, ii * norb:(ii + 1) * norb] = blk
-            R[:, ii * norb:(ii + 1) * norb] = (1j / h) * D[i][k] * row[n] + h * w[L] * (row[n] @ Sig[n, m])
-        X = np.linalg.solve(C.T, R.T).T
-        for uu, m in enumerate(U):
-            row[m] = X[:, uu * norb:(uu + 1) * norb]
+        row[m] = bulk_column(G[m:n, m], Sig[n], eps[n], n, m, h, k)
+    if k > 0:
+        near = [[Sig[n - k + u, n - k + i] for i in range(k)] for u in range(k)]
+        row[n - k:n] = near_block(near, Sig[n], eps, n, h, k)
     return row
 
 

@@ -160,6 +160,7 @@ struct hnessi_hodlr_s {
     double tol = 0.0;
     Weights W{};
     StepWeights SW{};   // weights of the retarded time step
+    cd* step_minv = nullptr;   // the step's M^{-1} (npair entries), allocated by the first step
     Geometry g;
     int MW = 0;           // merge width (kWSmall or kWLarge)
     DevAlloc al;
@@ -1112,6 +1113,13 @@ int hnessi_step_R(hnessi_hodlr_t H, int n, const void* eps, const void* sigR_row
         a.prev[l] = static_cast<const cd*>(prev_rows[l]);
     }
     hipStream_t st = (hipStream_t)stream;
+    if (!H->step_minv) {
+        if (dev_alloc(H->al, H->step_minv, (size_t)H->npair, false) != HNESSI_OK) {
+            H->step_minv = nullptr;
+            return fail(HNESSI_E_NOMEM, "device allocation of the step scratch failed");
+        }
+        HIP_TRY(hipStreamSynchronize(H->al.st));
+    }
     // the history sum over the stored rows, into the output row
     rc = do_history(H, n, sigR_row, nullptr, h, row_out, nullptr, true, false, st, 0, 0, false, false, true);
     if (rc != HNESSI_OK) return rc;
@@ -1125,6 +1133,7 @@ int hnessi_step_R(hnessi_hodlr_t H, int n, const void* eps, const void* sigR_row
     a.sigR = static_cast<const cd*>(sigR_row);
     a.sigNear = static_cast<const cd*>(sig_near);
     a.row = static_cast<cd*>(row_out);
+    a.minv = H->step_minv;
     if (H->prof.want(n)) {
         hipEvent_t ev[3] = {H->prof.ev(), H->prof.ev(), H->prof.ev()};
         HIP_TRY(launch_step(a, st, ev));

@@ -8,17 +8,20 @@
 // the differentiation weights); the integrals by the interval weights of the
 // section "Numerical integration".
 //
-//  * step_bulk, columns m < n-k (interval length L = n-m >= k+1): the left form,
-//      M G(n,m) = -(i/h) sum_{l=1..k} a_l G(n-l,m) + h sum_{j=m}^{n-1} w^{(L)}_{j-m} Sigma(n,j) G(j,m),
-//      M = (i a_0/h) 1 - eps(t_n) - h w^{(L)}_L Sigma(n,n).
-//    Since L >= k+1, w^{(L)}_L is the end weight omega_0 for every such column: M is
-//    the same matrix for the whole row, inverted once per workgroup (a 2 norb wide
-//    Gauss-Jordan sweep in LDS) and applied to each column's right side.
-//  * step_near, columns n-k..n-1: the right form at (t_n, t_m), whose integral
-//    over [t_m, t_n] and t'-derivative only touch the entries G(n, n-k..n); the k
-//    unknown norb x norb entries multiply known matrices from the right, so the
-//    norb rows of G decouple and one k norb x k norb system with norb right sides
-//    is solved (Gauss-Jordan with partial pivoting in LDS, one workgroup).
+//  * step_near (one workgroup): the matrix of the left form,
+//      M = (i a_0/h) 1 - eps(t_n) - h w^{(L)}_L Sigma(n,n),
+//    is the same for every column m < n-k (L = n-m >= k+1 makes w^{(L)}_L the end weight
+//    omega_0), so it is inverted once; then the right form at (t_n, t_m), m = n-k..n-1,
+//    whose integral over [t_m, t_n] and t'-derivative only touch the entries
+//    G(n, n-k..n): the k unknown norb x norb entries multiply known matrices from the
+//    right, so the norb rows of G decouple and one k norb x k norb system with norb
+//    right sides is solved.  Both by Gauss-Jordan elimination with partial pivoting in
+//    LDS.
+//  * step_bulk, columns m < n-k: the left form
+//      M G(n,m) = -(i/h) sum_{l=1..k} a_l G(n-l,m) + h sum_{j=m}^{n-1} w^{(L)}_{j-m} Sigma(n,j) G(j,m)
+//    (the history sum comes in through the output row), one streaming pass: every
+//    thread forms one entry of a column's right side, the block's right sides are
+//    staged in LDS and multiplied by M^{-1}.
 //
 // Both kernels are FP64.  A singular system (zero pivot) leaves non-finite entries.
 #include "step.h"
@@ -28,23 +31,29 @@ namespace {
 
 constexpr int NT = 256;
 
-// Gauss-Jordan elimination with partial pivoting by one workgroup on the
-// K x ld row-major matrix T in LDS, [A | B] with A of K columns: on return the
-// columns K..ld-1 hold A^{-1} B.  fcol: K entries of LDS, piv: one int of LDS.
-__device__ void gauss_jordan(cd* T, int K, int ld, cd* fcol, int* piv) {
+// Gauss-Jordan elimination with partial pivoting by one workgroup on the K x ld
+// row-major matrix T = [A | B] in LDS (A of K columns).  Rows are never exchanged:
+// the pivot of column p is the not yet used row prow[p] with the largest |T(r, p)|,
+// and every other row r loses T(r, p) / T(prow[p], p) times it in the columns right
+// of p (a column left of the current one is not read again, so it is not cleared).
+// Two barriers per column.  On return (A^{-1} B)[p][c] =
+// T[prow[p]][K + c] / T[prow[p]][p].  used, prow: K ints of LDS each.
+__device__ void gauss_jordan(cd* T, int K, int ld, int* used, int* prow) {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    for (int r = t; r < K; r += NT) used[r] = 0;
+    __syncthreads();
     for (int p = 0; p < K; ++p) {
-        if (wave == 0) {   // pivot row: the largest |A(r, p)|, r >= p (first one on ties)
+        if (wave == 0) {
             double best = -1.0;
-            int bi = p;
-            for (int r = p + lane; r < K; r += 64) {
-                const double v = norm2(T[r * ld + p]);
+            int bi = K;
+            for (int r = lane; r < K; r += 64) {
+                const double v = used[r] ? -1.0 : norm2(T[r * ld + p]);
                 if (v > best) {
                     best = v;
                     bi = r;
                 }
             }
-            for (int off = 32; off > 0; off >>= 1) {
+            for (int off = 32; off > 0; off >>= 1) {   // largest value, first row on ties
                 const double ov = __shfl_xor(best, off);
                 const int oi = __shfl_xor(bi, off);
                 if (ov > best || (ov == best && oi < bi)) {
@@ -52,35 +61,34 @@ __device__ void gauss_jordan(cd* T, int K, int ld, cd* fcol, int* piv) {
                     bi = oi;
                 }
             }
-            if (lane == 0) *piv = bi;
+            if (lane == 0) {
+                prow[p] = bi;
+                used[bi] = 1;
+            }
         }
         __syncthreads();
-        const int q = *piv;
-        if (q != p)   // the columns left of p are zero in both rows
-            for (int j = p + t; j < ld; j += NT) {
-                const cd x = T[p * ld + j];
-                T[p * ld + j] = T[q * ld + j];
-                T[q * ld + j] = x;
-            }
-        __syncthreads();
-        const cd d = T[p * ld + p];
+        const int q = prow[p];
+        const cd d = T[q * ld + p];
         const double s = 1.0 / norm2(d);
         const cd inv = mk(d.x * s, -d.y * s);
-        for (int r = t; r < K; r += NT) fcol[r] = T[r * ld + p];
-        __syncthreads();
-        for (int j = p + t; j < ld; j += NT) T[p * ld + j] = T[p * ld + j] * inv;
-        __syncthreads();
-        // remove column p from every other row (columns left of p are not read again)
-        const int w = ld - p;
-        for (int e = t; e < K * w; e += NT) {
-            const int r = e / w, j = p + e % w;
-            if (r != p) T[r * ld + j] = T[r * ld + j] - fcol[r] * T[p * ld + j];
+        const int w = ld - p - 1;
+        for (int e = t; e < K * w; e += NT) {   // T(r, p) is read here and written by no one
+            const int r = e / w, j = p + 1 + e % w;
+            if (r != q) T[r * ld + j] = T[r * ld + j] - (T[r * ld + p] * inv) * T[q * ld + j];
         }
         __syncthreads();
     }
 }
 
-// the near-diagonal system of the right form: with the unknowns
+// (A^{-1} B)[p][c] after gauss_jordan
+__device__ inline cd gj_solution(const cd* T, int K, int ld, const int* prow, int p, int c) {
+    const int q = prow[p];
+    const cd d = T[q * ld + p];
+    const double s = 1.0 / norm2(d);
+    return T[q * ld + K + c] * mk(d.x * s, -d.y * s);
+}
+
+// M^{-1} into A.minv, then the near-diagonal system of the right form: with the unknowns
 // Y[(u, a)][c] = G(n, n-k+u)[c][a], u = 0..k-1, and the equation of column
 // m = n-k+i (interval length L = k-i) as the row block (i, b):
 //   sum_{u,a} C_{u,i}[a][b] Y[(u,a)][c] = R_i[c][b],
@@ -90,10 +98,27 @@ template <int NORB>
 __global__ void __launch_bounds__(NT) step_near(StepArgs A) {
     constexpr int npair = NORB * NORB, KMAX = 5 * NORB, LDMAX = KMAX + NORB;
     __shared__ cd T[KMAX * LDMAX];
-    __shared__ cd fcol[KMAX];
-    __shared__ int piv;
+    __shared__ int used[KMAX], prow[KMAX];
     const int n = A.n, k = A.k, K = k * NORB, ld = K + NORB;
     const double h = A.h;
+    {   // [M | 1], NORB x 2 NORB
+        constexpr int l2 = 2 * NORB;
+        const double wl = h * A.W.om[0];   // h w^{(L)}_L for L >= k+1
+        for (int e = threadIdx.x; e < NORB * l2; e += NT) {
+            const int r = e / l2, col = e % l2;
+            cd v;
+            if (col < NORB)
+                v = mk(0.0, r == col ? A.S.a[0] / h : 0.0) - A.eps[(size_t)k * npair + r * NORB + col] -
+                    wl * A.sigR[(size_t)n * npair + r * NORB + col];
+            else
+                v = mk(r == col - NORB ? 1.0 : 0.0, 0.0);
+            T[e] = v;
+        }
+        __syncthreads();
+        gauss_jordan(T, NORB, l2, used, prow);
+        for (int e = threadIdx.x; e < npair; e += NT) A.minv[e] = gj_solution(T, NORB, l2, prow, e / NORB, e % NORB);
+        __syncthreads();
+    }
     for (int e = threadIdx.x; e < K * ld; e += NT) {
         const int r = e / ld, col = e % ld, i = r / NORB, b = r % NORB;
         cd v;
@@ -112,60 +137,46 @@ __global__ void __launch_bounds__(NT) step_near(StepArgs A) {
         T[e] = v;
     }
     __syncthreads();
-    gauss_jordan(T, K, ld, fcol, &piv);
+    gauss_jordan(T, K, ld, used, prow);
     for (int e = threadIdx.x; e < K * NORB; e += NT) {
         const int r = e / NORB, c = e % NORB, u = r / NORB, a = r % NORB;
-        A.row[(size_t)(n - k + u) * npair + c * NORB + a] = T[r * ld + K + c];
+        A.row[(size_t)(n - k + u) * npair + c * NORB + a] = gj_solution(T, K, ld, prow, r, c);
     }
     for (int e = threadIdx.x; e < npair; e += NT)
         A.row[(size_t)n * npair + e] = mk(0.0, e / NORB == e % NORB ? -1.0 : 0.0);
 }
 
-// columns m < n-k: thread (m, a) takes column a of the right side of column m
-// (it reads and then overwrites exactly the entries [m][b][a], b = 0..norb-1, of the
-// row) and applies M^{-1}
+// columns m < n-k, NT / npair columns per workgroup: thread (m, e) forms entry e = (b, a)
+// of column m's right side (reading exactly the row entry it later overwrites with entry
+// e = (c, a) of the solution; the barrier separates every read of the block's columns
+// from every write)
 template <int NORB>
 __global__ void __launch_bounds__(NT) step_bulk(StepArgs A) {
-    constexpr int npair = NORB * NORB, ld = 2 * NORB;
-    __shared__ cd T[NORB * ld];
-    __shared__ cd fcol[NORB];
-    __shared__ int piv;
-    const int n = A.n, k = A.k;
-    const double h = A.h;
-    const double wl = h * A.W.om[0];   // h w^{(L)}_L for L >= k+1
-    for (int e = threadIdx.x; e < NORB * ld; e += NT) {
-        const int r = e / ld, col = e % ld;
-        cd v;
-        if (col < NORB) {
-            v = mk(0.0, r == col ? A.S.a[0] / h : 0.0) - A.eps[(size_t)k * npair + r * NORB + col] -
-                wl * A.sigR[(size_t)n * npair + r * NORB + col];
-        } else {
-            v = mk(r == col - NORB ? 1.0 : 0.0, 0.0);
-        }
-        T[e] = v;
+    constexpr int npair = NORB * NORB, CPB = NT / npair;
+    __shared__ cd Mi[npair];
+    __shared__ cd R[CPB * npair];
+    const int t = threadIdx.x;
+    if (t < npair) Mi[t] = A.minv[t];
+    const long long m = (long long)blockIdx.x * CPB + t / npair;
+    const int e = t % npair;
+    const bool on = t < CPB * npair && m < A.n - A.k;
+    const double ih = 1.0 / A.h;
+    const size_t o = (size_t)m * npair + e;
+    if (on) {
+        cd s = mk(0.0, 0.0);
+#pragma unroll
+        for (int l = 1; l <= 5; ++l)
+            if (l <= A.k) s = s + A.S.a[l] * A.prev[l - 1][o];
+        const cd hist = A.row[o];
+        R[t] = mk(hist.x + s.y * ih, hist.y - s.x * ih);   // hist - (i/h) s
     }
     __syncthreads();
-    gauss_jordan(T, NORB, ld, fcol, &piv);   // T[:, NORB:] = M^{-1}
-    const long long t = (long long)blockIdx.x * NT + threadIdx.x;
-    const int m = (int)(t / NORB), a = (int)(t % NORB);
-    if (m >= n - k) return;
-    const double ih = 1.0 / h;
-    cd x[NORB];
+    if (!on) return;
+    const int c = e / NORB, a = e % NORB, base = t - e;
+    cd y = mk(0.0, 0.0);
 #pragma unroll
-    for (int b = 0; b < NORB; ++b) {
-        const size_t o = (size_t)m * npair + b * NORB + a;
-        cd s = mk(0.0, 0.0);
-        for (int l = 1; l <= k; ++l) s = s + A.S.a[l] * A.prev[l - 1][o];
-        const cd hist = A.row[o];
-        x[b] = mk(hist.x + s.y * ih, hist.y - s.x * ih);   // hist - (i/h) s
-    }
-#pragma unroll
-    for (int c = 0; c < NORB; ++c) {
-        cd y = mk(0.0, 0.0);
-#pragma unroll
-        for (int b = 0; b < NORB; ++b) fma_(y, T[c * ld + NORB + b], x[b]);
-        A.row[(size_t)m * npair + c * NORB + a] = y;
-    }
+    for (int b = 0; b < NORB; ++b) fma_(y, Mi[c * NORB + b], R[base + b * NORB + a]);
+    A.row[o] = y;
 }
 
 template <int NORB>
@@ -173,8 +184,9 @@ hipError_t launch_step_t(const StepArgs& a, hipStream_t st, hipEvent_t* ev) {
     if (ev) hipEventRecord(ev[0], st);
     step_near<NORB><<<1, NT, 0, st>>>(a);
     if (ev) hipEventRecord(ev[1], st);
-    const long long threads = (long long)(a.n - a.k) * NORB;
-    if (threads > 0) step_bulk<NORB><<<(unsigned)((threads + NT - 1) / NT), NT, 0, st>>>(a);
+    constexpr int CPB = NT / (NORB * NORB);
+    const int nb = a.n - a.k;
+    if (nb > 0) step_bulk<NORB><<<(nb + CPB - 1) / CPB, NT, 0, st>>>(a);
     if (ev) hipEventRecord(ev[2], st);
     return hipGetLastError();
 }

@@ -135,3 +135,103 @@ def test_step_argument_errors(P):
     ref = step(G0, S, eps, k, h, k)
     got = out[:k + 1].cpu().numpy()
     assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+# ---------------------------------------------------------------------------
+# Full-size grids: norb 4 on the N_t = 8192 grid with FP64 factors at SVD tolerance 1e-10
+# (all 8192 steps), norb 16 on the N_t = 8192 grid with FP32 factors at 1e-6 (first 2048
+# steps).  The march runs on the GPU with Sigma^R rows from the device row source; at
+# sampled steps, sampled bulk columns (level boundaries 64*2^l and their neighbours, leaf
+# starts, random) are recomputed by the oracle's column step from the GPU's own earlier
+# rows, and the near-diagonal entries by the oracle's near-diagonal solve.  Errors are
+# scaled by the oracle's largest entry over the sampled columns of the row.
+# A marched G^R is not low-rank by construction: its blocks carry every pole of
+# (omega - eps - Sigma(omega))^{-1}, norb (1 + terms) of them, and a time-dependent eps
+# adds more.  The inputs are therefore chosen so that the block ranks stay within the
+# storage's rank capacity (32 at norb 4, 16 with FP32 factors at norb 16): a constant
+# Hermitian eps with a 2-term Sigma^R at norb 4 (12 poles), and at norb 16 eps
+# and a 1-term Sigma^R sharing one eigenbasis with 4 distinct channels (8 poles); the
+# multistep scheme adds parasitic modes that decay within a few dozen steps.
+
+def _inputs_norb4(cfg):
+    N, h = cfg["nt"], cfg["h"]
+    return hermitian_drive(cfg["seed_s"] + 100, cfg["norb"], N, h, amp=0.0), hermitian_terms(cfg["seed_s"], 2, cfg["norb"])
+
+
+def _inputs_channels(cfg):
+    from kbe_inputs import channel_terms
+    eps0, pS = channel_terms(cfg["seed_s"], cfg["norb"], 4, 1)
+    return np.broadcast_to(eps0, (cfg["nt"],) + eps0.shape).copy(), pS
+
+
+def _full_march(P, key, n_march, checks, ncols, f32, make_inputs):
+    from gpu_common import boundary_columns
+    from kbe_inputs import make_config_inputs
+    from kbe_inputs.packed import RowSource
+    from oracle.step_solve import bulk_column, near_block
+
+    cfg = make_config_inputs(key)[0]
+    N, norb, h, k, tol = cfg["nt"], cfg["norb"], cfg["h"], cfg["k"], cfg["tol"]
+    eps_h, pS = make_inputs(cfg)
+    nlvl = int(round(np.log2(N // cfg["leaf"])))
+    rng = np.random.default_rng(17)
+    steps = sorted(set(checks))
+    colset = {n: [m for m in boundary_columns(n, cfg["leaf"], nlvl, rng, ncols) if m < n - k] for n in steps}
+    mcols = np.array(sorted(set().union(*colset.values())), dtype=np.int64)
+    pos = {int(m): i for i, m in enumerate(mcols)}
+    src = RowSource(pS, N, h, "cuda")
+    eps_d = to_dev(eps_h)
+    near_h = np.zeros((k, k, norb, norb), dtype=np.complex128)
+    for u in range(k):
+        for i in range(u + 1):
+            near_h[u, i] = retarded(pS, (u - i) * h, 0.0)
+    near_d = to_dev(near_h)
+    H = P.Hodlr(N, nlvl, norb, k=k, tol=tol, panel=16, max_rank=16 if f32 else 32,
+                flags=P.FLAG_FP32_FACTORS if f32 else 0)
+    mc_d = torch.as_tensor(mcols, device="cuda")
+    Gc = torch.zeros((n_march, len(mcols), norb, norb), dtype=torch.complex128, device="cuda")
+    saved, ring = {}, []
+    say(f"full-size march {key}: N {N} norb {norb} steps {n_march}, {len(mcols)} sampled columns")
+    for n in range(n_march):
+        if n < k:
+            row = to_dev(np.stack([-1j * expm(-1j * eps_h[0] * (n - m) * h) for m in range(n + 1)]))
+        else:
+            row = torch.empty((n + 1, norb, norb), dtype=torch.complex128, device="cuda")
+            H.step_R(n, eps_d[n - k:n + 1], src.ret(n), near_d, ring[::-1], h, row)
+        H.append_row(P.RET, n, row)
+        sel = int(np.searchsorted(mcols, n, side="right"))
+        if sel:
+            Gc[n, :sel] = row[mc_d[:sel]]
+        if n in colset:
+            saved[n] = row.cpu().numpy()
+        ring = (ring + [row])[-k:]
+        if n % 1024 == 1023:
+            torch.cuda.synchronize()
+            say(f"  step {n + 1}")
+    torch.cuda.synchronize()
+    say(f"  max rank {int(H.ranks(P.RET).max())}")
+    H.status()   # raises if a truncation needed more than max_rank values
+    Gc_h = Gc.cpu().numpy()
+    bar = 1e-5 if f32 else max(1e-10, tol)
+    worst = 0.0
+    t = np.arange(N) * h
+    for n in steps:
+        srow = retarded(pS, t[n], t[:n + 1])
+        got = saved[n]
+        ref = {m: bulk_column(Gc_h[m:n, pos[m]], srow, eps_h[n], n, m, h, k) for m in colset[n]}
+        nb = near_block(near_h, srow, eps_h, n, h, k)
+        scale = max([np.abs(r).max() for r in ref.values()] + [np.abs(nb).max()])
+        err = max([np.abs(got[m] - r).max() for m, r in ref.items()] + [np.abs(got[n - k:n] - nb).max()]) / scale
+        assert np.array_equal(got[n], -1j * np.eye(norb)), n
+        worst = max(worst, err)
+        say(f"  step {n}: {len(ref)} bulk columns + {k} near-diagonal, relative error {err:.2e}")
+        assert err <= bar, (n, err, bar)
+    say(f"  worst {worst:.2e} (bar {bar:.0e})")
+
+
+def test_step_full_size_norb4(P):
+    _full_march(P, "c2", 8192, [5, 6, 63, 64, 1023, 1024, 4096, 8191], 40, False, _inputs_norb4)
+
+
+def test_step_full_size_norb16_fp32(P):
+    _full_march(P, "c4", 2048, [5, 64, 1023, 2047], 24, True, _inputs_channels)
