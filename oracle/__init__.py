@@ -11,6 +11,8 @@ library computes, written from the paper's definitions:
   tsvd         truncated SVD with the absolute epsilon_SVD rule
                (section "Hierarchical decomposition")
   adjoint      dense gradient of the adjoint loss
+  step_solve   the retarded time step (Volterra step solve) and its march
+  born         the lattice second-Born self-energy of one time step
 
 Only tests, the smoke entry point and the benchmark's CPU-baseline leg may
 import this package.  The device library never calls it, links it or falls
