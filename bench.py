@@ -301,6 +301,67 @@ def _lattice_inputs(G, S, sel, N, h, dev):
     return arrs
 
 
+def born_lattice_bench(P, B, arrs, N, h, nk, side, tot, ptr, oR, oL, run_state, U=0.5):
+    """Lattice second-Born self-energy (hnessi_born_lattice) at the lattice workload:
+    (1) the kernel alone at every step n (G^R row n and G^< slice n of all momenta read
+    from the packed triangles, Sigma rows written to row buffers), HIP events around every
+    8th launch on the launch stream; (2) a sweep whose history step takes its Sigma from
+    the Born kernel (append the two G rows, Born self-energy of the step into the Sigma
+    triangles, history step), timed as a whole."""
+    import ctypes as C
+    import numpy as np
+    import torch
+    L, chk, st = run_state
+    dev = torch.device("cuda:0")
+    sR = torch.empty((nk, N), dtype=torch.complex128, device=dev)
+    sL = torch.empty_like(sR)
+    pR, pL = C.c_void_p(sR.data_ptr()), C.c_void_p(sL.data_ptr())
+    ev = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for n in range(N):
+        off = n * (n + 1) // 2 * 16
+        if n % 8 == 7:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+        chk(L.hnessi_born_lattice(side, n, U, C.c_void_p(ptr[0] + off), C.c_void_p(ptr[1] + off), tot, pR, pL, N,
+                                  st))
+        if n % 8 == 7:
+            e1.record()
+            ev.append((n, e0, e1))
+    torch.cuda.synchronize()
+    dt1 = time.perf_counter() - t0
+    ms = np.array([a.elapsed_time(b) for _, a, b in ev])
+    nb = np.array([4.0 * nk * (n + 1) * 16 for n, _, _ in ev])
+    gbs = float(nb.sum() / (ms.sum() * 1e-3) / 1e9)
+
+    def run(n_end):
+        B.reset()
+        for n in range(n_end):
+            off = n * (n + 1) // 2 * 16
+            chk(L.hnessi_hodlr_append_row_batched(B.h, 0, n, C.c_void_p(ptr[0] + off), tot, st))
+            chk(L.hnessi_hodlr_append_row_batched(B.h, 1, n, C.c_void_p(ptr[1] + off), tot, st))
+            chk(L.hnessi_born_lattice(side, n, U, C.c_void_p(ptr[0] + off), C.c_void_p(ptr[1] + off), tot,
+                                      C.c_void_p(ptr[2] + off), C.c_void_p(ptr[3] + off), tot, st))
+            chk(L.hnessi_history_step_batched(B.h, n, C.c_void_p(ptr[2] + off), C.c_void_p(ptr[3] + off), tot,
+                                              h, oR, oL, N, st))
+
+    B.profile(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(N)
+    torch.cuda.synchronize()
+    dt2 = time.perf_counter() - t0
+    log(f"born: kernel alone {N / dt1:.0f} steps/s, {gbs:.0f} GB/s; sweep with born {N / dt2:.1f} steps/s")
+    del sR, sL
+    return dict(kernel_steps_per_s=round(N / dt1, 1), unit="time steps/s (all momenta)", U=U, L=side,
+                kernel_gbs=round(gbs, 1), kernel_frac=round(gbs / HBM_PEAK_GBS, 4),
+                avg_launch_us=round(1e3 * float(ms.mean()), 2), launches_timed=int(len(ms)),
+                alg_bytes_note="4 N_k (n+1) complex128 per step: G^R row and G^< slice read, Sigma^R row "
+                               "and Sigma^< slice written",
+                sweep_with_born_steps_per_s=round(N / dt2, 2), sweep_status=B.status())
+
+
 def lattice_bench(P, prof_stride):
     """Batched form at the lattice workload: 32x32 momenta (nk = 1024), N_t = 2048, norb = 1,
     one handle for all momenta, one timed launch-by-launch sweep (append both rows, merges,
@@ -357,8 +418,9 @@ def lattice_bench(P, prof_stride):
     st0, ms0 = B.profile_read(0)
     _, ms1 = B.profile_read(1)
     b_tasks, b_comb = algorithmic_bytes(N, 1, 16, B.blocks(), B.leaves(), ranks, list(st0), nk=nk)
+    born = born_lattice_bench(P, B, arrs, N, h, nk, cfg["nk_side"], tot, ptr, oR, oL, run_state=(L, chk, st))
     out = dict(value=round(N / dt, 2), unit="time steps/s (all momenta)", nk=nk, n_t=N, norb=1,
-               sweep_s=round(dt, 3), status=status,
+               sweep_s=round(dt, 3), status=status, born=born,
                hist_tasks_gbs=round(float(b_tasks.sum() / (ms0.sum() * 1e-3) / 1e9), 1),
                hist_combine_gbs=round(float(b_comb.sum() / (ms1.sum() * 1e-3) / 1e9), 1),
                max_rank=int(max(r.max() for r in ranks)), device_gib=round(B.nbytes() / 2**30, 2),

@@ -135,6 +135,32 @@ int hnessi_get_tile_shape(hnessi_hodlr_t H);
  * approximations".  Returns HNESSI_E_ARG for k outside 1..5 or L < 0. */
 int hnessi_weights(int k, int L, double* w_host);
 
+/* Lattice second-Born self-energy of one time step (section "Driven 2D Hubbard
+ * example", Eq. BornApproxLG, evaluated in real space as its "Implementation
+ * details" describe: G_k -> G_r, local product, Sigma_r -> Sigma_k):
+ *   Sigma^>_r(t,t') = U^2 G^>_r(t,t')^2 G^<_{-r}(t',t),
+ *   Sigma^<_r(t,t') = U^2 G^<_r(t,t')^2 G^>_{-r}(t',t),
+ * one band on the L x L square lattice (L = 2, 4, 8, 16 or 32), momenta
+ * k = 2 pi (kx, ky)/L and sites r = (x, y) both x-major, G_r = (1/L^2) sum_k
+ * e^{i k.r} G_k, Sigma_k = sum_r e^{-i k.r} Sigma_r.  Row t = t_n, t' = t_j,
+ * j = 0..n; the greater and lesser values follow from the stored ones by the
+ * definitions of the components (G^R = G^> - G^< for t >= t', anti-Hermitian
+ * greater and lesser functions).
+ * Device arrays of complex128; object (momentum) k starts k * stride entries after
+ * the array's start, entry j of its row at +j:
+ *   GR_rows    G^R_k(t_n, t_j)           GL_slices  G^<_k(t_j, t_n)   (in_stride)
+ *   SR_rows    Sigma^R_k(t_n, t_j)       SL_slices  Sigma^<_k(t_j, t_n) (out_stride)
+ * i.e. the retarded row and the lesser slice in the orientations of
+ * hnessi_hodlr_append_row and of the history calls, so the outputs are the Sigma
+ * inputs of step n of a batched lattice handle.  The outputs may alias the inputs
+ * only exactly (SR_rows == GR_rows, SL_slices == GL_slices, equal strides);
+ * otherwise they must not overlap them.  Errors: L not allowed, a NULL pointer, a
+ * stride below n+1 or a non-finite U (HNESSI_E_ARG); n < 0 (HNESSI_E_RANGE).
+ * Enqueued on stream; the call does not wait for the device. */
+int hnessi_born_lattice(int L, int n, double U, const void* GR_rows, const void* GL_slices,
+                        long long in_stride, void* SR_rows, void* SL_slices,
+                        long long out_stride, void* stream);
+
 /* Weights of the retarded time step (hnessi_step_R) for order k (1..5), host
  * outputs: a_host[0..k] the backward differentiation weights a_l = -D_{0l}
  * (f'(t_n) h ~ sum_l a_l f(t_{n-l})) and D_host[i*(k+1) + p], i, p = 0..k, the

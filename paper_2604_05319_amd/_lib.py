@@ -39,6 +39,8 @@ _SIGS = {
     "hnessi_set_allocator": ([ALLOC_FN, FREE_FN, C.c_void_p], C.c_int),
     "hnessi_weights": ([C.c_int, C.c_int, C.c_void_p], C.c_int),
     "hnessi_step_weights": ([C.c_int, C.c_void_p, C.c_void_p], C.c_int),
+    "hnessi_born_lattice": ([C.c_int, C.c_int, C.c_double, C.c_void_p, C.c_void_p, C.c_longlong, C.c_void_p,
+                             C.c_void_p, C.c_longlong, C.c_void_p], C.c_int),
     "hnessi_hodlr_create": ([C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
                              C.c_int, C.c_int, C.c_int, C.c_void_p], C.c_int),
     "hnessi_hodlr_create_batched": ([C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
@@ -208,6 +210,14 @@ def weights(k: int, L: int) -> np.ndarray:
     w = np.zeros(L + 1, dtype=np.float64)
     _check(lib().hnessi_weights(k, L, w.ctypes.data_as(C.c_void_p)))
     return w
+
+
+def born_lattice(L, n, U, GR, GL, in_stride, SR, SL, out_stride):
+    """Lattice second-Born self-energy of step n: Sigma^R_k(t_n, t_j) into SR and
+    Sigma^<_k(t_j, t_n) into SL from G^R_k(t_n, t_j) and G^<_k(t_j, t_n) (device tensors,
+    object k at k * stride, entries j = 0..n)."""
+    _check(lib().hnessi_born_lattice(L, n, U, _ptr(GR), _ptr(GL), in_stride, _ptr(SR), _ptr(SL), out_stride,
+                                     _stream()))
 
 
 def step_weights(k: int):

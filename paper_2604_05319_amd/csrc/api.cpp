@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -10,6 +11,7 @@
 
 #include "../../include/hnessi.h"
 #include "alloc.h"
+#include "born.h"
 #include "common.h"
 #include "dense.h"
 #include "history.h"
@@ -304,6 +306,29 @@ int hnessi_weights(int k, int L, double* w_host) {
     std::string err;
     if (!interval_weights_exact(k, L, w, err)) return fail(HNESSI_E_ARG, err);
     std::memcpy(w_host, w.data(), w.size() * sizeof(double));
+    return HNESSI_OK;
+}
+
+int hnessi_born_lattice(int L, int n, double U, const void* GR_rows, const void* GL_slices, long long in_stride,
+                        void* SR_rows, void* SL_slices, long long out_stride, void* stream) {
+    if (!(L == 2 || L == 4 || L == 8 || L == 16 || L == 32)) return fail(HNESSI_E_ARG, "L must be 2, 4, 8, 16 or 32");
+    if (n < 0) return fail(HNESSI_E_RANGE, "n must be >= 0");
+    if (!GR_rows || !GL_slices || !SR_rows || !SL_slices) return fail(HNESSI_E_ARG, "a pointer is NULL");
+    if (in_stride < n + 1 || out_stride < n + 1) return fail(HNESSI_E_ARG, "object stride shorter than a row");
+    if (!std::isfinite(U)) return fail(HNESSI_E_ARG, "U must be finite");
+    int rc = lib_init();
+    if (rc != HNESSI_OK) return rc;
+    BornArgs a{};
+    a.L = L;
+    a.n = n;
+    a.u2 = U * U;
+    a.GR = static_cast<const cd*>(GR_rows);
+    a.GL = static_cast<const cd*>(GL_slices);
+    a.inStride = in_stride;
+    a.SR = static_cast<cd*>(SR_rows);
+    a.SL = static_cast<cd*>(SL_slices);
+    a.outStride = out_stride;
+    HIP_TRY(launch_born(a, (hipStream_t)stream));
     return HNESSI_OK;
 }
 
