@@ -489,10 +489,11 @@ __global__ void __launch_bounds__(NT) merge_down_kernel(MergeArgs a) {
     constexpr int CH = merge_ch(W), NQ = node_q(W), CQ = chunk_q(W);
     constexpr int XR = CH > 2 * W ? CH : 2 * W;      // rows of X (a chunk, or a tree node)
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cd* A = reinterpret_cast<cd*>(smem_raw);       // CH x W
-    cd* X = A + (size_t)CH * W;                     // XR x RC (the updated V rows, rank <= RC)
+    // the chunk's and the tree nodes' reflectors are read from global memory (each
+    // reflector twice per application), so that the workgroup's LDS leaves room on its
+    // compute unit for history workgroups
+    cd* X = reinterpret_cast<cd*>(smem_raw);        // XR x RC (the updated V rows, rank <= RC)
     cd* T = X + (size_t)XR * a.RC;                  // W x W
-    cd* tau = T + (size_t)W * W;                    // W
 
     if ((int)blockIdx.x < a.ntask_v) {
         Ctx c = decode_task(a, blockIdx.x);
@@ -502,12 +503,8 @@ __global__ void __launch_bounds__(NT) merge_down_kernel(MergeArgs a) {
         const int r_old = clamp_rank(m_rold(a)[pidx], min(a.RCr, W - a.pp));
         const int rnew = clamp_rank(wr_rank(a, B)[fq], a.RC);
         const int w = r_old + a.pp;
-        {   // the chunk's reflectors from merge_up
-            const cd* cq = m_chunkQ(a) + (size_t)(B.chunk_base + (long long)c.q * B.nchunks + c.chunk) * CQ;
-            for (int e = threadIdx.x; e < CH * w; e += NT) A[e] = cq[e];
-            for (int e = threadIdx.x; e < w; e += NT) tau[e] = cq[CH * W + e];
-        }
-        __syncthreads();
+        // the chunk's reflectors from merge_up
+        const cd* cq = m_chunkQ(a) + (size_t)(B.chunk_base + (long long)c.q * B.nchunks + c.chunk) * CQ;
         const cd* VR = m_VR(a) + pidx * W * W;
         for (int e = threadIdx.x; e < W * W; e += NT) {
             int col = e / W, i = e % W;
@@ -544,7 +541,7 @@ __global__ void __launch_bounds__(NT) merge_down_kernel(MergeArgs a) {
             X[e] = (i < w) ? T[(size_t)col * W + i] : mk(0.0, 0.0);
         }
         __syncthreads();
-        hh_apply_q<W>(A, CH, w, tau, X, rnew);
+        hh_apply_q<W>(cq, CH, w, cq + (size_t)CH * W, X, rnew);
         const int row0 = c.chunk * CH;
         const int nr = min(CH, B.ncols - row0);
         const size_t vo = B.Voff + (size_t)c.q * a.RC * B.ncols;
@@ -609,8 +606,7 @@ size_t merge_up_smem() {
 template <int W>
 size_t merge_down_smem(int RC) {
     constexpr int CH = merge_ch(W), XR = CH > 2 * W ? CH : 2 * W;
-    return (size_t)CH * W * sizeof(cd) + (size_t)XR * RC * sizeof(cd) + (size_t)W * W * sizeof(cd) +
-           (size_t)W * sizeof(cd) + 16 * sizeof(double);
+    return (size_t)XR * RC * sizeof(cd) + (size_t)W * W * sizeof(cd) + 16 * sizeof(double);
 }
 
 template <int W>
