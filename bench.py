@@ -544,6 +544,58 @@ def step_solve_bench(P, prof_stride=8):
     return out
 
 
+def lattice_step_bench(P):
+    """The retarded time step of every momentum of the 32x32 lattice (hnessi_step_R_batched,
+    N_t = 2048, norb 1): each step the batched history sum over the stored rows, the step
+    solves and the batched append; Sigma_k^R from the lattice generator, eps_k the
+    dispersion, rows 0..k-1 the free propagators.  Timed as a whole march."""
+    import numpy as np
+    import torch
+    from kbe_inputs import make_config_inputs, retarded
+    cfg, _, Sg = make_config_inputs("c3")
+    N, h, k = cfg["nt"], cfg["h"], cfg["k"]
+    nk = len(Sg)
+    nlvl = int(round(np.log2(N // cfg["leaf"])))
+    dev = torch.device("cuda:0")
+    eps_k = np.array([s.meta["eps"] for s in Sg])
+    t = np.arange(N) * h
+    Td = torch.from_numpy(np.stack([retarded(s, t[::-1], 0.0)[:, 0, 0] for s in Sg])).to(dev)
+    E = torch.from_numpy(np.repeat(eps_k[:, None], k + 1, axis=1).astype(np.complex128)).to(dev)
+    near = np.zeros((nk, k, k), dtype=np.complex128)
+    for o in range(nk):
+        for u in range(k):
+            for i in range(u + 1):
+                near[o, u, i] = retarded(Sg[o], (u - i) * h, 0.0)[0, 0]
+    nearD = torch.from_numpy(near).to(dev)
+    start = torch.from_numpy(-1j * np.exp(-1j * eps_k[:, None] * t[None, :])).to(dev)   # -i e^{-i eps_k t}
+    ring = torch.zeros((k + 1, nk, N), dtype=torch.complex128, device=dev)
+    B = P.HodlrBatch(nk, N, nlvl, 1, k=k, tol=cfg["tol"], panel=16, max_rank=32)
+
+    def march(n_end):
+        B.reset()
+        for n in range(n_end):
+            slot = ring[n % (k + 1)]
+            if n < k:
+                slot[:, :n + 1] = start[:, :n + 1].flip(1)
+            else:
+                prev = [ring[(n - l) % (k + 1)] for l in range(1, k + 1)]
+                B.step_R(n, E.view(-1), k + 1, Td.view(-1)[N - 1 - n:], N, nearD.view(-1), k * k, prev, N, h,
+                         slot, N)
+            B.append_row(P.RET, n, slot, N)
+
+    march(256)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    march(N)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = dict(value=round(N / dt, 2), unit="time steps/s (all 1024 momenta: batched history sum, step solves, "
+                                            "append)", nk=nk, n_t=N, seconds=round(dt, 3),
+               max_rank=int(B.ranks(P.RET).max()), status=B.status())
+    B.close()
+    return out
+
+
 def adjoint_bench(P):
     """Adjoint form at its workload (norb = 2, N_t = 2048, leaf 64): forward sweep of I^R and
     the backward sweep over the frozen compressed state (dL/dSigma^R and dL/d(U, S, V) at
@@ -761,6 +813,7 @@ def main():
     step_solve = None
     if not args.no_step:
         step_solve = step_solve_bench(P, args.prof_stride)
+        step_solve["lattice"] = lattice_step_bench(P)
         log("step solve:", step_solve)
 
     adjoint = None

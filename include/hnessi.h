@@ -405,6 +405,18 @@ int hnessi_history_step_batched(hnessi_hodlr_t H, int n, const void* sigR_rows, 
                                 long long in_stride, double h, void* outR, void* outL, long long out_stride,
                                 void* stream);
 
+/* hnessi_step_R for every object (the retarded time step per momentum, each object
+ * with its own eps and Sigma^R): object o's arrays start o * stride complex entries
+ * after the given pointers -- eps (k+1 matrices) at eps_stride, the Sigma^R row at
+ * in_stride, the k*k near-diagonal Sigma^R matrices at near_stride, each previous row
+ * prev_rows[l-1] at prev_stride, the output row at out_stride.  On a handle of more
+ * than one object a stride smaller than one object's data (k+1, n+1, k*k, n-k and n+1
+ * matrices) gives HNESSI_E_ARG; other errors as for hnessi_step_R. */
+int hnessi_step_R_batched(hnessi_hodlr_t H, int n, const void* eps, long long eps_stride,
+                          const void* sigR_rows, long long in_stride, const void* sig_near,
+                          long long near_stride, const void* const* prev_rows, long long prev_stride,
+                          double h, void* rows_out, long long out_stride, void* stream);
+
 /* hnessi_sweep for every object (the time-stepping loop per momentum):
  * the six packed triangles of object o start
  * at o*k_stride elements (k_stride >= nt(nt+1)/2 * norb^2). */

@@ -58,6 +58,9 @@ _SIGS = {
     "hnessi_history_R": ([C.c_void_p, C.c_int, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p], C.c_int),
     "hnessi_step_R": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                        C.c_void_p, C.c_void_p], C.c_int),
+    "hnessi_step_R_batched": ([C.c_void_p, C.c_int, C.c_void_p, C.c_longlong, C.c_void_p, C.c_longlong, C.c_void_p,
+                               C.c_longlong, C.c_void_p, C.c_longlong, C.c_double, C.c_void_p, C.c_longlong,
+                               C.c_void_p], C.c_int),
     "hnessi_history_lesser": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p,
                                C.c_void_p], C.c_int),
     "hnessi_history_R_adjoint": ([C.c_void_p, C.c_int, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p],
@@ -386,6 +389,15 @@ class HodlrBatch(Hodlr):
     def history_step(self, n, sigR, sigL, in_stride, h, outR, outL, out_stride):
         _check(lib().hnessi_history_step_batched(self.h, n, _ptr(sigR), _ptr(sigL), in_stride, h, _ptr(outR),
                                                  _ptr(outL), out_stride, _stream()))
+
+    def step_R(self, n, eps, eps_stride, sigR, in_stride, sig_near, near_stride, prev_rows, prev_stride, h,
+               out, out_stride):
+        """Row n of G^R of every object (strides in complex entries between objects)."""
+        if len(prev_rows) != self.k:
+            raise ValueError(f"prev_rows must hold the k = {self.k} previous rows")
+        ptrs = (C.c_void_p * self.k)(*[_ptr(r).value for r in prev_rows])
+        _check(lib().hnessi_step_R_batched(self.h, n, _ptr(eps), eps_stride, _ptr(sigR), in_stride, _ptr(sig_near),
+                                           near_stride, ptrs, prev_stride, h, _ptr(out), out_stride, _stream()))
 
     def sweep(self, n_begin, n_end, GR, GL, SR, SL, h, IR, IL, k_stride=None):
         """Packed triangles of every object, object-major (k_stride defaults to one triangle)."""

@@ -1123,30 +1123,38 @@ int hnessi_history_R(hnessi_hodlr_t H, int n, const void* sigR_row, double h, vo
     return rc != HNESSI_OK ? rc : mark(H, (hipStream_t)stream);
 }
 
-int hnessi_step_R(hnessi_hodlr_t H, int n, const void* eps, const void* sigR_row, const void* sig_near,
-                  const void* const* prev_rows, double h, void* row_out, void* stream) {
-    int rc = single_only(H);
-    if (rc != HNESSI_OK) return rc;
+}  // extern "C"
+
+namespace {
+
+// one step of every object: strides in complex entries from one object's array to the next
+int step_impl(hnessi_hodlr_t H, int n, const void* eps, long long eps_stride, const void* sigR_rows,
+              long long in_stride, const void* sig_near, long long near_stride, const void* const* prev_rows,
+              long long prev_stride, double h, void* rows_out, long long out_stride, hipStream_t st) {
     const int k = H->k;
+    const long long np = H->npair;
     if (n < 0 || n >= H->nt) return fail(HNESSI_E_RANGE, "n outside the grid");
     if (n < k) return fail(HNESSI_E_RANGE, "the step needs n >= k (the first k rows are a start-up)");
-    if (!eps || !sigR_row || !sig_near || !prev_rows || !row_out) return fail(HNESSI_E_ARG, "a pointer is NULL");
+    if (!eps || !sigR_rows || !sig_near || !prev_rows || !rows_out) return fail(HNESSI_E_ARG, "a pointer is NULL");
     if (!(h > 0.0)) return fail(HNESSI_E_ARG, "h must be > 0");
+    if (H->nk > 1 && (eps_stride < (k + 1) * np || in_stride < (n + 1) * np || near_stride < (long long)k * k * np ||
+                      prev_stride < (n - k) * np || out_stride < (n + 1) * np))
+        return fail(HNESSI_E_ARG, "object stride smaller than one object's data");
     StepArgs a{};
     for (int l = 0; l < k; ++l) {
         if (!prev_rows[l]) return fail(HNESSI_E_ARG, "a previous row is NULL");
         a.prev[l] = static_cast<const cd*>(prev_rows[l]);
     }
-    hipStream_t st = (hipStream_t)stream;
     if (!H->step_minv) {
-        if (dev_alloc(H->al, H->step_minv, (size_t)H->npair, false) != HNESSI_OK) {
+        if (dev_alloc(H->al, H->step_minv, (size_t)(np * H->nk), false) != HNESSI_OK) {
             H->step_minv = nullptr;
             return fail(HNESSI_E_NOMEM, "device allocation of the step scratch failed");
         }
         HIP_TRY(hipStreamSynchronize(H->al.st));
     }
-    // the history sum over the stored rows, into the output row
-    rc = do_history(H, n, sigR_row, nullptr, h, row_out, nullptr, true, false, st, 0, 0, false, false, true);
+    // the history sum over the stored rows, into the output rows
+    int rc = do_history(H, n, sigR_rows, nullptr, h, rows_out, nullptr, true, false, st, in_stride, out_stride,
+                        false, false, true);
     if (rc != HNESSI_OK) return rc;
     a.n = n;
     a.k = k;
@@ -1155,10 +1163,16 @@ int hnessi_step_R(hnessi_hodlr_t H, int n, const void* eps, const void* sigR_row
     a.W = H->W;
     a.S = H->SW;
     a.eps = static_cast<const cd*>(eps);
-    a.sigR = static_cast<const cd*>(sigR_row);
+    a.sigR = static_cast<const cd*>(sigR_rows);
     a.sigNear = static_cast<const cd*>(sig_near);
-    a.row = static_cast<cd*>(row_out);
+    a.row = static_cast<cd*>(rows_out);
     a.minv = H->step_minv;
+    a.nk = H->nk;
+    a.kEps = eps_stride;
+    a.kSig = in_stride;
+    a.kNear = near_stride;
+    a.kPrev = prev_stride;
+    a.kRow = out_stride;
     if (H->prof.want(n)) {
         hipEvent_t ev[3] = {H->prof.ev(), H->prof.ev(), H->prof.ev()};
         HIP_TRY(launch_step(a, st, ev));
@@ -1167,7 +1181,29 @@ int hnessi_step_R(hnessi_hodlr_t H, int n, const void* eps, const void* sigR_row
     } else {
         HIP_TRY(launch_step(a, st));
     }
-    return mark(H, st);
+    return HNESSI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hnessi_step_R(hnessi_hodlr_t H, int n, const void* eps, const void* sigR_row, const void* sig_near,
+                  const void* const* prev_rows, double h, void* row_out, void* stream) {
+    int rc = single_only(H);
+    if (rc != HNESSI_OK) return rc;
+    rc = step_impl(H, n, eps, 0, sigR_row, 0, sig_near, 0, prev_rows, 0, h, row_out, 0, (hipStream_t)stream);
+    return rc != HNESSI_OK ? rc : mark(H, (hipStream_t)stream);
+}
+
+int hnessi_step_R_batched(hnessi_hodlr_t H, int n, const void* eps, long long eps_stride, const void* sigR_rows,
+                          long long in_stride, const void* sig_near, long long near_stride,
+                          const void* const* prev_rows, long long prev_stride, double h, void* rows_out,
+                          long long out_stride, void* stream) {
+    if (!H) return fail(HNESSI_E_ARG, "handle is NULL");
+    int rc = step_impl(H, n, eps, eps_stride, sigR_rows, in_stride, sig_near, near_stride, prev_rows, prev_stride, h,
+                       rows_out, out_stride, (hipStream_t)stream);
+    return rc != HNESSI_OK ? rc : mark(H, (hipStream_t)stream);
 }
 
 int hnessi_history_lesser(hnessi_hodlr_t H, int n, const void* sigR_row, const void* sigL_slice,

@@ -23,8 +23,12 @@ struct StepArgs {
     const cd* prev[5];  // prev[l-1]: row n-l of G^R, G^R(n-l, m) at [m][npair]
     cd* row;            // in: h sum_{j=m}^{n-1} w^{(n-m)}_{j-m} Sigma^R(n,j) G^R(j,m) for m < n-k
                         // out: G^R(n, m), m = 0..n
-    cd* minv;           // scratch of npair entries: M^{-1} of the left form (written by the
-                        // near-diagonal kernel, read by the bulk kernel)
+    cd* minv;           // scratch of npair entries per object: M^{-1} of the left form
+                        // (written by the near-diagonal kernel, read by the bulk kernel)
+    // batched objects (grid dimension y): element strides from one object's data to the
+    // next (0 for one object)
+    int nk;
+    long long kEps, kSig, kNear, kPrev, kRow;
 };
 
 // ev: nullptr, or three events recorded before the near-diagonal kernel, between

@@ -31,6 +31,9 @@ namespace {
 
 constexpr int NT = 256;
 
+// object blockIdx.y of a batch: its arrays start one stride per object further
+#define OBJ ((long long)blockIdx.y)
+
 // Gauss-Jordan elimination with partial pivoting by one workgroup on the K x ld
 // row-major matrix T = [A | B] in LDS (A of K columns).  Rows are never exchanged:
 // the pivot of column p is the not yet used row prow[p] with the largest |T(r, p)|,
@@ -101,6 +104,11 @@ __global__ void __launch_bounds__(NT) step_near(StepArgs A) {
     __shared__ int used[KMAX], prow[KMAX];
     const int n = A.n, k = A.k, K = k * NORB, ld = K + NORB;
     const double h = A.h;
+    const cd* eps = A.eps + OBJ * A.kEps;
+    const cd* sigR = A.sigR + OBJ * A.kSig;
+    const cd* sigNear = A.sigNear + OBJ * A.kNear;
+    cd* row = A.row + OBJ * A.kRow;
+    cd* minv = A.minv + OBJ * npair;
     {   // [M | 1], NORB x 2 NORB
         constexpr int l2 = 2 * NORB;
         const double wl = h * A.W.om[0];   // h w^{(L)}_L for L >= k+1
@@ -108,15 +116,15 @@ __global__ void __launch_bounds__(NT) step_near(StepArgs A) {
             const int r = e / l2, col = e % l2;
             cd v;
             if (col < NORB)
-                v = mk(0.0, r == col ? A.S.a[0] / h : 0.0) - A.eps[(size_t)k * npair + r * NORB + col] -
-                    wl * A.sigR[(size_t)n * npair + r * NORB + col];
+                v = mk(0.0, r == col ? A.S.a[0] / h : 0.0) - eps[(size_t)k * npair + r * NORB + col] -
+                    wl * sigR[(size_t)n * npair + r * NORB + col];
             else
                 v = mk(r == col - NORB ? 1.0 : 0.0, 0.0);
             T[e] = v;
         }
         __syncthreads();
         gauss_jordan(T, NORB, l2, used, prow);
-        for (int e = threadIdx.x; e < npair; e += NT) A.minv[e] = gj_solution(T, NORB, l2, prow, e / NORB, e % NORB);
+        for (int e = threadIdx.x; e < npair; e += NT) minv[e] = gj_solution(T, NORB, l2, prow, e / NORB, e % NORB);
         __syncthreads();
     }
     for (int e = threadIdx.x; e < K * ld; e += NT) {
@@ -125,12 +133,12 @@ __global__ void __launch_bounds__(NT) step_near(StepArgs A) {
         if (col < K) {
             const int u = col / NORB, a = col % NORB;
             v = mk(0.0, a == b ? -A.S.D[i][u] / h : 0.0);
-            if (u == i) v = v - A.eps[(size_t)i * npair + a * NORB + b];
+            if (u == i) v = v - eps[(size_t)i * npair + a * NORB + b];
             if (u >= i)
-                v = v - (h * interval_w(A.W, k - i, u - i)) * A.sigNear[((size_t)u * k + i) * npair + a * NORB + b];
+                v = v - (h * interval_w(A.W, k - i, u - i)) * sigNear[((size_t)u * k + i) * npair + a * NORB + b];
         } else {
             const int c = col - K;
-            const cd sg = A.sigR[(size_t)(n - k + i) * npair + c * NORB + b];
+            const cd sg = sigR[(size_t)(n - k + i) * npair + c * NORB + b];
             const double wh = h * interval_w(A.W, k - i, k - i);
             v = mk((c == b ? A.S.D[i][k] / h : 0.0) + wh * sg.y, -wh * sg.x);
         }
@@ -140,10 +148,10 @@ __global__ void __launch_bounds__(NT) step_near(StepArgs A) {
     gauss_jordan(T, K, ld, used, prow);
     for (int e = threadIdx.x; e < K * NORB; e += NT) {
         const int r = e / NORB, c = e % NORB, u = r / NORB, a = r % NORB;
-        A.row[(size_t)(n - k + u) * npair + c * NORB + a] = gj_solution(T, K, ld, prow, r, c);
+        row[(size_t)(n - k + u) * npair + c * NORB + a] = gj_solution(T, K, ld, prow, r, c);
     }
     for (int e = threadIdx.x; e < npair; e += NT)
-        A.row[(size_t)n * npair + e] = mk(0.0, e / NORB == e % NORB ? -1.0 : 0.0);
+        row[(size_t)n * npair + e] = mk(0.0, e / NORB == e % NORB ? -1.0 : 0.0);
 }
 
 // columns m < n-k, NT / npair columns per workgroup: thread (m, e) forms entry e = (b, a)
@@ -156,7 +164,8 @@ __global__ void __launch_bounds__(NT) step_bulk(StepArgs A) {
     __shared__ cd Mi[npair];
     __shared__ cd R[CPB * npair];
     const int t = threadIdx.x;
-    if (t < npair) Mi[t] = A.minv[t];
+    cd* row = A.row + OBJ * A.kRow;
+    if (t < npair) Mi[t] = A.minv[OBJ * npair + t];
     const long long m = (long long)blockIdx.x * CPB + t / npair;
     const int e = t % npair;
     const bool on = t < CPB * npair && m < A.n - A.k;
@@ -166,8 +175,8 @@ __global__ void __launch_bounds__(NT) step_bulk(StepArgs A) {
         cd s = mk(0.0, 0.0);
 #pragma unroll
         for (int l = 1; l <= 5; ++l)
-            if (l <= A.k) s = s + A.S.a[l] * A.prev[l - 1][o];
-        const cd hist = A.row[o];
+            if (l <= A.k) s = s + A.S.a[l] * A.prev[l - 1][OBJ * A.kPrev + o];
+        const cd hist = row[o];
         R[t] = mk(hist.x + s.y * ih, hist.y - s.x * ih);   // hist - (i/h) s
     }
     __syncthreads();
@@ -176,17 +185,17 @@ __global__ void __launch_bounds__(NT) step_bulk(StepArgs A) {
     cd y = mk(0.0, 0.0);
 #pragma unroll
     for (int b = 0; b < NORB; ++b) fma_(y, Mi[c * NORB + b], R[base + b * NORB + a]);
-    A.row[o] = y;
+    row[o] = y;
 }
 
 template <int NORB>
 hipError_t launch_step_t(const StepArgs& a, hipStream_t st, hipEvent_t* ev) {
     if (ev) hipEventRecord(ev[0], st);
-    step_near<NORB><<<1, NT, 0, st>>>(a);
+    step_near<NORB><<<dim3(1, a.nk), NT, 0, st>>>(a);
     if (ev) hipEventRecord(ev[1], st);
     constexpr int CPB = NT / (NORB * NORB);
     const int nb = a.n - a.k;
-    if (nb > 0) step_bulk<NORB><<<(nb + CPB - 1) / CPB, NT, 0, st>>>(a);
+    if (nb > 0) step_bulk<NORB><<<dim3((nb + CPB - 1) / CPB, a.nk), NT, 0, st>>>(a);
     if (ev) hipEventRecord(ev[2], st);
     return hipGetLastError();
 }
@@ -194,7 +203,7 @@ hipError_t launch_step_t(const StepArgs& a, hipStream_t st, hipEvent_t* ev) {
 }  // namespace
 
 hipError_t launch_step(const StepArgs& a, hipStream_t st, hipEvent_t* ev) {
-    if (a.k < 1 || a.k > 5 || a.n < a.k) return hipErrorInvalidValue;
+    if (a.k < 1 || a.k > 5 || a.n < a.k || a.nk < 1 || a.nk > 65535) return hipErrorInvalidValue;
     switch (a.norb) {
         case 1: return launch_step_t<1>(a, st, ev);
         case 2: return launch_step_t<2>(a, st, ev);

@@ -235,3 +235,125 @@ def test_step_full_size_norb4(P):
 
 def test_step_full_size_norb16_fp32(P):
     _full_march(P, "c4", 2048, [5, 64, 1023, 2047], 24, True, _inputs_channels)
+
+
+# ---------------------------------------------------------------------------
+# Batched objects (one handle, each object with its own eps and Sigma^R)
+
+def test_step_batched_against_oracle(P):
+    """5 objects, norb 2, k 4, N 100: every step of every object against the oracle's step
+    on the GPU's own rows of that object, and each object's march against the oracle's."""
+    nk, norb, k, N, h = 5, 2, 4, 100, 0.02
+    npair = norb * norb
+    data = [_inputs(N, norb, h, k, seed=60 + o) for o in range(nk)]
+    S = torch.from_numpy(np.stack([d[0] for d in data])).to("cuda")          # (nk, N, N, norb, norb)
+    E = torch.from_numpy(np.stack([d[1] for d in data])).to("cuda")          # (nk, N, norb, norb)
+    Gd = torch.zeros((nk, N, N, norb, norb), dtype=torch.complex128, device="cuda")
+    for o in range(nk):
+        Gd[o, :k] = torch.from_numpy(data[o][2][:k]).to("cuda")
+    B = P.HodlrBatch(nk, N, 1, norb, k=k, tol=1e-12, panel=16, max_rank=16)
+    rs = N * N * npair            # object stride of the dense G and Sigma arrays
+    flatG, flatS, flatE = Gd.view(-1), S.view(-1), E.view(-1)
+    for n in range(k):
+        B.append_row(P.RET, n, flatG[n * N * npair:], rs)
+    for n in range(k, N):
+        near = torch.zeros((nk, k, k, norb, norb), dtype=torch.complex128, device="cuda")
+        for u in range(k):
+            for i in range(u + 1):
+                near[:, u, i] = S[:, n - k + u, n - k + i]
+        prev = [flatG[(n - l) * N * npair:] for l in range(1, k + 1)]
+        B.step_R(n, flatE[(n - k) * npair:], N * npair, flatS[n * N * npair:], rs, near.view(-1), k * k * npair,
+                 prev, rs, h, flatG[n * N * npair:], rs)
+        B.append_row(P.RET, n, flatG[n * N * npair:], rs)
+    torch.cuda.synchronize()
+    B.status()
+    G = Gd.cpu().numpy()
+    for o in range(nk):
+        So, eo, G0 = data[o]
+        worst = 0.0
+        for n in range(k, N):
+            ref = step(G[o], So, eo, n, h, k)
+            err = np.abs(G[o, n, :n + 1] - ref).max() / np.abs(ref).max()
+            worst = max(worst, err)
+            assert err <= 1e-10, (o, n, err)
+        ref = solve(So, eo, G0, h, k, N)
+        errN = max(np.abs(G[o, n, :n + 1] - ref[n, :n + 1]).max() / np.abs(ref[n, :n + 1]).max() for n in range(N))
+        say(f"  object {o}: one-step worst {worst:.2e}, march {errN:.2e}")
+        assert errN <= 1e-8, (o, errN)
+
+
+def test_step_batched_lattice_workload(P):
+    """The 32 x 32 lattice (1024 momenta, N_t = 2048, norb 1, leaf 64, tolerance 1e-10):
+    G_k^R marched for every momentum with its own Sigma_k^R (the lattice generator's) and
+    eps_k (the dispersion), rows 0..k-1 the free propagator; at sampled steps, sampled bulk
+    columns and the near-diagonal entries of 8 momenta against the oracle's column step on
+    the GPU's own earlier rows of that momentum."""
+    from gpu_common import boundary_columns
+    from kbe_inputs import make_config_inputs
+    from oracle.step_solve import bulk_column, near_block
+    cfg, _, Sg = make_config_inputs("c3")
+    N, h, k = cfg["nt"], cfg["h"], cfg["k"]
+    nk = len(Sg)
+    nlvl = int(round(np.log2(N // cfg["leaf"])))
+    eps_k = np.array([s.meta["eps"] for s in Sg])
+    t = np.arange(N) * h
+    # Sigma_k^R(t_n, t_j) depends on t_n - t_j: row n of object o is T[o, N-1-n:]
+    T = np.stack([retarded(s, t[::-1], 0.0)[:, 0, 0] for s in Sg])
+    Td = torch.from_numpy(T).to("cuda")
+    E = torch.from_numpy(np.repeat(eps_k[:, None], k + 1, axis=1).astype(np.complex128)).to("cuda")
+    near = np.zeros((nk, k, k), dtype=np.complex128)
+    for o in range(nk):
+        for u in range(k):
+            for i in range(u + 1):
+                near[o, u, i] = retarded(Sg[o], (u - i) * h, 0.0)[0, 0]
+    nearD = torch.from_numpy(near).to("cuda")
+    ring = torch.zeros((k + 1, nk, N), dtype=torch.complex128, device="cuda")
+    B = P.HodlrBatch(nk, N, nlvl, 1, k=k, tol=cfg["tol"], panel=16, max_rank=32)
+    sel = np.arange(5, nk, nk // 8)[:8]
+    rng = np.random.default_rng(23)
+    steps = [5, 64, 1023, N - 1]
+    colset = {n: [m for m in boundary_columns(n, cfg["leaf"], nlvl, rng, 24) if m < n - k] for n in steps}
+    mcols = np.array(sorted(set().union(*colset.values())), dtype=np.int64)
+    pos = {int(m): i for i, m in enumerate(mcols)}
+    mc_d = torch.as_tensor(mcols, device="cuda")
+    sel_d = torch.as_tensor(sel, device="cuda")
+    Gc = torch.zeros((N, len(sel), len(mcols)), dtype=torch.complex128, device="cuda")
+    saved = {}
+    say(f"lattice step march: {nk} momenta, N {N}, {len(sel)} sampled momenta, {len(mcols)} columns")
+    for n in range(N):
+        slot = ring[n % (k + 1)]
+        if n < k:
+            slot[:, :n + 1] = torch.from_numpy(-1j * np.exp(-1j * eps_k[:, None] * (n - np.arange(n + 1))[None, :] * h)).to("cuda")
+        else:
+            prev = [ring[(n - l) % (k + 1)] for l in range(1, k + 1)]
+            B.step_R(n, E.view(-1), k + 1, Td.view(-1)[N - 1 - n:], N,
+                     nearD.view(-1), k * k, prev, N, h, slot, N)
+        B.append_row(P.RET, n, slot, N)
+        s = int(np.searchsorted(mcols, n, side="right"))
+        if s:
+            Gc[n, :, :s] = slot[sel_d][:, mc_d[:s]]
+        if n in colset:
+            saved[n] = slot[sel_d, :n + 1].cpu().numpy()
+        if n % 512 == 511:
+            torch.cuda.synchronize()
+            say(f"  step {n + 1}")
+    torch.cuda.synchronize()
+    B.status()
+    say(f"  max rank {int(B.ranks(P.RET).max())}")
+    Gc_h = Gc.cpu().numpy()
+    worst = 0.0
+    for n in steps:
+        for si, o in enumerate(sel):
+            srow = retarded(Sg[o], t[n], t[:n + 1])
+            eo = np.broadcast_to(np.array([[eps_k[o]]], dtype=np.complex128), (N, 1, 1))
+            got = saved[n][si]
+            ref = {m: bulk_column(Gc_h[m:n, si, pos[m]].reshape(-1, 1, 1), srow, eo[n], n, m, h, k)[0, 0]
+                   for m in colset[n]}
+            nearo = near[o][:, :, None, None]
+            nb = near_block(nearo, srow, eo, n, h, k)[:, 0, 0]
+            scale = max([abs(r) for r in ref.values()] + [np.abs(nb).max()])
+            err = max([abs(got[m] - r) for m, r in ref.items()] + [np.abs(got[n - k:n] - nb).max()]) / scale
+            assert got[n] == -1j, (n, o)
+            worst = max(worst, err)
+            assert err <= 1e-10, (n, o, err)
+    say(f"  worst {worst:.2e}")
