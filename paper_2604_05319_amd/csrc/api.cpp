@@ -162,7 +162,9 @@ struct hnessi_hodlr_s {
     double tol = 0.0;
     Weights W{};
     StepWeights SW{};   // weights of the retarded time step
-    cd* step_minv = nullptr;   // the step's M^{-1} (npair entries), allocated by the first step
+    cd* step_scr = nullptr;    // the step's scratch ((k+1) npair entries per object), allocated by the first step
+    hipStream_t sstream = nullptr;   // the step's near-diagonal solves, beside the history kernels
+    hipEvent_t ev_sfork = nullptr, ev_sjoin = nullptr;
     Geometry g;
     int MW = 0;           // merge width (kWSmall or kWLarge)
     DevAlloc al;
@@ -359,6 +361,7 @@ int wait_handle(hnessi_hodlr_t H) {
     if (H->ev_last) HIP_TRY(hipEventSynchronize(H->ev_last));
     for (int c = 0; c < 2; ++c)
         if (H->mstream[c]) HIP_TRY(hipStreamSynchronize(H->mstream[c]));
+    if (H->sstream) HIP_TRY(hipStreamSynchronize(H->sstream));
     return HNESSI_OK;
 }
 
@@ -374,6 +377,14 @@ void release_streams(hnessi_hodlr_t H) {
         if (H->mstream[c]) hipStreamDestroy(H->mstream[c]);
         H->mstream[c] = nullptr;
     }
+    if (H->sstream) {
+        hipStreamSynchronize(H->sstream);
+        hipStreamDestroy(H->sstream);
+        H->sstream = nullptr;
+    }
+    if (H->ev_sfork) hipEventDestroy(H->ev_sfork);
+    if (H->ev_sjoin) hipEventDestroy(H->ev_sjoin);
+    H->ev_sfork = H->ev_sjoin = nullptr;
 }
 
 int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, double svd_tol, int panel,
@@ -1145,17 +1156,24 @@ int step_impl(hnessi_hodlr_t H, int n, const void* eps, long long eps_stride, co
         if (!prev_rows[l]) return fail(HNESSI_E_ARG, "a previous row is NULL");
         a.prev[l] = static_cast<const cd*>(prev_rows[l]);
     }
-    if (!H->step_minv) {
-        if (dev_alloc(H->al, H->step_minv, (size_t)(np * H->nk), false) != HNESSI_OK) {
-            H->step_minv = nullptr;
+    if (!H->step_scr) {
+        if (dev_alloc(H->al, H->step_scr, (size_t)((k + 1) * np * H->nk), false) != HNESSI_OK) {
+            H->step_scr = nullptr;
             return fail(HNESSI_E_NOMEM, "device allocation of the step scratch failed");
         }
         HIP_TRY(hipStreamSynchronize(H->al.st));
     }
-    // the history sum over the stored rows, into the output rows
-    int rc = do_history(H, n, sigR_rows, nullptr, h, rows_out, nullptr, true, false, st, in_stride, out_stride,
-                        false, false, true);
-    if (rc != HNESSI_OK) return rc;
+    if (!H->sstream) {   // default priority, like every stream of the library
+        if (hipStreamCreateWithFlags(&H->sstream, hipStreamNonBlocking) != hipSuccess) {
+            H->sstream = nullptr;
+            return fail(HNESSI_E_DEVICE, "stream creation failed");
+        }
+        if (hipEventCreateWithFlags(&H->ev_sfork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&H->ev_sjoin, hipEventDisableTiming) != hipSuccess)
+            return fail(HNESSI_E_DEVICE, "event creation failed");
+    }
+    // an order check before anything is enqueued (the history call repeats it)
+    if (n != H->last[0] + 1) return fail(HNESSI_E_ORDER, "the step solve needs rows 0..n-1 appended and row n not");
     a.n = n;
     a.k = k;
     a.norb = H->norb;
@@ -1166,20 +1184,38 @@ int step_impl(hnessi_hodlr_t H, int n, const void* eps, long long eps_stride, co
     a.sigR = static_cast<const cd*>(sigR_rows);
     a.sigNear = static_cast<const cd*>(sig_near);
     a.row = static_cast<cd*>(rows_out);
-    a.minv = H->step_minv;
+    a.scr = H->step_scr;
     a.nk = H->nk;
     a.kEps = eps_stride;
     a.kSig = in_stride;
     a.kNear = near_stride;
     a.kPrev = prev_stride;
     a.kRow = out_stride;
-    if (H->prof.want(n)) {
-        hipEvent_t ev[3] = {H->prof.ev(), H->prof.ev(), H->prof.ev()};
-        HIP_TRY(launch_step(a, st, ev));
+    const bool timed = H->prof.want(n);
+    // the near-diagonal solves on the side stream, after the work queued so far on st
+    // (and after the previous step's bulk kernel, the scratch's last reader)
+    HIP_TRY(hipEventRecord(H->ev_sfork, st));
+    HIP_TRY(hipStreamWaitEvent(H->sstream, H->ev_sfork, 0));
+    if (timed) {
+        hipEvent_t ev[2] = {H->prof.ev(), H->prof.ev()};
+        HIP_TRY(launch_step_near(a, H->sstream, ev));
         H->prof.recs.push_back({4, n, ev[0], ev[1]});
-        H->prof.recs.push_back({5, n, ev[1], ev[2]});
     } else {
-        HIP_TRY(launch_step(a, st));
+        HIP_TRY(launch_step_near(a, H->sstream));
+    }
+    HIP_TRY(hipEventRecord(H->ev_sjoin, H->sstream));
+    // the history sum over the stored rows, into the output rows (on st, beside them)
+    int rc = do_history(H, n, sigR_rows, nullptr, h, rows_out, nullptr, true, false, st, in_stride, out_stride,
+                        false, false, true);
+    // joined also when the history call failed, so that no work of this call is left behind
+    HIP_TRY(hipStreamWaitEvent(st, H->ev_sjoin, 0));
+    if (rc != HNESSI_OK) return rc;
+    if (timed) {
+        hipEvent_t ev[2] = {H->prof.ev(), H->prof.ev()};
+        HIP_TRY(launch_step_bulk(a, st, ev));
+        H->prof.recs.push_back({5, n, ev[0], ev[1]});
+    } else {
+        HIP_TRY(launch_step_bulk(a, st));
     }
     return HNESSI_OK;
 }

@@ -23,16 +23,19 @@ struct StepArgs {
     const cd* prev[5];  // prev[l-1]: row n-l of G^R, G^R(n-l, m) at [m][npair]
     cd* row;            // in: h sum_{j=m}^{n-1} w^{(n-m)}_{j-m} Sigma^R(n,j) G^R(j,m) for m < n-k
                         // out: G^R(n, m), m = 0..n
-    cd* minv;           // scratch of npair entries per object: M^{-1} of the left form
-                        // (written by the near-diagonal kernel, read by the bulk kernel)
+    cd* scr;            // scratch of (k+1) npair entries per object: M^{-1} of the left form,
+                        // then the near-diagonal entries G(n, n-k+u) at [1 + u][c][a] (written
+                        // by the near-diagonal kernel, read by the bulk kernel)
     // batched objects (grid dimension y): element strides from one object's data to the
     // next (0 for one object)
     int nk;
     long long kEps, kSig, kNear, kPrev, kRow;
 };
 
-// ev: nullptr, or three events recorded before the near-diagonal kernel, between
-// the two kernels and after the bulk kernel
-hipError_t launch_step(const StepArgs& a, hipStream_t st, hipEvent_t* ev = nullptr);
+// The near-diagonal kernel needs no history sum, so it can run beside the history
+// kernels; the bulk kernel (after them) also copies its results into the row and writes
+// G(n, n).  ev: nullptr, or two events recorded around the launch on its stream.
+hipError_t launch_step_near(const StepArgs& a, hipStream_t st, hipEvent_t* ev = nullptr);
+hipError_t launch_step_bulk(const StepArgs& a, hipStream_t st, hipEvent_t* ev = nullptr);
 
 }  // namespace hn

@@ -8,7 +8,8 @@
 // the differentiation weights); the integrals by the interval weights of the
 // section "Numerical integration".
 //
-//  * step_near (one workgroup): the matrix of the left form,
+//  * step_near (one workgroup per object, beside the history kernels): the matrix of the
+//    left form,
 //      M = (i a_0/h) 1 - eps(t_n) - h w^{(L)}_L Sigma(n,n),
 //    is the same for every column m < n-k (L = n-m >= k+1 makes w^{(L)}_L the end weight
 //    omega_0), so it is inverted once; then the right form at (t_n, t_m), m = n-k..n-1,
@@ -16,12 +17,13 @@
 //    G(n, n-k..n): the k unknown norb x norb entries multiply known matrices from the
 //    right, so the norb rows of G decouple and one k norb x k norb system with norb
 //    right sides is solved.  Both by Gauss-Jordan elimination with partial pivoting in
-//    LDS.
+//    LDS; M^{-1} and the k entries go to a scratch buffer.
 //  * step_bulk, columns m < n-k: the left form
 //      M G(n,m) = -(i/h) sum_{l=1..k} a_l G(n-l,m) + h sum_{j=m}^{n-1} w^{(L)}_{j-m} Sigma(n,j) G(j,m)
 //    (the history sum comes in through the output row), one streaming pass: every
 //    thread forms one entry of a column's right side, the block's right sides are
-//    staged in LDS and multiplied by M^{-1}.
+//    staged in LDS and multiplied by M^{-1}; one more workgroup copies the near-diagonal
+//    entries from the scratch into the row and writes G(n, n) = -i.
 //
 // Both kernels are FP64.  A singular system (zero pivot) leaves non-finite entries.
 #include "step.h"
@@ -91,7 +93,7 @@ __device__ inline cd gj_solution(const cd* T, int K, int ld, const int* prow, in
     return T[q * ld + K + c] * mk(d.x * s, -d.y * s);
 }
 
-// M^{-1} into A.minv, then the near-diagonal system of the right form: with the unknowns
+// M^{-1} into the scratch, then the near-diagonal system of the right form: with the unknowns
 // Y[(u, a)][c] = G(n, n-k+u)[c][a], u = 0..k-1, and the equation of column
 // m = n-k+i (interval length L = k-i) as the row block (i, b):
 //   sum_{u,a} C_{u,i}[a][b] Y[(u,a)][c] = R_i[c][b],
@@ -107,8 +109,8 @@ __global__ void __launch_bounds__(NT) step_near(StepArgs A) {
     const cd* eps = A.eps + OBJ * A.kEps;
     const cd* sigR = A.sigR + OBJ * A.kSig;
     const cd* sigNear = A.sigNear + OBJ * A.kNear;
-    cd* row = A.row + OBJ * A.kRow;
-    cd* minv = A.minv + OBJ * npair;
+    cd* minv = A.scr + OBJ * (k + 1) * npair;
+    cd* nearOut = minv + npair;
     {   // [M | 1], NORB x 2 NORB
         constexpr int l2 = 2 * NORB;
         const double wl = h * A.W.om[0];   // h w^{(L)}_L for L >= k+1
@@ -148,13 +150,12 @@ __global__ void __launch_bounds__(NT) step_near(StepArgs A) {
     gauss_jordan(T, K, ld, used, prow);
     for (int e = threadIdx.x; e < K * NORB; e += NT) {
         const int r = e / NORB, c = e % NORB, u = r / NORB, a = r % NORB;
-        row[(size_t)(n - k + u) * npair + c * NORB + a] = gj_solution(T, K, ld, prow, r, c);
+        nearOut[(size_t)u * npair + c * NORB + a] = gj_solution(T, K, ld, prow, r, c);
     }
-    for (int e = threadIdx.x; e < npair; e += NT)
-        row[(size_t)n * npair + e] = mk(0.0, e / NORB == e % NORB ? -1.0 : 0.0);
 }
 
-// columns m < n-k, NT / npair columns per workgroup: thread (m, e) forms entry e = (b, a)
+// columns m < n-k, NT / npair columns per workgroup (the last workgroup of the grid
+// copies the near-diagonal entries and writes G(n, n)): thread (m, e) forms entry e = (b, a)
 // of column m's right side (reading exactly the row entry it later overwrites with entry
 // e = (c, a) of the solution; the barrier separates every read of the block's columns
 // from every write)
@@ -165,7 +166,13 @@ __global__ void __launch_bounds__(NT) step_bulk(StepArgs A) {
     __shared__ cd R[CPB * npair];
     const int t = threadIdx.x;
     cd* row = A.row + OBJ * A.kRow;
-    if (t < npair) Mi[t] = A.minv[OBJ * npair + t];
+    const cd* scr = A.scr + OBJ * (A.k + 1) * npair;
+    if (blockIdx.x == gridDim.x - 1) {   // whole workgroup: no barrier below is reached
+        for (int e = t; e < A.k * npair; e += NT) row[(size_t)(A.n - A.k) * npair + e] = scr[npair + e];
+        for (int e = t; e < npair; e += NT) row[(size_t)A.n * npair + e] = mk(0.0, e / NORB == e % NORB ? -1.0 : 0.0);
+        return;
+    }
+    if (t < npair) Mi[t] = scr[t];
     const long long m = (long long)blockIdx.x * CPB + t / npair;
     const int e = t % npair;
     const bool on = t < CPB * npair && m < A.n - A.k;
@@ -189,27 +196,49 @@ __global__ void __launch_bounds__(NT) step_bulk(StepArgs A) {
 }
 
 template <int NORB>
-hipError_t launch_step_t(const StepArgs& a, hipStream_t st, hipEvent_t* ev) {
+hipError_t launch_near_t(const StepArgs& a, hipStream_t st, hipEvent_t* ev) {
     if (ev) hipEventRecord(ev[0], st);
     step_near<NORB><<<dim3(1, a.nk), NT, 0, st>>>(a);
     if (ev) hipEventRecord(ev[1], st);
+    return hipGetLastError();
+}
+
+template <int NORB>
+hipError_t launch_bulk_t(const StepArgs& a, hipStream_t st, hipEvent_t* ev) {
     constexpr int CPB = NT / (NORB * NORB);
     const int nb = a.n - a.k;
-    if (nb > 0) step_bulk<NORB><<<dim3((nb + CPB - 1) / CPB, a.nk), NT, 0, st>>>(a);
-    if (ev) hipEventRecord(ev[2], st);
+    if (ev) hipEventRecord(ev[0], st);
+    step_bulk<NORB><<<dim3((nb + CPB - 1) / CPB + 1, a.nk), NT, 0, st>>>(a);
+    if (ev) hipEventRecord(ev[1], st);
     return hipGetLastError();
+}
+
+bool step_args_ok(const StepArgs& a) {
+    return a.k >= 1 && a.k <= 5 && a.n >= a.k && a.nk >= 1 && a.nk <= 65535;
 }
 
 }  // namespace
 
-hipError_t launch_step(const StepArgs& a, hipStream_t st, hipEvent_t* ev) {
-    if (a.k < 1 || a.k > 5 || a.n < a.k || a.nk < 1 || a.nk > 65535) return hipErrorInvalidValue;
+hipError_t launch_step_near(const StepArgs& a, hipStream_t st, hipEvent_t* ev) {
+    if (!step_args_ok(a)) return hipErrorInvalidValue;
     switch (a.norb) {
-        case 1: return launch_step_t<1>(a, st, ev);
-        case 2: return launch_step_t<2>(a, st, ev);
-        case 4: return launch_step_t<4>(a, st, ev);
-        case 8: return launch_step_t<8>(a, st, ev);
-        case 16: return launch_step_t<16>(a, st, ev);
+        case 1: return launch_near_t<1>(a, st, ev);
+        case 2: return launch_near_t<2>(a, st, ev);
+        case 4: return launch_near_t<4>(a, st, ev);
+        case 8: return launch_near_t<8>(a, st, ev);
+        case 16: return launch_near_t<16>(a, st, ev);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_step_bulk(const StepArgs& a, hipStream_t st, hipEvent_t* ev) {
+    if (!step_args_ok(a)) return hipErrorInvalidValue;
+    switch (a.norb) {
+        case 1: return launch_bulk_t<1>(a, st, ev);
+        case 2: return launch_bulk_t<2>(a, st, ev);
+        case 4: return launch_bulk_t<4>(a, st, ev);
+        case 8: return launch_bulk_t<8>(a, st, ev);
+        case 16: return launch_bulk_t<16>(a, st, ev);
         default: return hipErrorInvalidValue;
     }
 }
