@@ -161,6 +161,37 @@ int hnessi_born_lattice(int L, int n, double U, const void* GR_rows, const void*
                         long long in_stride, void* SR_rows, void* SL_slices,
                         long long out_stride, void* stream);
 
+/* One time step of the lesser component (section "Kadanoff-Baym equations", Eq. KBEL
+ * without the mixed term, in its left form and in the conjugate-transposed right form):
+ * the new lesser slice G^<(t_s, t_n), s = 0..n, into slice_out (device, (n+1)*norb*norb
+ * complex128, the orientation of hnessi_hodlr_append_row), from the stored lesser rows
+ * 0..n-1 and the retarded row n.  Not appended: the caller appends it.
+ *   columns m <= n-k of the row G^<(t_n, t_m): the left form, t-derivative by the
+ *     backward differentiation weights (every point below the diagonal), the two history
+ *     integrals over the stored rows (hnessi_history_lesser without the s = n term of
+ *     the first, which is taken to the left): one norb x norb solve per column;
+ *   columns n-k+1..n (the equal-time entry included): the right form at (t_n, t_m), its
+ *     t'-derivative by the differentiation weights D_ip on the points n-k..n of the row,
+ *     the integrals over [0, t_m] and [0, t_n]: one system for the k entries.  (A column
+ *     derivative up to the diagonal, with points above it from the row being solved, is
+ *     unstable.)
+ * Arguments (device pointers unless stated, complex128, orbital matrices row-major):
+ *   eps          k+1 matrices eps(t_{n-k+i}), i = 0..k
+ *   sigR_rows    host array of k device pointers: Sigma^R row n-k+u at [u-1] (u = 1..k),
+ *                Sigma^R(t_{n-k+u}, t_s) at [s]; [k-1] is the current row n
+ *   sigL_slices  host array of k device pointers: Sigma^< slice n-k+u at [u-1],
+ *                Sigma^<(t_s, t_{n-k+u}) at [s]; [k-1] is the current slice n
+ *   GR_row       the retarded row n, G^R(t_n, t_s), s = 0..n (hnessi_step_R's output)
+ *   prev_slices  host array of k device pointers: lesser slice n-l at [l-1]
+ *   h            time step (> 0)
+ * Needs lesser rows 0..n-1 appended, lesser row n not, and retarded rows up to n-1 or n
+ * (HNESSI_E_ORDER); n < k: HNESSI_E_RANGE; a batched handle, a NULL pointer or h <= 0:
+ * HNESSI_E_ARG.  A singular system leaves non-finite entries; the call does not wait for
+ * the device; slice_out must not overlap the inputs. */
+int hnessi_step_lesser(hnessi_hodlr_t H, int n, const void* eps, const void* const* sigR_rows,
+                       const void* const* sigL_slices, const void* GR_row,
+                       const void* const* prev_slices, double h, void* slice_out, void* stream);
+
 /* Weights of the retarded time step (hnessi_step_R) for order k (1..5), host
  * outputs: a_host[0..k] the backward differentiation weights a_l = -D_{0l}
  * (f'(t_n) h ~ sum_l a_l f(t_{n-l})) and D_host[i*(k+1) + p], i, p = 0..k, the
@@ -465,8 +496,8 @@ int hnessi_hodlr_profile(hnessi_hodlr_t H, int stride);
 
 /* Synchronizes the recorded events; for kernel kind 0 (projection / leaf /
  * tail tasks), 1 (combine), 2 (panel merge, both of its kernels), 3 (sum of
- * the projection chunk partials), 4 (time step: near-diagonal system) or 5
- * (time step: columns m < n-k) returns the
+ * the projection chunk partials), 4 (time step: near-diagonal system), 5
+ * (time step: columns m < n-k) or 6 (lesser step after its history) returns the
  * number of timed launches and writes, for the first `capacity` of them, the
  * step n (host int) and the duration in ms (host double).  Either output
  * pointer may be NULL. */

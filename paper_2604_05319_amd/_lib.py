@@ -58,6 +58,8 @@ _SIGS = {
     "hnessi_history_R": ([C.c_void_p, C.c_int, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p], C.c_int),
     "hnessi_step_R": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                        C.c_void_p, C.c_void_p], C.c_int),
+    "hnessi_step_lesser": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                            C.c_double, C.c_void_p, C.c_void_p], C.c_int),
     "hnessi_step_R_batched": ([C.c_void_p, C.c_int, C.c_void_p, C.c_longlong, C.c_void_p, C.c_longlong, C.c_void_p,
                                C.c_longlong, C.c_void_p, C.c_longlong, C.c_double, C.c_void_p, C.c_longlong,
                                C.c_void_p], C.c_int),
@@ -278,6 +280,17 @@ class Hodlr:
         ptrs = (C.c_void_p * self.k)(*[_ptr(r).value for r in prev_rows])
         _check(lib().hnessi_step_R(self.h, n, _ptr(eps), _ptr(sigR), _ptr(sig_near), ptrs, h, _ptr(out),
                                    _stream()))
+
+    def step_lesser(self, n, eps, sigR_rows, sigL_slices, GR_row, prev_slices, h, out):
+        """Lesser slice n (G^<(t_s, t_n), s <= n) into out: sigR_rows / sigL_slices the Sigma^R
+        rows and Sigma^< slices n-k+1..n, GR_row the retarded row n, prev_slices the lesser
+        slices n-1..n-k (all device tensors)."""
+        k = self.k
+        if len(sigR_rows) != k or len(sigL_slices) != k or len(prev_slices) != k:
+            raise ValueError(f"sigR_rows, sigL_slices and prev_slices must each hold k = {k} arrays")
+        arr = lambda xs: (C.c_void_p * k)(*[_ptr(x).value for x in xs])
+        _check(lib().hnessi_step_lesser(self.h, n, _ptr(eps), arr(sigR_rows), arr(sigL_slices), _ptr(GR_row),
+                                        arr(prev_slices), h, _ptr(out), _stream()))
 
     def history_lesser(self, n, sigR, sigL, h, out):
         _check(lib().hnessi_history_lesser(self.h, n, _ptr(sigR), _ptr(sigL), h, _ptr(out), _stream()))

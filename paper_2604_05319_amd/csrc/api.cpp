@@ -163,6 +163,7 @@ struct hnessi_hodlr_s {
     Weights W{};
     StepWeights SW{};   // weights of the retarded time step
     cd* step_scr = nullptr;    // the step's scratch ((k+1) npair entries per object), allocated by the first step
+    cd* lstep_scr = nullptr;   // the lesser step's scratch, allocated by its first call
     hipStream_t sstream = nullptr;   // the step's near-diagonal solves, beside the history kernels
     hipEvent_t ev_sfork = nullptr, ev_sjoin = nullptr;
     Geometry g;
@@ -814,12 +815,15 @@ int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, doub
     if (wantL && (!sigL || (!outL && !fgrad))) return fail(HNESSI_E_ARG, "input or output is NULL");
     const bool ronly = !wantL || adj;
     if (implicit) {
-        if (wantL || adj || fgrad || n != H->last[0] + 1)
+        // retarded: rows 0..n-1 stored; lesser: lesser rows 0..n-1 and retarded rows to n-1 or n
+        const bool okR = wantR && !wantL && n == H->last[0] + 1;
+        const bool okL = wantL && !wantR && n == H->last[1] + 1 && H->last[0] >= n - 1 && H->last[0] <= n;
+        if (adj || fgrad || !(okR || okL))
             return fail(HNESSI_E_ORDER, "the step solve needs rows 0..n-1 appended and row n not");
     } else if (n > H->last[0] || (n < H->last[0] && !ronly)) {
         return fail(HNESSI_E_ORDER, "retarded row n has not been appended (or later rows have)");
     }
-    if (wantL && !adj && H->last[1] != n)
+    if (wantL && !adj && !implicit && H->last[1] != n)
         return fail(HNESSI_E_ORDER, "lesser row n has not been appended (or later rows have)");
     const bool frozen = n < H->last[0];
     if (frozen) {
@@ -1232,6 +1236,77 @@ int hnessi_step_R(hnessi_hodlr_t H, int n, const void* eps, const void* sigR_row
     return rc != HNESSI_OK ? rc : mark(H, (hipStream_t)stream);
 }
 
+int hnessi_step_lesser(hnessi_hodlr_t H, int n, const void* eps, const void* const* sigR_rows,
+                       const void* const* sigL_slices, const void* GR_row, const void* const* prev_slices, double h,
+                       void* slice_out, void* stream) {
+    int rc = single_only(H);
+    if (rc != HNESSI_OK) return rc;
+    const int k = H->k;
+    const long long np = H->npair;
+    hipStream_t st = (hipStream_t)stream;
+    if (n < 0 || n >= H->nt) return fail(HNESSI_E_RANGE, "n outside the grid");
+    if (n < k) return fail(HNESSI_E_RANGE, "the step needs n >= k (the first k rows are a start-up)");
+    if (!eps || !sigR_rows || !sigL_slices || !GR_row || !prev_slices || !slice_out)
+        return fail(HNESSI_E_ARG, "a pointer is NULL");
+    if (!(h > 0.0)) return fail(HNESSI_E_ARG, "h must be > 0");
+    LesserStepArgs a{};
+    for (int l = 0; l < k; ++l) {
+        if (!sigR_rows[l] || !sigL_slices[l] || !prev_slices[l]) return fail(HNESSI_E_ARG, "a row pointer is NULL");
+        a.sigRn[l] = static_cast<const cd*>(sigR_rows[l]);
+        a.sigLn[l] = static_cast<const cd*>(sigL_slices[l]);
+        a.prev[l] = static_cast<const cd*>(prev_slices[l]);
+    }
+    if (n != H->last[1] + 1 || H->last[0] < n - 1 || H->last[0] > n)
+        return fail(HNESSI_E_ORDER, "the lesser step needs lesser rows 0..n-1 appended (row n not) and retarded rows to n-1");
+    const int nch_max = lesser_sum_chunks(H->nt - 1);
+    if (!H->lstep_scr) {
+        if (dev_alloc(H->al, H->lstep_scr, (size_t)((1 + k) * np + (long long)k * nch_max * np), false) != HNESSI_OK) {
+            H->lstep_scr = nullptr;
+            return fail(HNESSI_E_NOMEM, "device allocation of the lesser step scratch failed");
+        }
+        HIP_TRY(hipStreamSynchronize(H->al.st));
+    }
+    if (!H->sstream) {
+        if (hipStreamCreateWithFlags(&H->sstream, hipStreamNonBlocking) != hipSuccess) {
+            H->sstream = nullptr;
+            return fail(HNESSI_E_DEVICE, "stream creation failed");
+        }
+        if (hipEventCreateWithFlags(&H->ev_sfork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&H->ev_sjoin, hipEventDisableTiming) != hipSuccess)
+            return fail(HNESSI_E_DEVICE, "event creation failed");
+    }
+    a.n = n;
+    a.k = k;
+    a.norb = H->norb;
+    a.h = h;
+    a.W = H->W;
+    a.S = H->SW;
+    a.eps = static_cast<const cd*>(eps);
+    a.GRn = static_cast<const cd*>(GR_row);
+    a.slice = static_cast<cd*>(slice_out);
+    a.scr = H->lstep_scr;
+    a.part = H->lstep_scr + (1 + k) * np;
+    a.nchunk = lesser_sum_chunks(n);
+    // M_L^{-1} on the side stream, beside the history kernels
+    HIP_TRY(hipEventRecord(H->ev_sfork, st));
+    HIP_TRY(hipStreamWaitEvent(H->sstream, H->ev_sfork, 0));
+    HIP_TRY(launch_lesser_prep(a, H->sstream));
+    HIP_TRY(hipEventRecord(H->ev_sjoin, H->sstream));
+    // I^<(n, m) over the stored rows (the first integral without its s = n term), into the output
+    rc = do_history(H, n, sigR_rows[k - 1], sigL_slices[k - 1], h, nullptr, slice_out, false, true, st, 0, 0, false,
+                    false, true);
+    HIP_TRY(hipStreamWaitEvent(st, H->ev_sjoin, 0));
+    if (rc != HNESSI_OK) return rc;
+    if (H->prof.want(n)) {
+        hipEvent_t ev[2] = {H->prof.ev(), H->prof.ev()};
+        HIP_TRY(launch_lesser_rest(a, st, ev));
+        H->prof.recs.push_back({6, n, ev[0], ev[1]});
+    } else {
+        HIP_TRY(launch_lesser_rest(a, st));
+    }
+    return mark(H, st);
+}
+
 int hnessi_step_R_batched(hnessi_hodlr_t H, int n, const void* eps, long long eps_stride, const void* sigR_rows,
                           long long in_stride, const void* sig_near, long long near_stride,
                           const void* const* prev_rows, long long prev_stride, double h, void* rows_out,
@@ -1548,7 +1623,7 @@ int hnessi_hodlr_profile(hnessi_hodlr_t H, int stride) {
 }
 
 int hnessi_hodlr_profile_read(hnessi_hodlr_t H, int kind, int* steps_host, double* ms_host, int capacity) {
-    if (!H || kind < 0 || kind > 5) return fail(HNESSI_E_ARG, "bad argument");
+    if (!H || kind < 0 || kind > 6) return fail(HNESSI_E_ARG, "bad argument");
     return H->prof.read(kind, steps_host, ms_host, capacity);
 }
 

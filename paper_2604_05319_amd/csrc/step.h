@@ -32,6 +32,32 @@ struct StepArgs {
     long long kEps, kSig, kNear, kPrev, kRow;
 };
 
+// One lesser step n >= k with lesser rows 0..n-1 and the retarded row n known: columns
+// m <= n-k from the left form of the lesser equation (t-derivative by backward
+// differentiation, the history sums without the newest term of the first), columns
+// n-k+1..n (the equal-time entry included) from its right form on row n's points n-k..n
+// (the integrals over [0, t_m] and [0, t_n]), one linear system for the k unknowns.
+// Output in the stored orientation: slice[s] = G^<(t_s, t_n).
+struct LesserStepArgs {
+    int n, k, norb;
+    double h;
+    Weights W;
+    StepWeights S;
+    const cd* eps;        // [k+1][npair]: eps(t_{n-k+i})
+    const cd* sigRn[5];   // sigRn[u-1]: Sigma^R row n-k+u (u = 1..k), Sigma^R(t_{n-k+u}, t_s) at [s]
+    const cd* sigLn[5];   // sigLn[u-1]: Sigma^< slice n-k+u, Sigma^<(t_s, t_{n-k+u}) at [s]
+    const cd* GRn;        // G^R(t_n, t_s), s <= n
+    const cd* prev[5];    // prev[l-1]: lesser slice n-l, G^<(t_s, t_{n-l}) at [s]
+    cd* slice;            // in: I^<(t_n, t_m) without the s = n term of the first integral, m <= n-k
+                          // out: G^<(t_s, t_n), s = 0..n
+    cd* scr;              // (1 + k) npair: M^{-1}, then per near column the known sum
+    cd* part;             // [k][chunk][npair] partial sums of the near columns' integrals
+    int nchunk;           // chunks of lesser_sums
+};
+int lesser_sum_chunks(int n);
+hipError_t launch_lesser_prep(const LesserStepArgs& a, hipStream_t st);
+hipError_t launch_lesser_rest(const LesserStepArgs& a, hipStream_t st, hipEvent_t* ev = nullptr);
+
 // The near-diagonal kernel needs no history sum, so it can run beside the history
 // kernels; the bulk kernel (after them) also copies its results into the row and writes
 // G(n, n).  ev: nullptr, or two events recorded around the launch on its stream.

@@ -195,6 +195,166 @@ __global__ void __launch_bounds__(NT) step_bulk(StepArgs A) {
     row[o] = y;
 }
 
+// ---------------------------------------------------------------------------
+// lesser step
+
+constexpr int kSumChunk = 256;   // time points s per workgroup of lesser_sums
+
+// M_L^{-1}, M_L = (i a_0/h) 1 - eps(t_n) - h w^{(n)}_n Sigma^R(n, n), into scr[0..npair)
+template <int NORB>
+__global__ void __launch_bounds__(NT) lesser_prep(LesserStepArgs A) {
+    constexpr int npair = NORB * NORB, l2 = 2 * NORB;
+    __shared__ cd T[NORB * l2];
+    __shared__ int used[NORB], prow[NORB];
+    const int n = A.n, k = A.k;
+    const double wl = A.h * interval_w(A.W, n, n);
+    const cd* sRn = A.sigRn[k - 1] + (size_t)n * npair;
+    for (int e = threadIdx.x; e < NORB * l2; e += NT) {
+        const int r = e / l2, col = e % l2;
+        T[e] = col < NORB ? mk(0.0, r == col ? A.S.a[0] / A.h : 0.0) - A.eps[(size_t)k * npair + r * NORB + col] -
+                                wl * sRn[r * NORB + col]
+                          : mk(r == col - NORB ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    gauss_jordan(T, NORB, l2, used, prow);
+    for (int e = threadIdx.x; e < npair; e += NT) A.scr[e] = gj_solution(T, NORB, l2, prow, e / NORB, e % NORB);
+}
+
+// columns m <= n-k: thread (m, e = (b, a)) forms entry e of the right side
+//   I^<(n,m) - (i/h) sum_l a_l G^<(n-l, m),  G^<(n-l, m)[b][a] = -conj(prev[l-1][m][a][b])
+//   below the diagonal, the stored equal-time value prev[l-1][m][b][a] itself on it (m = n-l),
+// the block's right sides are staged in LDS; thread (m, (c, a)) then writes the slice entry
+// G^<(t_m, t_n)[a][c] = -conj(G^<(n, m)[c][a]) with G^<(n, m) = M_L^{-1} rhs
+template <int NORB>
+__global__ void __launch_bounds__(NT) lesser_bulk(LesserStepArgs A) {
+    constexpr int npair = NORB * NORB, CPB = NT / npair;
+    __shared__ cd Mi[npair];
+    __shared__ cd R[CPB * npair];
+    const int t = threadIdx.x;
+    if (t < npair) Mi[t] = A.scr[t];
+    const long long m = (long long)blockIdx.x * CPB + t / npair;
+    const int e = t % npair;
+    const bool on = t < CPB * npair && m <= A.n - A.k;
+    const double ih = 1.0 / A.h;
+    if (on) {
+        const int b = e / NORB, a = e % NORB;
+        const size_t ot = (size_t)m * npair + a * NORB + b;   // transposed entry
+        cd s = mk(0.0, 0.0);
+#pragma unroll
+        for (int l = 1; l <= 5; ++l)
+            if (l <= A.k) {
+                const cd v = m == A.n - l ? A.prev[l - 1][(size_t)m * npair + e] : -conj(A.prev[l - 1][ot]);
+                s = s + A.S.a[l] * v;
+            }
+        const cd hist = A.slice[(size_t)m * npair + e];
+        R[t] = mk(hist.x + s.y * ih, hist.y - s.x * ih);   // hist - (i/h) s
+    }
+    __syncthreads();
+    if (!on) return;
+    const int c = e / NORB, a = e % NORB, base = t - e;
+    cd y = mk(0.0, 0.0);
+#pragma unroll
+    for (int b = 0; b < NORB; ++b) fma_(y, Mi[c * NORB + b], R[base + b * NORB + a]);
+    A.slice[(size_t)m * npair + a * NORB + c] = mk(-y.x, y.y);   // -conj
+}
+
+// partial sums, near column i = 1..k (m = n-k+i, grid y), time points s of chunk blockIdx.x:
+//   h sum_{s <= n-k} w^{(m)}_s G^<(n,s) Sigma^A(s,m) + h sum_{s <= n} w^{(n)}_s G^R(n,s) Sigma^<(s,m)
+// thread (s group g, entry e = (c, a)) accumulates entry e over its time points
+template <int NORB>
+__global__ void __launch_bounds__(NT) lesser_sums(LesserStepArgs A) {
+    constexpr int npair = NORB * NORB, SG = NT / npair;
+    __shared__ cd red[NT];
+    const int n = A.n, k = A.k, i = blockIdx.y + 1, m = n - k + i;
+    const int t = threadIdx.x, e = t % npair, g = t / npair, c = e / NORB, a = e % NORB;
+    const cd* sRm = A.sigRn[i - 1];
+    const int s0 = blockIdx.x * kSumChunk, s1 = min(s0 + kSumChunk, n + 1);
+    cd acc = mk(0.0, 0.0);
+    for (int s = s0 + g; s < s1; s += SG) {
+        if (s <= n - k) {   // G^<(n,s)[c][b] = -conj(slice[s][b][c]);  Sigma^A(s,m)[b][a] = conj(Sigma^R(m,s)[a][b])
+            const double w = A.h * interval_w(A.W, m, s);
+            cd x = mk(0.0, 0.0);
+#pragma unroll
+            for (int b = 0; b < NORB; ++b)
+                x = x - conj(A.slice[(size_t)s * npair + b * NORB + c]) * conj(sRm[(size_t)s * npair + a * NORB + b]);
+            acc = acc + w * x;
+        }
+        {   // Sigma^<(s,m): slice m at s (s <= m), else -conj(slice s at m)^T
+            const double w = A.h * interval_w(A.W, n, s);
+            cd x = mk(0.0, 0.0);
+#pragma unroll
+            for (int b = 0; b < NORB; ++b) {
+                const cd sl = s <= m ? A.sigLn[i - 1][(size_t)s * npair + b * NORB + a]
+                                     : -conj(A.sigLn[s - (n - k) - 1][(size_t)m * npair + a * NORB + b]);
+                fma_(x, A.GRn[(size_t)s * npair + c * NORB + b], sl);
+            }
+            acc = acc + w * x;
+        }
+    }
+    red[t] = acc;
+    __syncthreads();
+    if (g == 0) {
+        cd sum = mk(0.0, 0.0);
+        for (int q = 0; q < SG; ++q) sum = sum + red[q * npair + e];
+        A.part[((size_t)(i - 1) * A.nchunk + blockIdx.x) * npair + e] = sum;
+    }
+}
+
+// the near system: unknowns Y[(p, a)][c] = G^<(n, n-k+p)[c][a], p = 1..k; equation of column
+// m = n-k+i as the row block (i, b):
+//   sum_{p,a} C_{p,i}[a][b] Y[(p,a)][c] = R_i[c][b],
+//   C_{p,i} = -(i/h) D_{ip} 1 - [p = i] eps(t_m) - [p <= i] h w^{(m)}_{n-k+p} Sigma^A(n-k+p, m),
+//   R_i     = (i/h) D_{i0} G^<(n, n-k) + (the partial sums of column i)
+template <int NORB>
+__global__ void __launch_bounds__(NT) lesser_near(LesserStepArgs A) {
+    constexpr int npair = NORB * NORB, KMAX = 5 * NORB, LDMAX = KMAX + NORB;
+    __shared__ cd T[KMAX * LDMAX];
+    __shared__ int used[KMAX], prow[KMAX];
+    const int n = A.n, k = A.k, K = k * NORB, ld = K + NORB;
+    const double h = A.h;
+    for (int e = threadIdx.x; e < K * ld; e += NT) {
+        const int r = e / ld, col = e % ld, i = r / NORB + 1, b = r % NORB, m = n - k + i;
+        cd v;
+        if (col < K) {
+            const int p = col / NORB + 1, a = col % NORB, s = n - k + p;
+            v = mk(0.0, a == b ? -A.S.D[i][p] / h : 0.0);
+            if (p == i) v = v - A.eps[(size_t)i * npair + a * NORB + b];
+            if (p <= i)   // Sigma^A(s,m)[a][b] = conj(Sigma^R(m,s)[b][a])
+                v = v - (h * interval_w(A.W, m, s)) * conj(A.sigRn[i - 1][(size_t)s * npair + b * NORB + a]);
+        } else {
+            const int c = col - K;
+            // (i/h) D_{i0} G^<(n, n-k)[c][b],  G^<(n, n-k)[c][b] = -conj(slice[n-k][b][c])
+            const cd g0 = A.slice[(size_t)(n - k) * npair + b * NORB + c];
+            const double d = A.S.D[i][0] / h;
+            v = mk(-d * g0.y, -d * g0.x);   // (i d) (-conj(g0))
+            for (int q = 0; q < A.nchunk; ++q) v = v + A.part[((size_t)(i - 1) * A.nchunk + q) * npair + c * NORB + b];
+        }
+        T[e] = v;
+    }
+    __syncthreads();
+    gauss_jordan(T, K, ld, used, prow);
+    for (int e = threadIdx.x; e < K * NORB; e += NT) {
+        const int r = e / NORB, c = e % NORB, p = r / NORB + 1, a = r % NORB, s = n - k + p;
+        const cd y = gj_solution(T, K, ld, prow, r, c);   // G^<(n, s)[c][a]
+        if (s < n)
+            A.slice[(size_t)s * npair + a * NORB + c] = mk(-y.x, y.y);   // G^<(t_s, t_n)[a][c] = -conj
+        else
+            A.slice[(size_t)n * npair + c * NORB + a] = y;               // G^<(t_n, t_n) itself
+    }
+}
+
+template <int NORB>
+hipError_t launch_lesser_rest_t(const LesserStepArgs& a, hipStream_t st, hipEvent_t* ev) {
+    constexpr int CPB = NT / (NORB * NORB);
+    const int nb = a.n - a.k + 1;
+    if (ev) hipEventRecord(ev[0], st);
+    lesser_bulk<NORB><<<(nb + CPB - 1) / CPB, NT, 0, st>>>(a);
+    lesser_sums<NORB><<<dim3(a.nchunk, a.k), NT, 0, st>>>(a);
+    lesser_near<NORB><<<1, NT, 0, st>>>(a);
+    if (ev) hipEventRecord(ev[1], st);
+    return hipGetLastError();
+}
+
 template <int NORB>
 hipError_t launch_near_t(const StepArgs& a, hipStream_t st, hipEvent_t* ev) {
     if (ev) hipEventRecord(ev[0], st);
@@ -218,6 +378,33 @@ bool step_args_ok(const StepArgs& a) {
 }
 
 }  // namespace
+
+int lesser_sum_chunks(int n) { return (n + 1 + kSumChunk - 1) / kSumChunk; }
+
+hipError_t launch_lesser_prep(const LesserStepArgs& a, hipStream_t st) {
+    if (a.k < 1 || a.k > 5 || a.n < a.k) return hipErrorInvalidValue;
+    switch (a.norb) {
+        case 1: lesser_prep<1><<<1, NT, 0, st>>>(a); break;
+        case 2: lesser_prep<2><<<1, NT, 0, st>>>(a); break;
+        case 4: lesser_prep<4><<<1, NT, 0, st>>>(a); break;
+        case 8: lesser_prep<8><<<1, NT, 0, st>>>(a); break;
+        case 16: lesser_prep<16><<<1, NT, 0, st>>>(a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_lesser_rest(const LesserStepArgs& a, hipStream_t st, hipEvent_t* ev) {
+    if (a.k < 1 || a.k > 5 || a.n < a.k || a.nchunk != lesser_sum_chunks(a.n)) return hipErrorInvalidValue;
+    switch (a.norb) {
+        case 1: return launch_lesser_rest_t<1>(a, st, ev);
+        case 2: return launch_lesser_rest_t<2>(a, st, ev);
+        case 4: return launch_lesser_rest_t<4>(a, st, ev);
+        case 8: return launch_lesser_rest_t<8>(a, st, ev);
+        case 16: return launch_lesser_rest_t<16>(a, st, ev);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_step_near(const StepArgs& a, hipStream_t st, hipEvent_t* ev) {
     if (!step_args_ok(a)) return hipErrorInvalidValue;

@@ -357,3 +357,85 @@ def test_step_batched_lattice_workload(P):
             worst = max(worst, err)
             assert err <= 1e-10, (n, o, err)
     say(f"  worst {worst:.2e}")
+
+
+# ---------------------------------------------------------------------------
+# the lesser step: a two-component march (retarded step, append, lesser step, append)
+
+def _inputs_lesser(N, norb, h, k, seed):
+    from kbe_inputs import lesser as lesser_fn
+    pS = scalar_terms(seed, 8) if norb == 1 else hermitian_terms(seed, 8, norb)
+    t = np.arange(N) * h
+    SR = np.zeros((N, N, norb, norb), dtype=np.complex128)
+    for n in range(N):
+        SR[n, :n + 1] = retarded(pS, t[n], t[:n + 1])
+    SL = lesser_fn(pS, t[:, None], t[None, :])                 # Sigma^<(t_a, t_b), every pair
+    eps = hermitian_drive(seed + 1, norb, N, h)
+    rng = np.random.default_rng(seed + 2)
+    B = rng.standard_normal((norb, norb)) + 1j * rng.standard_normal((norb, norb))
+    rho = 0.5 * (B @ B.conj().T) / norb
+    U = [expm(-1j * eps[0] * n * h) for n in range(N)]
+    GR0 = np.zeros((N, N, norb, norb), dtype=np.complex128)
+    GL0 = np.zeros((N, N, norb, norb), dtype=np.complex128)
+    for n in range(k):
+        for m in range(k):
+            GL0[n, m] = 1j * U[n] @ rho @ U[m].conj().T
+            if m <= n:
+                GR0[n, m] = -1j * U[n - m]
+    return SR, SL, eps, GR0, GL0
+
+
+LESSER_CASES = [(1, 5, 110, 2), (2, 4, 100, 1), (4, 3, 96, 1), (4, 5, 130, 2)]
+
+
+@pytest.mark.parametrize("norb,k,N,nlvl", LESSER_CASES)
+def test_lesser_step_march_against_oracle(P, norb, k, N, nlvl):
+    from oracle.step_solve import solve_lesser, step_lesser
+    h = 0.02
+    say(f"lesser march: norb {norb} k {k} N {N} nlvl {nlvl}")
+    SR, SL, eps, GR0, GL0 = _inputs_lesser(N, norb, h, k, seed=70 + norb + k)
+    H = P.Hodlr(N, nlvl, norb, k=k, tol=1e-12, panel=16, max_rank=32)
+    rR, sL = [], []        # retarded rows, lesser slices (device)
+    for n in range(k):
+        r = to_dev(GR0[n, :n + 1])
+        s = to_dev(GL0[:n + 1, n])
+        H.append_row(P.RET, n, r)
+        H.append_row(P.LES, n, s)
+        rR.append(r)
+        sL.append(s)
+    dSR = [to_dev(SR[j, :j + 1]) for j in range(N)]
+    dSL = [to_dev(SL[:j + 1, j]) for j in range(N)]           # Sigma^< slices (t_s, t_j), s <= j
+    for n in range(k, N):
+        e = to_dev(eps[n - k:n + 1])
+        near = np.zeros((k, k, norb, norb), dtype=np.complex128)
+        for u in range(k):
+            for i in range(u + 1):
+                near[u, i] = SR[n - k + u, n - k + i]
+        r = torch.empty((n + 1, norb, norb), dtype=torch.complex128, device="cuda")
+        H.step_R(n, e, dSR[n], to_dev(near), rR[n - k:n][::-1], h, r)
+        H.append_row(P.RET, n, r)
+        rR.append(r)
+        s = torch.empty((n + 1, norb, norb), dtype=torch.complex128, device="cuda")
+        H.step_lesser(n, e, dSR[n - k + 1:n + 1], dSL[n - k + 1:n + 1], r, sL[n - k:n][::-1], h, s)
+        H.append_row(P.LES, n, s)
+        sL.append(s)
+    torch.cuda.synchronize()
+    H.status()
+    GR = np.zeros((N, N, norb, norb), dtype=np.complex128)
+    GL = np.zeros((N, N, norb, norb), dtype=np.complex128)
+    for n in range(N):
+        GR[n, :n + 1] = rR[n].cpu().numpy()
+        col = sL[n].cpu().numpy()                              # G^<(t_s, t_n), s <= n
+        GL[:n + 1, n] = col
+        GL[n, :n] = -np.conj(np.swapaxes(col[:n], -1, -2))
+    assert np.all(np.isfinite(GL))
+    worst = 0.0
+    for n in range(k, N):
+        ref = step_lesser(GR, GL, SR, SL, eps, n, h, k)        # from the GPU's rows before n
+        err = np.abs(GL[n, :n + 1] - ref).max() / np.abs(ref).max()
+        worst = max(worst, err)
+        assert err <= 1e-10, (n, err)
+    _, refL = solve_lesser(SR, SL, eps, GR0, GL0, h, k, N)
+    errN = np.abs(GL - refL).max() / np.abs(refL).max()
+    say(f"  lesser one-step worst {worst:.2e}, march {errN:.2e}")
+    assert errN <= 1e-8, errN
