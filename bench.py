@@ -544,6 +544,73 @@ def step_solve_bench(P, prof_stride=8):
     return out
 
 
+def two_component_bench(P):
+    """Both components of the time step marched over the norb-4 N_t = 8192 grid: per step the
+    retarded step (hnessi_step_R), its append, the lesser step (hnessi_step_lesser) and its
+    append, with the merges that fall due; the inputs of the retarded march (constant
+    Hermitian eps, 2-term Sigma, retarded and lesser parts), rows 0..k-1 the free
+    propagators with a seeded density matrix."""
+    import numpy as np
+    import torch
+    from scipy.linalg import expm
+    from kbe_inputs import hermitian_drive, hermitian_terms, make_config_inputs, retarded
+    from kbe_inputs.packed import RowSource
+    cfg = make_config_inputs("c2")[0]
+    N, h, norb, k = cfg["nt"], cfg["h"], cfg["norb"], cfg["k"]
+    nlvl = int(round(np.log2(N // cfg["leaf"])))
+    dev = torch.device("cuda:0")
+    S = hermitian_terms(cfg["seed_s"], 2, norb)
+    src = RowSource(S, N, h, dev)
+    eps_h = hermitian_drive(cfg["seed_s"] + 100, norb, N, h, amp=0.0)
+    eps_d = torch.as_tensor(eps_h, device=dev)
+    near = np.zeros((k, k, norb, norb), dtype=np.complex128)
+    for u in range(k):
+        for i in range(u + 1):
+            near[u, i] = retarded(S, (u - i) * h, 0.0)
+    near_d = torch.as_tensor(near, device=dev)
+    rng = np.random.default_rng(31)
+    B = rng.standard_normal((norb, norb)) + 1j * rng.standard_normal((norb, norb))
+    rho = 0.5 * (B @ B.conj().T) / norb
+    U = [expm(-1j * eps_h[0] * n * h) for n in range(k)]
+    startR = [torch.as_tensor(np.stack([-1j * U[n - m] for m in range(n + 1)]), device=dev) for n in range(k)]
+    startL = [torch.as_tensor(np.stack([1j * U[m] @ rho @ U[n].conj().T for m in range(n + 1)]), device=dev)
+              for n in range(k)]
+    H = P.Hodlr(N, nlvl, norb, k=k, tol=cfg["tol"], panel=16, max_rank=32)
+
+    def march(n_end):
+        H.reset()
+        rR, rL, rSL = [], [], []
+        for n in range(n_end):
+            sl_n = torch.empty((n + 1, norb, norb), dtype=torch.complex128, device=dev)
+            src.les(n, out=sl_n)
+            rSL = (rSL + [sl_n])[-k:]
+            if n < k:
+                r, s = startR[n], startL[n]
+                H.append_row(P.RET, n, r)
+            else:
+                r = torch.empty((n + 1, norb, norb), dtype=torch.complex128, device=dev)
+                H.step_R(n, eps_d[n - k:n + 1], src.ret(n), near_d, rR[::-1], h, r)
+                H.append_row(P.RET, n, r)
+                s = torch.empty((n + 1, norb, norb), dtype=torch.complex128, device=dev)
+                H.step_lesser(n, eps_d[n - k:n + 1], [src.ret(j) for j in range(n - k + 1, n + 1)], rSL, r,
+                              rL[::-1], h, s)
+            H.append_row(P.LES, n, s)
+            rR = (rR + [r])[-k:]
+            rL = (rL + [s])[-k:]
+
+    march(512)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    march(N)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = dict(value=round(N / dt, 1), unit="time steps/s (retarded and lesser step solves with their history "
+                                           "sums and appends)", n_t=N, norb=norb, seconds=round(dt, 3),
+               max_rank=int(max(H.ranks(P.RET).max(), H.ranks(P.LES).max())), status=H.status())
+    H.close()
+    return out
+
+
 def lattice_step_bench(P):
     """The retarded time step of every momentum of the 32x32 lattice (hnessi_step_R_batched,
     N_t = 2048, norb 1): each step the batched history sum over the stored rows, the step
@@ -813,6 +880,7 @@ def main():
     step_solve = None
     if not args.no_step:
         step_solve = step_solve_bench(P, args.prof_stride)
+        step_solve["two_component"] = two_component_bench(P)
         step_solve["lattice"] = lattice_step_bench(P)
         log("step solve:", step_solve)
 

@@ -119,25 +119,46 @@ def step_lesser(GR, GL, SR, SL, eps, n: int, h: float, k: int):
     GR[t, t'] (t' <= t, rows 0..n, row n the new retarded row), GL[t, t'] (every t, t' < n,
     both triangles), SR[t, t'] (t' <= t <= n), SL[t, t'] (Sigma^<, every t, t' <= n), eps[t]."""
     norb = eps.shape[-1]
-    I = np.eye(norb, dtype=np.complex128)
-    a = bdf(k)
-    D = diff_matrix(k)
-    wn = interval_weights_f64(k, n)
-    M = (1j * a[0] / h) * I - eps[n] - h * wn[n] * SR[n, n]
     row = np.zeros((n + 1, norb, norb), dtype=np.complex128)
     for m in range(0, n - k + 1):
-        wm = interval_weights_f64(k, m)
-        rhs = -(1j / h) * sum(a[l] * GL[n - l, m] for l in range(1, k + 1))
-        rhs = rhs + h * sum(wn[s] * (SR[n, s] @ GL[s, m]) for s in range(0, n))
-        rhs = rhs + h * sum(wm[s] * (SL[n, s] @ GR[m, s].conj().T) for s in range(0, m + 1))
-        row[m] = np.linalg.solve(M, rhs)
-    # X C = R over the unknowns X = [G^<(n, n-k+p)], p = 1..k
+        row[m] = lesser_bulk_column(lambda s, m=m: GL[s, m], GR[m, :m + 1], SR[n], SL[n], eps[n], n, m, h, k)
+    near = [[SL[s, n - k + i] for s in range(n + 1)] for i in range(1, k + 1)]
+    row[n - k + 1:] = lesser_near_block(row[:n - k + 1], GR[n], [SR[n - k + i] for i in range(1, k + 1)], near,
+                                        eps, n, h, k)
+    return row
+
+
+def lesser_bulk_column(Gcol, GRm, SRn, SLn, eps_n, n: int, m: int, h: float, k: int):
+    """G^<(n, m) for a column m <= n-k from the left form: Gcol(s) = G^<(t_s, t_m) for s < n,
+    GRm[s] = G^R(t_m, t_s) (s <= m), SRn[s] = Sigma^R(t_n, t_s), SLn[s] = Sigma^<(t_n, t_s)
+    (s <= n), eps_n = eps(t_n)."""
+    norb = eps_n.shape[-1]
+    I = np.eye(norb, dtype=np.complex128)
+    a = bdf(k)
+    wn = interval_weights_f64(k, n)
+    wm = interval_weights_f64(k, m)
+    M = (1j * a[0] / h) * I - eps_n - h * wn[n] * SRn[n]
+    rhs = -(1j / h) * sum(a[l] * Gcol(n - l) for l in range(1, k + 1))
+    rhs = rhs + h * sum(wn[s] * (SRn[s] @ Gcol(s)) for s in range(0, n))
+    rhs = rhs + h * sum(wm[s] * (SLn[s] @ GRm[s].conj().T) for s in range(0, m + 1))
+    return np.linalg.solve(M, rhs)
+
+
+def lesser_near_block(row, GRn, SRnear, SLnear, eps, n: int, h: float, k: int):
+    """G^<(n, n-k+p), p = 1..k (shape (k, norb, norb)) from the right form: row[s] =
+    G^<(t_n, t_s) for s <= n-k (the left-form columns), GRn[s] = G^R(t_n, t_s) (s <= n),
+    SRnear[i-1][s] = Sigma^R(t_m, t_s) (s <= m) and SLnear[i-1][s] = Sigma^<(t_s, t_m)
+    (s <= n) for m = n-k+i, eps[t] (t = n-k+1..n read)."""
+    norb = eps.shape[-1]
+    I = np.eye(norb, dtype=np.complex128)
+    D = diff_matrix(k)
+    wn = interval_weights_f64(k, n)
     C = np.zeros((k * norb, k * norb), dtype=np.complex128)
     R = np.zeros((norb, k * norb), dtype=np.complex128)
     for i in range(1, k + 1):
         m = n - k + i
         wm = interval_weights_f64(k, m)
-        SA = lambda s: SR[m, s].conj().T            # Sigma^A(s, m), s <= m
+        SA = lambda s, i=i: SRnear[i - 1][s].conj().T            # Sigma^A(s, m), s <= m
         for p in range(1, k + 1):
             blk = -(1j / h) * D[i][p] * I
             if p == i:
@@ -148,12 +169,10 @@ def step_lesser(GR, GL, SR, SL, eps, n: int, h: float, k: int):
             C[(p - 1) * norb:p * norb, (i - 1) * norb:i * norb] = blk
         r = (1j / h) * D[i][0] * row[n - k]
         r = r + h * sum(wm[s] * (row[s] @ SA(s)) for s in range(0, n - k + 1))
-        r = r + h * sum(wn[s] * (GR[n, s] @ SL[s, m]) for s in range(0, n + 1))
+        r = r + h * sum(wn[s] * (GRn[s] @ SLnear[i - 1][s]) for s in range(0, n + 1))
         R[:, (i - 1) * norb:i * norb] = r
-    X = np.linalg.solve(C.T, R.T).T
-    for p in range(1, k + 1):
-        row[n - k + p] = X[:, (p - 1) * norb:p * norb]
-    return row
+    X = np.linalg.solve(C.T, R.T).T                # X C = R over X = [G^<(n, n-k+p)]_p
+    return np.stack([X[:, (p - 1) * norb:p * norb] for p in range(1, k + 1)])
 
 
 def solve_lesser(SR, SL, eps, GR_init, GL_init, h: float, k: int, N: int):

@@ -439,3 +439,107 @@ def test_lesser_step_march_against_oracle(P, norb, k, N, nlvl):
     errN = np.abs(GL - refL).max() / np.abs(refL).max()
     say(f"  lesser one-step worst {worst:.2e}, march {errN:.2e}")
     assert errN <= 1e-8, errN
+
+
+def test_lesser_step_full_size_norb4(P):
+    """Both components marched over all 8192 steps of the norb-4 grid (FP64 factors,
+    tolerance 1e-10): constant Hermitian eps, 2-term Sigma (retarded and lesser parts of the
+    damped-exponential generator), rows 0..k-1 the free propagators with a seeded density
+    matrix.  At sampled steps, sampled left-form columns and the right-form entries of the
+    lesser row against the oracle's column step and near-diagonal solve on the GPU's own
+    earlier rows; errors scaled by the oracle's largest entry of the row's samples."""
+    from gpu_common import boundary_columns
+    from kbe_inputs import lesser as lesser_fn
+    from kbe_inputs import make_config_inputs
+    from kbe_inputs.packed import RowSource
+    from oracle.step_solve import lesser_bulk_column, lesser_near_block
+    cfg = make_config_inputs("c2")[0]
+    N, norb, h, k, tol = cfg["nt"], cfg["norb"], cfg["h"], cfg["k"], cfg["tol"]
+    npair = norb * norb
+    nlvl = int(round(np.log2(N // cfg["leaf"])))
+    pS = hermitian_terms(cfg["seed_s"], 2, norb)
+    eps_h = hermitian_drive(cfg["seed_s"] + 100, norb, N, h, amp=0.0)
+    e0 = eps_h[0]
+    rng = np.random.default_rng(31)
+    B = rng.standard_normal((norb, norb)) + 1j * rng.standard_normal((norb, norb))
+    rho = 0.5 * (B @ B.conj().T) / norb
+    U = [expm(-1j * e0 * n * h) for n in range(k)]
+    src = RowSource(pS, N, h, "cuda")
+    eps_d = to_dev(eps_h)
+    near_h = np.zeros((k, k, norb, norb), dtype=np.complex128)
+    for u in range(k):
+        for i in range(u + 1):
+            near_h[u, i] = retarded(pS, (u - i) * h, 0.0)
+    near_d = to_dev(near_h)
+    H = P.Hodlr(N, nlvl, norb, k=k, tol=tol, panel=16, max_rank=32)
+    steps = [5, 9, 10, 64, 1023, 4096, N - 1]
+    colset = {n: [m for m in boundary_columns(n, cfg["leaf"], nlvl, rng, 24) if m <= n - k] for n in steps}
+    mcols = np.array(sorted(set().union(*colset.values())), dtype=np.int64)
+    pos = {int(m): j for j, m in enumerate(mcols)}
+    mc_d = torch.as_tensor(mcols, device="cuda")
+    GcL = torch.zeros((N, len(mcols), norb, norb), dtype=torch.complex128, device="cuda")
+    savedL, savedR = {}, {}
+    rR, rL, rSL = [], [], []          # last k+1 retarded rows, lesser slices, Sigma^< slices
+    say(f"two-component march: N {N} norb {norb}, {len(mcols)} sampled columns")
+    t = np.arange(N) * h
+    for n in range(N):
+        sl_n = torch.empty((n + 1, norb, norb), dtype=torch.complex128, device="cuda")
+        src.les(n, out=sl_n)
+        rSL = (rSL + [sl_n])[-k:]
+        if n < k:
+            r = to_dev(np.stack([-1j * U[n - m] for m in range(n + 1)]))
+            s = to_dev(np.stack([1j * U[m] @ rho @ U[n].conj().T for m in range(n + 1)]))
+        else:
+            r = torch.empty((n + 1, norb, norb), dtype=torch.complex128, device="cuda")
+            H.step_R(n, eps_d[n - k:n + 1], src.ret(n), near_d, rR[-k:][::-1], h, r)
+            s = torch.empty((n + 1, norb, norb), dtype=torch.complex128, device="cuda")
+            H.append_row(P.RET, n, r)
+            H.step_lesser(n, eps_d[n - k:n + 1], [src.ret(j) for j in range(n - k + 1, n + 1)], rSL, r,
+                          rL[-k:][::-1], h, s)
+        if n < k:
+            H.append_row(P.RET, n, r)
+        H.append_row(P.LES, n, s)
+        rR = (rR + [r])[-(k + 1):]
+        rL = (rL + [s])[-(k + 1):]
+        sel = int(np.searchsorted(mcols, n, side="right"))
+        if sel:
+            GcL[n, :sel] = s[mc_d[:sel]]
+        if n in pos:
+            savedL[n] = s.cpu().numpy()
+            savedR[n] = r.cpu().numpy()
+        if n in colset:
+            savedL[("row", n)] = s.cpu().numpy()
+            savedR[("row", n)] = r.cpu().numpy()
+        if n % 2048 == 2047:
+            torch.cuda.synchronize()
+            say(f"  step {n + 1}")
+    torch.cuda.synchronize()
+    say(f"  max rank R {int(H.ranks(P.RET).max())}, < {int(H.ranks(P.LES).max())}")
+    H.status()
+    GcL_h = GcL.cpu().numpy()
+    herm = lambda x: np.conj(np.swapaxes(x, -1, -2))
+    worst = 0.0
+    for n in steps:
+        sl = savedL[("row", n)]                  # G^<(t_s, t_n), s <= n
+        grow = -herm(sl[:n])                      # G^<(t_n, t_s), s < n
+        SRn = retarded(pS, t[n], t[:n + 1])
+        SLn = lesser_fn(pS, np.full(n + 1, t[n]), t[:n + 1])          # Sigma^<(t_n, t_s)
+        refs, gots = [], []
+        for m in colset[n]:
+            j = pos[m]
+
+            def Gcol(s, m=m, j=j):
+                return savedL[m][s] if s <= m else -herm(GcL_h[s, j])
+            refs.append(lesser_bulk_column(Gcol, savedR[m], SRn, SLn, eps_h[n], n, m, h, k))
+            gots.append(grow[m])
+        rown = np.concatenate([grow[:n - k + 1]])
+        SRnear = [retarded(pS, t[n - k + i], t[:n - k + i + 1]) for i in range(1, k + 1)]
+        SLnear = [lesser_fn(pS, t[:n + 1], np.full(n + 1, t[n - k + i])) for i in range(1, k + 1)]
+        nb = lesser_near_block(rown, savedR[("row", n)], SRnear, SLnear, eps_h, n, h, k)
+        gnear = np.concatenate([grow[n - k + 1:n], sl[n:n + 1]])
+        scale = max([np.abs(x).max() for x in refs] + [np.abs(nb).max()])
+        err = max([np.abs(g - r).max() for g, r in zip(gots, refs)] + [np.abs(gnear - nb).max()]) / scale
+        worst = max(worst, err)
+        say(f"  step {n}: {len(refs)} left-form columns + {k} right-form entries, relative error {err:.2e}")
+        assert err <= 1e-10, (n, err)
+    say(f"  worst {worst:.2e}")
