@@ -6,6 +6,8 @@ number of singular values >= tol (a value within 1e-3 * tol of tol may go either
 the spectral error |A - U S V^dagger|_2 is below tol, U and V are orthonormal, and the
 reconstruction agrees with the oracle's TSVD within 2 * tol.
 """
+import gc
+
 import numpy as np
 import pytest
 
@@ -193,6 +195,9 @@ def test_torch_caching_allocator_serves_the_handle(P):
         if use_torch:
             P.use_torch_allocator()
         try:
+            # objects of earlier tests that the collector frees later would shift the count
+            gc.collect()
+            torch.cuda.synchronize()
             before = torch.cuda.memory_allocated()
             H = P.Hodlr(N, 3, norb, k=5, tol=1e-12, panel=8, max_rank=12)
             held = torch.cuda.memory_allocated() - before
@@ -202,8 +207,8 @@ def test_torch_caching_allocator_serves_the_handle(P):
             if use_torch:
                 assert held >= H.nbytes()          # served by torch's allocator
             H.close()
-            if use_torch:
-                assert torch.cuda.memory_allocated() - before == 0   # and returned to it
+            if use_torch:   # and returned to it: nothing of the handle is still held
+                assert torch.cuda.memory_allocated() - before <= 0
             outs.append((IR.cpu(), IL.cpu()))
         finally:
             P.set_allocator()
