@@ -190,6 +190,37 @@ def solve_lesser(SR, SL, eps, GR_init, GL_init, h: float, k: int, N: int):
     return GR, GL
 
 
+def row_march(Sig, eps, n: int, h: float, k: int):
+    """Row n of G^R by the paper's orientation (Eq. KBER: the derivative in the relative
+    time, the current G row times the Sigma history): the right form
+        -i d/dt' G^R(t_n, t') - G^R(t_n, t') eps(t') = int_{t'}^{t_n} G^R(t_n, s) Sigma^R(s, t') ds
+    marched along the row from the diagonal, G^R(n, n) = -i, needs no other row.  Columns
+    n-k..n-1: the k-unknown start of `step` (polynomial differentiation weights on the
+    points n-k..n); columns m < n-k, leftwards: the t'-derivative by the backward
+    differentiation weights on the points m, m+1, .., m+k of the row (f'(t_m) h ~
+    -sum_l a_l f(t_{m+l})), the integral over [t_m, t_n] with w^{(n-m)}, its term s = m
+    taken to the left:
+        G(n,m) [i a_0/h - eps(m) - h w^{(n-m)}_0 Sigma(m,m)]
+            = -(i/h) sum_{l>=1} a_l G(n, m+l) + h sum_{s=m+1}^{n} w^{(n-m)}_{s-m} G(n,s) Sigma(s,m).
+    Sig[s, m] (m <= s <= n), eps[t] (t <= n).  Returns (n+1, norb, norb)."""
+    norb = eps.shape[-1]
+    I = np.eye(norb, dtype=np.complex128)
+    a = bdf(k)
+    row = np.zeros((n + 1, norb, norb), dtype=np.complex128)
+    row[n] = -1j * I
+    if k > 0:
+        near = [[Sig[n - k + u, n - k + i] for i in range(k)] for u in range(k)]
+        row[n - k:n] = near_block(near, Sig[n], eps, n, h, k)
+    for m in range(n - k - 1, -1, -1):
+        L = n - m
+        w = interval_weights_f64(k, L)
+        M = (1j * a[0] / h) * I - eps[m] - h * w[0] * Sig[m, m]
+        rhs = -(1j / h) * sum(a[l] * row[m + l] for l in range(1, k + 1))
+        rhs = rhs + h * sum(w[s - m] * (row[s] @ Sig[s, m]) for s in range(m + 1, n + 1))
+        row[m] = np.linalg.solve(M.T, rhs.T).T        # X M = rhs
+    return row
+
+
 def solve(Sig, eps, G_init, h: float, k: int, N: int):
     """G^R on the whole grid (dense, G[n, m] for m <= n): rows 0..k-1 from G_init, the
     rest by successive steps."""

@@ -191,3 +191,55 @@ def test_lesser_memory_and_lesser_self_energy_closed_form_order():
     for k, errs in res.items():
         order = np.log2(errs[0] / errs[1])
         assert errs[1] < 1e-3 and order > min(k, 3) - 0.3, (k, errs, order)
+
+
+# ---------------------------------------------------------------------------
+# the paper's orientation: each row marched along t' in the right form
+
+from oracle.step_solve import row_march  # noqa: E402
+
+
+@pytest.mark.parametrize("k", [2, 3, 5])
+def test_row_march_free_propagator_order(k):
+    T, norb = 1.6, 2
+    errs = []
+    for N in (65, 129):
+        h = T / (N - 1)
+        eps, S, G = _free_case(N, h, norb, k)
+        n = N - 1
+        errs.append(np.abs(row_march(S, eps, n, h, k) - G[n, :n + 1]).max())
+    order = np.log2(errs[0] / errs[1])
+    assert errs[1] < 1e-2 and order > k - 0.3, (k, errs, order)
+
+
+@pytest.mark.parametrize("k", [3, 5])
+def test_row_march_memory_kernel_order(k):
+    T, lam = 1.6, 0.8
+    errs = []
+    for N in (65, 129):
+        h = T / (N - 1)
+        eps, S, G = _memory_case(N, h, lam)
+        n = N - 1
+        errs.append(np.abs(row_march(S, eps, n, h, k) - G[n, :n + 1]).max())
+    order = np.log2(errs[0] / errs[1])
+    assert errs[1] < 1e-3 and order > min(k, 4) - 0.3, (k, errs, order)
+
+
+def test_row_march_time_dependent_eps_closed_form():
+    """Sigma = 0, scalar eps(t) = e0 + a cos(w t): G^R(t,t') = -i exp(-i int_{t'}^{t} eps) =
+    -i exp(-i [e0 (t - t') + (a/w)(sin w t - sin w t')]); the row march takes eps at every
+    column t', so this pins its use of eps(t'); order k."""
+    e0, amp, om, T = 0.6, 0.8, 3.0, 1.6
+    for k in (3, 5):
+        errs = []
+        for N in (65, 129):
+            h = T / (N - 1)
+            t = np.arange(N) * h
+            eps = (e0 + amp * np.cos(om * t)).astype(np.complex128).reshape(N, 1, 1)
+            n = N - 1
+            ph = e0 * (t[n] - t[:n + 1]) + (amp / om) * (np.sin(om * t[n]) - np.sin(om * t[:n + 1]))
+            exact = (-1j * np.exp(-1j * ph)).reshape(n + 1, 1, 1)
+            S = np.zeros((N, N, 1, 1), dtype=np.complex128)
+            errs.append(np.abs(row_march(S, eps, n, h, k) - exact).max())
+        order = np.log2(errs[0] / errs[1])
+        assert errs[1] < 1e-3 and order > k - 0.3, (k, errs, order)
