@@ -192,6 +192,27 @@ int hnessi_step_lesser(hnessi_hodlr_t H, int n, const void* eps, const void* con
                        const void* const* sigL_slices, const void* GR_row,
                        const void* const* prev_slices, double h, void* slice_out, void* stream);
 
+/* Rows n_lo..n_hi of G^R in the paper's orientation (section "Kadanoff-Baym
+ * equations", Eq. KBER: the derivative in the relative time, the current G row times
+ * the compressed Sigma history).  H holds the Sigma^R rows (appended as its retarded
+ * component, up to n_hi at least).  Every row solves its own problem: the right form
+ *   -i d/dt' G(t_n, t') - G(t_n, t') eps(t') = int_{t'}^{t_n} G(t_n, s) Sigma(s, t') ds
+ * marched from G(n, n) = -i leftwards along the row, the first k columns by the
+ * k-unknown start of hnessi_step_R, then backward differentiation weights (appendix
+ * "Integral and derivative approximations") on the points m..m+k of the row and the
+ * Gregory interval weights over [t_m, t_n], the sum over the Sigma history taken from
+ * the compressed storage (leaf triangles, low-rank blocks through projections of the
+ * row's finished part, the dense tail) -- sequential within a row, one workgroup per
+ * row.  Waits for the handle's merges (the stored state must be complete).
+ *   eps       device, eps(t_j) for j = 0..n_hi (nt matrices may be passed)
+ *   rows_out  device, row n at rows_out + (n - n_lo) * row_stride complex entries,
+ *             G^R(t_n, t_m) at [m][a][b], m = 0..n
+ * norb must be 1, 2 or 4 and the rank capacity at most 32 (HNESSI_E_ARG); a batched
+ * handle, a NULL pointer, a row stride below (n_hi+1)*norb^2 or h <= 0: HNESSI_E_ARG;
+ * rows outside k..nt-1: HNESSI_E_RANGE; Sigma rows not appended: HNESSI_E_ORDER. */
+int hnessi_row_march_R(hnessi_hodlr_t H, int n_lo, int n_hi, const void* eps, double h,
+                       void* rows_out, long long row_stride, void* stream);
+
 /* Weights of the retarded time step (hnessi_step_R) for order k (1..5), host
  * outputs: a_host[0..k] the backward differentiation weights a_l = -D_{0l}
  * (f'(t_n) h ~ sum_l a_l f(t_{n-l})) and D_host[i*(k+1) + p], i, p = 0..k, the

@@ -58,6 +58,8 @@ _SIGS = {
     "hnessi_history_R": ([C.c_void_p, C.c_int, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p], C.c_int),
     "hnessi_step_R": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                        C.c_void_p, C.c_void_p], C.c_int),
+    "hnessi_row_march_R": ([C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_double, C.c_void_p, C.c_longlong,
+                            C.c_void_p], C.c_int),
     "hnessi_step_lesser": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                             C.c_double, C.c_void_p, C.c_void_p], C.c_int),
     "hnessi_step_R_batched": ([C.c_void_p, C.c_int, C.c_void_p, C.c_longlong, C.c_void_p, C.c_longlong, C.c_void_p,
@@ -280,6 +282,11 @@ class Hodlr:
         ptrs = (C.c_void_p * self.k)(*[_ptr(r).value for r in prev_rows])
         _check(lib().hnessi_step_R(self.h, n, _ptr(eps), _ptr(sigR), _ptr(sig_near), ptrs, h, _ptr(out),
                                    _stream()))
+
+    def row_march_R(self, n_lo, n_hi, eps, h, out, row_stride):
+        """Rows n_lo..n_hi of G^R in the paper's orientation over the stored Sigma^R (this
+        handle's retarded component): row n at out + (n - n_lo) * row_stride entries."""
+        _check(lib().hnessi_row_march_R(self.h, n_lo, n_hi, _ptr(eps), h, _ptr(out), row_stride, _stream()))
 
     def step_lesser(self, n, eps, sigR_rows, sigL_slices, GR_row, prev_slices, h, out):
         """Lesser slice n (G^<(t_s, t_n), s <= n) into out: sigR_rows / sigL_slices the Sigma^R

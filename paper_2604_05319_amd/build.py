@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhnessi.so")
 
-SOURCES = ["api.cpp", "plan.cpp", "store.hip", "history.hip", "merge.hip", "compress.hip", "dense.hip", "step.hip", "born.hip"]
+SOURCES = ["api.cpp", "plan.cpp", "store.hip", "history.hip", "merge.hip", "compress.hip", "dense.hip", "step.hip", "born.hip", "march.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC",

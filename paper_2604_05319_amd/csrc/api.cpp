@@ -15,6 +15,7 @@
 #include "common.h"
 #include "dense.h"
 #include "history.h"
+#include "march.h"
 #include "merge.h"
 #include "step.h"
 #include "store.h"
@@ -164,6 +165,7 @@ struct hnessi_hodlr_s {
     StepWeights SW{};   // weights of the retarded time step
     cd* step_scr = nullptr;    // the step's scratch ((k+1) npair entries per object), allocated by the first step
     cd* lstep_scr = nullptr;   // the lesser step's scratch, allocated by its first call
+    cd* march_scr = nullptr;   // projections of the row march (kMarchRows rows), allocated by its first call
     hipStream_t sstream = nullptr;   // the step's near-diagonal solves, beside the history kernels
     hipEvent_t ev_sfork = nullptr, ev_sjoin = nullptr;
     Geometry g;
@@ -174,6 +176,7 @@ struct hnessi_hodlr_s {
     int* d_blk = nullptr;
     int* d_leaf = nullptr;
     int* d_cover = nullptr;
+    int* d_rowleaf = nullptr;   // leaf index of each row
     long long* d_Uoff = nullptr;
     long long* d_Voff = nullptr;
     long long* d_Loff = nullptr;
@@ -485,6 +488,7 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
     HALLOC(H->d_blk, blk.size(), false);
     HALLOC(H->d_leaf, lf.size(), false);
     HALLOC(H->d_cover, g.cover.size(), false);
+    HALLOC(H->d_rowleaf, g.row_leaf.size(), false);
     HALLOC(H->d_Uoff, std::max(nb, 1), false);
     HALLOC(H->d_Voff, std::max(nb, 1), false);
     HALLOC(H->d_Loff, g.nleaf, false);
@@ -590,6 +594,7 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
     };
     if (!h2d(H->d_blk, blk.data(), blk.size() * sizeof(int)) || !h2d(H->d_leaf, lf.data(), lf.size() * sizeof(int)) ||
         !h2d(H->d_cover, g.cover.data(), g.cover.size() * sizeof(int)) ||
+        !h2d(H->d_rowleaf, g.row_leaf.data(), g.row_leaf.size() * sizeof(int)) ||
         !h2d(H->d_Uoff, H->Uoff.data(), nb * sizeof(long long)) ||
         !h2d(H->d_Voff, H->Voff.data(), nb * sizeof(long long)) ||
         !h2d(H->d_Loff, H->Loff.data(), g.nleaf * sizeof(long long)) ||
@@ -1303,6 +1308,77 @@ int hnessi_step_lesser(hnessi_hodlr_t H, int n, const void* eps, const void* con
         H->prof.recs.push_back({6, n, ev[0], ev[1]});
     } else {
         HIP_TRY(launch_lesser_rest(a, st));
+    }
+    return mark(H, st);
+}
+
+int hnessi_row_march_R(hnessi_hodlr_t H, int n_lo, int n_hi, const void* eps, double h, void* rows_out,
+                       long long row_stride, void* stream) {
+    int rc = single_only(H);
+    if (rc != HNESSI_OK) return rc;
+    const int k = H->k;
+    if (!(H->norb == 1 || H->norb == 2 || H->norb == 4)) return fail(HNESSI_E_ARG, "the row march takes norb 1, 2 or 4");
+    if (H->RC > 32) return fail(HNESSI_E_ARG, "the row march takes a rank capacity of at most 32");
+    if (n_lo < k || n_hi < n_lo || n_hi >= H->nt) return fail(HNESSI_E_RANGE, "rows must satisfy k <= n_lo <= n_hi < nt");
+    if (n_hi > H->last[0]) return fail(HNESSI_E_ORDER, "Sigma^R rows up to n_hi must be appended");
+    if (!eps || !rows_out) return fail(HNESSI_E_ARG, "a pointer is NULL");
+    if (row_stride < (long long)(n_hi + 1) * H->npair) return fail(HNESSI_E_ARG, "row_stride shorter than row n_hi");
+    if (!(h > 0.0)) return fail(HNESSI_E_ARG, "h must be > 0");
+    constexpr int kMarchRows = 1024;   // rows per launch (the projection scratch is sized for them)
+    const long long per_row = (long long)H->nlvl * H->norb * H->npair * 32;
+    if (!H->march_scr) {
+        if (dev_alloc(H->al, H->march_scr, (size_t)(per_row * kMarchRows), false) != HNESSI_OK) {
+            H->march_scr = nullptr;
+            return fail(HNESSI_E_NOMEM, "device allocation of the row-march scratch failed");
+        }
+        HIP_TRY(hipStreamSynchronize(H->al.st));
+    }
+    hipStream_t st = (hipStream_t)stream;
+    // every merge finished: the stored state is frozen (tail rows n0..last hold columns [0, ls))
+    rc = drain(H);
+    if (rc != HNESSI_OK) return rc;
+    for (int c = 0; c < 2; ++c) HIP_TRY(hipStreamSynchronize(H->mstream[c]));
+    const Geometry& g = H->g;
+    MarchArgs a{};
+    a.nt = H->nt;
+    a.norb = H->norb;
+    a.npair = H->npair;
+    a.RC = H->RC;
+    a.k = k;
+    a.nlvl = H->nlvl;
+    a.ring = kTailRows;
+    a.n0 = H->n0[0];
+    a.ls = H->n0[0] <= H->last[0] ? g.s0[g.row_leaf[H->n0[0]]] : 0;
+    a.h = h;
+    a.W = H->W;
+    a.S = H->SW;
+    a.U = H->U[0];
+    a.V = H->V[0];
+    a.Sv = H->S[0];
+    a.rank = H->rank[0];
+    a.cur = H->d_cur[0];
+    a.bU = H->bU;
+    a.bV = H->bV;
+    a.bS = H->bS;
+    a.bRank = H->bRank;
+    a.Uoff = H->d_Uoff;
+    a.Voff = H->d_Voff;
+    a.Loff = H->d_Loff;
+    a.blk = H->d_blk;
+    a.leafs = H->d_leaf;
+    a.rowLeaf = H->d_rowleaf;
+    a.cover = H->d_cover;
+    a.leaf = H->leaf[0];
+    a.tail = H->tail[0];
+    a.band = H->band;
+    a.eps = static_cast<const cd*>(eps);
+    a.rowStride = row_stride;
+    a.proj = H->march_scr;
+    for (int lo = n_lo; lo <= n_hi; lo += kMarchRows) {
+        a.nlo = lo;
+        a.nhi = std::min(n_hi, lo + kMarchRows - 1);
+        a.rows = static_cast<cd*>(rows_out) + (size_t)(lo - n_lo) * row_stride;
+        HIP_TRY(launch_row_march(a, st));
     }
     return mark(H, st);
 }
