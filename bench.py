@@ -611,6 +611,57 @@ def two_component_bench(P):
     return out
 
 
+def paper_orientation_bench(P):
+    """The paper's orientation on the norb-4 N_t = 8192 grid: the Sigma^R rows of the
+    workload's generator appended to a handle (their compression, with its merges), then
+    every row of G^R (n = k..N_t-1) marched along the relative time over that compressed
+    history by hnessi_row_march_R (one workgroup per row, rows in parallel, the march
+    sequential within a row); eps a seeded Hermitian drive."""
+    import numpy as np
+    import torch
+    from kbe_inputs import hermitian_drive, make_config_inputs
+    from kbe_inputs.packed import RowSource
+    cfg, _, S = make_config_inputs("c2")
+    N, h, norb, k = cfg["nt"], cfg["h"], cfg["norb"], cfg["k"]
+    npair = norb * norb
+    nlvl = int(round(np.log2(N // cfg["leaf"])))
+    dev = torch.device("cuda:0")
+    src = RowSource(S, N, h, dev)
+    eps = torch.as_tensor(hermitian_drive(cfg["seed_s"] + 100, norb, N, h), device=dev)
+    H = P.Hodlr(N, nlvl, norb, k=k, tol=cfg["tol"], panel=16, max_rank=16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for n in range(N):
+        H.append_row(P.RET, n, src.ret(n))
+    torch.cuda.synchronize()
+    t_app = time.perf_counter() - t0
+    out = torch.empty((N - k, N * npair), dtype=torch.complex128, device=dev)
+    H.row_march_R(N - 64, N - 1, eps, h, out, N * npair)    # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    H.row_march_R(k, N - 1, eps, h, out, N * npair)
+    e1.record()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    fin = bool(torch.isfinite(torch.view_as_real(out[-1])).all())
+    # one row alone (the last, n = N_t - 1): the latency of a time step in this orientation
+    e0.record()
+    H.row_march_R(N - 1, N - 1, eps, h, out, N * npair)
+    e1.record()
+    torch.cuda.synchronize()
+    one_ms = e0.elapsed_time(e1)
+    res = dict(value=round((N - k) / dt, 1), unit="rows of G^R per second (each a time step's row, all rows in "
+                                                  "parallel, each marched sequentially)",
+               rows=N - k, seconds=round(dt, 3), event_ms=round(ms, 1), sigma_append_s=round(t_app, 3),
+               last_row_alone_ms=round(one_ms, 2), finite=fin, max_rank=int(H.ranks(P.RET).max()),
+               status=H.status())
+    H.close()
+    return res
+
+
 def lattice_step_bench(P):
     """The retarded time step of every momentum of the 32x32 lattice (hnessi_step_R_batched,
     N_t = 2048, norb 1): each step the batched history sum over the stored rows, the step
@@ -881,6 +932,7 @@ def main():
     if not args.no_step:
         step_solve = step_solve_bench(P, args.prof_stride)
         step_solve["two_component"] = two_component_bench(P)
+        step_solve["paper_orientation"] = paper_orientation_bench(P)
         step_solve["lattice"] = lattice_step_bench(P)
         log("step solve:", step_solve)
 
