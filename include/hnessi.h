@@ -203,7 +203,11 @@ int hnessi_step_lesser(hnessi_hodlr_t H, int n, const void* eps, const void* con
  * Gregory interval weights over [t_m, t_n], the sum over the Sigma history taken from
  * the compressed storage (leaf triangles, low-rank blocks through projections of the
  * row's finished part, the dense tail) -- sequential within a row, one workgroup per
- * row.  Waits for the handle's merges (the stored state must be complete).
+ * row, all rows of the call in one launch, the longest first.  Waits for the handle's merges
+ * (the stored state must be complete).  The first call allocates a scratch that the handle
+ * keeps: nlvl * norb^3 * 32 complex entries per row for min(nt - k, rows within 2 GiB) rows
+ * (larger calls run in several launches), and nt * norb^2 entries for the inverses of the
+ * columns' left-side matrices.
  *   eps       device, eps(t_j) for j = 0..n_hi (nt matrices may be passed)
  *   rows_out  device, row n at rows_out + (n - n_lo) * row_stride complex entries,
  *             G^R(t_n, t_m) at [m][a][b], m = 0..n

@@ -165,7 +165,7 @@ struct hnessi_hodlr_s {
     StepWeights SW{};   // weights of the retarded time step
     cd* step_scr = nullptr;    // the step's scratch ((k+1) npair entries per object), allocated by the first step
     cd* lstep_scr = nullptr;   // the lesser step's scratch, allocated by its first call
-    cd* march_scr = nullptr;   // projections of the row march (kMarchRows rows), allocated by its first call
+    cd* march_scr = nullptr;   // row march: projections of the rows of a launch and M_m^{-1}, allocated by its first call
     hipStream_t sstream = nullptr;   // the step's near-diagonal solves, beside the history kernels
     hipEvent_t ev_sfork = nullptr, ev_sjoin = nullptr;
     Geometry g;
@@ -1324,10 +1324,15 @@ int hnessi_row_march_R(hnessi_hodlr_t H, int n_lo, int n_hi, const void* eps, do
     if (!eps || !rows_out) return fail(HNESSI_E_ARG, "a pointer is NULL");
     if (row_stride < (long long)(n_hi + 1) * H->npair) return fail(HNESSI_E_ARG, "row_stride shorter than row n_hi");
     if (!(h > 0.0)) return fail(HNESSI_E_ARG, "h must be > 0");
-    constexpr int kMarchRows = 1024;   // rows per launch (the projection scratch is sized for them)
+    // rows per launch: every row of the grid when the projection scratch stays within
+    // 2 GiB, so that one launch holds all rows (longest first); the scratch also holds
+    // M_m^{-1} of every column
     const long long per_row = (long long)H->nlvl * H->norb * H->npair * 32;
+    const long long cap_rows = std::max(1024LL, (2LL << 30) / (per_row * (long long)sizeof(hn::cd)));
+    const int march_rows = (int)std::min<long long>(cap_rows, (long long)H->nt - k);
     if (!H->march_scr) {
-        if (dev_alloc(H->al, H->march_scr, (size_t)(per_row * kMarchRows), false) != HNESSI_OK) {
+        const size_t cnt = (size_t)(per_row * march_rows) + (size_t)H->nt * H->npair;
+        if (dev_alloc(H->al, H->march_scr, cnt, false) != HNESSI_OK) {
             H->march_scr = nullptr;
             return fail(HNESSI_E_NOMEM, "device allocation of the row-march scratch failed");
         }
@@ -1374,10 +1379,12 @@ int hnessi_row_march_R(hnessi_hodlr_t H, int n_lo, int n_hi, const void* eps, do
     a.eps = static_cast<const cd*>(eps);
     a.rowStride = row_stride;
     a.proj = H->march_scr;
-    for (int lo = n_lo; lo <= n_hi; lo += kMarchRows) {
-        a.nlo = lo;
-        a.nhi = std::min(n_hi, lo + kMarchRows - 1);
-        a.rows = static_cast<cd*>(rows_out) + (size_t)(lo - n_lo) * row_stride;
+    a.minv = H->march_scr + (size_t)(per_row * march_rows);
+    HIP_TRY(launch_march_minv(a, n_hi - k, st));   // columns 0..n_hi-k-1
+    for (int hi = n_hi; hi >= n_lo; hi -= march_rows) {   // the longest rows first
+        a.nhi = hi;
+        a.nlo = std::max(n_lo, hi - march_rows + 1);
+        a.rows = static_cast<cd*>(rows_out) + (size_t)(a.nlo - n_lo) * row_stride;
         HIP_TRY(launch_row_march(a, st));
     }
     return mark(H, st);

@@ -38,8 +38,12 @@ struct MarchArgs {
     cd* rows;            // row n at rows + (n - nlo) * rowStride: G^R(t_n, t_m), m = 0..n
     long long rowStride;
     cd* proj;            // per row and level: the current block's projections [NORB][npair][32]
+    cd* minv;            // [m][a][b]: M_m^{-1}, M_m = i a_0/h - eps(t_m) - h omega_0 Sigma(m, m)
 };
 
+// M_m^{-1} for the columns m = 0..mcount-1 (the same for every row), then the rows
+// nlo..nhi, longest first; a.proj holds nhi - nlo + 1 rows of projections.
+hipError_t launch_march_minv(const MarchArgs& a, int mcount, hipStream_t st);
 hipError_t launch_row_march(const MarchArgs& a, hipStream_t st);
 
 }  // namespace hn

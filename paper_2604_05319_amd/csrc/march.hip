@@ -72,24 +72,120 @@ __device__ inline cd gj_sol(const cd* T, int K, int ld, const int* prow, int p, 
     return T[q * ld + K + c] * mk(d.x * s, -d.y * s);
 }
 
+// M_m^{-1} for one column per thread (the matrix of the left side of the column's
+// equation, the same for every row): Gauss-Jordan with partial pivoting; the row
+// exchanges are value selects, so that every register index is static.
+// the end-weight fold of the row sums, 1 + (omega_{n-j} - 1)[n-j <= k], with omega staged
+// in LDS: a per-lane index into the weights held in the kernel arguments would be a
+// global-memory load at every use
+__device__ inline double wend_lds(const double* om, int k, int n, int j) {
+    const int d = n - j;
+    return d <= k ? om[d] : 1.0;
+}
+
+// sum over the 64 lanes of the wave (every lane gets the sum)
+__device__ inline double wsum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+template <int NORB>
+__global__ void __launch_bounds__(256) march_minv(MarchArgs A, int mcount) {
+    constexpr int npair = NORB * NORB;
+    const int m = blockIdx.x * 256 + threadIdx.x;
+    if (m >= mcount) return;
+    const int kb = A.k + 1;
+    const double d0 = A.S.a[0] / A.h, wh = A.h * A.W.om[0];
+    cd M[NORB][NORB], X[NORB][NORB];
+#pragma unroll
+    for (int a = 0; a < NORB; ++a)
+#pragma unroll
+        for (int b = 0; b < NORB; ++b) {
+            const int q = a * NORB + b;
+            M[a][b] = mk(0.0, a == b ? d0 : 0.0) - A.eps[(size_t)m * npair + q] -
+                      wh * A.band[(size_t)m * kb * npair + q];
+            X[a][b] = mk(a == b ? 1.0 : 0.0, 0.0);
+        }
+#pragma unroll
+    for (int p = 0; p < NORB; ++p) {
+        int piv = p;
+        double best = norm2(M[p][p]);
+#pragma unroll
+        for (int r = p + 1; r < NORB; ++r) {
+            const double v = norm2(M[r][p]);
+            if (v > best) {
+                best = v;
+                piv = r;
+            }
+        }
+#pragma unroll
+        for (int r = p + 1; r < NORB; ++r) {
+            const bool sw = r == piv;
+#pragma unroll
+            for (int j = 0; j < NORB; ++j) {
+                const cd mp = M[p][j], mr = M[r][j], xp = X[p][j], xr = X[r][j];
+                M[p][j] = sw ? mr : mp;
+                M[r][j] = sw ? mp : mr;
+                X[p][j] = sw ? xr : xp;
+                X[r][j] = sw ? xp : xr;
+            }
+        }
+        const cd d = M[p][p];
+        const double s = 1.0 / norm2(d);
+        const cd inv = mk(d.x * s, -d.y * s);
+#pragma unroll
+        for (int j = 0; j < NORB; ++j) {
+            M[p][j] = M[p][j] * inv;
+            X[p][j] = X[p][j] * inv;
+        }
+#pragma unroll
+        for (int r = 0; r < NORB; ++r) {
+            if (r == p) continue;
+            const cd f = M[r][p];
+#pragma unroll
+            for (int j = 0; j < NORB; ++j) {
+                M[r][j] = M[r][j] - f * M[p][j];
+                X[r][j] = X[r][j] - f * X[p][j];
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < NORB; ++a)
+#pragma unroll
+        for (int b = 0; b < NORB; ++b) A.minv[(size_t)m * npair + a * NORB + b] = X[a][b];
+}
+
 template <int NORB>
 __global__ void __launch_bounds__(NTM) row_march(MarchArgs A) {
-    constexpr int npair = NORB * NORB, SG = NTM / npair;
+    constexpr int npair = NORB * NORB;
+    // leaf sum of a column: thread (jg, a, bo) takes the rows j = m+1+jg, +SG, .. of the
+    // leaf and the left orbital a, for every output orbital c
+    constexpr int SG = NTM / npair;
+    constexpr int NU = (63 + SG - 1) / SG;   // rows per thread (a leaf has at most 64)
+    constexpr int NBD = (5 + SG - 1) / SG;   // band offsets i = jg+1, jg+1+SG, .. <= k per thread
     constexpr int KMAX = 5 * NORB, LDMAX = KMAX + NORB;
-    __shared__ cd T[KMAX * LDMAX];
-    __shared__ int used[KMAX], prow[KMAX];
-    __shared__ cd F[64 * npair];     // far-field sums of the current leaf's columns
-    __shared__ cd red[NTM];
+    static_assert(KMAX * LDMAX <= 64 * npair, "the start system fits the leaf buffer");
+    // FR: the start system, then per leaf the far-field sums of the columns not yet
+    // marched and G(n, j) of the marched ones (slot j - s0)
+    __shared__ cd FR[64 * npair];
+    __shared__ cd ring[8 * npair];        // G(n, j) at slot j % 8: the k columns right of m
+    __shared__ cd red[NTM * NORB];        // partial sums of the leaf and band terms
     __shared__ cd rhs[npair];
-    const int n = A.nlo + blockIdx.x;
-    if (n > A.nhi) return;
+    __shared__ int used[KMAX], prow[KMAX];
+    __shared__ double om[8];              // Gregory end weights omega_0..omega_k
+    cd* T = FR;
+    const int n = A.nhi - (int)blockIdx.x;   // longest rows first
+    if (n < A.nlo) return;
     const int k = A.k, nt = A.nt, kb = k + 1;
     const double h = A.h;
-    const int t = threadIdx.x, e = t % npair, g = t / npair, c = e / NORB, bo = e % NORB;
-    cd* row = A.rows + (size_t)blockIdx.x * A.rowStride;
+    const int t = threadIdx.x, e = t % npair, c = e / NORB, bo = e % NORB;
+    const int jg = t / npair;                  // (jg, a = c, bo) in the leaf-sum role
+    cd* row = A.rows + (size_t)(n - A.nlo) * A.rowStride;
     cd* P = A.proj + (size_t)blockIdx.x * A.nlvl * NORB * npair * RCMAX;
     auto sig_band = [&](int j, int m, int q) { return A.band[((size_t)m * kb + (j - m)) * npair + q]; };
     auto epsm = [&](int m, int a, int b) { return A.eps[(size_t)m * npair + a * NORB + b]; };
+    if (t < 6) om[t] = A.W.om[t];
 
     // ---- columns n-k..n-1 (unknowns Y[(u,a)][c] = G(n, n-k+u)[c][a]) and G(n, n) = -i
     {
@@ -114,126 +210,252 @@ __global__ void __launch_bounds__(NTM) row_march(MarchArgs A) {
         gj64(T, K, ld, used, prow);
         for (int x = t; x < K * NORB; x += NTM) {
             const int r = x / NORB, cc = x % NORB, u = r / NORB, a = r % NORB;
-            row[(size_t)(n - k + u) * npair + cc * NORB + a] = gj_sol(T, K, ld, prow, r, cc);
+            const cd y = gj_sol(T, K, ld, prow, r, cc);
+            row[(size_t)(n - k + u) * npair + cc * NORB + a] = y;
+            ring[((n - k + u) & 7) * npair + cc * NORB + a] = y;
         }
-        for (int x = t; x < npair; x += NTM) row[(size_t)n * npair + x] = mk(0.0, x / NORB == x % NORB ? -1.0 : 0.0);
+        for (int x = t; x < npair; x += NTM) {
+            const cd v = mk(0.0, x / NORB == x % NORB ? -1.0 : 0.0);
+            row[(size_t)n * npair + x] = v;
+            ring[(n & 7) * npair + x] = v;
+        }
         __syncthreads();
     }
     const int mlast = n - k - 1;
     if (mlast < 0) return;
     const int rows_merged_end = A.n0 < n + 1 ? A.n0 : n + 1;   // block rows j < this count
-    int leaf = A.rowLeaf[mlast];
+    const int leaf0 = A.rowLeaf[mlast];
+    int leaf = leaf0;
     int m = mlast;
     while (m >= 0) {
         const int s0 = A.leafs[2 * leaf], s1 = A.leafs[2 * leaf + 1];
         const int mhi = m;                    // the leaf's columns marched: s0..mhi
-        // (i) projections of the blocks whose column range starts its march in this leaf
+        // (i) projections of the blocks whose column range starts its march in this leaf:
+        // P[cc][q][r] = S_r sum_j w_end(n, j) G(n, j)[cc][a] U_q(j, r), q = (a, bb), one
+        // lane per row j (U rows coalesced), four ranks and the NORB orbitals cc per pass,
+        // summed over the wave
         for (int l = 0; l < A.nlvl; ++l) {
             const int b = A.cover[(size_t)l * nt + s0];
             if (b < 0) continue;
             const int* bk = A.blk + 5 * b;
             const int r0 = bk[1], r1 = bk[2], c1 = bk[4];
-            if (c1 != s1 && leaf != A.rowLeaf[mlast]) continue;   // computed at an earlier leaf
+            if (c1 != s1 && leaf != leaf0) continue;   // computed at an earlier leaf
             const int jend = min(r1, rows_merged_end);
+            if (r0 >= jend) continue;                   // no merged rows: the far field skips it
             cd* Pl = P + (size_t)l * NORB * npair * RCMAX;
-            const int cb = A.cur[b] & 1;
-            for (int o = t; o < NORB * npair * RCMAX; o += NTM) {
-                const int cc = o / (npair * RCMAX), q = (o / RCMAX) % npair, r = o % RCMAX;
+            const int cb = A.cur[b] & 1, ld = r1 - r0;
+            for (int q = 0; q < npair; ++q) {
+                const int a = q / NORB;
                 const int rk = min(max(A.rank[cb * A.bRank + (size_t)b * npair + q], 0), A.RC);
-                cd acc = mk(0.0, 0.0);
-                if (r < rk && r0 < jend) {
-                    const int a = q / NORB, ld = r1 - r0;
-                    const cd* Uq = A.U + cb * A.bU + A.Uoff[b] + ((size_t)q * A.RC + r) * ld;
-                    for (int j = r0; j < jend; ++j)
-                        acc = acc + w_end(A.W, n, j) * (row[(size_t)j * npair + cc * NORB + a] * Uq[j - r0]);
-                    acc = A.Sv[cb * A.bS + ((size_t)b * npair + q) * A.RC + r] * acc;
+                const cd* Uq = A.U + cb * A.bU + A.Uoff[b] + (size_t)q * A.RC * ld;
+                const double* Sq = A.Sv + cb * A.bS + ((size_t)b * npair + q) * A.RC;
+                for (int rb = 0; rb < rk; rb += 4) {
+                    cd acc[NORB][4];
+#pragma unroll
+                    for (int cc = 0; cc < NORB; ++cc)
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) acc[cc][u] = mk(0.0, 0.0);
+                    for (int jb = r0; jb < jend; jb += 4 * NTM) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int j = jb + v * NTM + t;
+                            const bool on = j < jend;
+                            const int jc = on ? j : r0;
+                            const double w = on ? wend_lds(om, k, n, jc) : 0.0;
+                            cd x[NORB];
+#pragma unroll
+                            for (int cc = 0; cc < NORB; ++cc) x[cc] = w * row[(size_t)jc * npair + cc * NORB + a];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const int r = min(rb + u, rk - 1);
+                                const cd uv = Uq[(size_t)r * ld + (jc - r0)];
+#pragma unroll
+                                for (int cc = 0; cc < NORB; ++cc) fma_(acc[cc][u], x[cc], uv);
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int cc = 0; cc < NORB; ++cc)
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const double re = wsum(acc[cc][u].x), im = wsum(acc[cc][u].y);
+                            if (t == 0 && rb + u < rk) Pl[(cc * npair + q) * RCMAX + rb + u] = Sq[rb + u] * mk(re, im);
+                        }
                 }
-                Pl[o] = acc;
             }
         }
         __syncthreads();
-        // (ii) far-field sums of the leaf's columns: covering blocks and the dense tail
-        for (int x = t; x < (mhi - s0 + 1) * npair; x += NTM) {
-            const int mm = s0 + x / npair, ee = x % npair, cc = ee / NORB, bb = ee % NORB;
-            cd acc = mk(0.0, 0.0);
+        // (ii) far field of the leaf's columns, one lane per column: the covering blocks (the
+        // column's V rows, coalesced over the lanes, against the row's projections) and the
+        // dense tail; into FR, and the leaf's columns right of the march (the start columns)
+        // as row values
+        const int jtop = min(n, s1 - 1);
+        {
+            const int mm = s0 + t;
+            const bool on = mm <= mhi;
+            cd acc[npair];   // [cc][bb]
+#pragma unroll
+            for (int x = 0; x < npair; ++x) acc[x] = mk(0.0, 0.0);
             for (int l = 0; l < A.nlvl; ++l) {
-                const int b = A.cover[(size_t)l * nt + mm];
+                const int b = A.cover[(size_t)l * nt + s0];   // the same block for every column of the leaf
                 if (b < 0) continue;
                 const int* bk = A.blk + 5 * b;
                 const int r0 = bk[1], c0 = bk[3], c1 = bk[4];
                 if (r0 >= rows_merged_end) continue;
                 const int cb = A.cur[b] & 1, ldv = c1 - c0;
                 const cd* Pl = P + (size_t)l * NORB * npair * RCMAX;
-                for (int a = 0; a < NORB; ++a) {
-                    const int q = a * NORB + bb;
+                const int col = on ? mm - c0 : 0;
+#pragma unroll
+                for (int q = 0; q < npair; ++q) {   // q = a NORB + bb
+                    const int bb = q % NORB;
                     const int rk = min(max(A.rank[cb * A.bRank + (size_t)b * npair + q], 0), A.RC);
-                    const cd* Vq = A.V + cb * A.bV + A.Voff[b] + (size_t)q * A.RC * ldv + (mm - c0);
-                    for (int r = 0; r < rk; ++r)
-                        fmac_(acc, Vq[(size_t)r * ldv], Pl[(cc * npair + q) * RCMAX + r]);   // P conj(V)
+                    const cd* Vq = A.V + cb * A.bV + A.Voff[b] + (size_t)q * A.RC * ldv + col;
+                    for (int rb = 0; rb < rk; rb += 4) {
+                        cd v[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) v[u] = Vq[(size_t)min(rb + u, rk - 1) * ldv];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            if (rb + u < rk)
+#pragma unroll
+                                for (int cc = 0; cc < NORB; ++cc)
+                                    fmac_(acc[cc * NORB + bb], v[u], Pl[(cc * npair + q) * RCMAX + rb + u]);   // P conj(V)
+                    }
                 }
             }
-            if (mm < A.ls)   // tail rows n0..n (above the merged front) hold the columns < ls
+            if (on && mm < A.ls)   // tail rows n0..n (above the merged front) hold the columns < ls
                 for (int j = A.n0; j <= n; ++j) {
-                    const double w = w_end(A.W, n, j);
-                    for (int a = 0; a < NORB; ++a)
-                        acc = acc + w * (row[(size_t)j * npair + cc * NORB + a] *
-                                         A.tail[((size_t)(j % A.ring) * npair + a * NORB + bb) * nt + mm]);
+                    const double w = wend_lds(om, k, n, j);
+                    const cd* tj = A.tail + (size_t)(j % A.ring) * npair * nt + mm;   // [q] at q * nt
+                    cd tv[npair];
+#pragma unroll
+                    for (int q = 0; q < npair; ++q) tv[q] = tj[(size_t)q * nt];
+#pragma unroll
+                    for (int cc = 0; cc < NORB; ++cc)
+#pragma unroll
+                        for (int a = 0; a < NORB; ++a) {
+                            const cd g = w * row[(size_t)j * npair + cc * NORB + a];
+#pragma unroll
+                            for (int bb = 0; bb < NORB; ++bb) fma_(acc[cc * NORB + bb], g, tv[a * NORB + bb]);
+                        }
                 }
-            F[(mm - s0) * npair + ee] = acc;
-        }
-        __syncthreads();
-        // (iii) the leaf's columns, right to left
-        const long long lw = s1 - s0;
-        const cd* Lf = A.leaf + A.Loff[leaf];
-        const int jtop = min(n, s1 - 1);
-        for (; m >= s0; --m) {
-            cd acc = mk(0.0, 0.0);   // rows j of this leaf, j > m (thread group g takes j = m+1+g, +SG, ..)
-            for (int j = m + 1 + g; j <= jtop; j += SG) {
-                const double w = w_end(A.W, n, j);
-                const long long tj = (long long)(j - s0) * (j - s0 + 1) / 2 + (m - s0);
-                for (int a = 0; a < NORB; ++a)
-                    acc = acc + w * (row[(size_t)j * npair + c * NORB + a] *
-                                     Lf[(size_t)(a * NORB + bo) * (lw * (lw + 1) / 2) + tj]);
+            if (on) {
+#pragma unroll
+                for (int x = 0; x < npair; ++x) FR[t * npair + x] = acc[x];
+            } else if (mm <= jtop) {
+#pragma unroll
+                for (int x = 0; x < npair; ++x) FR[t * npair + x] = row[(size_t)mm * npair + x];
             }
-            red[t] = acc;
+        }
+        // (iii) the leaf's columns, right to left.  Per column: the leaf rows j > m and the
+        // band corrections (start weights of s = m+1..m+k) as partial sums per (jg, a),
+        // their sum with the far field into the right side, then G(n, m) = rhs M_m^{-1}.
+        // The column's Sigma entries and M_m^{-1} do not depend on the march: those of
+        // column m-1 are loaded while column m is solved.
+        const long long lw = s1 - s0, tl = lw * (lw + 1) / 2;
+        const cd* Lf = A.leaf + A.Loff[leaf] + (size_t)(c * NORB + bo) * tl;   // (a = c, bo) triangle
+        cd lc[NU], bc[NBD], mc[NORB];
+        auto load_col = [&](int mm, cd (&lv)[NU], cd (&bv)[NBD], cd (&mv)[NORB]) {
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                const int j = mm + 1 + jg + SG * u;
+                lv[u] = j <= jtop ? Lf[(long long)(j - s0) * (j - s0 + 1) / 2 + (mm - s0)] : mk(0.0, 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < NBD; ++u) {
+                const int i = jg + 1 + SG * u;
+                bv[u] = i <= k ? sig_band(mm + i, mm, c * NORB + bo) : mk(0.0, 0.0);
+            }
+#pragma unroll
+            for (int a = 0; a < NORB; ++a) mv[a] = t < npair ? A.minv[(size_t)mm * npair + a * NORB + bo] : mk(0.0, 0.0);
+        };
+        load_col(m, lc, bc, mc);
+        // vmcnt(0) (expcnt and lgkmcnt left at their maxima): the first column's loads are
+        // complete on entering the loop, so that no wait inside it covers the loads in flight
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+        __syncthreads();
+        for (; m >= s0; --m) {
+            // partial sums: acc[cc] = sum_j w_end(n, j) G(n, j)[cc][a] Sigma(j, m)[a][bo]
+            //                        + sum_i (omega_i - 1) G(n, m+i)[cc][a] Sigma(m+i, m)[a][bo]
+            cd acc[NORB];
+#pragma unroll
+            for (int cc = 0; cc < NORB; ++cc) acc[cc] = mk(0.0, 0.0);
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                const int j = m + 1 + jg + SG * u;
+                if (j <= jtop) {
+                    const cd lv = wend_lds(om, k, n, j) * lc[u];
+#pragma unroll
+                    for (int cc = 0; cc < NORB; ++cc) fma_(acc[cc], FR[(j - s0) * npair + cc * NORB + c], lv);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < NBD; ++u) {
+                const int i = jg + 1 + SG * u;
+                if (i <= k) {
+                    const cd bv = (om[i] - 1.0) * bc[u];
+#pragma unroll
+                    for (int cc = 0; cc < NORB; ++cc) fma_(acc[cc], ring[((m + i) & 7) * npair + cc * NORB + c], bv);
+                }
+            }
+            // the next column's loads fly while this column is solved
+            cd ln[NU], bn[NBD], mn[NORB];
+            if (m > s0) load_col(m - 1, ln, bn, mn);
+            // red[(jg NORB + a) npair + cc NORB + bo]
+#pragma unroll
+            for (int cc = 0; cc < NORB; ++cc) red[(jg * NORB + c) * npair + cc * NORB + bo] = acc[cc];
             __syncthreads();
-            if (g == 0) {
-                cd s = F[(m - s0) * npair + e];
-                for (int q = 0; q < SG; ++q) s = s + red[q * npair + e];
-                for (int i = 1; i <= k; ++i)   // start weights of s = m+i on the band
-                    for (int a = 0; a < NORB; ++a)
-                        s = s + (A.W.om[i] - 1.0) * (row[(size_t)(m + i) * npair + c * NORB + a] *
-                                                     sig_band(m + i, m, a * NORB + bo));
+            if (t < npair) {
+                cd s = FR[(m - s0) * npair + e];
+                for (int r = 0; r < SG * NORB; ++r) s = s + red[r * npair + e];
                 cd bd = mk(0.0, 0.0);
-                for (int l = 1; l <= k; ++l) bd = bd + A.S.a[l] * row[(size_t)(m + l) * npair + e];
+#pragma unroll
+                for (int l = 1; l <= 5; ++l)
+                    if (l <= k) bd = bd + A.S.a[l] * ring[((m + l) & 7) * npair + e];
                 rhs[e] = mk(h * s.x + bd.y / h, h * s.y - bd.x / h);   // h s - (i/h) bd
             }
             __syncthreads();
-            // X M_m = rhs  <=>  M_m^T X^T = rhs^T: [M^T | rhs^T] with M = i a_0/h - eps(m) - h omega_0 Sigma(m,m)
-            for (int x = t; x < NORB * 2 * NORB; x += NTM) {
-                const int r = x / (2 * NORB), col = x % (2 * NORB);
-                cd v;
-                if (col < NORB)   // M^T[r][col] = M[col][r]
-                    v = mk(0.0, r == col ? A.S.a[0] / h : 0.0) - epsm(m, col, r) -
-                        (h * A.W.om[0]) * sig_band(m, m, col * NORB + r);
-                else
-                    v = rhs[(col - NORB) * NORB + r];   // rhs^T[r][cc] = rhs[cc][r]
-                T[x] = v;
+            if (t < npair) {   // G(n, m)[c][bo] = sum_a rhs[c][a] M_m^{-1}[a][bo]
+                cd x = mk(0.0, 0.0);
+#pragma unroll
+                for (int a = 0; a < NORB; ++a) fma_(x, rhs[c * NORB + a], mc[a]);
+                FR[(m - s0) * npair + e] = x;
+                ring[(m & 7) * npair + e] = x;
             }
             __syncthreads();
-            gj64(T, NORB, 2 * NORB, used, prow);
-            if (t < npair)   // X[c][a] = Y[a][c]
-                row[(size_t)m * npair + c * NORB + bo] = gj_sol(T, NORB, 2 * NORB, prow, bo, c);
-            __syncthreads();
+            if (m > s0) {
+#pragma unroll
+                for (int u = 0; u < NU; ++u) lc[u] = ln[u];
+#pragma unroll
+                for (int u = 0; u < NBD; ++u) bc[u] = bn[u];
+#pragma unroll
+                for (int a = 0; a < NORB; ++a) mc[a] = mn[a];
+            }
         }
+        // the leaf's marched columns to the output row (read by the next leaves' projections
+        // and tail sums)
+        for (int x = t; x < (mhi - s0 + 1) * npair; x += NTM) row[(size_t)s0 * npair + x] = FR[x];
+        __syncthreads();
         --leaf;
     }
 }
 
 }  // namespace
 
+hipError_t launch_march_minv(const MarchArgs& a, int mcount, hipStream_t st) {
+    if (mcount <= 0) return hipSuccess;
+    const unsigned nb = (unsigned)((mcount + 255) / 256);
+    switch (a.norb) {
+        case 1: march_minv<1><<<nb, 256, 0, st>>>(a, mcount); break;
+        case 2: march_minv<2><<<nb, 256, 0, st>>>(a, mcount); break;
+        case 4: march_minv<4><<<nb, 256, 0, st>>>(a, mcount); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_row_march(const MarchArgs& a, hipStream_t st) {
-    if (a.nlo < a.k || a.nhi < a.nlo || a.RC > RCMAX) return hipErrorInvalidValue;
+    if (a.nlo < a.k || a.nhi < a.nlo || a.RC > RCMAX || a.k > 5) return hipErrorInvalidValue;
     const int nrows = a.nhi - a.nlo + 1;
     switch (a.norb) {
         case 1: row_march<1><<<nrows, NTM, 0, st>>>(a); break;
