@@ -83,13 +83,6 @@ __device__ inline double wend_lds(const double* om, int k, int n, int j) {
     return d <= k ? om[d] : 1.0;
 }
 
-// sum over the 64 lanes of the wave (every lane gets the sum)
-__device__ inline double wsum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
 template <int NORB>
 __global__ void __launch_bounds__(256) march_minv(MarchArgs A, int mcount) {
     constexpr int npair = NORB * NORB;
@@ -231,56 +224,62 @@ __global__ void __launch_bounds__(NTM) row_march(MarchArgs A) {
         const int s0 = A.leafs[2 * leaf], s1 = A.leafs[2 * leaf + 1];
         const int mhi = m;                    // the leaf's columns marched: s0..mhi
         // (i) projections of the blocks whose column range starts its march in this leaf:
-        // P[cc][q][r] = S_r sum_j w_end(n, j) G(n, j)[cc][a] U_q(j, r), q = (a, bb), one
-        // lane per row j (U rows coalesced), four ranks and the NORB orbitals cc per pass,
-        // summed over the wave
-        for (int l = 0; l < A.nlvl; ++l) {
-            const int b = A.cover[(size_t)l * nt + s0];
-            if (b < 0) continue;
-            const int* bk = A.blk + 5 * b;
-            const int r0 = bk[1], r1 = bk[2], c1 = bk[4];
-            if (c1 != s1 && leaf != leaf0) continue;   // computed at an earlier leaf
-            const int jend = min(r1, rows_merged_end);
-            if (r0 >= jend) continue;                   // no merged rows: the far field skips it
-            cd* Pl = P + (size_t)l * NORB * npair * RCMAX;
-            const int cb = A.cur[b] & 1, ld = r1 - r0;
-            for (int q = 0; q < npair; ++q) {
-                const int a = q / NORB;
+        // P[cc][q][r] = S_r sum_j w_end(n, j) G(n, j)[cc][a] U_q(j, r), q = (a, bb).  One lane
+        // per pair q and ranks r = lane % LPQ + LPQ s (each lane streams its U columns along
+        // j, no sums across lanes); the block's weighted row entries are staged in FR 64 rows
+        // at a time and read by every lane of a pair.
+        {
+            constexpr int LPQ = NTM / npair, NR = (RCMAX + LPQ - 1) / LPQ;
+            const int q = t / LPQ, a = q / NORB, rl = t % LPQ;
+            for (int l = 0; l < A.nlvl; ++l) {
+                const int b = A.cover[(size_t)l * nt + s0];
+                if (b < 0) continue;
+                const int* bk = A.blk + 5 * b;
+                const int r0 = bk[1], r1 = bk[2], c1 = bk[4];
+                if (c1 != s1 && leaf != leaf0) continue;   // computed at an earlier leaf
+                const int jend = min(r1, rows_merged_end);
+                if (r0 >= jend) continue;                   // no merged rows: the far field skips it
+                cd* Pl = P + (size_t)l * NORB * npair * RCMAX;
+                const int cb = A.cur[b] & 1, ld = r1 - r0;
                 const int rk = min(max(A.rank[cb * A.bRank + (size_t)b * npair + q], 0), A.RC);
                 const cd* Uq = A.U + cb * A.bU + A.Uoff[b] + (size_t)q * A.RC * ld;
-                const double* Sq = A.Sv + cb * A.bS + ((size_t)b * npair + q) * A.RC;
-                for (int rb = 0; rb < rk; rb += 4) {
-                    cd acc[NORB][4];
+                cd acc[NORB][NR];
 #pragma unroll
-                    for (int cc = 0; cc < NORB; ++cc)
+                for (int cc = 0; cc < NORB; ++cc)
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) acc[cc][u] = mk(0.0, 0.0);
-                    for (int jb = r0; jb < jend; jb += 4 * NTM) {
+                    for (int s2 = 0; s2 < NR; ++s2) acc[cc][s2] = mk(0.0, 0.0);
+                for (int jb = r0; jb < jend; jb += 64) {
+                    const int nj = min(64, jend - jb);
+                    __syncthreads();   // the previous chunk is consumed
+                    for (int x = t; x < nj * npair; x += NTM) {
+                        const int jj = jb + x / npair;
+                        FR[x] = wend_lds(om, k, n, jj) * row[(size_t)jj * npair + x % npair];
+                    }
+                    __syncthreads();
+                    const cd* Uj = Uq + (jb - r0);
+#pragma unroll 8
+                    for (int i = 0; i < nj; ++i) {
+                        cd xv[NORB];
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const int j = jb + v * NTM + t;
-                            const bool on = j < jend;
-                            const int jc = on ? j : r0;
-                            const double w = on ? wend_lds(om, k, n, jc) : 0.0;
-                            cd x[NORB];
+                        for (int cc = 0; cc < NORB; ++cc) xv[cc] = FR[i * npair + cc * NORB + a];
 #pragma unroll
-                            for (int cc = 0; cc < NORB; ++cc) x[cc] = w * row[(size_t)jc * npair + cc * NORB + a];
+                        for (int s2 = 0; s2 < NR; ++s2) {
+                            const int r = rl + LPQ * s2;
+                            if (r < rk) {
+                                const cd uv = Uj[(size_t)r * ld + i];
 #pragma unroll
-                            for (int u = 0; u < 4; ++u) {
-                                const int r = min(rb + u, rk - 1);
-                                const cd uv = Uq[(size_t)r * ld + (jc - r0)];
-#pragma unroll
-                                for (int cc = 0; cc < NORB; ++cc) fma_(acc[cc][u], x[cc], uv);
+                                for (int cc = 0; cc < NORB; ++cc) fma_(acc[cc][s2], xv[cc], uv);
                             }
                         }
                     }
+                }
+                const double* Sq = A.Sv + cb * A.bS + ((size_t)b * npair + q) * A.RC;
 #pragma unroll
-                    for (int cc = 0; cc < NORB; ++cc)
+                for (int s2 = 0; s2 < NR; ++s2) {
+                    const int r = rl + LPQ * s2;
+                    if (r < rk)
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const double re = wsum(acc[cc][u].x), im = wsum(acc[cc][u].y);
-                            if (t == 0 && rb + u < rk) Pl[(cc * npair + q) * RCMAX + rb + u] = Sq[rb + u] * mk(re, im);
-                        }
+                        for (int cc = 0; cc < NORB; ++cc) Pl[(cc * npair + q) * RCMAX + r] = Sq[r] * acc[cc][s2];
                 }
             }
         }
@@ -296,6 +295,7 @@ __global__ void __launch_bounds__(NTM) row_march(MarchArgs A) {
             cd acc[npair];   // [cc][bb]
 #pragma unroll
             for (int x = 0; x < npair; ++x) acc[x] = mk(0.0, 0.0);
+            cd* Ps = FR;   // [cc][q][16]: projections of 16 ranks of the level, staged
             for (int l = 0; l < A.nlvl; ++l) {
                 const int b = A.cover[(size_t)l * nt + s0];   // the same block for every column of the leaf
                 if (b < 0) continue;
@@ -305,24 +305,48 @@ __global__ void __launch_bounds__(NTM) row_march(MarchArgs A) {
                 const int cb = A.cur[b] & 1, ldv = c1 - c0;
                 const cd* Pl = P + (size_t)l * NORB * npair * RCMAX;
                 const int col = on ? mm - c0 : 0;
+                int rkq[npair], rkmax = 0;
 #pragma unroll
-                for (int q = 0; q < npair; ++q) {   // q = a NORB + bb
-                    const int bb = q % NORB;
-                    const int rk = min(max(A.rank[cb * A.bRank + (size_t)b * npair + q], 0), A.RC);
-                    const cd* Vq = A.V + cb * A.bV + A.Voff[b] + (size_t)q * A.RC * ldv + col;
-                    for (int rb = 0; rb < rk; rb += 4) {
-                        cd v[4];
+                for (int q = 0; q < npair; ++q) {
+                    rkq[q] = min(max(A.rank[cb * A.bRank + (size_t)b * npair + q], 0), A.RC);
+                    rkmax = max(rkmax, rkq[q]);
+                }
+                const cd* Vb = A.V + cb * A.bV + A.Voff[b] + col;
+                for (int rs = 0; rs < rkmax; rs += 16) {
+                    __syncthreads();   // the previous stage is consumed
+                    for (int x = t; x < NORB * npair * 16; x += NTM) {
+                        const int q = (x / 16) % npair, r = rs + x % 16;
+                        int rq = 0;
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) v[u] = Vq[(size_t)min(rb + u, rk - 1) * ldv];
+                        for (int qq = 0; qq < npair; ++qq) rq = qq == q ? rkq[qq] : rq;
+                        Ps[x] = r < rq ? Pl[(x / (16 * npair) * npair + q) * RCMAX + r] : mk(0.0, 0.0);
+                    }
+                    __syncthreads();
+                    const int nr = min(16, rkmax - rs);
+                    constexpr int RU = NORB == 4 ? 1 : 2;   // ranks per batch of loads
+                    for (int r = 0; r < nr; r += RU) {
+                        cd v[npair][RU];
 #pragma unroll
-                        for (int u = 0; u < 4; ++u)
-                            if (rb + u < rk)
+                        for (int q = 0; q < npair; ++q)
 #pragma unroll
-                                for (int cc = 0; cc < NORB; ++cc)
-                                    fmac_(acc[cc * NORB + bb], v[u], Pl[(cc * npair + q) * RCMAX + rb + u]);   // P conj(V)
+                            for (int u = 0; u < RU; ++u) {
+                                // beyond the pair's rank: a zero (the factor memory there is not
+                                // written, and zero weights would not clear a non-finite value)
+                                const int rr = max(min(rs + r + u, rkq[q] - 1), 0);
+                                const cd raw = Vb[((size_t)q * A.RC + rr) * ldv];
+                                v[q][u] = rs + r + u < rkq[q] ? raw : mk(0.0, 0.0);
+                            }
+#pragma unroll
+                        for (int q = 0; q < npair; ++q)
+#pragma unroll
+                            for (int u = 0; u < RU; ++u)
+#pragma unroll
+                                for (int cc = 0; cc < NORB; ++cc)   // P conj(V)
+                                    fmac_(acc[cc * NORB + q % NORB], v[q][u], Ps[(cc * npair + q) * 16 + min(r + u, 15)]);
                     }
                 }
             }
+            __syncthreads();   // the staged projections are consumed before FR is written
             if (on && mm < A.ls)   // tail rows n0..n (above the merged front) hold the columns < ls
                 for (int j = A.n0; j <= n; ++j) {
                     const double w = wend_lds(om, k, n, j);
