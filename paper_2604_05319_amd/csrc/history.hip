@@ -604,9 +604,11 @@ __device__ void leaf_task(const HistArgs& A, int leaf, int comp, int ag, int pg,
 // ---------------------------------------------------------------------------
 // One leaf triangle, component and orbital pair (qr, qc) for NORB <= 4.  The
 // triangle is loaded in one round trip (every thread's loads issued together)
-// and staged in LDS as a packed triangle: a row is contiguous, and a column read
-// by an aligned group of 8 lanes hits 8 distinct 16-byte bank groups (tri(r) mod 8
-// runs through all residues over 8 aligned rows).  Lane m owns column and row m,
+// and staged in LDS as a packed strictly lower triangle (row r's entries left of
+// the diagonal at tri(r - 1)): the diagonal entry (m, m) is only ever read by the
+// thread that owns m and sums index j = m, which loads it into a register, so that
+// the task's LDS (tri(63) + 128 NORB entries) leaves room for four workgroups per
+// compute unit.  Lane m owns column and row m,
 // wave w the summation indices = w (mod 4), and every thread carries all NORB left
 // orbitals, so each staged element feeds NORB complex FMAs.  Outputs (slot, orbital
 // entry) have one writer each; the combine sums the slots:
@@ -626,10 +628,12 @@ __device__ void leaf_pair_task(const HistArgs& A, int leaf, int comp, int q, uns
     const int nrow = min(s1, A.last[comp] + 1) - s0;   // stored rows (row n, or up to n-1 for a step solve)
     const cd* Lq = p_leaf(A, comp) + A.Loff[leaf] + (size_t)q * tri(lw);
     const long long tnow = tri(nrow);
-    cd* T = reinterpret_cast<cd*>(smem);   // tri(64)
-    cd* xa = T + tri(64);                  // 64 x NORB: Sigma entries with orbital qr
+    cd* T = reinterpret_cast<cd*>(smem);   // tri(63): (r, j < r) at tri(r - 1) + j
+    cd* xa = T + tri(63);                  // 64 x NORB: Sigma entries with orbital qr
     cd* xb = xa + 64 * NORB;               // 64 x NORB: Sigma entries with orbital qc
     const int w = threadIdx.x >> 6, m = threadIdx.x & 63;
+    // the diagonal entry (m, m), read by the wave whose summation indices j = w + 4t hit m
+    const cd dg = ((m & 3) == w && m < nrow) ? Lq[tri(m) + m] : mk(0.0, 0.0);
     const bool doR = A.wantR, doL = A.wantL;
     const bool colOn = comp == 1 || doR;
     const bool rowOn = (comp == 1 || doL) && (comp == 1 || A.adj || s0 + m > 0);
@@ -661,8 +665,13 @@ __device__ void leaf_pair_task(const HistArgs& A, int leaf, int comp, int q, uns
         }
 #pragma unroll
         for (int u = 0; u < TPT; ++u) {
-            const long long e = threadIdx.x + (long long)u * NT;
-            if (e < tnow) T[e] = v[u];
+            const int e = (int)threadIdx.x + u * NT;
+            // row r of element e (tri(r) <= e < tri(r + 1)): the float root is exact to
+            // well within one for e < 2080, the two tests settle the boundaries
+            int r = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+            if ((r + 1) * (r + 2) / 2 <= e) ++r;
+            if (r * (r + 1) / 2 > e) --r;
+            if (e < tnow && e - r * (r + 1) / 2 < r) T[e - r] = v[u];   // strictly lower entries
         }
     }
     __syncthreads();
@@ -674,16 +683,18 @@ __device__ void leaf_pair_task(const HistArgs& A, int leaf, int comp, int q, uns
     // j, m < 64 and are issued for every t; terms outside the triangle, the present rows
     // or the requested products are zeroed by selects (the x entries of absent rows are
     // zero), so the loop has a fixed trip count and no divergence.
-    const int trm = m * (m + 1) / 2;
+    const int trm = m * (m - 1) / 2;
 #pragma unroll 4
     for (int t = 0; t < 16; ++t) {
         const int j = w + 4 * t;
         const bool vc = colOn && m < nrow && j < nrow && (comp == 0 ? j >= m : j > m);
         const bool vr = rowOn && m < nrow && j <= m;
-        const cd tc0 = T[j * (j + 1) / 2 + m];
-        const cd tr0 = T[trm + j];
-        const cd tc = vc ? tc0 : mk(0.0, 0.0);
-        const cd tr = vr ? tr0 : mk(0.0, 0.0);
+        // (j, m) for j > m and (m, j) for j < m; the indices stay below tri(63) for
+        // every j, m < 64 except on the diagonal, which takes the register copy
+        const cd tc0 = T[min(j * (j - 1) / 2 + m, (int)tri(63) - 1)];
+        const cd tr0 = T[min(trm + j, (int)tri(63) - 1)];
+        const cd tc = vc ? (j == m ? dg : tc0) : mk(0.0, 0.0);
+        const cd tr = vr ? (j == m ? dg : tr0) : mk(0.0, 0.0);
 #pragma unroll
         for (int a = 0; a < NORB; ++a) {
             if (comp == 0) {
@@ -1781,7 +1792,8 @@ __global__ void __launch_bounds__(256) fgrad_kernel(HistArgs A, int xper) {
 size_t tasks_smem(int norb, bool mfproj, int kc) {
     const int ag = norb < 4 ? norb : 4;
     size_t fact = mfproj ? (size_t)kc * kXS * sizeof(cf) : (size_t)(kc * norb + 4 * 32 * norb) * sizeof(cd);
-    size_t leaf = (size_t)(tri(64) + 2 * 64 * ag) * sizeof(cd);
+    // per-pair leaf tasks (norb <= 4) stage the strictly lower triangle, the others all of it
+    size_t leaf = (size_t)((norb <= 4 ? tri(63) : tri(64)) + 2 * 64 * ag) * sizeof(cd);
     size_t tail = (size_t)(kTailRows * kTailCH + (kTailRows + kTailCH) * ag) * sizeof(cd);
     size_t s = fact > leaf ? fact : leaf;
     return s > tail ? s : tail;
