@@ -152,34 +152,51 @@ __device__ __attribute__((noinline)) void hh_qr(cd* A, int nrows, int ncols, cd*
     __syncthreads();
 }
 
-// X (nrows x nx, column-major, ldx = nrows) <- H_0 H_1 .. H_{nref-1} X
+// Explicit thin Q of hh_qr's factorization in place of the reflectors: A (nrows x
+// ncols, column-major) <- H_0 H_1 .. H_{ncols-1} [I; 0].  Formed from the last
+// reflector backwards: column j of the result is H_j e_j = e_j - tau_j v_j (rows
+// above j zero), and H_j is applied to the columns right of j, which hold the
+// columns formed so far.  One barrier per column: reflector j is copied to
+// vbuf[(j & 1) * nrows ..] a step ahead, so that column j can be overwritten while
+// the groups of the columns right of it still read v_j.  R (the upper triangle) is
+// overwritten; the caller stores it first.
 template <int W>
-__device__ __attribute__((noinline)) void hh_apply_q(const cd* A, int nrows, int nref,
-                                                     const cd* tau, cd* X, int nx) {
+__device__ __attribute__((noinline)) void hh_form_q(cd* A, int nrows, int ncols, const cd* tau, cd* vbuf) {
     constexpr int TPC = cols_tpc(W);
     const int tid = threadIdx.x;
     const int g = tid / TPC, l = tid % TPC;
-    for (int j = nref - 1; j >= 0; --j) {
-        const cd* aj = A + (size_t)j * nrows;
-        cd t = tau[j];
+    if (ncols <= 0) return;
+    {
+        const int j = ncols - 1;
+        cd* vb = vbuf + (size_t)(j & 1) * nrows;
+        for (int i = j + 1 + tid; i < nrows; i += NT) vb[i] = A[(size_t)j * nrows + i];
+    }
+    __syncthreads();
+    for (int j = ncols - 1; j >= 0; --j) {
+        const cd* v = vbuf + (size_t)(j & 1) * nrows;   // v_j below row j (v_j = 1 at row j)
+        const cd t = tau[j];
+        if (j > 0) {   // reflector j - 1 for the next step (its column is not touched here)
+            cd* vn = vbuf + (size_t)((j - 1) & 1) * nrows;
+            for (int i = j + tid; i < nrows; i += NT) vn[i] = A[(size_t)(j - 1) * nrows + i];
+        }
+        // columns c > j: a_c -= tau_j v_j (v_j^dagger a_c) over rows j..nrows-1
+        const int c = j + 1 + g;
         cd dot = mk(0.0, 0.0);
-        if (g < nx) {
-            cd* xc = X + (size_t)g * nrows;
-            for (int i = j + l; i < nrows; i += TPC) {
-                cd v = (i == j) ? mk(1.0, 0.0) : aj[i];
-                fmac_(dot, v, xc[i]);
-            }
+        if (c < ncols) {
+            const cd* ac = A + (size_t)c * nrows;
+            for (int i = j + l; i < nrows; i += TPC) fmac_(dot, i == j ? mk(1.0, 0.0) : v[i], ac[i]);
         }
-        dot.x = warp_sum(dot.x, TPC);
+        dot.x = warp_sum(dot.x, TPC);   // every lane takes part in the shuffles
         dot.y = warp_sum(dot.y, TPC);
-        if (g < nx) {
-            cd* xc = X + (size_t)g * nrows;
-            cd f = t * dot;
-            for (int i = j + l; i < nrows; i += TPC) {
-                cd v = (i == j) ? mk(1.0, 0.0) : aj[i];
-                xc[i] = xc[i] - v * f;
-            }
+        if (c < ncols) {
+            cd* ac = A + (size_t)c * nrows;
+            const cd f = t * dot;
+            for (int i = j + l; i < nrows; i += TPC) ac[i] = ac[i] - (i == j ? mk(1.0, 0.0) : v[i]) * f;
         }
+        // column j: e_j - tau_j v_j
+        cd* aj = A + (size_t)j * nrows;
+        for (int i = tid; i < nrows; i += NT)
+            aj[i] = i > j ? -(t * v[i]) : (i == j ? mk(1.0 - t.x, -t.y) : mk(0.0, 0.0));
         __syncthreads();
     }
 }
@@ -360,9 +377,11 @@ template <int W>
 __global__ void __launch_bounds__(NT) merge_up_kernel(MergeArgs a) {
     constexpr int CH = merge_ch(W), NQ = node_q(W), CQ = chunk_q(W);
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int XR = CH > 2 * W ? CH : 2 * W;
     cd* A = reinterpret_cast<cd*>(smem_raw);               // CH x W (also 2W x W, and M, J)
-    cd* tau = A + (size_t)(CH > 2 * W ? CH : 2 * W) * W;   // W
+    cd* tau = A + (size_t)XR * W;                          // W
     double* red = reinterpret_cast<double*>(tau + W);      // 16
+    cd* vbuf = reinterpret_cast<cd*>(red + 16);            // 2 XR: reflectors while Q is formed
     __shared__ int sflag;
     __shared__ double s_old[W];
     __shared__ double ssig[W];
@@ -380,11 +399,6 @@ __global__ void __launch_bounds__(NT) merge_up_kernel(MergeArgs a) {
     __syncthreads();
 
     chunk_qr<W>(a, c, r_old, s_old, A, tau, red);
-    {   // keep the chunk's reflectors for merge_down
-        cd* cq = m_chunkQ(a) + (size_t)(B.chunk_base + (long long)c.q * B.nchunks + c.chunk) * CQ;
-        for (int e = threadIdx.x; e < CH * w; e += NT) cq[e] = A[e];
-        for (int e = threadIdx.x; e < w; e += NT) cq[CH * W + e] = tau[e];
-    }
 
     const long long nbase = B.node_base + (long long)c.q * B.nnodes;
     cd* nodeR = m_nodeR(a) + (size_t)nbase * W * W;
@@ -396,6 +410,12 @@ __global__ void __launch_bounds__(NT) merge_up_kernel(MergeArgs a) {
             int col = e / W, i = e % W;
             dst[e] = (col < w && i <= col) ? A[(size_t)col * CH + i] : mk(0.0, 0.0);
         }
+    }
+    __syncthreads();   // R is read before the explicit Q overwrites it
+    hh_form_q<W>(A, CH, w, tau, vbuf);
+    {   // keep the chunk's explicit Q (CH x w) for merge_down
+        cd* cq = m_chunkQ(a) + (size_t)(B.chunk_base + (long long)c.q * B.nchunks + c.chunk) * CQ;
+        for (int e = threadIdx.x; e < CH * w; e += NT) cq[e] = A[e];
     }
     __threadfence();
     __syncthreads();
@@ -424,9 +444,10 @@ __global__ void __launch_bounds__(NT) merge_up_kernel(MergeArgs a) {
                 int col = e / W, i = e % W;
                 dst[e] = (col < w && i <= col) ? A[(size_t)col * nr2 + i] : mk(0.0, 0.0);
             }
-            cd* qd = nodeQ + (size_t)(offP + parent) * NQ;
+            __syncthreads();   // R is read before the explicit Q overwrites it
+            hh_form_q<W>(A, nr2, w, tau, vbuf);
+            cd* qd = nodeQ + (size_t)(offP + parent) * NQ;   // explicit Q (2w x w)
             for (int e = threadIdx.x; e < nr2 * w; e += NT) qd[e] = A[e];
-            for (int e = threadIdx.x; e < w; e += NT) qd[2 * W * W + e] = tau[e];
             __threadfence();
             __syncthreads();
         } else {
@@ -487,13 +508,12 @@ __global__ void __launch_bounds__(NT) merge_up_kernel(MergeArgs a) {
 template <int W>
 __global__ void __launch_bounds__(NT) merge_down_kernel(MergeArgs a) {
     constexpr int CH = merge_ch(W), NQ = node_q(W), CQ = chunk_q(W);
-    constexpr int XR = CH > 2 * W ? CH : 2 * W;      // rows of X (a chunk, or a tree node)
+    constexpr int YPT = (W * W + NT - 1) / NT;   // entries of T per thread
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    // the chunk's and the tree nodes' reflectors are read from global memory (each
-    // reflector twice per application), so that the workgroup's LDS leaves room on its
-    // compute unit for history workgroups
-    cd* X = reinterpret_cast<cd*>(smem_raw);        // XR x RC (the updated V rows, rank <= RC)
-    cd* T = X + (size_t)XR * a.RC;                  // W x W
+    // V_R pulled down the tree: at each level the half of the node's explicit Q that
+    // belongs to this chunk's side times T, then the chunk's explicit Q times T gives
+    // the chunk's rows of V' (plain products, the Q factors read from global memory)
+    cd* T = reinterpret_cast<cd*>(smem_raw);   // W x W (column-major, ld W)
 
     if ((int)blockIdx.x < a.ntask_v) {
         Ctx c = decode_task(a, blockIdx.x);
@@ -503,7 +523,7 @@ __global__ void __launch_bounds__(NT) merge_down_kernel(MergeArgs a) {
         const int r_old = clamp_rank(m_rold(a)[pidx], min(a.RCr, W - a.pp));
         const int rnew = clamp_rank(wr_rank(a, B)[fq], a.RC);
         const int w = r_old + a.pp;
-        // the chunk's reflectors from merge_up
+        // the chunk's explicit Q from merge_up (CH x w, column-major)
         const cd* cq = m_chunkQ(a) + (size_t)(B.chunk_base + (long long)c.q * B.nchunks + c.chunk) * CQ;
         const cd* VR = m_VR(a) + pidx * W * W;
         for (int e = threadIdx.x; e < W * W; e += NT) {
@@ -523,25 +543,29 @@ __global__ void __launch_bounds__(NT) merge_down_kernel(MergeArgs a) {
             if (2 * node + 1 >= cntBelow) continue;  // single child: Q = identity
             const int slot = child & 1;
             const int nr2 = 2 * w;
-            const cd* Qn = nodeQ + (size_t)(tree_levoff(B.nchunks, L) + node) * NQ;
-            for (int e = threadIdx.x; e < nr2 * rnew; e += NT) {
-                int col = e / nr2, i = e % nr2;
-                X[e] = (i < w) ? T[(size_t)col * W + i] : mk(0.0, 0.0);
+            // T <- Q_node[slot w .. slot w + w - 1, 0 .. w - 1] T
+            const cd* Qn = nodeQ + (size_t)(tree_levoff(B.nchunks, L) + node) * NQ + slot * w;
+            cd y[YPT];
+#pragma unroll
+            for (int u = 0; u < YPT; ++u) {
+                const int e = threadIdx.x + u * NT;
+                y[u] = mk(0.0, 0.0);
+                if (e < w * rnew) {
+                    const int col = e / w, i = e % w;
+                    cd acc = mk(0.0, 0.0);
+                    for (int kk = 0; kk < w; ++kk) fma_(acc, Qn[(size_t)kk * nr2 + i], T[(size_t)col * W + kk]);
+                    y[u] = acc;
+                }
             }
             __syncthreads();
-            hh_apply_q<W>(Qn, nr2, w, Qn + 2 * W * W, X, rnew);
-            for (int e = threadIdx.x; e < w * rnew; e += NT) {
-                int col = e / w, i = e % w;
-                T[(size_t)col * W + i] = X[(size_t)col * nr2 + slot * w + i];
+#pragma unroll
+            for (int u = 0; u < YPT; ++u) {
+                const int e = threadIdx.x + u * NT;
+                if (e < w * rnew) T[(size_t)(e / w) * W + e % w] = y[u];
             }
             __syncthreads();
         }
-        for (int e = threadIdx.x; e < CH * rnew; e += NT) {
-            int col = e / CH, i = e % CH;
-            X[e] = (i < w) ? T[(size_t)col * W + i] : mk(0.0, 0.0);
-        }
-        __syncthreads();
-        hh_apply_q<W>(cq, CH, w, cq + (size_t)CH * W, X, rnew);
+        // the chunk's rows of V' = Q_chunk T
         const int row0 = c.chunk * CH;
         const int nr = min(CH, B.ncols - row0);
         const size_t vo = B.Voff + (size_t)c.q * a.RC * B.ncols;
@@ -549,7 +573,8 @@ __global__ void __launch_bounds__(NT) merge_down_kernel(MergeArgs a) {
         cf* V32 = a.V32 ? wr_V32(a, B) + vo : nullptr;
         for (int e = threadIdx.x; e < nr * rnew; e += NT) {
             int col = e / nr, i = e % nr;
-            const cd x = X[(size_t)col * CH + i];
+            cd x = mk(0.0, 0.0);
+            for (int kk = 0; kk < w; ++kk) fma_(x, cq[(size_t)kk * CH + i], T[(size_t)col * W + kk]);
             V[(size_t)col * B.ncols + row0 + i] = x;
             if (V32) V32[(size_t)col * B.ncols + row0 + i] = from_cd<cf>(x);
         }
@@ -598,15 +623,13 @@ __global__ void __launch_bounds__(NT) merge_down_kernel(MergeArgs a) {
 
 template <int W>
 size_t merge_up_smem() {
-    constexpr int CH = merge_ch(W);
-    return (size_t)(CH > 2 * W ? CH : 2 * W) * W * sizeof(cd) + (size_t)W * sizeof(cd) + 16 * sizeof(double);
+    constexpr int CH = merge_ch(W), XR = CH > 2 * W ? CH : 2 * W;
+    return (size_t)XR * W * sizeof(cd) + (size_t)W * sizeof(cd) + 16 * sizeof(double) + (size_t)2 * XR * sizeof(cd);
 }
-// sized by the rank capacity, so that a merge_down workgroup leaves room on its
-// compute unit for a history workgroup
 template <int W>
 size_t merge_down_smem(int RC) {
-    constexpr int CH = merge_ch(W), XR = CH > 2 * W ? CH : 2 * W;
-    return (size_t)XR * RC * sizeof(cd) + (size_t)W * W * sizeof(cd) + 16 * sizeof(double);
+    (void)RC;
+    return (size_t)W * W * sizeof(cd);
 }
 
 template <int W>
