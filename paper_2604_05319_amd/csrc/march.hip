@@ -160,7 +160,7 @@ __global__ void __launch_bounds__(NTM) row_march(MarchArgs A) {
     constexpr int KMAX = 5 * NORB, LDMAX = KMAX + NORB;
     static_assert(KMAX * LDMAX <= 64 * npair, "the start system fits the leaf buffer");
     // FR: the start system, then per leaf the far-field sums of the columns not yet
-    // marched and G(n, j) of the marched ones (slot j - s0)
+    // marched and w_end(n, j) G(n, j) of the marched ones (slot j - s0)
     __shared__ cd FR[64 * npair];
     __shared__ cd ring[8 * npair];        // G(n, j) at slot j % 8: the k columns right of m
     __shared__ cd red[NTM * NORB];        // partial sums of the leaf and band terms
@@ -287,7 +287,7 @@ __global__ void __launch_bounds__(NTM) row_march(MarchArgs A) {
         // (ii) far field of the leaf's columns, one lane per column: the covering blocks (the
         // column's V rows, coalesced over the lanes, against the row's projections) and the
         // dense tail; into FR, and the leaf's columns right of the march (the start columns)
-        // as row values
+        // as row values with their end weights
         const int jtop = min(n, s1 - 1);
         {
             const int mm = s0 + t;
@@ -366,9 +366,10 @@ __global__ void __launch_bounds__(NTM) row_march(MarchArgs A) {
             if (on) {
 #pragma unroll
                 for (int x = 0; x < npair; ++x) FR[t * npair + x] = acc[x];
-            } else if (mm <= jtop) {
+            } else if (mm <= jtop) {   // the leaf sums take FR with the end weight folded in
+                const double we = wend_lds(om, k, n, mm);
 #pragma unroll
-                for (int x = 0; x < npair; ++x) FR[t * npair + x] = row[(size_t)mm * npair + x];
+                for (int x = 0; x < npair; ++x) FR[t * npair + x] = we * row[(size_t)mm * npair + x];
             }
         }
         // (iii) the leaf's columns, right to left.  Per column: the leaf rows j > m and the
@@ -383,7 +384,7 @@ __global__ void __launch_bounds__(NTM) row_march(MarchArgs A) {
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
                 const int j = mm + 1 + jg + SG * u;
-                lv[u] = j <= jtop ? Lf[(long long)(j - s0) * (j - s0 + 1) / 2 + (mm - s0)] : mk(0.0, 0.0);
+                lv[u] = j <= jtop ? Lf[(((j - s0) * (j - s0 + 1)) >> 1) + (mm - s0)] : mk(0.0, 0.0);
             }
 #pragma unroll
             for (int u = 0; u < NBD; ++u) {
@@ -407,11 +408,9 @@ __global__ void __launch_bounds__(NTM) row_march(MarchArgs A) {
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
                 const int j = m + 1 + jg + SG * u;
-                if (j <= jtop) {
-                    const cd lv = wend_lds(om, k, n, j) * lc[u];
+                if (j <= jtop)   // FR holds w_end(n, j) G(n, j) (the end weight is 1 left of n-k)
 #pragma unroll
-                    for (int cc = 0; cc < NORB; ++cc) fma_(acc[cc], FR[(j - s0) * npair + cc * NORB + c], lv);
-                }
+                    for (int cc = 0; cc < NORB; ++cc) fma_(acc[cc], FR[(j - s0) * npair + cc * NORB + c], lc[u]);
             }
 #pragma unroll
             for (int u = 0; u < NBD; ++u) {

@@ -15,8 +15,8 @@ constexpr int kW = kWLarge;             // widest merge
 constexpr int kMaxMergeBlk = 24;        // blocks merged by one panel (<= nlvl)
 
 __host__ __device__ constexpr int merge_ch(int W) { return W <= kWSmall ? 128 : 64; }   // rows of Z per chunk
-__host__ __device__ constexpr int node_q(int W) { return 2 * W * W + W; }            // reflectors (2W x W) + tau
-__host__ __device__ constexpr int chunk_q(int W) { return merge_ch(W) * W + W; }      // reflectors (CH x W) + tau
+__host__ __device__ constexpr int node_q(int W) { return 2 * W * W + W; }            // explicit Q (2W x W), W spare
+__host__ __device__ constexpr int chunk_q(int W) { return merge_ch(W) * W + W; }      // explicit Q (CH x W), W spare
 inline int merge_width(int rank_cap, int panel) { return rank_cap + panel <= kWSmall ? kWSmall : kWLarge; }
 
 struct MergeBlk {
@@ -68,8 +68,8 @@ struct MergeArgs {
     int src_first, src_ring;
     // scratch
     cd* nodeR;     // [node][W*W]
-    cd* nodeQ;     // [node][node_q(W)]
-    cd* chunkQ;    // [chunk slot][chunk_q(W)]: chunk QR of merge_up, reused by merge_down
+    cd* nodeQ;     // [node][node_q(W)]: explicit Q of each tree node's QR
+    cd* chunkQ;    // [chunk slot][chunk_q(W)]: explicit Q of merge_up's chunk QR, used by merge_down
     int* nodecnt;  // [node]
     cd* UK;        // [problem][W*W]
     cd* VR;        // [problem][W*W]

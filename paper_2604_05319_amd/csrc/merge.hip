@@ -12,14 +12,16 @@
 //
 // Device design (one problem = one block x one orbital pair):
 //   merge_up:   the columns of the block are cut into chunks of kCH rows of Z;
-//               each workgroup builds its chunk of Z in LDS and factors it with
-//               Householder reflections.  The R factors are combined pairwise
-//               up a binary tree; the last workgroup to arrive at a node does
+//               each workgroup builds its chunk of Z in LDS, factors it with
+//               Householder reflections and keeps the explicit thin Q.  The R
+//               factors are combined pairwise up a binary tree (each node's
+//               explicit Q kept too); the last workgroup to arrive at a node does
 //               the combine (no waiting), and the one arriving at the root
 //               runs a one-sided Jacobi SVD of R^dagger and truncates.
-//   merge_down: each chunk workgroup recomputes its chunk QR, pulls V_R down
-//               the tree to its chunk, applies its reflectors and writes its
-//               rows of V'; further workgroups rewrite the rows of U'.
+//   merge_down: each chunk workgroup pulls V_R down the tree to its chunk (at
+//               every level the node's Q rows of its side times the current
+//               factor), multiplies by its chunk's Q and writes its rows of V';
+//               further workgroups rewrite the rows of U'.
 #include "merge.h"
 #include "trunc.h"
 
