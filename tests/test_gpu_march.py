@@ -59,6 +59,37 @@ def test_row_march_against_oracle(P, norb, k, N, nlvl):
     say(f"  row march norb {norb} k {k} N {N}: worst {worst:.2e}")
 
 
+@pytest.mark.parametrize("norb,N,nlvl", [(4, 192, 2), (2, 256, 2)])
+def test_row_march_rank_above_16(P, norb, N, nlvl):
+    """Rank capacity 32 with block ranks above 16: the far field stages the projections of
+    16 ranks at a time (two stages here), a lane of the projections holds up to 32 / (64 /
+    norb^2) ranks, and the merges run at width 48.  Fast oscillations (|omega| up to 25) give
+    the off-diagonal blocks epsilon-ranks of about 16 to 24."""
+    h, k = 0.02, 5
+    pS = hermitian_terms(97, 24, norb, omega_range=(-25.0, 25.0))
+    S = _sigma(pS, N, h)
+    eps = hermitian_drive(98, norb, N, h)
+    H = P.Hodlr(N, nlvl, norb, k=k, tol=1e-12, panel=16, max_rank=32)
+    for n in range(N):
+        H.append_row(P.RET, n, to_dev(S[n, :n + 1]))
+    assert H.status() == 0
+    rmax = int(H.ranks(P.RET).max())
+    assert rmax > 16, rmax
+    npair = norb * norb
+    out = torch.zeros((N - k, N * npair), dtype=torch.complex128, device="cuda")
+    H.row_march_R(k, N - 1, to_dev(eps), h, out, N * npair)
+    torch.cuda.synchronize()
+    assert H.status() == 0
+    G = out.cpu().numpy().reshape(N - k, N, norb, norb)
+    worst = 0.0
+    for n in list(range(k, N, 11)) + list(range(N - 6, N)):
+        ref = row_march(S, eps, n, h, k)
+        err = np.abs(G[n - k, :n + 1] - ref).max() / np.abs(ref).max()
+        worst = max(worst, err)
+        assert err <= 1e-10, (n, err)
+    say(f"  row march norb {norb} N {N} max rank {rmax}: worst {worst:.2e}")
+
+
 def test_row_march_argument_errors(P):
     N, norb, k = 64, 2, 5
     H = P.Hodlr(N, 1, norb, k=k, tol=1e-12, panel=16, max_rank=16)
