@@ -35,7 +35,8 @@ def _sigma(pS, N, h):
     return S
 
 
-@pytest.mark.parametrize("norb,k,N,nlvl", [(1, 5, 150, 2), (2, 3, 140, 2), (4, 5, 128, 1), (4, 4, 141, 2)])
+@pytest.mark.parametrize("norb,k,N,nlvl", [(1, 5, 150, 2), (2, 3, 140, 2), (4, 5, 128, 1), (4, 4, 141, 2),
+                                           (2, 1, 130, 2), (4, 2, 128, 1)])
 def test_row_march_against_oracle(P, norb, k, N, nlvl):
     h = 0.02
     pS = scalar_terms(80 + k, 8) if norb == 1 else hermitian_terms(80 + k, 8, norb)

@@ -78,6 +78,7 @@ CASES = [  # norb, k, N, nlvl, fp32 factors
     (2, 3, 150, 2, False),
     (4, 5, 150, 2, False),
     (4, 2, 131, 2, False),
+    (2, 1, 120, 2, False),
     (8, 4, 120, 2, False),
     (16, 5, 100, 1, False),
     (16, 5, 128, 1, True),
@@ -385,7 +386,7 @@ def _inputs_lesser(N, norb, h, k, seed):
     return SR, SL, eps, GR0, GL0
 
 
-LESSER_CASES = [(1, 5, 110, 2), (2, 4, 100, 1), (4, 3, 96, 1), (4, 5, 130, 2)]
+LESSER_CASES = [(1, 5, 110, 2), (2, 4, 100, 1), (4, 3, 96, 1), (4, 5, 130, 2), (2, 1, 96, 1), (4, 2, 100, 1)]
 
 
 @pytest.mark.parametrize("norb,k,N,nlvl", LESSER_CASES)
