@@ -111,8 +111,9 @@ def test_row_march_argument_errors(P):
 
 def test_row_march_full_size_norb4(P):
     """The norb-4 N_t = 8192 grid (leaf 64, 7 levels, tolerance 1e-10) with the workload's
-    Sigma generator, every Sigma row appended; rows k..8191 marched in one call (eight
-    launches of 1024 rows); rows 5, 100, 1023 and 2047 against the oracle."""
+    Sigma generator, every Sigma row appended; rows k..8191 marched in one call (one launch,
+    the longest rows first); rows 5, 100, 1023, 1024, 2047 and 2048 against the oracle (1024
+    and 2048 are the first rows of a level-2 and a level-1 block's row range)."""
     from kbe_inputs import make_config_inputs
     from kbe_inputs.packed import RowSource
     cfg, _, pS = make_config_inputs("c2")
@@ -124,7 +125,7 @@ def test_row_march_full_size_norb4(P):
     H = P.Hodlr(N, nlvl, norb, k=k, tol=tol, panel=16, max_rank=16)
     for n in range(N):
         H.append_row(P.RET, n, src.ret(n))
-    checks = [5, 100, 1023, 2047]
+    checks = [5, 100, 1023, 1024, 2047, 2048]
     nmax = max(checks)
     out = torch.zeros((N - k, N * npair), dtype=torch.complex128, device="cuda")
     say(f"row march: rows {k}..{N - 1} of the N_t = {N} grid")
