@@ -555,7 +555,7 @@ int hnessi_compress_block(const void* A, int rows, int cols, int lda, double tol
 /* hnessi_compress_block for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): the same factorization and results, with the scratch taken from
- * a static device array of about 23 MB that each GPU the library runs on
+ * a static device array of about 18 MB that each GPU the library runs on
  * holds until the process ends.  It calls no allocation routine and no
  * allocator hook.  rows and cols must be at most 4096 (HNESSI_E_ARG beyond);
  * other arguments and errors as for hnessi_compress_block.  Every call on one

@@ -8,13 +8,13 @@ namespace hn {
 
 // Width w = r + panel of a merge (the size of its small SVD) is at most the
 // merge width W, one of two compiled widths: 32 (128-row chunks) or 48
-// (64-row chunks, for rank capacities above 32 - panel).
+// (96-row chunks, for rank capacities above 32 - panel).
 constexpr int kWSmall = 32;
 constexpr int kWLarge = 48;
 constexpr int kW = kWLarge;             // widest merge
 constexpr int kMaxMergeBlk = 24;        // blocks merged by one panel (<= nlvl)
 
-__host__ __device__ constexpr int merge_ch(int W) { return W <= kWSmall ? 128 : 64; }   // rows of Z per chunk
+__host__ __device__ constexpr int merge_ch(int W) { return W <= kWSmall ? 128 : 96; }   // rows of Z per chunk
 __host__ __device__ constexpr int node_q(int W) { return 2 * W * W + W; }            // explicit Q (2W x W), W spare
 __host__ __device__ constexpr int chunk_q(int W) { return merge_ch(W) * W + W; }      // explicit Q (CH x W), W spare
 inline int merge_width(int rank_cap, int panel) { return rank_cap + panel <= kWSmall ? kWSmall : kWLarge; }
