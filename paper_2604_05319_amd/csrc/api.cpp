@@ -571,13 +571,25 @@ int create_impl(hnessi_hodlr_t* out, int nk, int nt, int nlvl, int norb, int k, 
         // one task per shared orbital index instead of per pair: the matrix-core
         // projections of norb 16 and the wave-per-pair projections of norb 4
         const int ntq = (H->mfproj || norb == 4) ? norb : npair;
-        for (int b = 0; b < nb; ++b)
-            for (int q = 0; q < ntq; ++q) {
+        if (norb == 4 && !H->mfproj) {
+            // the four tasks of a chunk (one per shared index) next to each other: the
+            // kernel places each such group on one XCD, whose L2 then fetches the
+            // chunk's Sigma rows once
+            for (int b = 0; b < nb; ++b) {
                 for (int ch = 0; ch < div_up(g.r1[b] - g.r0[b], H->kch); ++ch)
-                    ts.push_back(FactTask{c, b, q, 0, ch, g.r0[b] + ch * H->kch});
+                    for (int q = 0; q < ntq; ++q) ts.push_back(FactTask{c, b, q, 0, ch, g.r0[b] + ch * H->kch});
                 for (int ch = 0; ch < div_up(g.c1[b] - g.c0[b], H->kch); ++ch)
-                    ts.push_back(FactTask{c, b, q, 1, ch, g.r0[b]});
+                    for (int q = 0; q < ntq; ++q) ts.push_back(FactTask{c, b, q, 1, ch, g.r0[b]});
             }
+        } else {
+            for (int b = 0; b < nb; ++b)
+                for (int q = 0; q < ntq; ++q) {
+                    for (int ch = 0; ch < div_up(g.r1[b] - g.r0[b], H->kch); ++ch)
+                        ts.push_back(FactTask{c, b, q, 0, ch, g.r0[b] + ch * H->kch});
+                    for (int ch = 0; ch < div_up(g.c1[b] - g.c0[b], H->kch); ++ch)
+                        ts.push_back(FactTask{c, b, q, 1, ch, g.r0[b]});
+                }
+        }
         std::stable_sort(ts.begin(), ts.end(),
                          [](const FactTask& x, const FactTask& y) { return x.act < y.act; });
         H->ft_act[c].resize(ts.size());
@@ -896,7 +908,8 @@ int do_history(hnessi_hodlr_t H, int n, const void* sigR, const void* sigL, doub
     A.Voff = H->d_Voff;
     A.Loff = H->d_Loff;
     A.partoff = H->d_partoff;
-    A.nfpad = div_up(A.nf[0] + A.nf[1], 8) * 8;
+    // norb 4: groups of four projection tasks share an XCD (blocks of 32 workgroups)
+    A.nfpad = H->norb == 4 ? div_up(A.nf[0] + A.nf[1], 32) * 32 : div_up(A.nf[0] + A.nf[1], 8) * 8;
     A.nleaf = g.row_leaf[n] + 1;
     const int ngroups = H->norb <= 4 ? 1 : H->norb / 4;   // left-orbital groups of 4 waves
     // dense-piece tasks per leaf and per tail chunk: one per orbital pair for norb <= 4,

@@ -59,7 +59,7 @@ struct HistArgs {
     const FactTask* ft[2];
     const long long* partoff;  // per (comp, b, q, which): first chunk-partial slot
     int nf[2];       // active projection tasks per component
-    int nfpad;       // nf[0] + nf[1] rounded up to a multiple of 8
+    int nfpad;       // nf[0] + nf[1] rounded up to a multiple of 8 (of 32 at norb 4)
     int nleaf;       // active leaves
     int nleaftask;   // leaf tasks in the grid (after the XCD-grouping remap)
     int ntailchunk[2];

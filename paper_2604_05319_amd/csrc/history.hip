@@ -1036,8 +1036,14 @@ __global__ void __launch_bounds__(NT) hist_tasks(HistArgs A) {
     }
     rel -= A.nleaftask;
     }
-    if (rel >= A.nf[0] + A.nf[1]) return;
-    const FactTask& t = rel < A.nf[0] ? A.ft[0][rel] : A.ft[1][rel - A.nf[0]];
+    int idx = rel;
+    if constexpr (NORB == 4) {   // the four tasks of a chunk (consecutive in the list) on one XCD
+        int g, mem;
+        if (!xcd_group(rel, (A.nf[0] + A.nf[1]) / 4, 4, g, mem)) return;
+        idx = 4 * g + mem;
+    }
+    if (idx >= A.nf[0] + A.nf[1]) return;
+    const FactTask& t = idx < A.nf[0] ? A.ft[0][idx] : A.ft[1][idx - A.nf[0]];
     if constexpr (NORB == 4) fact_task_beta<NORB, FT>(A, t, smem);   // tasks per shared index
     else fact_task<NORB, FT>(A, t, smem);
 }
