@@ -72,9 +72,6 @@ __device__ inline cd gj_sol(const cd* T, int K, int ld, const int* prow, int p, 
     return T[q * ld + K + c] * mk(d.x * s, -d.y * s);
 }
 
-// M_m^{-1} for one column per thread (the matrix of the left side of the column's
-// equation, the same for every row): Gauss-Jordan with partial pivoting; the row
-// exchanges are value selects, so that every register index is static.
 // the end-weight fold of the row sums, 1 + (omega_{n-j} - 1)[n-j <= k], with omega staged
 // in LDS: a per-lane index into the weights held in the kernel arguments would be a
 // global-memory load at every use
@@ -82,6 +79,10 @@ __device__ inline double wend_lds(const double* om, int k, int n, int j) {
     const int d = n - j;
     return d <= k ? om[d] : 1.0;
 }
+
+// M_m^{-1} for one column per thread (the matrix of the left side of the column's
+// equation, the same for every row): Gauss-Jordan with partial pivoting; the row
+// exchanges are value selects, so that every register index is static.
 
 template <int NORB>
 __global__ void __launch_bounds__(256) march_minv(MarchArgs A, int mcount) {
